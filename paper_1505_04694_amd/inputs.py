@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs: structured unit-square grids and analytic metric fields.
+
+This module is the only code shared between the HIP path and the CPU oracle. It
+builds input arrays and holds none of the adaptation arithmetic (no edge length,
+no quality, no colouring). The paper's own workloads (Section 4: viscous
+fingering, structural compliance, the synthetic psi benchmark) need solvers or a
+Hessian-to-metric rule that the paper does not give, so analytic anisotropic
+metric fields of the same character stand in for them: a boundary layer along a
+sinusoidal curve, resolved at 0.01 across and 0.1 along it.
+
+Numbering (all configurations):
+  vertex id  = j*n + i,  x = i/(n-1), y = j/(n-1)
+  cell (i,j) is split along '/' = (i,j)-(i+1,j+1) when (i+j) is even, else along
+  '\\' = (i,j+1)-(i+1,j); the lower triangle comes first, element id =
+  2*(j*(n-1)+i) + k, every triangle counter-clockwise.
+Metric entries are stored per vertex as (m00, m01, m11) of the symmetric 2x2
+tensor [[m00, m01], [m01, m11]].
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# boundary tag bits, derived from exact coordinates of the unit square
+TAG_X0, TAG_X1, TAG_Y0, TAG_Y1 = 1, 2, 4, 8
+
+
+@dataclass
+class MeshInput:
+    xy: np.ndarray          # (V, 2) float64
+    tri: np.ndarray         # (T, 3) int32, counter-clockwise
+    metric: np.ndarray      # (V, 3) float64: m00, m01, m11
+    tags: np.ndarray        # (V,) uint8
+    n: int = 0
+    info: dict = field(default_factory=dict)
+
+    @property
+    def V(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def T(self) -> int:
+        return int(self.tri.shape[0])
+
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.xy, self.tri, self.metric, self.tags):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()[:16]
+
+
+def grid(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Criss-cross triangulation of the unit square on an n x n vertex grid."""
+    if n < 2:
+        raise ValueError("grid needs n >= 2")
+    i = np.arange(n, dtype=np.float64)
+    xs = i / (n - 1)
+    X, Y = np.meshgrid(xs, xs, indexing="xy")          # X[j, i] = x_i
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1).copy()
+    ci, cj = np.meshgrid(np.arange(n - 1), np.arange(n - 1), indexing="xy")
+    ci = ci.ravel().astype(np.int64)
+    cj = cj.ravel().astype(np.int64)
+    v00 = cj * n + ci
+    v10 = v00 + 1
+    v01 = v00 + n
+    v11 = v01 + 1
+    slash = ((ci + cj) % 2) == 0
+    lower = np.where(slash[:, None],
+                     np.stack([v00, v10, v11], 1),
+                     np.stack([v00, v10, v01], 1))
+    upper = np.where(slash[:, None],
+                     np.stack([v00, v11, v01], 1),
+                     np.stack([v10, v11, v01], 1))
+    tri = np.empty((2 * (n - 1) ** 2, 3), dtype=np.int32)
+    tri[0::2] = lower
+    tri[1::2] = upper
+    return xy, tri
+
+
+def unit_square_tags(xy: np.ndarray) -> np.ndarray:
+    x, y = xy[:, 0], xy[:, 1]
+    t = np.zeros(xy.shape[0], dtype=np.uint8)
+    t |= np.where(x == 0.0, TAG_X0, 0).astype(np.uint8)
+    t |= np.where(x == 1.0, TAG_X1, 0).astype(np.uint8)
+    t |= np.where(y == 0.0, TAG_Y0, 0).astype(np.uint8)
+    t |= np.where(y == 1.0, TAG_Y1, 0).astype(np.uint8)
+    return t
+
+
+def _tensor(theta: np.ndarray, ht: np.ndarray | float, hn: np.ndarray) -> np.ndarray:
+    """R(theta) diag(1/ht^2, 1/hn^2) R(theta)^T as (m00, m01, m11)."""
+    c, s = np.cos(theta), np.sin(theta)
+    lt = 1.0 / (np.asarray(ht) ** 2)
+    ln = 1.0 / (hn ** 2)
+    return np.stack([c * c * lt + s * s * ln, c * s * (lt - ln), s * s * lt + c * c * ln], axis=1)
+
+
+def layer_y(xy: np.ndarray, amp: float = 0.1, width: float = 0.05, ht: float = 0.1) -> np.ndarray:
+    """Boundary layer along y = 0.5 + amp*sin(2 pi x): h_n across, h_t along the curve."""
+    x, y = xy[:, 0], xy[:, 1]
+    d = y - 0.5 - amp * np.sin(2 * math.pi * x)
+    hn = 0.01 + 0.2 * (1.0 - np.exp(-np.abs(d) / width))
+    theta = np.arctan(2 * math.pi * amp * np.cos(2 * math.pi * x))
+    return _tensor(theta, ht, hn)
+
+
+def layer_x(xy: np.ndarray, amp: float = 0.1, width: float = 0.05, ht: float = 0.1) -> np.ndarray:
+    """The same layer along the curve x = 0.5 + amp*sin(2 pi y)."""
+    x, y = xy[:, 0], xy[:, 1]
+    d = x - 0.5 - amp * np.sin(2 * math.pi * y)
+    hn = 0.01 + 0.2 * (1.0 - np.exp(-np.abs(d) / width))
+    theta = np.arctan2(np.ones_like(y), 2 * math.pi * amp * np.cos(2 * math.pi * y))
+    return _tensor(theta, ht, hn)
+
+
+def jitter(xy: np.ndarray, tags: np.ndarray, n: int, seed: int, frac: float = 0.2) -> np.ndarray:
+    """Move interior vertices uniformly by up to frac*h per coordinate (h = 1/(n-1))."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (n - 1)
+    d = rng.uniform(-frac * h, frac * h, size=xy.shape)
+    out = xy.copy()
+    inner = tags == 0
+    out[inner] += d[inner]
+    return out
+
+
+def make_mesh(n: int, *, layers: int = 1, jitter_seed: int | None = None,
+              amp: float = 0.1, width: float = 0.05, ht: float = 0.1) -> MeshInput:
+    xy, tri = grid(n)
+    tags = unit_square_tags(xy)
+    if jitter_seed is not None:
+        xy = jitter(xy, tags, n, jitter_seed)
+    met = layer_y(xy, amp, width, ht)
+    if layers == 2:
+        met = met + layer_x(xy, amp, width, ht)
+    return MeshInput(xy=xy, tri=tri, metric=np.ascontiguousarray(met), tags=tags, n=n,
+                     info=dict(n=n, layers=layers, jitter_seed=jitter_seed,
+                               amp=amp, width=width, ht=ht))
+
+
+# ---- named workloads -------------------------------------------------------
+
+def config0() -> MeshInput:
+    """33 x 33 grid, one-layer field; priority seed 0."""
+    return make_mesh(33)
+
+
+def config1() -> MeshInput:
+    """1025 x 1025 grid, one-layer field; priority seed 0."""
+    return make_mesh(1025)
+
+
+def config2(n: int = 2049) -> MeshInput:
+    """2049 x 2049 grid, interior jitter 0.2h from seed 1, two-layer field."""
+    return make_mesh(n, layers=2, jitter_seed=1)
+
+
+def config4(n: int = 4097) -> MeshInput:
+    """4097 x 4097 grid, two-layer field, jitter from seed 3."""
+    return make_mesh(n, layers=2, jitter_seed=3)
+
+
+def batch_params(count: int = 256, seed: int = 2) -> list[dict]:
+    """Per-mesh draw for the batched workload: n log-uniform in [17, 513] and
+    the one-layer field's amplitude, layer width and tangential size."""
+    rng = np.random.default_rng(seed)
+    out = []
+    lo, hi = math.log(17.0), math.log(513.0)
+    for _ in range(count):
+        n = int(round(math.exp(rng.uniform(lo, hi))))
+        amp = float(rng.uniform(0.05, 0.2))
+        width = float(rng.uniform(0.02, 0.1))
+        ht = float(rng.uniform(0.05, 0.2))
+        out.append(dict(n=n, amp=amp, width=width, ht=ht))
+    return out
+
+
+def config3(count: int = 256, seed: int = 2) -> list[MeshInput]:
+    return [make_mesh(p["n"], amp=p["amp"], width=p["width"], ht=p["ht"])
+            for p in batch_params(count, seed)]
+
+
+PRIORITY_SEED = {0: 0, 1: 0, 2: 1, 3: 2, 4: 3}
