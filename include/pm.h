@@ -1,0 +1,182 @@
+/*
+ * pmesh: thread-parallel anisotropic mesh adaptation on one MI355X (gfx950).
+ *
+ * C ABI of the adaptation hot path after Rokos, Gorman, Jensen and Kelly,
+ * "Thread Parallelism for Highly Irregular Computation in Anisotropic Mesh
+ * Adaptation" (arXiv:1505.04694). The problem statement is Algorithm 1 of
+ * Sec. 2.3: a piecewise-linear triangle mesh M and a node-wise metric tensor
+ * field S go in, an adapted mesh comes out, through coarsening, refinement,
+ * swapping and smoothing (Sec. 2.4). Each kernel runs in rounds of
+ * independent sets from a vertex colouring (Sec. 3.2) and commits adjacency
+ * changes with a deferred update (Sec. 3.3).
+ *
+ * Conventions
+ *  - Every call returns a pm_status. No C++ exception crosses this boundary.
+ *  - Mesh storage lives in device memory owned by the handle. Input arrays
+ *    are copied; the caller keeps ownership of everything it passes.
+ *  - All device work is ordered on the stream given at creation (a
+ *    hipStream_t passed as void*, NULL = the null stream). A call returns
+ *    after its work is complete whenever it reports host-side results
+ *    (stats, Q, counts); pm_quality's gradient outputs are written on the
+ *    stream and complete when the call returns.
+ *  - One handle is not thread-safe; distinct handles are independent.
+ *  - After an error other than PM_E_DEVICE the handle stays usable and
+ *    pm_last_error() describes the failure.
+ *  - Vertex data layout: xy is V x 2 doubles (x, y); metric is V x 3 doubles
+ *    (m00, m01, m11) of the symmetric tensor [[m00, m01], [m01, m11]];
+ *    tri is T x 3 int32 vertex ids, counter-clockwise; tags is V bytes with
+ *    bit 1: x = 0, 2: x = 1, 4: y = 0, 8: y = 1 (the unit square's sides).
+ */
+#ifndef PMESH_PM_H
+#define PMESH_PM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PM_OK = 0,
+  PM_E_ARG = 1,      /* bad argument (null pointer, size, option range)        */
+  PM_E_MESH = 2,     /* invalid mesh: orientation, manifoldness, ids, metric   */
+  PM_E_NOMEM = 3,    /* device allocation failed                               */
+  PM_E_DEVICE = 4,   /* HIP runtime error; the handle should be destroyed      */
+  PM_W_NOT_CONVERGED = 5 /* round/pass cap reached; the mesh is valid          */
+} pm_status;
+
+enum { PM_MEM_HOST = 0, PM_MEM_DEVICE = 1 };
+enum { PM_SMOOTH_LAPLACE = 0, PM_SMOOTH_GRADIENT = 1 };
+
+typedef struct {
+  const double* xy;      /* V x 2 */
+  const int32_t* tri;    /* T x 3, counter-clockwise */
+  const double* metric;  /* V x 3 (m00, m01, m11), symmetric positive definite */
+  const uint8_t* tags;   /* V, or NULL: derived from exact coordinates 0 and 1 */
+  int64_t V, T;
+  int32_t mem_kind;      /* PM_MEM_HOST or PM_MEM_DEVICE for all four arrays */
+} pm_mesh_desc;
+
+/* Thresholds are squared metric lengths. Defaults (pm_default_options):
+ * L_low2 = 0.5, L_up2 = 2.0, q_min = 0.1, seed = 0, sweep = 0,
+ * coarsen_rounds = 200, swap_rounds = 100, refine_passes = 32,
+ * smooth_kind = PM_SMOOTH_LAPLACE, smooth_sweeps = 1, slack = 2.0. */
+typedef struct {
+  double L_low2;          /* collapse an edge when L^2 < L_low2                 */
+  double L_up2;           /* split an edge when L^2 > L_up2                     */
+  double q_min;           /* a collapse may not create an element with q < q_min */
+  uint64_t seed;          /* priority seed (fixed at creation; see pm_mesh_create) */
+  int32_t sweep;          /* outer sweep index, part of the priority context    */
+  int32_t coarsen_rounds; /* round cap of pm_coarsen                            */
+  int32_t swap_rounds;    /* round cap of pm_swap                               */
+  int32_t refine_passes;  /* pass cap of pm_refine                              */
+  int32_t smooth_kind;    /* PM_SMOOTH_LAPLACE or PM_SMOOTH_GRADIENT            */
+  int32_t smooth_sweeps;  /* coloured sweeps of pm_smooth                       */
+  double slack;           /* adjacency row capacity factor (>= 1)               */
+  int32_t wg_size;        /* work-group size, 0 = library default               */
+  int32_t reserved;
+} pm_options;
+
+/* Per-phase counters, all integers:
+ * v[0] rounds (coarsen, swap), passes (refine), sweeps (smooth)
+ * v[1] vertices coloured, summed over colourings
+ * v[2] members evaluated after re-validation
+ * v[3] members deferred by re-validation
+ * v[4] committed operations: collapses, split edges, flips, accepted moves
+ * v[5] colours used, summed over colourings
+ * v[6] edges tested by refinement
+ * v[7] 1 when the phase ran out of work (converged)
+ * v[8] vertices created, v[9] elements created
+ * v[10] deferred-update records committed
+ * v[11] adjacency rows relocated by the commit
+ * v[12] JP colouring iterations */
+typedef struct {
+  int64_t v[16];
+} pm_stats;
+
+typedef struct pm_mesh pm_mesh;
+
+/* Fills o with the defaults listed above. */
+pm_status pm_default_options(pm_options* o);
+
+/* Builds the device store (Sec. 3.1: per-vertex adjacency lists of vertices
+ * and elements) from a triangle list: slack-padded rows, each a sorted id set.
+ * Validates ids, orientation (every triangle counter-clockwise with positive
+ * area), manifoldness (no directed edge used twice), finite SPD metric.
+ * o may be NULL (defaults); o->seed becomes the handle's priority seed.
+ * stream: hipStream_t as void*. On success *out owns all device memory. */
+pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* stream, pm_mesh** out);
+
+/* Frees the handle and all its device memory. NULL is accepted. */
+pm_status pm_mesh_destroy(pm_mesh* m);
+
+/* Current slot counts. After pm_coarsen all slots are live (the phase ends
+ * with a stable renumbering); otherwise dead slots may be included. */
+pm_status pm_mesh_sizes(const pm_mesh* m, int64_t* V, int64_t* T);
+
+/* Copies the live mesh out (V x 2, T x 3, V x 3, V) in slot order, which is
+ * the live order after pm_coarsen. Any output may be NULL. mem_kind says
+ * whether the outputs are host or device pointers; they must hold the sizes
+ * reported by pm_mesh_sizes. valive/talive (host or device, may be NULL)
+ * receive 1 for live slots. */
+pm_status pm_mesh_export(pm_mesh* m, double* xy, int32_t* tri, double* metric, uint8_t* tags,
+                         uint8_t* valive, uint8_t* talive, int32_t mem_kind);
+
+/* Adjacency rows as host CSR: nn_off/ne_off hold V+1 entries. Call first with
+ * NULL arrays to get the totals. */
+pm_status pm_mesh_rows(pm_mesh* m, int64_t* nn_total, int64_t* ne_total, int64_t* nn_off, int32_t* nn,
+                       int64_t* ne_off, int32_t* ne);
+
+/* Jones-Plassmann colouring (Sec. 3.2) of the subgraph induced by the active
+ * live vertices: priorities are the uint32 SplitMix64 values of
+ * (handle seed, ctx, vertex id), ties by id, and a vertex takes the smallest
+ * colour unused by its active neighbours of larger key (the result equals the
+ * greedy colouring in descending key order). active: V bytes, host or device
+ * per mem_kind, NULL = all live vertices. colour_out: V int32 (-1 inactive),
+ * host or device per mem_kind, may be NULL. */
+pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* colour_out,
+                    int32_t* ncolours, int32_t mem_kind);
+
+/* Coarsening (Sec. 2.4.1): rounds of edge collapses over colour classes until
+ * no vertex with a short edge is left or o->coarsen_rounds is reached; ends
+ * with a stable renumbering of live vertices and elements. */
+pm_status pm_coarsen(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Refinement (Sec. 2.4.2): passes that split every edge with L^2 > L_up2 and
+ * cut elements with the 1-, 2- and 3-edge templates, until none is long or
+ * o->refine_passes is reached. */
+pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Swapping (Sec. 2.4.3): rounds of edge flips that raise the smaller quality
+ * of the two elements, until none is left or o->swap_rounds is reached. */
+pm_status pm_swap(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Smoothing (Sec. 2.4.4): o->smooth_sweeps coloured sweeps over interior
+ * vertices, Laplacian in the metric or a gradient step on the local quality
+ * functional, each move kept only if the patch's minimum quality does not
+ * drop and every area stays positive. */
+pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Quality functional (Sec. 2.2): Q = sum over elements of the mean ratio
+ * q = 4 sqrt(3) sqrt(det M) A / sum of squared metric edge lengths, M the mean
+ * of the element's vertex tensors; qmin = the smallest q. Q and qmin are host
+ * pointers (may be NULL). dQdx (V x 2) and dQdM (V x 3, stored entries) are
+ * device pointers or NULL; when given, the adjoint is written there. */
+pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM);
+
+/* Diagnostic: computes quot[i] = a[i] / b[i] and root[i] = sqrt(a[i]) in FP64
+ * on the current device (host arrays of n doubles), so a caller can check
+ * that the device rounds division and square root exactly as IEEE-754 binary64
+ * does; every threshold decision of the path relies on that. */
+pm_status pm_fp64_selfcheck(const double* a, const double* b, int64_t n, double* quot, double* root);
+
+/* Message for the last non-OK status on this handle (never NULL). With a NULL
+ * handle: the message of the calling thread's last failed pm_mesh_create. */
+const char* pm_last_error(const pm_mesh* m);
+
+/* Library build string. */
+const char* pm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,763 @@
+// C ABI and host-side phase drivers: round loops, colour-class sequencing,
+// commit points, compaction and store growth.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pm.h"
+#include "kern.hpp"
+
+using namespace pm;
+
+namespace {
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct pm_mesh {
+  hipStream_t s = nullptr;
+  Store st;
+  uint64_t seed = 0;
+  double slack = 2.0;
+  std::string err;
+  int* ctr = nullptr;   // device counters
+  int* hctr = nullptr;  // pinned mirror
+  double* hq = nullptr; // pinned doubles
+  // scratch
+  DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, partial, mid;
+  DBuf<uint8_t> act, col, nxt, u8tmp;
+  DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
+  DBuf<double> qpart;
+  int64_t peak_bytes = 0, cur_bytes = 0;
+};
+
+namespace {
+
+// message of the last failed pm_mesh_create on this thread (no handle survives it)
+thread_local std::string g_create_err;
+
+pm_status fail(pm_mesh* m, pm_status st, const std::string& msg) {
+  if (m) m->err = msg;
+  return st;
+}
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(m, PM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define TRY(x)                      \
+  do {                              \
+    pm_status r_ = (x);             \
+    if (r_ != PM_OK) return r_;     \
+  } while (0)
+
+template <class T>
+pm_status dalloc(pm_mesh* m, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  }
+  m->cur_bytes += (int64_t)(n * sizeof(T));
+  m->peak_bytes = std::max(m->peak_bytes, m->cur_bytes);
+  return PM_OK;
+}
+template <class T>
+void dfree(pm_mesh* m, T*& p, size_t n) {
+  if (p) {
+    (void)hipFree(p);
+    m->cur_bytes -= (int64_t)(std::max<size_t>(n, 1) * sizeof(T));
+  }
+  p = nullptr;
+}
+
+// grow-only scratch; contents are not preserved; zero = clear new memory
+template <class T>
+pm_status ensure(pm_mesh* m, DBuf<T>& b, size_t n, bool zero = false) {
+  if (b.n >= n && b.p) return PM_OK;
+  HIPCHK(hipStreamSynchronize(m->s));
+  dfree(m, b.p, b.n);
+  b.n = 0;
+  size_t want = std::max<size_t>(n + n / 4, 64);
+  TRY(dalloc(m, &b.p, want));
+  b.n = want;
+  if (zero) HIPCHK(hipMemsetAsync(b.p, 0, want * sizeof(T), m->s));
+  return PM_OK;
+}
+
+pm_status sync(pm_mesh* m) {
+  HIPCHK(hipStreamSynchronize(m->s));
+  return PM_OK;
+}
+
+// copy device counters [lo, lo+n) to the pinned mirror and wait
+pm_status read_ctr(pm_mesh* m, int lo, int n) {
+  HIPCHK(hipMemcpyAsync(m->hctr + lo, m->ctr + lo, n * sizeof(int), hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipStreamSynchronize(m->s));
+  return PM_OK;
+}
+
+pm_status check_err(pm_mesh* m) {
+  TRY(read_ctr(m, C_ERR, 1));
+  int e = m->hctr[C_ERR];
+  if (!e) return PM_OK;
+  std::string msg = "device error bits " + std::to_string(e) + ":";
+  if (e & E_MESH_ID) msg += " element id out of range or repeated;";
+  if (e & E_MESH_ORIENT) msg += " element not counter-clockwise (area <= 0);";
+  if (e & E_MESH_MANIFOLD) msg += " non-manifold edge/vertex or inconsistent orientation;";
+  if (e & E_MESH_METRIC) msg += " metric not SPD or non-finite coordinates;";
+  if (e & (E_NN_POOL | E_NE_POOL)) msg += " adjacency pool exhausted;";
+  if (e & E_STAGE) msg += " commit staging exhausted;";
+  if (e & E_REC) msg += " record buffer exhausted;";
+  if (e & E_COLOURS) msg += " more than 254 colours;";
+  set_int(m->ctr + C_ERR, 0, m->s);
+  pm_status st = (e & (E_MESH_ID | E_MESH_ORIENT | E_MESH_MANIFOLD | E_MESH_METRIC)) ? PM_E_MESH : PM_E_NOMEM;
+  if (e & E_COLOURS) st = PM_E_MESH;
+  return fail(m, st, msg);
+}
+
+// ---- store allocation -----------------------------------------------------------------------
+pm_status grow_vertices(pm_mesh* m, int need) {
+  Store& s = m->st;
+  if (need <= s.Vcap) return PM_OK;
+  int nc = std::max(need, s.Vcap + s.Vcap / 2);
+  double2* xy;
+  Met* met;
+  uint8_t *tag, *va;
+  Hdr* hdr;
+  int2* cap;
+  TRY(dalloc(m, &xy, nc));
+  TRY(dalloc(m, &met, nc));
+  TRY(dalloc(m, &tag, nc));
+  TRY(dalloc(m, &va, nc));
+  TRY(dalloc(m, &hdr, nc));
+  TRY(dalloc(m, &cap, nc));
+  HIPCHK(hipMemsetAsync(va, 0, nc, m->s));
+  HIPCHK(hipMemsetAsync(hdr, 0, sizeof(Hdr) * (size_t)nc, m->s));
+  HIPCHK(hipMemsetAsync(cap, 0, sizeof(int2) * (size_t)nc, m->s));
+  if (s.V > 0) {
+    HIPCHK(hipMemcpyAsync(xy, s.xy, sizeof(double2) * s.V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(met, s.met, sizeof(Met) * s.V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(tag, s.tag, s.V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(va, s.valive, s.V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(hdr, s.hdr, sizeof(Hdr) * s.V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(cap, s.cap, sizeof(int2) * s.V, hipMemcpyDeviceToDevice, m->s));
+  }
+  HIPCHK(hipStreamSynchronize(m->s));
+  dfree(m, s.xy, s.Vcap);
+  dfree(m, s.met, s.Vcap);
+  dfree(m, s.tag, s.Vcap);
+  dfree(m, s.valive, s.Vcap);
+  dfree(m, s.hdr, s.Vcap);
+  dfree(m, s.cap, s.Vcap);
+  s.xy = xy;
+  s.met = met;
+  s.tag = tag;
+  s.valive = va;
+  s.hdr = hdr;
+  s.cap = cap;
+  s.Vcap = nc;
+  return PM_OK;
+}
+
+pm_status grow_elements(pm_mesh* m, int need) {
+  Store& s = m->st;
+  if (need <= s.Tcap) return PM_OK;
+  int nc = std::max(need, s.Tcap + s.Tcap / 2);
+  Elem* tri;
+  TRY(dalloc(m, &tri, nc));
+  HIPCHK(hipMemsetAsync(tri, 0, sizeof(Elem) * (size_t)nc, m->s));
+  if (s.T > 0) HIPCHK(hipMemcpyAsync(tri, s.tri, sizeof(Elem) * s.T, hipMemcpyDeviceToDevice, m->s));
+  HIPCHK(hipStreamSynchronize(m->s));
+  dfree(m, s.tri, s.Tcap);
+  s.tri = tri;
+  s.Tcap = nc;
+  return PM_OK;
+}
+
+// (Re)build every adjacency row from the element list into fresh pools.
+pm_status build_rows(pm_mesh* m) {
+  Store& st = m->st;
+  int V = st.V;
+  TRY(ensure(m, m->vt0, V));
+  TRY(ensure(m, m->vt1, V));
+  TRY(ensure(m, m->vt2, V));
+  TRY(ensure(m, m->vt3, V));
+  TRY(ensure(m, m->vt4, V));
+  TRY(ensure(m, m->partial, scan_partials_needed(std::max(V, st.T)) + 2));
+  zero_ints(m->vt0.p, V, m->s);
+  build_count(st, m->vt0.p, m->s);
+  build_caps(st, m->vt0.p, m->slack, m->vt1.p, m->vt2.p, m->s);
+  scan_excl(m->vt1.p, m->vt3.p, V, m->ctr + C_TOTAL, m->partial.p, m->s);
+  scan_excl(m->vt2.p, m->vt4.p, V, m->ctr + C_TOTAL2, m->partial.p, m->s);
+  TRY(read_ctr(m, C_TOTAL, 2));
+  int64_t nn_used = m->hctr[C_TOTAL], ne_used = m->hctr[C_TOTAL2];
+  // room for rows that outgrow their slot before the next rebuild
+  int64_t nn_need = 3 * nn_used + 4096, ne_need = 3 * ne_used + 4096;
+  if (nn_need > INT32_MAX || ne_need > INT32_MAX) return fail(m, PM_E_NOMEM, "adjacency pool beyond 2^31 entries");
+  if (st.nn_pool < nn_need || st.ne_pool < ne_need) {
+    TRY(sync(m));
+    dfree(m, st.nn, st.nn_pool);
+    dfree(m, st.ne, st.ne_pool);
+    st.nn_pool = st.ne_pool = 0;
+    TRY(dalloc(m, &st.nn, nn_need));
+    TRY(dalloc(m, &st.ne, ne_need));
+    st.nn_pool = nn_need;
+    st.ne_pool = ne_need;
+  }
+  set_int(m->ctr + C_NN_TOP, (int)nn_used, m->s);
+  set_int(m->ctr + C_NE_TOP, (int)ne_used, m->s);
+  set_headers(st, m->vt3.p, m->vt4.p, m->vt1.p, m->vt2.p, m->s);
+  build_fill(st, nullptr, m->s);
+  build_finish(st, m->ctr, m->s);
+  return check_err(m);
+}
+
+// free pool space check between rounds: rebuild (repack) when a round could
+// plausibly exhaust it
+pm_status maybe_repack(pm_mesh* m) {
+  TRY(read_ctr(m, C_NN_TOP, 2));
+  int64_t nn_top = m->hctr[C_NN_TOP], ne_top = m->hctr[C_NE_TOP];
+  if (nn_top * 3 > m->st.nn_pool * 2 || ne_top * 3 > m->st.ne_pool * 2) return build_rows(m);
+  return PM_OK;
+}
+
+pm_status ensure_phase_scratch(pm_mesh* m) {
+  int V = std::max(m->st.V, 1), T = std::max(m->st.T, 1);
+  TRY(ensure(m, m->listA, V));
+  TRY(ensure(m, m->listB, V));
+  TRY(ensure(m, m->jpU0, V));
+  TRY(ensure(m, m->jpU1, V));
+  TRY(ensure(m, m->cls, V));
+  TRY(ensure(m, m->act, V, true));
+  TRY(ensure(m, m->col, V));
+  TRY(ensure(m, m->nxt, V, true));
+  TRY(ensure(m, m->dirty, V, true));
+  TRY(ensure(m, m->pend, V, true));
+  TRY(ensure(m, m->dlist, V));
+  TRY(ensure(m, m->dbase, V));
+  int rec = 2 * V + 64;
+  TRY(ensure(m, m->rec_row, rec));
+  TRY(ensure(m, m->rec_val, rec));
+  TRY(ensure(m, m->rec_off, rec));
+  // staging bound: 3 (|NE(x)| + additions) + 4 per dirty row, summed
+  size_t stage = 12 * (size_t)T + 10 * (size_t)V + 1024;
+  TRY(ensure(m, m->stage, stage));
+  return PM_OK;
+}
+
+Commit commit_of(pm_mesh* m) {
+  Commit c;
+  c.dirty = m->dirty.p;
+  c.dlist = m->dlist.p;
+  c.pend = m->pend.p;
+  c.dbase = m->dbase.p;
+  c.rec_row = m->rec_row.p;
+  c.rec_val = m->rec_val.p;
+  c.rec_off = m->rec_off.p;
+  c.rec_cap = (int)std::min<size_t>(m->rec_row.n, INT32_MAX);
+  c.stage = m->stage.p;
+  c.stage_cap = (int64_t)m->stage.n;
+  c.nxt = m->nxt.p;
+  return c;
+}
+
+struct Classes {
+  int ncol = 0;
+  std::vector<int> size, off;
+  int jp_iters = 0;
+};
+
+// Jones-Plassmann on list A (n entries): colours in m->col, act flags set,
+// class lists in m->cls. The caller clears the act flags afterwards.
+pm_status colour_list(pm_mesh* m, const int* A, int n, uint64_t sseed, Classes& out) {
+  out = Classes();
+  if (n == 0) return PM_OK;
+  Round rd{sseed, nullptr};
+  jp_init(A, n, m->col.p, m->act.p, m->s);
+  const int* cur = A;
+  int cn = n;
+  int* bufs[2] = {m->jpU0.p, m->jpU1.p};
+  int it = 0;
+  while (cn > 0) {
+    int* nxt = bufs[it & 1];
+    set_int(m->ctr + C_LIST_A, 0, m->s);
+    jp_step(m->st, cur, cn, nxt, m->ctr + C_LIST_A, m->act.p, m->col.p, rd, m->ctr, m->s);
+    TRY(read_ctr(m, C_LIST_A, 1));
+    int nn = m->hctr[C_LIST_A];
+    if (nn >= cn) return fail(m, PM_E_DEVICE, "colouring made no progress");
+    cn = nn;
+    cur = nxt;
+    ++it;
+  }
+  out.jp_iters = it;
+  zero_ints(m->ctr + C_HIST, 256, m->s);
+  class_lists(A, n, m->col.p, m->ctr, m->cls.p, m->s);
+  TRY(read_ctr(m, C_HIST, C_NCOL + 1 - C_HIST));
+  TRY(check_err(m));
+  out.ncol = m->hctr[C_NCOL];
+  out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
+  out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
+  return PM_OK;
+}
+
+void stats_zero(pm_mesh* m) { zero_ints(m->ctr + C_EVAL, 6, m->s); }
+
+pm_status stats_read(pm_mesh* m, pm_stats* st) {
+  TRY(read_ctr(m, C_EVAL, 6));
+  if (st) {
+    st->v[2] += m->hctr[C_EVAL];
+    st->v[3] += m->hctr[C_DEFER];
+    st->v[4] += m->hctr[C_COMMIT];
+    st->v[11] += m->hctr[C_RELOC];
+    st->v[10] += m->hctr[C_RECS];
+    st->v[6] += m->hctr[C_EDGES];
+  }
+  return PM_OK;
+}
+
+pm_status compact(pm_mesh* m) {
+  Store& st = m->st;
+  int V = st.V, T = st.T;
+  TRY(ensure(m, m->vt0, V));
+  TRY(ensure(m, m->vt1, V));
+  TRY(ensure(m, m->tt0, T));
+  TRY(ensure(m, m->tt1, T));
+  TRY(ensure(m, m->partial, scan_partials_needed(std::max(V, T)) + 2));
+  flag_live_vertices(st, m->vt0.p, m->s);
+  scan_excl(m->vt0.p, m->vt1.p, V, m->ctr + C_TOTAL, m->partial.p, m->s);
+  flag_live_elements(st, m->tt0.p, m->s);
+  scan_excl(m->tt0.p, m->tt1.p, T, m->ctr + C_TOTAL2, m->partial.p, m->s);
+  TRY(read_ctr(m, C_TOTAL, 2));
+  int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
+  double2* xy2;
+  Met* met2;
+  uint8_t* tag2;
+  Elem* tri2;
+  TRY(dalloc(m, &xy2, st.Vcap));
+  TRY(dalloc(m, &met2, st.Vcap));
+  TRY(dalloc(m, &tag2, st.Vcap));
+  TRY(dalloc(m, &tri2, st.Tcap));
+  compact_vertices(st, m->vt1.p, xy2, met2, tag2, m->s);
+  compact_elements(st, m->vt1.p, m->tt1.p, tri2, m->s);
+  HIPCHK(hipStreamSynchronize(m->s));
+  dfree(m, st.xy, st.Vcap);
+  dfree(m, st.met, st.Vcap);
+  dfree(m, st.tag, st.Vcap);
+  dfree(m, st.tri, st.Tcap);
+  st.xy = xy2;
+  st.met = met2;
+  st.tag = tag2;
+  st.tri = tri2;
+  st.V = nv;
+  st.T = nt;
+  fill_u8(st.valive, st.Vcap, 0, m->s);
+  fill_u8(st.valive, nv, 1, m->s);
+  return build_rows(m);
+}
+
+bool bad_opts(const pm_options* o) {
+  return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
+         o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
+         (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0);
+}
+
+// rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1)
+pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
+  TRY(ensure_phase_scratch(m));
+  int mode = kind == 0 ? 1 : 2;
+  int max_rounds = kind == 0 ? o->coarsen_rounds : o->swap_rounds;
+  int phase = kind == 0 ? PH_COARSEN : PH_SWAP;
+  double qmin2 = o->q_min * o->q_min;
+  stats_zero(m);
+  set_int(m->ctr + C_LIST_B, 0, m->s);
+  select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  TRY(read_ctr(m, C_LIST_B, 1));
+  int nA = m->hctr[C_LIST_B];
+  int r = 0;
+  Commit cm = commit_of(m);
+  while (nA > 0 && r < max_rounds) {
+    TRY(maybe_repack(m));
+    uint64_t sseed = stream_seed(m->seed, make_ctx(o->sweep, phase, r));
+    Classes cl;
+    TRY(colour_list(m, m->listA.p, nA, sseed, cl));
+    st->v[1] += nA;
+    st->v[5] += cl.ncol;
+    st->v[12] += cl.jp_iters;
+    for (int c = 0; c < cl.ncol; ++c) {
+      if (cl.size[c] == 0) continue;
+      zero_ints(m->ctr + C_DIRTY, 3, m->s);  // dirty, records, staging
+      OpArgs a{m->act.p, m->col.p, c, Round{sseed, nullptr}, o->L_low2, qmin2};
+      if (kind == 0) collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
+      else flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
+      commit_rows(m->st, cm, m->ctr, m->st.V, m->s);
+    }
+    set_flags(m->listA.p, nA, m->act.p, 0, m->s);
+    set_int(m->ctr + C_LIST_B, 0, m->s);
+    select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->s);
+    TRY(read_ctr(m, C_LIST_B, 1));
+    TRY(check_err(m));
+    nA = m->hctr[C_LIST_B];
+    std::swap(m->listA, m->listB);
+    ++r;
+  }
+  TRY(stats_read(m, st));
+  st->v[0] = r;
+  st->v[7] = nA == 0 ? 1 : 0;
+  return PM_OK;
+}
+
+void fill_defaults(pm_options* o) {
+  o->L_low2 = 0.5;
+  o->L_up2 = 2.0;
+  o->q_min = 0.1;
+  o->seed = 0;
+  o->sweep = 0;
+  o->coarsen_rounds = 200;
+  o->swap_rounds = 100;
+  o->refine_passes = 32;
+  o->smooth_kind = PM_SMOOTH_LAPLACE;
+  o->smooth_sweeps = 1;
+  o->slack = 2.0;
+  o->wg_size = 0;
+  o->reserved = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pm_version(void) { return "pmesh 0.1 gfx950"; }
+
+pm_status pm_default_options(pm_options* o) {
+  if (!o) return PM_E_ARG;
+  fill_defaults(o);
+  return PM_OK;
+}
+
+const char* pm_last_error(const pm_mesh* m) {
+  if (!m) return g_create_err.empty() ? "null handle" : g_create_err.c_str();
+  return m->err.c_str();
+}
+
+pm_status pm_mesh_destroy(pm_mesh* m) {
+  if (!m) return PM_OK;
+  (void)hipStreamSynchronize(m->s);
+  Store& s = m->st;
+  dfree(m, s.xy, s.Vcap);
+  dfree(m, s.met, s.Vcap);
+  dfree(m, s.tag, s.Vcap);
+  dfree(m, s.valive, s.Vcap);
+  dfree(m, s.hdr, s.Vcap);
+  dfree(m, s.cap, s.Vcap);
+  dfree(m, s.tri, s.Tcap);
+  dfree(m, s.nn, s.nn_pool);
+  dfree(m, s.ne, s.ne_pool);
+  DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
+                     &m->vt4, &m->tt0, &m->tt1, &m->partial, &m->mid, &m->dirty, &m->dlist, &m->pend, &m->dbase,
+                     &m->rec_row, &m->rec_val, &m->rec_off, &m->stage};
+  for (auto* b : ib) dfree(m, b->p, b->n);
+  DBuf<uint8_t>* ub[] = {&m->act, &m->col, &m->nxt, &m->u8tmp};
+  for (auto* b : ub) dfree(m, b->p, b->n);
+  dfree(m, m->qpart.p, m->qpart.n);
+  if (m->ctr) (void)hipFree(m->ctr);
+  if (m->hctr) (void)hipHostFree(m->hctr);
+  if (m->hq) (void)hipHostFree(m->hq);
+  delete m;
+  return PM_OK;
+}
+
+pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* stream, pm_mesh** out) {
+  if (!out) return PM_E_ARG;
+  *out = nullptr;
+  if (!d || !d->xy || !d->tri || !d->metric) return PM_E_ARG;
+  if (d->V < 3 || d->T < 1 || d->V > (1ll << 30) || d->T > (1ll << 30)) return PM_E_ARG;
+  if (d->mem_kind != PM_MEM_HOST && d->mem_kind != PM_MEM_DEVICE) return PM_E_ARG;
+  pm_options def;
+  fill_defaults(&def);
+  if (!o) o = &def;
+  if (bad_opts(o)) return PM_E_ARG;
+  pm_mesh* m = new (std::nothrow) pm_mesh();
+  if (!m) return PM_E_NOMEM;
+  m->s = (hipStream_t)stream;
+  m->seed = o->seed;
+  m->slack = o->slack;
+  g_create_err.clear();
+  auto bail = [&](pm_status st) {
+    g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
+    pm_mesh_destroy(m);
+    return st;
+  };
+  if (hipMalloc((void**)&m->ctr, C_COUNT * sizeof(int)) != hipSuccess) return bail(PM_E_NOMEM);
+  if (hipHostMalloc((void**)&m->hctr, C_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(PM_E_NOMEM);
+  if (hipHostMalloc((void**)&m->hq, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(PM_E_NOMEM);
+  zero_ints(m->ctr, C_COUNT, m->s);
+  int V = (int)d->V, T = (int)d->T;
+  if (grow_vertices(m, V) != PM_OK || grow_elements(m, T) != PM_OK) return bail(PM_E_NOMEM);
+  Store& st = m->st;
+  st.V = V;
+  st.T = T;
+  hipMemcpyKind kind = d->mem_kind == PM_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  int* tri3 = nullptr;
+  double* xyraw = nullptr;
+  if (dalloc(m, &tri3, 3 * (size_t)T) != PM_OK || dalloc(m, &xyraw, 2 * (size_t)V) != PM_OK)
+    return bail(PM_E_NOMEM);
+  bool ok = hipMemcpyAsync(tri3, d->tri, sizeof(int) * 3 * (size_t)T, kind, m->s) == hipSuccess &&
+            hipMemcpyAsync(xyraw, d->xy, sizeof(double) * 2 * (size_t)V, kind, m->s) == hipSuccess &&
+            hipMemcpyAsync(st.met, d->metric, sizeof(double) * 3 * (size_t)V, kind, m->s) == hipSuccess;
+  if (ok && d->tags) ok = hipMemcpyAsync(st.tag, d->tags, (size_t)V, kind, m->s) == hipSuccess;
+  if (!ok) {
+    dfree(m, tri3, 3 * (size_t)T);
+    dfree(m, xyraw, 2 * (size_t)V);
+    return bail(PM_E_DEVICE);
+  }
+  xy_in(xyraw, V, st.xy, m->s);
+  if (!d->tags) tags_from_xy(st.xy, V, st.tag, m->s);
+  tri_in(tri3, T, st.tri, m->s);
+  fill_u8(st.valive, V, 1, m->s);
+  (void)hipStreamSynchronize(m->s);
+  dfree(m, tri3, 3 * (size_t)T);
+  dfree(m, xyraw, 2 * (size_t)V);
+  k_validate(st, m->ctr, m->s);
+  pm_status r = check_err(m);
+  if (r != PM_OK) return bail(r);
+  r = build_rows(m);
+  if (r != PM_OK) return bail(r);
+  *out = m;
+  return PM_OK;
+}
+
+pm_status pm_mesh_sizes(const pm_mesh* m, int64_t* V, int64_t* T) {
+  if (!m) return PM_E_ARG;
+  if (V) *V = m->st.V;
+  if (T) *T = m->st.T;
+  return PM_OK;
+}
+
+pm_status pm_mesh_export(pm_mesh* m, double* xy, int32_t* tri, double* metric, uint8_t* tags, uint8_t* valive,
+                         uint8_t* talive, int32_t mem_kind) {
+  if (!m) return PM_E_ARG;
+  if (mem_kind != PM_MEM_HOST && mem_kind != PM_MEM_DEVICE) return fail(m, PM_E_ARG, "bad mem_kind");
+  Store& st = m->st;
+  hipMemcpyKind k = mem_kind == PM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (xy) HIPCHK(hipMemcpyAsync(xy, st.xy, sizeof(double2) * st.V, k, m->s));
+  if (metric) HIPCHK(hipMemcpyAsync(metric, st.met, sizeof(Met) * st.V, k, m->s));
+  if (tags) HIPCHK(hipMemcpyAsync(tags, st.tag, st.V, k, m->s));
+  if (valive) HIPCHK(hipMemcpyAsync(valive, st.valive, st.V, k, m->s));
+  if (tri || talive) {
+    TRY(ensure(m, m->tt0, 3 * (size_t)st.T));
+    TRY(ensure(m, m->u8tmp, (size_t)std::max(st.T, 1)));
+    export_tri(st, m->tt0.p, m->u8tmp.p, m->s);
+    if (tri) HIPCHK(hipMemcpyAsync(tri, m->tt0.p, sizeof(int) * 3 * (size_t)st.T, k, m->s));
+    if (talive) HIPCHK(hipMemcpyAsync(talive, m->u8tmp.p, st.T, k, m->s));
+  }
+  return sync(m);
+}
+
+pm_status pm_mesh_rows(pm_mesh* m, int64_t* nn_total, int64_t* ne_total, int64_t* nn_off, int32_t* nn,
+                       int64_t* ne_off, int32_t* ne) {
+  if (!m || !nn_total || !ne_total) return PM_E_ARG;
+  Store& st = m->st;
+  std::vector<Hdr> hdr(st.V);
+  HIPCHK(hipMemcpyAsync(hdr.data(), st.hdr, sizeof(Hdr) * st.V, hipMemcpyDeviceToHost, m->s));
+  TRY(sync(m));
+  int64_t a = 0, b = 0;
+  for (int v = 0; v < st.V; ++v) {
+    a += hdr[v].y;
+    b += hdr[v].w;
+  }
+  *nn_total = a;
+  *ne_total = b;
+  if (!nn_off || !nn || !ne_off || !ne) return PM_OK;
+  std::vector<int> pnn(st.nn_pool), pne(st.ne_pool);
+  HIPCHK(hipMemcpyAsync(pnn.data(), st.nn, sizeof(int) * st.nn_pool, hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipMemcpyAsync(pne.data(), st.ne, sizeof(int) * st.ne_pool, hipMemcpyDeviceToHost, m->s));
+  TRY(sync(m));
+  a = b = 0;
+  for (int v = 0; v < st.V; ++v) {
+    nn_off[v] = a;
+    ne_off[v] = b;
+    for (int k = 0; k < hdr[v].y; ++k) nn[a++] = pnn[hdr[v].x + k];
+    for (int k = 0; k < hdr[v].w; ++k) ne[b++] = pne[hdr[v].z + k];
+  }
+  nn_off[st.V] = a;
+  ne_off[st.V] = b;
+  return PM_OK;
+}
+
+pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* colour_out, int32_t* ncolours,
+                    int32_t mem_kind) {
+  if (!m) return PM_E_ARG;
+  if (mem_kind != PM_MEM_HOST && mem_kind != PM_MEM_DEVICE) return fail(m, PM_E_ARG, "bad mem_kind");
+  TRY(ensure_phase_scratch(m));
+  Store& st = m->st;
+  const uint8_t* act_in = nullptr;
+  if (active) {
+    TRY(ensure(m, m->u8tmp, st.V));
+    HIPCHK(hipMemcpyAsync(m->u8tmp.p, active, st.V,
+                          mem_kind == PM_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, m->s));
+    act_in = m->u8tmp.p;
+  }
+  set_int(m->ctr + C_LIST_B, 0, m->s);
+  select_vertices(st, 0, 0.0, act_in, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  TRY(read_ctr(m, C_LIST_B, 1));
+  int n = m->hctr[C_LIST_B];
+  Classes cl;
+  TRY(colour_list(m, m->listA.p, n, stream_seed(m->seed, ctx), cl));
+  if (ncolours) *ncolours = cl.ncol;
+  if (colour_out) {
+    TRY(ensure(m, m->vt0, st.V));
+    pm::colour_out(st, m->act.p, m->col.p, m->vt0.p, m->s);
+    HIPCHK(hipMemcpyAsync(colour_out, m->vt0.p, sizeof(int) * st.V,
+                          mem_kind == PM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, m->s));
+  }
+  set_flags(m->listA.p, n, m->act.p, 0, m->s);
+  return sync(m);
+}
+
+pm_status pm_coarsen(pm_mesh* m, const pm_options* o, pm_stats* st) {
+  if (!m || !o) return PM_E_ARG;
+  if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  pm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  TRY(run_rounds(m, o, st, 0));
+  TRY(compact(m));
+  return st->v[7] ? PM_OK : PM_W_NOT_CONVERGED;
+}
+
+pm_status pm_swap(pm_mesh* m, const pm_options* o, pm_stats* st) {
+  if (!m || !o) return PM_E_ARG;
+  if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  pm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  TRY(run_rounds(m, o, st, 1));
+  return st->v[7] ? PM_OK : PM_W_NOT_CONVERGED;
+}
+
+pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
+  if (!m || !o) return PM_E_ARG;
+  if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  pm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  TRY(ensure_phase_scratch(m));
+  stats_zero(m);
+  set_int(m->ctr + C_LIST_B, 0, m->s);
+  select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  TRY(read_ctr(m, C_LIST_B, 1));
+  int n = m->hctr[C_LIST_B];
+  Classes cl;
+  TRY(colour_list(m, m->listA.p, n, stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), cl));
+  st->v[1] = n;
+  st->v[5] = cl.ncol;
+  st->v[12] = cl.jp_iters;
+  for (int s = 0; s < o->smooth_sweeps; ++s)
+    for (int c = 0; c < cl.ncol; ++c)
+      smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, m->s);
+  set_flags(m->listA.p, n, m->act.p, 0, m->s);
+  TRY(stats_read(m, st));
+  st->v[0] = o->smooth_sweeps;
+  st->v[7] = 1;
+  return PM_OK;
+}
+
+pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
+  if (!m || !o) return PM_E_ARG;
+  if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  pm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  stats_zero(m);
+  Store& s = m->st;
+  int p = 0;
+  bool done = false;
+  for (; p < o->refine_passes; ++p) {
+    int V0 = s.V, T0 = s.T;
+    TRY(ensure(m, m->vt0, V0));
+    TRY(ensure(m, m->vt1, V0));
+    TRY(ensure(m, m->tt0, T0));
+    TRY(ensure(m, m->tt1, T0));
+    TRY(ensure(m, m->partial, scan_partials_needed(std::max(V0, T0)) + 2));
+    refine_mark(s, o->L_up2, m->vt0.p, m->ctr, m->s);
+    scan_excl(m->vt0.p, m->vt1.p, V0, m->ctr + C_TOTAL, m->partial.p, m->s);
+    refine_count(s, o->L_up2, m->tt0.p, m->s);
+    scan_excl(m->tt0.p, m->tt1.p, T0, m->ctr + C_TOTAL2, m->partial.p, m->s);
+    TRY(read_ctr(m, C_TOTAL, 2));
+    int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
+    if (nv == 0) {
+      done = true;
+      break;
+    }
+    if ((int64_t)V0 + nv > (1ll << 30) || (int64_t)T0 + nt > (1ll << 30))
+      return fail(m, PM_E_NOMEM, "refinement beyond 2^30 vertices or elements");
+    TRY(grow_vertices(m, V0 + nv));
+    TRY(grow_elements(m, T0 + nt));
+    TRY(ensure(m, m->mid, (size_t)s.nn_pool));
+    refine_mint(s, o->L_up2, m->vt1.p, m->mid.p, V0, m->s);
+    refine_split(s, o->L_up2, m->mid.p, m->tt1.p, T0, m->s);
+    s.V = V0 + nv;
+    s.T = T0 + nt;
+    st->v[4] += nv;
+    st->v[8] += nv;
+    st->v[9] += nt;
+    TRY(build_rows(m));
+  }
+  TRY(stats_read(m, st));
+  st->v[0] = p;
+  st->v[7] = done ? 1 : 0;
+  return done ? PM_OK : PM_W_NOT_CONVERGED;
+}
+
+pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM) {
+  if (!m) return PM_E_ARG;
+  int nparts = std::min(std::max((m->st.T + 255) / 256, 1), 2048);
+  TRY(ensure(m, m->qpart, 2 * (size_t)nparts + 2));
+  if (Q || qmin) {
+    quality_sum(m->st, m->qpart.p, m->qpart.p + nparts, nparts, m->qpart.p + 2 * nparts, m->s);
+    HIPCHK(hipMemcpyAsync(m->hq, m->qpart.p + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, m->s));
+  }
+  if (dQdx || dQdM) quality_adjoint(m->st, dQdx, dQdM, m->s);
+  TRY(sync(m));
+  if (Q) *Q = m->hq[0];
+  if (qmin) *qmin = m->hq[1];
+  return PM_OK;
+}
+
+pm_status pm_fp64_selfcheck(const double* a, const double* b, int64_t n, double* quot, double* root) {
+  if (!a || !b || !quot || !root || n < 0 || n > (1ll << 28)) return PM_E_ARG;
+  if (n == 0) return PM_OK;
+  double* d = nullptr;
+  size_t bytes = sizeof(double) * (size_t)n;
+  if (hipMalloc((void**)&d, 4 * bytes) != hipSuccess) return PM_E_NOMEM;
+  bool ok = hipMemcpy(d, a, bytes, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(d + n, b, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  if (ok) {
+    fp64_probe(d, d + n, (int)n, d + 2 * n, d + 3 * n, nullptr);
+    ok = hipDeviceSynchronize() == hipSuccess &&
+         hipMemcpy(quot, d + 2 * n, bytes, hipMemcpyDeviceToHost) == hipSuccess &&
+         hipMemcpy(root, d + 3 * n, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+  }
+  (void)hipFree(d);
+  return ok ? PM_OK : PM_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,743 @@
+// Adaptation kernels: Jones-Plassmann colouring, colour-class lists, the four
+// operations (collapse, flip, smoothing; refinement lives in store.hip), the
+// deferred-update commit and the quality functional with its adjoint.
+//
+// Round structure (Sec. 3.2-3.4): the active vertices are coloured once per
+// round; the colour classes run one kernel after another. A class kernel
+// re-validates each member against same-class neighbours in the current
+// graph, evaluates its operation from the state left by the previous class,
+// rewrites only elements the member owns, marks the adjacency rows it touches
+// dirty and queues the additions those rows need. The commit then lets the
+// owner of each dirty row rebuild it, so no two threads ever write one row.
+#include "kern.hpp"
+
+namespace pm {
+
+__device__ __forceinline__ uint64_t key_of(const Round& rd, int v) {
+  return vkey(rd.sseed, (uint32_t)(rd.lid ? rd.lid[v] : v));
+}
+
+// ---- flags and lists -----------------------------------------------------------------
+__global__ void k_set_flags(const int* __restrict__ list, int n, uint8_t* __restrict__ flag, uint8_t val) {
+  for (int i = gtid(); i < n; i += gstride()) flag[list[i]] = val;
+}
+void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s) {
+  if (n > 0) k_set_flags<<<grid_for(n), kBlock, 0, s>>>(list, n, flag, val);
+}
+
+__device__ bool has_candidate(const Store& st, int v, double L_low2) {
+  Hdr h = st.hdr[v];
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  uint8_t tv = st.tag[v];
+  for (int j = 0; j < h.y; ++j) {
+    int u = st.nn[h.x + j];
+    if (tv & ~st.tag[u]) continue;
+    if (len2(pv, mv, st.xy[u], st.met[u]) < L_low2) return true;
+  }
+  return false;
+}
+
+// mode: 0 colour (active flags or all live), 1 coarsen (has a short edge),
+// 2 swap (all live), 3 smooth (live interior)
+__device__ __forceinline__ bool want(const Store& st, int v, int mode, double L_low2, const uint8_t* active) {
+  if (!st.valive[v]) return false;
+  switch (mode) {
+    case 0: return active ? active[v] != 0 : true;
+    case 1: return has_candidate(st, v, L_low2);
+    case 2: return true;
+    default: return st.tag[v] == 0;
+  }
+}
+
+// every vertex v with (nxt == null or nxt[v]) and want(v); clears nxt
+__global__ void k_select(Store st, int mode, double L_low2, const uint8_t* __restrict__ active,
+                         uint8_t* __restrict__ nxt, int* __restrict__ out, int* __restrict__ n) {
+  for (int v = gtid(); v < st.V; v += gstride()) {
+    bool on = nxt ? nxt[v] != 0 : true;
+    if (nxt && on) nxt[v] = 0;
+    if (on && want(st, v, mode, L_low2, active)) out[wave_append_slot(n)] = v;
+  }
+}
+void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
+                     int* n, hipStream_t s) {
+  k_select<<<grid_for(st.V), kBlock, 0, s>>>(st, mode, L_low2, active, nxt, out, n);
+}
+
+// ---- Jones-Plassmann colouring (Sec. 3.2) ------------------------------------------------
+__global__ void k_jp_init(const int* __restrict__ A, int n, uint8_t* __restrict__ col, uint8_t* __restrict__ act) {
+  for (int i = gtid(); i < n; i += gstride()) {
+    int v = A[i];
+    col[v] = 0xFF;
+    act[v] = 1;
+  }
+}
+void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, hipStream_t s) {
+  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(A, n, col, act);
+}
+
+// A vertex is ready once every active neighbour of larger key has a colour;
+// it then takes the smallest colour none of them has. Colours read while a
+// neighbour is being written are either unset (not ready yet) or final, so
+// the result does not depend on timing.
+__global__ void k_jp_step(Store st, const int* __restrict__ U, int n, int* __restrict__ U2, int* __restrict__ nU2,
+                          const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
+  int i = gtid();
+  if (i >= n) return;
+  int v = U[i];
+  uint64_t kv = key_of(rd, v);
+  Hdr h = st.hdr[v];
+  uint64_t used = 0;
+  bool big = false, ready = true;
+  for (int j = 0; j < h.y; ++j) {
+    int w = st.nn[h.x + j];
+    if (!act[w]) continue;
+    if (key_of(rd, w) < kv) continue;
+    int c = ((volatile const uint8_t*)col)[w];
+    if (c == 0xFF) {
+      ready = false;
+      break;
+    }
+    if (c < 64) used |= 1ull << c;
+    else big = true;
+  }
+  if (!ready) {
+    U2[wave_append_slot(nU2)] = v;
+    return;
+  }
+  int c;
+  if (~used != 0ull && !big) {
+    c = __ffsll((unsigned long long)~used) - 1;
+  } else {
+    // slow path: colours beyond 63 among the neighbours
+    c = 0;
+    for (;;) {
+      bool taken = false;
+      for (int j = 0; j < h.y && !taken; ++j) {
+        int w = st.nn[h.x + j];
+        if (!act[w] || key_of(rd, w) < kv) continue;
+        taken = ((volatile const uint8_t*)col)[w] == c;
+      }
+      if (!taken) break;
+      ++c;
+    }
+  }
+  if (c >= kMaxColours) {
+    atomicOr(&ctr[C_ERR], E_COLOURS);
+    c = kMaxColours - 1;
+  }
+  ((volatile uint8_t*)col)[v] = (uint8_t)c;
+}
+void jp_step(const Store& st, const int* U, int n, int* U2, int* nU2, const uint8_t* act, uint8_t* col, Round rd,
+             int* ctr, hipStream_t s) {
+  if (n > 0) k_jp_step<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, U, n, U2, nU2, act, col, rd, ctr);
+}
+
+// class sizes (LDS histogram, one global atomic per colour per block)
+__global__ void k_class_hist(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int* ctr) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int i = gtid();
+  if (i < n) atomicAdd(&h[col[A[i]]], 1);
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&ctr[C_HIST + threadIdx.x], h[threadIdx.x]);
+}
+__global__ void k_class_offsets(int* ctr) {
+  __shared__ int lds[256];
+  int c = threadIdx.x;
+  lds[c] = ctr[C_HIST + c];
+  __syncthreads();
+  if (c == 0) {
+    int acc = 0, ncol = 0;
+    for (int k = 0; k < 256; ++k) {
+      ctr[C_OFF + k] = acc;
+      ctr[C_CUR + k] = 0;
+      acc += lds[k];
+      if (lds[k]) ncol = k + 1;
+    }
+    ctr[C_NCOL] = ncol;
+  }
+}
+__global__ void k_class_scatter(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int* ctr,
+                                int* __restrict__ out) {
+  __shared__ int cnt[256], base[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int i = gtid();
+  int v = -1, c = 0, r = 0;
+  if (i < n) {
+    v = A[i];
+    c = col[v];
+    r = atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr[C_CUR + threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (v >= 0) out[ctr[C_OFF + c] + base[c] + r] = v;
+}
+void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, hipStream_t s) {
+  static_assert(kBlock == 256, "class kernels use one LDS slot per colour and thread");
+  int g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  k_class_hist<<<g, kBlock, 0, s>>>(A, n, col, ctr);
+  k_class_offsets<<<1, 256, 0, s>>>(ctr);
+  k_class_scatter<<<g, kBlock, 0, s>>>(A, n, col, ctr, out);
+}
+
+__global__ void k_colour_out(int V, const uint8_t* __restrict__ act, const uint8_t* __restrict__ col,
+                             int* __restrict__ out) {
+  for (int v = gtid(); v < V; v += gstride()) out[v] = act[v] ? (int)col[v] : -1;
+}
+void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s) {
+  k_colour_out<<<grid_for(st.V), kBlock, 0, s>>>(st.V, act, col, out);
+}
+
+// ---- deferred update: queueing (Sec. 3.3) -----------------------------------------------
+__device__ __forceinline__ void mark_dirty(const Commit& cm, int x, int* ctr) {
+  if (atomicExch(&cm.dirty[x], 1) == 0) cm.dlist[wave_append_slot(&ctr[C_DIRTY])] = x;
+}
+// queue an addition to NE(x): val >= 0 absorbs NE(val) (a collapsed vertex),
+// val < 0 adds element -val-1; weight = number of ids it may add
+__device__ __forceinline__ void queue_add(const Commit& cm, int x, int val, int weight, int* ctr) {
+  int off = atomicAdd(&cm.pend[x], weight);
+  int r = wave_append_slot(&ctr[C_REC]);
+  if (r < cm.rec_cap) {
+    cm.rec_row[r] = x;
+    cm.rec_val[r] = val;
+    cm.rec_off[r] = off;
+  } else {
+    atomicOr(&ctr[C_ERR], E_REC);
+  }
+}
+
+// a member is deferred when a same-class active neighbour has a larger key
+__device__ __forceinline__ bool beaten(const Store& st, int v, const OpArgs& a) {
+  uint64_t kv = key_of(a.rd, v);
+  Hdr h = st.hdr[v];
+  for (int j = 0; j < h.y; ++j) {
+    int w = st.nn[h.x + j];
+    if (a.act[w] && a.col[w] == a.cls && key_of(a.rd, w) > kv) return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ Geo geo_of(const Store& st, int3 t) {
+  return make_geo(st.xy[t.x], st.xy[t.y], st.xy[t.z], st.met[t.x], st.met[t.y], st.met[t.z]);
+}
+__device__ __forceinline__ Geo geo_of(const Store& st, const Elem& e) {
+  return make_geo(st.xy[e.x], st.xy[e.y], st.xy[e.z], st.met[e.x], st.met[e.y], st.met[e.z]);
+}
+
+// per-wave stats: evaluated / deferred / committed
+__device__ __forceinline__ void count_status(int status, int* ctr) {
+  // status: -1 idle lane, 0 deferred, 1 evaluated, 2 evaluated + committed
+  uint64_t d = __ballot(status == 0);
+  uint64_t e = __ballot(status >= 1);
+  uint64_t c = __ballot(status == 2);
+  if (__lane_id() == 0) {
+    if (d) atomicAdd(&ctr[C_DEFER], __popcll(d));
+    if (e) atomicAdd(&ctr[C_EVAL], __popcll(e));
+    if (c) atomicAdd(&ctr[C_COMMIT], __popcll(c));
+  }
+}
+
+// ---- coarsening (Sec. 2.4.1) --------------------------------------------------------------
+// Candidates u: neighbours on every boundary side v lies on, with L^2 < L_low2,
+// tried in ascending (L^2, u); the first whose re-pointed elements all keep
+// area > 0 and q^2 >= q_min^2 is taken.
+__device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
+  if (beaten(st, v, a)) {
+    cm.nxt[v] = 1;
+    return 0;
+  }
+  Hdr h = st.hdr[v];
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  uint8_t tv = st.tag[v];
+  double lastL = -INFINITY;
+  int lastU = -1;
+  int u = -1;
+  for (;;) {
+    double bL = INFINITY;
+    int bU = -1;
+    for (int j = 0; j < h.y; ++j) {
+      int w = st.nn[h.x + j];
+      if (tv & ~st.tag[w]) continue;
+      double L = len2(pv, mv, st.xy[w], st.met[w]);
+      if (!(L < a.L_low2)) continue;
+      bool after = L > lastL || (L == lastL && w > lastU);
+      bool better = bU < 0 || L < bL || (L == bL && w < bU);
+      if (after && better) {
+        bL = L;
+        bU = w;
+      }
+    }
+    if (bU < 0) break;
+    bool ok = true;
+    for (int i = 0; i < h.w && ok; ++i) {
+      Elem e = st.tri[st.ne[h.z + i]];
+      if (holds(e, bU)) continue;
+      int k = slot_of(e, v);
+      int3 r = rot_min(k == 0 ? bU : e.x, k == 1 ? bU : e.y, k == 2 ? bU : e.z);
+      Geo g = geo_of(st, r);
+      if (!(area2(g) > 0.0) || !(qual2(g) >= a.qmin2)) ok = false;
+    }
+    if (ok) {
+      u = bU;
+      break;
+    }
+    lastL = bL;
+    lastU = bU;
+  }
+  if (u < 0) return 1;
+  // apply: v's elements are owned by v within this independent set
+  for (int i = 0; i < h.w; ++i) {
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    if (holds(e, u)) {
+      e.w = 0;
+    } else {
+      int k = slot_of(e, v);
+      int3 r = rot_min(k == 0 ? u : e.x, k == 1 ? u : e.y, k == 2 ? u : e.z);
+      e = make_int4(r.x, r.y, r.z, 1);
+    }
+    st.tri[t] = e;
+  }
+  st.valive[v] = 0;
+  for (int j = 0; j < h.y; ++j) mark_dirty(cm, st.nn[h.x + j], ctr);
+  queue_add(cm, u, v, h.w, ctr);
+  return 2;
+}
+
+__global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  int i = gtid();
+  int status = -1;
+  if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
+  count_status(status, ctr);
+}
+void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
+  if (n > 0) k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+}
+
+// ---- swapping (Sec. 2.4.3) ------------------------------------------------------------------
+// For every interior edge (v, w): (v,w,a) and (w,v,b) become (v,b,a) and (w,a,b)
+// when both areas stay positive and the smaller q^2 rises strictly; the best
+// new minimum wins, ties to the smaller w; the element holding v keeps the
+// smaller id.
+__device__ int flip_one(Store st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
+  if (beaten(st, v, a)) {
+    cm.nxt[v] = 1;
+    return 0;
+  }
+  Hdr h = st.hdr[v];
+  double best = 0.0;
+  int bw = -1, bT1 = -1, bT2 = -1, ba = -1, bb = -1;
+  for (int i = 0; i < h.w; ++i) {
+    int T1 = st.ne[h.z + i];
+    Elem e1 = st.tri[T1];
+    int k1 = slot_of(e1, v);
+    int w = at(e1, k1 == 2 ? 0 : k1 + 1);
+    int av = at(e1, k1 == 0 ? 2 : k1 - 1);
+    int T2 = -1, bv = -1;
+    Elem e2;
+    for (int j = 0; j < h.w; ++j) {
+      int t = st.ne[h.z + j];
+      Elem e = st.tri[t];
+      int k = slot_of(e, v);
+      if (at(e, k == 0 ? 2 : k - 1) == w) {
+        T2 = t;
+        e2 = e;
+        bv = at(e, k == 2 ? 0 : k + 1);
+        break;
+      }
+    }
+    if (T2 < 0) continue;
+    Geo gv = geo_of(st, rot_min(v, bv, av));
+    Geo gw = geo_of(st, rot_min(w, av, bv));
+    if (!(area2(gv) > 0.0) || !(area2(gw) > 0.0)) continue;
+    double qv = qual2(gv), qw = qual2(gw);
+    double q1 = qual2(geo_of(st, e1)), q2 = qual2(geo_of(st, e2));
+    double nmin = qw < qv ? qw : qv;
+    double omin = q2 < q1 ? q2 : q1;
+    if (!(nmin > omin)) continue;
+    if (bw < 0 || nmin > best || (nmin == best && w < bw)) {
+      best = nmin;
+      bw = w;
+      bT1 = T1;
+      bT2 = T2;
+      ba = av;
+      bb = bv;
+    }
+  }
+  if (bw < 0) return 1;
+  int lo = min(bT1, bT2), hi = max(bT1, bT2);
+  int3 tv = rot_min(v, bb, ba), tw = rot_min(bw, ba, bb);
+  st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
+  st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
+  mark_dirty(cm, v, ctr);
+  mark_dirty(cm, bw, ctr);
+  mark_dirty(cm, ba, ctr);
+  mark_dirty(cm, bb, ctr);
+  queue_add(cm, ba, -bT2 - 1, 1, ctr);
+  queue_add(cm, bb, -bT1 - 1, 1, ctr);
+  return 2;
+}
+
+__global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  int i = gtid();
+  int status = -1;
+  if (i < n) status = flip_one(st, list[i], a, cm, ctr);
+  count_status(status, ctr);
+}
+void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
+  if (n > 0) k_flip<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+}
+
+// ---- deferred update: commit ------------------------------------------------------------------
+// Every dirty row gets a private staging range. Its owner copies the old NE
+// row and the queued additions there, keeps the elements that are live and
+// still hold the row's vertex, sorts them (the canonical order), and derives
+// NN from them: NN(x) is the set of other vertices of x's elements.
+__global__ void k_commit_alloc(Store st, Commit cm, int* ctr) {
+  int n = ctr[C_DIRTY];
+  int stride = gstride();
+  for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
+    int i = i0 + (int)threadIdx.x;
+    int need = 0, x = -1;
+    if (i < n) {
+      x = cm.dlist[i];
+      need = 3 * (st.hdr[x].w + cm.pend[x]) + 4;
+    }
+    int base = wave_add_full(&ctr[C_STAGE], need);
+    if (x >= 0) {
+      if ((int64_t)base + need > cm.stage_cap) {
+        atomicOr(&ctr[C_ERR], E_STAGE);
+        cm.dbase[x] = -1;
+      } else {
+        cm.dbase[x] = base;
+      }
+    }
+  }
+}
+
+__global__ void k_commit_fill(Store st, Commit cm, int* ctr) {
+  int n = min(ctr[C_REC], cm.rec_cap);
+  if (gtid() == 0) ctr[C_RECS] += n;
+  for (int r = gtid(); r < n; r += gstride()) {
+    int x = cm.rec_row[r];
+    int base = cm.dbase[x];
+    if (base < 0) continue;
+    int* dst = cm.stage + base + st.hdr[x].w + cm.rec_off[r];
+    int val = cm.rec_val[r];
+    if (val >= 0) {
+      Hdr hv = st.hdr[val];
+      for (int k = 0; k < hv.w; ++k) dst[k] = st.ne[hv.z + k];
+    } else {
+      dst[0] = -val - 1;
+    }
+  }
+}
+
+__device__ void sort_unique(int* a, int& n) {
+  for (int i = 1; i < n; ++i) {
+    int x = a[i];
+    int j = i - 1;
+    while (j >= 0 && a[j] > x) {
+      a[j + 1] = a[j];
+      --j;
+    }
+    a[j + 1] = x;
+  }
+  int m = 0;
+  for (int i = 0; i < n; ++i)
+    if (m == 0 || a[i] != a[m - 1]) a[m++] = a[i];
+  n = m;
+}
+
+// write a sorted row, in place when it fits, else in fresh pool space; on
+// pool exhaustion the row keeps its slot and is cut to its capacity (the
+// error bit fails the phase), so no later read leaves the pool
+__device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap, const int* src, int n, int err,
+                       int* ctr) {
+  if (n > cap) {
+    int nc = max(8, (2 * n + 3) & ~3);
+    int o = atomicAdd(top, nc);
+    if ((int64_t)o + nc > pool_cap) {
+      atomicOr(&ctr[C_ERR], err);
+      n = cap;
+    } else {
+      off = o;
+      cap = nc;
+      atomicAdd(&ctr[C_RELOC], 1);
+    }
+  }
+  for (int k = 0; k < n; ++k) pool[off + k] = src[k];
+  return n;
+}
+
+__global__ void k_commit_merge(Store st, Commit cm, int* ctr) {
+  int n = ctr[C_DIRTY];
+  for (int i = gtid(); i < n; i += gstride()) {
+    int x = cm.dlist[i];
+    int base = cm.dbase[x];
+    Hdr h = st.hdr[x];
+    int2 cp = st.cap[x];
+    int added = cm.pend[x];
+    cm.dirty[x] = 0;
+    cm.pend[x] = 0;
+    cm.nxt[x] = 1;
+    if (base < 0) continue;
+    int* s = cm.stage + base;
+    for (int k = 0; k < h.w; ++k) s[k] = st.ne[h.z + k];
+    int m = 0, tot = h.w + added;
+    for (int k = 0; k < tot; ++k) {
+      int t = s[k];
+      Elem e = st.tri[t];
+      if (e.w && holds(e, x)) s[m++] = t;
+    }
+    sort_unique(s, m);
+    int* q = s + tot;
+    int nq = 0;
+    for (int k = 0; k < m; ++k) {
+      Elem e = st.tri[s[k]];
+      if (e.x != x) q[nq++] = e.x;
+      if (e.y != x) q[nq++] = e.y;
+      if (e.z != x) q[nq++] = e.z;
+    }
+    sort_unique(q, nq);
+    int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
+    m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
+    nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
+    st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
+    st.cap[x] = make_int2(nn_cap, ne_cap);
+  }
+}
+
+void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s) {
+  int g = grid_for(vmax, 4096);
+  k_commit_alloc<<<g, kBlock, 0, s>>>(st, cm, ctr);
+  k_commit_fill<<<g, kBlock, 0, s>>>(st, cm, ctr);
+  k_commit_merge<<<g, kBlock, 0, s>>>(st, cm, ctr);
+}
+
+// ---- smoothing (Sec. 2.4.4) ---------------------------------------------------------------------
+// smallest q^2 over v's elements with v placed at p; valid = all areas positive
+__device__ double patch_min_q2(const Store& st, int v, Hdr h, double2 p, bool& valid) {
+  valid = true;
+  double mn = 0.0;
+  bool first = true;
+  for (int i = 0; i < h.w; ++i) {
+    Elem e = st.tri[st.ne[h.z + i]];
+    double2 p0 = e.x == v ? p : st.xy[e.x];
+    double2 p1 = e.y == v ? p : st.xy[e.y];
+    double2 p2 = e.z == v ? p : st.xy[e.z];
+    Geo g = make_geo(p0, p1, p2, st.met[e.x], st.met[e.y], st.met[e.z]);
+    if (!(area2(g) > 0.0)) valid = false;
+    double q2 = qual2(g);
+    if (first || q2 < mn) mn = q2;
+    first = false;
+  }
+  return mn;
+}
+
+__device__ double patch_q(const Store& st, int v, Hdr h, double2 p) {
+  double s = 0.0;
+  for (int i = 0; i < h.w; ++i) {
+    Elem e = st.tri[st.ne[h.z + i]];
+    double2 p0 = e.x == v ? p : st.xy[e.x];
+    double2 p1 = e.y == v ? p : st.xy[e.y];
+    double2 p2 = e.z == v ? p : st.xy[e.z];
+    s = s + qual(make_geo(p0, p1, p2, st.met[e.x], st.met[e.y], st.met[e.z]));
+  }
+  return s;
+}
+
+__device__ bool smooth_laplace(Store st, int v) {
+  Hdr h = st.hdr[v];
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  double Ga = 0.0, Gb = 0.0, Gc = 0.0, rx = 0.0, ry = 0.0;
+  for (int j = 0; j < h.y; ++j) {
+    int w = st.nn[h.x + j];
+    Met mw = st.met[w];
+    double2 pw = st.xy[w];
+    double ea = (mv.a + mw.a) * 0.5;
+    double eb = (mv.b + mw.b) * 0.5;
+    double ec = (mv.c + mw.c) * 0.5;
+    double dx = pw.x - pv.x, dy = pw.y - pv.y;
+    Ga = Ga + ea;
+    Gb = Gb + eb;
+    Gc = Gc + ec;
+    rx = rx + (ea * dx + eb * dy);
+    ry = ry + (eb * dx + ec * dy);
+  }
+  double det = Ga * Gc - Gb * Gb;
+  double2 p = make_double2(pv.x + (Gc * rx - Gb * ry) / det, pv.y + (Ga * ry - Gb * rx) / det);
+  bool vo, vn;
+  double oldmin = patch_min_q2(st, v, h, pv, vo);
+  double newmin = patch_min_q2(st, v, h, p, vn);
+  if (vn && newmin >= oldmin) {
+    st.xy[v] = p;
+    return true;
+  }
+  return false;
+}
+
+__device__ bool smooth_gradient(Store st, int v) {
+  Hdr h = st.hdr[v];
+  double2 pv = st.xy[v];
+  double gx = 0.0, gy = 0.0;
+  for (int i = 0; i < h.w; ++i) {
+    Elem e = st.tri[st.ne[h.z + i]];
+    double ex, ey;
+    qual_grad_x(geo_of(st, e), slot_of(e, v), ex, ey);
+    gx = gx + ex;
+    gy = gy + ey;
+  }
+  if (gx == 0.0 && gy == 0.0) return false;
+  double ax = fabs(gx), ay = fabs(gy);
+  double nrm = ax < ay ? ay : ax;
+  double dx = gx / nrm, dy = gy / nrm;
+  double hh = 0.0;
+  bool first = true;
+  for (int j = 0; j < h.y; ++j) {
+    double2 pw = st.xy[st.nn[h.x + j]];
+    double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
+    double hj = hx < hy ? hy : hx;
+    if (first || hj < hh) hh = hj;
+    first = false;
+  }
+  bool vo;
+  double oldmin = patch_min_q2(st, v, h, pv, vo);
+  double Qold = patch_q(st, v, h, pv);
+  double step = hh;
+  for (int k = 1; k <= 4; ++k) {
+    step = step * 0.5;
+    double2 p = make_double2(pv.x + step * dx, pv.y + step * dy);
+    bool vn;
+    double newmin = patch_min_q2(st, v, h, p, vn);
+    if (!vn || !(newmin >= oldmin)) continue;
+    if (!(patch_q(st, v, h, p) > Qold)) continue;
+    st.xy[v] = p;
+    return true;
+  }
+  return false;
+}
+
+__global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+  int i = gtid();
+  int status = -1;
+  if (i < n) {
+    int v = list[i];
+    bool moved = kind == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v);
+    status = moved ? 2 : 1;
+  }
+  count_status(status, ctr);
+}
+void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, hipStream_t s) {
+  if (n > 0) k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+}
+
+// ---- quality functional and adjoint (Sec. 2.2) --------------------------------------------------
+constexpr int QB = 256;
+
+__global__ void k_quality(Store st, double* __restrict__ psum, double* __restrict__ pmin) {
+  __shared__ double ls[QB], lm[QB];
+  double s = 0.0, mn = INFINITY;
+  for (int t = gtid(); t < st.T; t += gstride()) {
+    Elem e = st.tri[t];
+    if (!e.w) continue;
+    double q = qual(geo_of(st, e));
+    s = s + q;
+    mn = q < mn ? q : mn;
+  }
+  ls[threadIdx.x] = s;
+  lm[threadIdx.x] = mn;
+  __syncthreads();
+  for (int d = QB / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) {
+      ls[threadIdx.x] = ls[threadIdx.x] + ls[threadIdx.x + d];
+      double o = lm[threadIdx.x + d];
+      lm[threadIdx.x] = o < lm[threadIdx.x] ? o : lm[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    psum[blockIdx.x] = ls[0];
+    pmin[blockIdx.x] = lm[0];
+  }
+}
+__global__ void k_quality_final(const double* __restrict__ psum, const double* __restrict__ pmin, int np,
+                                double* __restrict__ out) {
+  __shared__ double ls[QB], lm[QB];
+  double s = 0.0, mn = INFINITY;
+  for (int i = threadIdx.x; i < np; i += QB) {
+    s = s + psum[i];
+    mn = pmin[i] < mn ? pmin[i] : mn;
+  }
+  ls[threadIdx.x] = s;
+  lm[threadIdx.x] = mn;
+  __syncthreads();
+  for (int d = QB / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) {
+      ls[threadIdx.x] = ls[threadIdx.x] + ls[threadIdx.x + d];
+      double o = lm[threadIdx.x + d];
+      lm[threadIdx.x] = o < lm[threadIdx.x] ? o : lm[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = ls[0];
+    out[1] = lm[0];
+  }
+}
+void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s) {
+  k_quality<<<nparts, QB, 0, s>>>(st, psum, pmin);
+  k_quality_final<<<1, QB, 0, s>>>(psum, pmin, nparts, out2);
+}
+
+// per vertex, summed over NE(v) in ascending element id: no floating-point atomics
+__global__ void k_adjoint(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
+  for (int v = gtid(); v < st.V; v += gstride()) {
+    Hdr h = st.hdr[v];
+    double gx = 0.0, gy = 0.0, ga = 0.0, gb = 0.0, gc = 0.0;
+    for (int i = 0; i < h.w; ++i) {
+      Elem e = st.tri[st.ne[h.z + i]];
+      Geo g = geo_of(st, e);
+      double ex, ey, da, db, dc;
+      qual_grad_x(g, slot_of(e, v), ex, ey);
+      qual_grad_m(g, da, db, dc);
+      gx = gx + ex;
+      gy = gy + ey;
+      ga = ga + da / 3.0;
+      gb = gb + db / 3.0;
+      gc = gc + dc / 3.0;
+    }
+    if (dQdx) {
+      dQdx[2 * v] = gx;
+      dQdx[2 * v + 1] = gy;
+    }
+    if (dQdM) {
+      dQdM[3 * v] = ga;
+      dQdM[3 * v + 1] = gb;
+      dQdM[3 * v + 2] = gc;
+    }
+  }
+}
+void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s) {
+  k_adjoint<<<grid_for(st.V), kBlock, 0, s>>>(st, dQdx, dQdM);
+}
+
+__global__ void k_fp64_probe(const double* __restrict__ a, const double* __restrict__ b, int n,
+                             double* __restrict__ q, double* __restrict__ r) {
+  for (int i = gtid(); i < n; i += gstride()) {
+    q[i] = a[i] / b[i];
+    r[i] = sqrt(a[i]);
+  }
+}
+void fp64_probe(const double* a, const double* b, int n, double* q, double* r, hipStream_t s) {
+  k_fp64_probe<<<grid_for(n), kBlock, 0, s>>>(a, b, n, q, r);
+}
+
+}  // namespace pm

@@ -1,0 +1,292 @@
+"""Python binding of libpmesh.so (ctypes; argument marshalling only).
+
+Every function carries the name of the C entry point it calls (include/pm.h).
+Device memory and streams come from PyTorch: device-side inputs and gradient
+outputs are torch tensors on the current GPU, and work is issued on
+torch.cuda.current_stream(). The HIP library is required: if it is missing
+or fails to load, every call raises, there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmesh.so")
+
+PM_OK, PM_E_ARG, PM_E_MESH, PM_E_NOMEM, PM_E_DEVICE, PM_W_NOT_CONVERGED = range(6)
+PM_MEM_HOST, PM_MEM_DEVICE = 0, 1
+PM_SMOOTH_LAPLACE, PM_SMOOTH_GRADIENT = 0, 1
+STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_DEVICE", 5: "PM_W_NOT_CONVERGED"}
+STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colours", "edges", "converged",
+              "new_vertices", "new_elements", "records", "relocated", "jp_iterations"]
+
+EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_export",
+           "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
+           "pm_last_error", "pm_version", "pm_fp64_selfcheck"]
+
+
+class PMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("L_low2", C.c_double), ("L_up2", C.c_double), ("q_min", C.c_double), ("seed", C.c_uint64),
+                ("sweep", C.c_int32), ("coarsen_rounds", C.c_int32), ("swap_rounds", C.c_int32),
+                ("refine_passes", C.c_int32), ("smooth_kind", C.c_int32), ("smooth_sweeps", C.c_int32),
+                ("slack", C.c_double), ("wg_size", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("v", C.c_int64 * 16)]
+
+    def as_dict(self):
+        return {k: int(self.v[i]) for i, k in enumerate(STAT_NAMES)}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("xy", C.c_void_p), ("tri", C.c_void_p), ("metric", C.c_void_p), ("tags", C.c_void_p),
+                ("V", C.c_int64), ("T", C.c_int64), ("mem_kind", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpmesh.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1505_04694_amd/build.py")
+        # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+        # this library binds to, so torch and the library share one runtime
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        P, S = C.c_void_p, C.c_int
+        L.pm_default_options.restype = S
+        L.pm_default_options.argtypes = [C.POINTER(Options)]
+        L.pm_mesh_create.restype = S
+        L.pm_mesh_create.argtypes = [C.POINTER(MeshDesc), C.POINTER(Options), P, C.POINTER(P)]
+        L.pm_mesh_destroy.restype = S
+        L.pm_mesh_destroy.argtypes = [P]
+        L.pm_mesh_sizes.restype = S
+        L.pm_mesh_sizes.argtypes = [P, P, P]
+        L.pm_mesh_export.restype = S
+        L.pm_mesh_export.argtypes = [P, P, P, P, P, P, P, C.c_int32]
+        L.pm_mesh_rows.restype = S
+        L.pm_mesh_rows.argtypes = [P, P, P, P, P, P, P]
+        L.pm_colour.restype = S
+        L.pm_colour.argtypes = [P, P, C.c_uint32, P, P, C.c_int32]
+        for f in ("pm_coarsen", "pm_refine", "pm_swap", "pm_smooth"):
+            getattr(L, f).restype = S
+            getattr(L, f).argtypes = [P, C.POINTER(Options), C.POINTER(Stats)]
+        L.pm_quality.restype = S
+        L.pm_quality.argtypes = [P, P, P, P, P]
+        L.pm_last_error.restype = C.c_char_p
+        L.pm_last_error.argtypes = [P]
+        L.pm_version.restype = C.c_char_p
+        L.pm_version.argtypes = []
+        L.pm_fp64_selfcheck.restype = S
+        L.pm_fp64_selfcheck.argtypes = [P, P, C.c_int64, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(h, status, allow_warn=True):
+    if status == PM_OK or (allow_warn and status == PM_W_NOT_CONVERGED):
+        return status
+    msg = lib().pm_last_error(h).decode() if h else ""
+    raise PMError(status, msg)
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def pm_default_options(**kw) -> Options:
+    o = Options()
+    _check(None, lib().pm_default_options(C.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def pm_fp64_selfcheck(a, b):
+    a = np.ascontiguousarray(a, np.float64); b = np.ascontiguousarray(b, np.float64)
+    q = np.empty_like(a); r = np.empty_like(a)
+    _check(None, lib().pm_fp64_selfcheck(_p(a), _p(b), a.size, _p(q), _p(r)))
+    return q, r
+
+
+def pm_version() -> str:
+    return lib().pm_version().decode()
+
+
+def pm_mesh_create(xy, tri, metric, tags=None, options: Options | None = None, stream=None):
+    """Create a handle from host numpy arrays or device torch tensors."""
+    on_dev = hasattr(xy, "is_cuda") and xy.is_cuda
+    if on_dev:
+        import torch
+        xy = xy.to(torch.float64).contiguous()
+        tri = tri.to(torch.int32).contiguous()
+        metric = metric.to(torch.float64).contiguous()
+        tags = None if tags is None else tags.to(torch.uint8).contiguous()
+        V, T = xy.shape[0], tri.shape[0]
+    else:
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        metric = np.ascontiguousarray(metric, dtype=np.float64)
+        tags = None if tags is None else np.ascontiguousarray(tags, dtype=np.uint8)
+        V, T = xy.shape[0], tri.shape[0]
+    d = MeshDesc()
+    d.V, d.T = V, T
+    d.mem_kind = PM_MEM_DEVICE if on_dev else PM_MEM_HOST
+    d.xy = _p(xy).value
+    d.tri = _p(tri).value
+    d.metric = _p(metric).value
+    d.tags = _p(tags).value if tags is not None else None
+    h = C.c_void_p()
+    o = options if options is not None else pm_default_options()
+    st = lib().pm_mesh_create(C.byref(d), C.byref(o), stream if stream is not None else _stream(), C.byref(h))
+    if st != PM_OK:
+        raise PMError(st, "pm_mesh_create: " + lib().pm_last_error(None).decode())
+    return h
+
+
+def pm_mesh_destroy(h):
+    _check(h, lib().pm_mesh_destroy(h))
+
+
+def pm_mesh_sizes(h):
+    V, T = C.c_int64(), C.c_int64()
+    _check(h, lib().pm_mesh_sizes(h, C.byref(V), C.byref(T)))
+    return V.value, T.value
+
+
+def pm_mesh_export(h):
+    V, T = pm_mesh_sizes(h)
+    xy = np.empty((V, 2)); met = np.empty((V, 3)); tri = np.empty((T, 3), np.int32)
+    tags = np.empty(V, np.uint8); va = np.empty(V, np.uint8); ta = np.empty(max(T, 1), np.uint8)
+    _check(h, lib().pm_mesh_export(h, _p(xy), _p(tri), _p(met), _p(tags), _p(va), _p(ta), PM_MEM_HOST))
+    return dict(xy=xy, tri=tri, metric=met, tags=tags, valive=va.astype(bool), talive=ta[:T].astype(bool))
+
+
+def pm_mesh_rows(h):
+    a, b = C.c_int64(), C.c_int64()
+    _check(h, lib().pm_mesh_rows(h, C.byref(a), C.byref(b), None, None, None, None))
+    V, _ = pm_mesh_sizes(h)
+    nn_off = np.empty(V + 1, np.int64); ne_off = np.empty(V + 1, np.int64)
+    nn = np.empty(max(a.value, 1), np.int32); ne = np.empty(max(b.value, 1), np.int32)
+    _check(h, lib().pm_mesh_rows(h, C.byref(a), C.byref(b), _p(nn_off), _p(nn), _p(ne_off), _p(ne)))
+    return nn_off, nn[:a.value], ne_off, ne[:b.value]
+
+
+def pm_colour(h, active=None, ctx: int = 0):
+    V, _ = pm_mesh_sizes(h)
+    out = np.empty(V, np.int32)
+    n = C.c_int32()
+    act = None if active is None else np.ascontiguousarray(active, dtype=np.uint8)
+    _check(h, lib().pm_colour(h, _p(act), ctx, _p(out), C.byref(n), PM_MEM_HOST))
+    return out, n.value
+
+
+def _phase(fn, h, options):
+    st = Stats()
+    o = options if options is not None else pm_default_options()
+    status = _check(h, getattr(lib(), fn)(h, C.byref(o), C.byref(st)))
+    d = st.as_dict()
+    d["status"] = STATUS[status]
+    return d
+
+
+def pm_coarsen(h, options: Options | None = None):
+    return _phase("pm_coarsen", h, options)
+
+
+def pm_refine(h, options: Options | None = None):
+    return _phase("pm_refine", h, options)
+
+
+def pm_swap(h, options: Options | None = None):
+    return _phase("pm_swap", h, options)
+
+
+def pm_smooth(h, options: Options | None = None):
+    return _phase("pm_smooth", h, options)
+
+
+def pm_quality(h, grad: bool = False):
+    """Q and qmin; with grad, also dQ/dx (V x 2) and dQ/dM (V x 3) as torch tensors on the GPU."""
+    Q, qmin = C.c_double(), C.c_double()
+    if not grad:
+        _check(h, lib().pm_quality(h, C.byref(Q), C.byref(qmin), None, None))
+        return Q.value, qmin.value
+    import torch
+    V, _ = pm_mesh_sizes(h)
+    gx = torch.empty((V, 2), dtype=torch.float64, device="cuda")
+    gm = torch.empty((V, 3), dtype=torch.float64, device="cuda")
+    _check(h, lib().pm_quality(h, C.byref(Q), C.byref(qmin), _p(gx), _p(gm)))
+    return Q.value, qmin.value, gx, gm
+
+
+class Mesh:
+    """Owning wrapper around a pm_mesh handle."""
+
+    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None):
+        self.h = pm_mesh_create(xy, tri, metric, tags, pm_default_options(seed=seed, slack=slack), stream)
+
+    @classmethod
+    def from_input(cls, mi, seed: int = 0, **kw):
+        return cls(mi.xy, mi.tri, mi.metric, mi.tags, seed=seed, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pm_mesh_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def sizes(self):
+        return pm_mesh_sizes(self.h)
+
+    def export(self):
+        return pm_mesh_export(self.h)
+
+    def rows(self):
+        return pm_mesh_rows(self.h)
+
+    def colour(self, active=None, ctx: int = 0):
+        return pm_colour(self.h, active, ctx)
+
+    def coarsen(self, sweep=0, L_low2=0.5, q_min=0.1, max_rounds=200):
+        return pm_coarsen(self.h, pm_default_options(sweep=sweep, L_low2=L_low2, q_min=q_min,
+                                                     coarsen_rounds=max_rounds))
+
+    def refine(self, L_up2=2.0, max_passes=32):
+        return pm_refine(self.h, pm_default_options(L_up2=L_up2, refine_passes=max_passes))
+
+    def swap(self, sweep=0, max_rounds=100):
+        return pm_swap(self.h, pm_default_options(sweep=sweep, swap_rounds=max_rounds))
+
+    def smooth(self, sweep=0, kind=0, sweeps=1):
+        return pm_smooth(self.h, pm_default_options(sweep=sweep, smooth_kind=kind, smooth_sweeps=sweeps))
+
+    def quality(self, grad: bool = False):
+        return pm_quality(self.h, grad)
+
+    def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1):
+        return dict(coarsen=self.coarsen(sweep), refine=self.refine(), swap=self.swap(sweep),
+                    smooth=self.smooth(sweep, smooth_kind, smooth_sweeps))

@@ -1,0 +1,101 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Topology must match exactly (element arrays, adjacency rows, live flags,
+op counts per phase); coordinates within 1e-12 relative (they come out
+bitwise equal when the device rounds like the host); the quality functional
+within 1e-12 relative and its adjoint within 1e-12 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+from paper_1505_04694_amd import inputs, pmesh
+from tests import checker
+from tests.parity import both, compare_mesh, compare_quality, compare_stats, run_sweeps
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    ("grid9", lambda: inputs.make_mesh(9, ht=0.3), 0),
+    ("jit17", lambda: inputs.make_mesh(17, layers=2, jitter_seed=5), 5),
+    ("cfg0", inputs.config0, 0),
+    ("cfg2_65", lambda: inputs.config2(65), 1),
+    ("batch40", lambda: inputs.make_mesh(40, amp=0.17, width=0.03, ht=0.07), 2),
+    ("grid129", lambda: inputs.make_mesh(129, layers=2), 4),
+]
+
+
+def test_fp64_division_and_sqrt_round_like_ieee():
+    rng = np.random.default_rng(0)
+    n = 1 << 20
+    a = np.exp(rng.uniform(-40, 40, n)) * rng.choice([1.0, 3.0, 7.0], n)
+    b = np.exp(rng.uniform(-40, 40, n))
+    a[:4] = [1.0, 2.0, 3.0, 0.1]
+    b[:4] = [3.0, 3.0, 7.0, 3.0]
+    q, r = pmesh.pm_fp64_selfcheck(a, b)
+    assert np.array_equal(q, a / b)
+    assert np.array_equal(r, np.sqrt(a))
+
+
+@pytest.mark.parametrize("name,make,seed", SMALL)
+def test_create_rows_and_colouring(name, make, seed):
+    mi = make()
+    om, gm = both(mi, seed)
+    compare_mesh(om, gm, "create")
+    rng = np.random.default_rng(seed)
+    for ctx, frac in ((0, None), (0x12345, 0.5), ((3 << 20) | (2 << 16) | 7, 0.2)):
+        act = None if frac is None else (rng.uniform(size=mi.V) < frac).astype(np.uint8)
+        co, no = om.colour(act, ctx)
+        cg, ng = gm.colour(act, ctx)
+        assert no == ng and np.array_equal(co, cg), f"colouring ctx={ctx}"
+
+
+@pytest.mark.parametrize("name,make,seed", SMALL)
+def test_quality_and_adjoint(name, make, seed):
+    om, gm = both(make(), seed)
+    compare_quality(om, gm, "initial")
+
+
+def test_config0_round_then_smooth():
+    # one coloured coarsening round, then one smoothing sweep
+    mi = inputs.config0()
+    om, gm = both(mi, 0)
+    compare_stats(om.coarsen(max_rounds=1), gm.coarsen(max_rounds=1), "coarsen round")
+    compare_mesh(om, gm, "coarsen round")
+    checker.check_mesh(gm.export(), exact=True, rows=gm.rows())
+    compare_stats(om.smooth(kind=0), gm.smooth(kind=0), "smooth")
+    compare_mesh(om, gm, "smooth")
+    compare_quality(om, gm, "end")
+
+
+@pytest.mark.parametrize("name,make,seed", SMALL)
+def test_full_sweeps(name, make, seed):
+    mi = make()
+    om, gm = both(mi, seed)
+    run_sweeps(om, gm, 2, smooth_kinds=(0, 1))
+    checker.check_mesh(gm.export(), exact=True, rows=gm.rows())
+    compare_quality(om, gm, "end")
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_smoothing_sweeps_on_jittered_mesh(kind):
+    mi = inputs.config2(129)
+    om, gm = both(mi, 1)
+    compare_stats(om.smooth(0, kind, 3), gm.smooth(0, kind, 3), "smooth")
+    compare_mesh(om, gm, "smooth", rows=False)
+    compare_quality(om, gm, "after smoothing")
+
+
+def test_invalid_meshes_are_rejected():
+    xy = np.array([[0, 0], [1, 0], [0, 1]], float)
+    met = np.tile([1.0, 0, 1.0], (3, 1))
+    for tri, m in ((np.array([[0, 2, 1]], np.int32), met),        # clockwise
+                   (np.array([[0, 1, 3]], np.int32), met),        # id out of range
+                   (np.array([[0, 1, 2]], np.int32), np.tile([1.0, 2.0, 1.0], (3, 1)))):  # not SPD
+        with pytest.raises(pmesh.PMError) as e:
+            pmesh.Mesh(xy, tri, m)
+        assert e.value.status == pmesh.PM_E_MESH
+    # a directed edge used twice (two overlapping triangles with the same orientation)
+    xy2 = np.array([[0, 0], [1, 0], [0, 1], [1, 1]], float)
+    tri2 = np.array([[0, 1, 2], [0, 1, 3]], np.int32)
+    with pytest.raises(pmesh.PMError):
+        pmesh.Mesh(xy2, tri2, np.tile([1.0, 0, 1.0], (4, 1)))
