@@ -169,6 +169,28 @@ pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* 
  * does; every threshold decision of the path relies on that. */
 pm_status pm_fp64_selfcheck(const double* a, const double* b, int64_t n, double* quot, double* root);
 
+/* Per-kernel timing. Kernel ids for pm_profile / pm_profile_read: */
+enum {
+  PM_K_JP = 0,       /* Jones-Plassmann iteration; units: active vertices visited   */
+  PM_K_COLLAPSE = 1, /* collapse class kernel; units: class members                 */
+  PM_K_FLIP = 2,     /* flip class kernel; units: class members                     */
+  PM_K_SMOOTH = 3,   /* smoothing class kernel; units: class members                */
+  PM_K_COMMIT = 4,   /* deferred-update commit (three kernels); units: dirty rows   */
+  PM_K_ADJOINT = 5,  /* quality adjoint; units: vertices                            */
+  PM_K_QUALITY = 6,  /* quality functional; units: elements                         */
+  PM_K_SELECT = 7,   /* worklist selection over all vertices; units: vertices       */
+  PM_K_COUNT = 8
+};
+
+/* Enables HIP-event timing (on the handle's stream) around every launch of
+ * the kernels whose bit (1 << id) is set in mask; 0 disables it. Resets the
+ * accumulated totals. Timing adds two event records per timed launch. */
+pm_status pm_profile(pm_mesh* m, uint32_t mask);
+
+/* Totals since pm_profile for kernel id: device milliseconds, launches and
+ * units of work (see the enum). Host pointers, any may be NULL. */
+pm_status pm_profile_read(pm_mesh* m, int32_t id, double* ms, int64_t* launches, int64_t* units);
+
 /* Message for the last non-OK status on this handle (never NULL). With a NULL
  * handle: the message of the calling thread's last failed pm_mesh_create. */
 const char* pm_last_error(const pm_mesh* m);

@@ -24,8 +24,24 @@ struct DBuf {
 
 }  // namespace
 
+// per-kernel HIP-event timing
+struct Prof {
+  uint32_t mask = 0;
+  struct Rec {
+    int k;
+    hipEvent_t a, b;
+    int64_t units;
+  };
+  std::vector<hipEvent_t> pool;
+  std::vector<Rec> open;
+  double ms[PM_K_COUNT] = {};
+  int64_t launches[PM_K_COUNT] = {};
+  int64_t units[PM_K_COUNT] = {};
+};
+
 struct pm_mesh {
   hipStream_t s = nullptr;
+  Prof prof;
   Store st;
   uint64_t seed = 0;
   double slack = 2.0;
@@ -38,6 +54,7 @@ struct pm_mesh {
   DBuf<uint8_t> act, col, nxt, u8tmp;
   DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
   DBuf<double> qpart;
+  DBuf<uint64_t> key;
   int64_t peak_bytes = 0, cur_bytes = 0;
 };
 
@@ -103,6 +120,46 @@ pm_status ensure(pm_mesh* m, DBuf<T>& b, size_t n, bool zero = false) {
 pm_status sync(pm_mesh* m) {
   HIPCHK(hipStreamSynchronize(m->s));
   return PM_OK;
+}
+
+hipEvent_t prof_event(pm_mesh* m) {
+  if (m->prof.pool.empty()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = m->prof.pool.back();
+  m->prof.pool.pop_back();
+  return e;
+}
+
+// time one launch (or launch sequence) of kernel k when its bit is enabled
+template <class F>
+void timed(pm_mesh* m, int k, int64_t units, F&& launch) {
+  if (!(m->prof.mask & (1u << k))) {
+    launch();
+    return;
+  }
+  hipEvent_t a = prof_event(m), b = prof_event(m);
+  if (a) (void)hipEventRecord(a, m->s);
+  launch();
+  if (b) (void)hipEventRecord(b, m->s);
+  if (a && b) m->prof.open.push_back({k, a, b, units});
+}
+
+// fold finished event pairs into the totals (call after a stream sync)
+void prof_flush(pm_mesh* m) {
+  for (auto& r : m->prof.open) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      m->prof.ms[r.k] += t;
+      m->prof.launches[r.k] += 1;
+      m->prof.units[r.k] += r.units;
+    }
+    m->prof.pool.push_back(r.a);
+    m->prof.pool.push_back(r.b);
+  }
+  m->prof.open.clear();
 }
 
 // copy device counters [lo, lo+n) to the pinned mirror and wait
@@ -244,6 +301,7 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->jpU0, V));
   TRY(ensure(m, m->jpU1, V));
   TRY(ensure(m, m->cls, V));
+  TRY(ensure(m, m->key, V));
   TRY(ensure(m, m->act, V, true));
   TRY(ensure(m, m->col, V));
   TRY(ensure(m, m->nxt, V, true));
@@ -283,27 +341,35 @@ struct Classes {
   int jp_iters = 0;
 };
 
-// Jones-Plassmann on list A (n entries): colours in m->col, act flags set,
-// class lists in m->cls. The caller clears the act flags afterwards.
-pm_status colour_list(pm_mesh* m, const int* A, int n, uint64_t sseed, Classes& out) {
+// Jones-Plassmann on list A (n entries): colours in m->col, keys in m->key,
+// act flags set, class lists in m->cls. The caller clears the act flags.
+// Iterations are launched in batches between count read-backs; a launch past
+// the end of the work finds an empty list and returns at once.
+constexpr int kJpBatch = 4;
+
+pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
-  Round rd{sseed, nullptr};
-  jp_init(A, n, m->col.p, m->act.p, m->s);
-  const int* cur = A;
-  int cn = n;
+  jp_init(A, n, m->col.p, m->act.p, rd, m->s);
   int* bufs[2] = {m->jpU0.p, m->jpU1.p};
+  const int* cur = A;
+  int known = n;  // upper bound of the current list length
   int it = 0;
-  while (cn > 0) {
-    int* nxt = bufs[it & 1];
-    set_int(m->ctr + C_LIST_A, 0, m->s);
-    jp_step(m->st, cur, cn, nxt, m->ctr + C_LIST_A, m->act.p, m->col.p, rd, m->ctr, m->s);
-    TRY(read_ctr(m, C_LIST_A, 1));
-    int nn = m->hctr[C_LIST_A];
-    if (nn >= cn) return fail(m, PM_E_DEVICE, "colouring made no progress");
-    cn = nn;
-    cur = nxt;
-    ++it;
+  set_int(m->ctr + C_JP, n, m->s);
+  for (;;) {
+    for (int b = 0; b < kJpBatch; ++b, ++it) {
+      int* nxt = bufs[it & 1];
+      int* cin = m->ctr + C_JP + (it % 32);
+      int* cout = m->ctr + C_JP + ((it + 1) % 32);
+      set_int(cout, 0, m->s);
+      timed(m, PM_K_JP, 0, [&] { jp_step(m->st, cur, cin, known, nxt, cout, m->act.p, m->col.p, rd, m->ctr, m->s); });
+      cur = nxt;
+    }
+    TRY(read_ctr(m, C_JP + (it % 32), 1));
+    int left = m->hctr[C_JP + (it % 32)];
+    if (left == 0) break;
+    if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
+    known = left;
   }
   out.jp_iters = it;
   zero_ints(m->ctr + C_HIST, 256, m->s);
@@ -320,6 +386,7 @@ void stats_zero(pm_mesh* m) { zero_ints(m->ctr + C_EVAL, 6, m->s); }
 
 pm_status stats_read(pm_mesh* m, pm_stats* st) {
   TRY(read_ctr(m, C_EVAL, 6));
+  prof_flush(m);
   if (st) {
     st->v[2] += m->hctr[C_EVAL];
     st->v[3] += m->hctr[C_DEFER];
@@ -386,30 +453,36 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   double qmin2 = o->q_min * o->q_min;
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
-  select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  timed(m, PM_K_SELECT, m->st.V,
+        [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s); });
   TRY(read_ctr(m, C_LIST_B, 1));
   int nA = m->hctr[C_LIST_B];
   int r = 0;
   Commit cm = commit_of(m);
   while (nA > 0 && r < max_rounds) {
     TRY(maybe_repack(m));
-    uint64_t sseed = stream_seed(m->seed, make_ctx(o->sweep, phase, r));
+    Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), nullptr, m->key.p};
     Classes cl;
-    TRY(colour_list(m, m->listA.p, nA, sseed, cl));
+    TRY(colour_list(m, m->listA.p, nA, rd, cl));
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
     for (int c = 0; c < cl.ncol; ++c) {
       if (cl.size[c] == 0) continue;
       zero_ints(m->ctr + C_DIRTY, 3, m->s);  // dirty, records, staging
-      OpArgs a{m->act.p, m->col.p, c, Round{sseed, nullptr}, o->L_low2, qmin2};
-      if (kind == 0) collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
-      else flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
-      commit_rows(m->st, cm, m->ctr, m->st.V, m->s);
+      OpArgs a{m->act.p, m->col.p, c, rd, o->L_low2, qmin2};
+      if (kind == 0)
+        timed(m, PM_K_COLLAPSE, cl.size[c],
+              [&] { collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
+      else
+        timed(m, PM_K_FLIP, cl.size[c],
+              [&] { flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
+      timed(m, PM_K_COMMIT, 0, [&] { commit_rows(m->st, cm, m->ctr, m->st.V, m->s); });
     }
     set_flags(m->listA.p, nA, m->act.p, 0, m->s);
     set_int(m->ctr + C_LIST_B, 0, m->s);
-    select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->s);
+    timed(m, PM_K_SELECT, m->st.V,
+          [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->s); });
     TRY(read_ctr(m, C_LIST_B, 1));
     TRY(check_err(m));
     nA = m->hctr[C_LIST_B];
@@ -475,6 +548,9 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   DBuf<uint8_t>* ub[] = {&m->act, &m->col, &m->nxt, &m->u8tmp};
   for (auto* b : ub) dfree(m, b->p, b->n);
   dfree(m, m->qpart.p, m->qpart.n);
+  dfree(m, m->key.p, m->key.n);
+  prof_flush(m);
+  for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
   if (m->ctr) (void)hipFree(m->ctr);
   if (m->hctr) (void)hipHostFree(m->hctr);
   if (m->hq) (void)hipHostFree(m->hq);
@@ -620,7 +696,7 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, stream_seed(m->seed, ctx), cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, ctx), nullptr, m->key.p}, cl));
   if (ncolours) *ncolours = cl.ncol;
   if (colour_out) {
     TRY(ensure(m, m->vt0, st.V));
@@ -666,13 +742,15 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), nullptr, m->key.p},
+                  cl));
   st->v[1] = n;
   st->v[5] = cl.ncol;
   st->v[12] = cl.jp_iters;
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
-      smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, m->s);
+      timed(m, PM_K_SMOOTH, cl.size[c],
+            [&] { smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, m->s); });
   set_flags(m->listA.p, n, m->act.p, 0, m->s);
   TRY(stats_read(m, st));
   st->v[0] = o->smooth_sweeps;
@@ -732,13 +810,43 @@ pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* 
   int nparts = std::min(std::max((m->st.T + 255) / 256, 1), 2048);
   TRY(ensure(m, m->qpart, 2 * (size_t)nparts + 2));
   if (Q || qmin) {
-    quality_sum(m->st, m->qpart.p, m->qpart.p + nparts, nparts, m->qpart.p + 2 * nparts, m->s);
+    timed(m, PM_K_QUALITY, m->st.T,
+          [&] { quality_sum(m->st, m->qpart.p, m->qpart.p + nparts, nparts, m->qpart.p + 2 * nparts, m->s); });
     HIPCHK(hipMemcpyAsync(m->hq, m->qpart.p + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, m->s));
   }
-  if (dQdx || dQdM) quality_adjoint(m->st, dQdx, dQdM, m->s);
+  if (dQdx || dQdM) timed(m, PM_K_ADJOINT, m->st.V, [&] { quality_adjoint(m->st, dQdx, dQdM, m->s); });
   TRY(sync(m));
+  prof_flush(m);
   if (Q) *Q = m->hq[0];
   if (qmin) *qmin = m->hq[1];
+  return PM_OK;
+}
+
+pm_status pm_profile(pm_mesh* m, uint32_t mask) {
+  if (!m) return PM_E_ARG;
+  TRY(sync(m));
+  prof_flush(m);
+  m->prof.mask = mask;
+  for (int k = 0; k < PM_K_COUNT; ++k) {
+    m->prof.ms[k] = 0.0;
+    m->prof.launches[k] = m->prof.units[k] = 0;
+  }
+  zero_ints(m->ctr + C_PROF_JP, 2, m->s);
+  return sync(m);
+}
+
+pm_status pm_profile_read(pm_mesh* m, int32_t id, double* ms, int64_t* launches, int64_t* units) {
+  if (!m || id < 0 || id >= PM_K_COUNT) return PM_E_ARG;
+  TRY(sync(m));
+  prof_flush(m);
+  TRY(read_ctr(m, C_PROF_JP, 2));
+  if (ms) *ms = m->prof.ms[id];
+  if (launches) *launches = m->prof.launches[id];
+  if (units) {
+    *units = m->prof.units[id];
+    if (id == PM_K_JP) *units = m->hctr[C_PROF_JP];
+    if (id == PM_K_COMMIT) *units = m->hctr[C_PROF_DIRTY];
+  }
   return PM_OK;
 }
 

@@ -92,16 +92,24 @@ __device__ __forceinline__ double qual(const Geo& g) {
   return ((kK4R3 * sqrt(p.det)) * p.A) / p.S;
 }
 
+// value of slot k of a 3-array without dynamic indexing (keeps it in registers)
+__device__ __forceinline__ double sel3(double a0, double a1, double a2, int k) {
+  return k == 0 ? a0 : (k == 1 ? a1 : a2);
+}
+
 // dq/dx for the vertex in slot k
 __device__ __forceinline__ void qual_grad_x(const Geo& g, int k, double& gx, double& gy) {
   Parts p = parts(g);
   double s = sqrt(p.det);
-  int k1 = k == 2 ? 0 : k + 1;
-  int k2 = k == 0 ? 2 : k - 1;
-  double dAx = 0.5 * (g.y[k1] - g.y[k2]);
-  double dAy = 0.5 * (g.x[k2] - g.x[k1]);
-  double ux = p.ex[k2] - p.ex[k];
-  double uy = p.ey[k2] - p.ey[k];
+  // slots k+1 and k+2 (= k-1), cyclically
+  double x1 = sel3(g.x[1], g.x[2], g.x[0], k), x2 = sel3(g.x[2], g.x[0], g.x[1], k);
+  double y1 = sel3(g.y[1], g.y[2], g.y[0], k), y2 = sel3(g.y[2], g.y[0], g.y[1], k);
+  double exk = sel3(p.ex[0], p.ex[1], p.ex[2], k), exm = sel3(p.ex[2], p.ex[0], p.ex[1], k);
+  double eyk = sel3(p.ey[0], p.ey[1], p.ey[2], k), eym = sel3(p.ey[2], p.ey[0], p.ey[1], k);
+  double dAx = 0.5 * (y1 - y2);
+  double dAy = 0.5 * (x2 - x1);
+  double ux = exm - exk;
+  double uy = eym - eyk;
   double dSx = 2.0 * (g.a * ux + g.b * uy);
   double dSy = 2.0 * (g.b * ux + g.c * uy);
   double Ks = kK4R3 * s;

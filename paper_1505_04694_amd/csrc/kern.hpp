@@ -32,6 +32,8 @@ enum Ctr {
   C_OFF = 320,      // 320..575: class offsets
   C_CUR = 576,      // 576..831: class cursors
   C_NCOL = 832,     // number of colours
+  C_PROF_JP = 833,  // profiling: active vertices visited by JP iterations
+  C_PROF_DIRTY = 834,  // profiling: dirty rows committed
   C_COUNT = 896
 };
 constexpr int kMaxColours = 255;  // colour 0xFF marks "uncoloured"
@@ -111,6 +113,7 @@ void export_tri(const Store& st, int* tri3, uint8_t* talive, hipStream_t s);
 struct Round {
   uint64_t sseed;      // stream seed of this round's priorities
   const int* lid;      // local ids (batched meshes) or null
+  uint64_t* key;       // per vertex: (priority, id) of the active vertices
 };
 
 struct Commit {
@@ -139,9 +142,10 @@ void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
                      int* n, hipStream_t s);
-void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, hipStream_t s);
-void jp_step(const Store& st, const int* U, int n, int* U2, int* nU2, const uint8_t* act, uint8_t* col, Round rd,
-             int* ctr, hipStream_t s);
+void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s);
+// one JP iteration over *nU entries of U (grid sized for nmax >= *nU)
+void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
+             uint8_t* col, Round rd, int* ctr, hipStream_t s);
 void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, hipStream_t s);
 void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s);
 

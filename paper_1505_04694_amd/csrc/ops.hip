@@ -16,6 +16,8 @@ namespace pm {
 __device__ __forceinline__ uint64_t key_of(const Round& rd, int v) {
   return vkey(rd.sseed, (uint32_t)(rd.lid ? rd.lid[v] : v));
 }
+// key of an active vertex, computed once per colouring by jp_init
+__device__ __forceinline__ uint64_t akey(const Round& rd, int v) { return rd.key[v]; }
 
 // ---- flags and lists -----------------------------------------------------------------
 __global__ void k_set_flags(const int* __restrict__ list, int n, uint8_t* __restrict__ flag, uint8_t val) {
@@ -65,34 +67,38 @@ void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* ac
 }
 
 // ---- Jones-Plassmann colouring (Sec. 3.2) ------------------------------------------------
-__global__ void k_jp_init(const int* __restrict__ A, int n, uint8_t* __restrict__ col, uint8_t* __restrict__ act) {
+__global__ void k_jp_init(const int* __restrict__ A, int n, uint8_t* __restrict__ col, uint8_t* __restrict__ act,
+                          Round rd) {
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
     col[v] = 0xFF;
     act[v] = 1;
+    rd.key[v] = key_of(rd, v);
   }
 }
-void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, hipStream_t s) {
-  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(A, n, col, act);
+void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s) {
+  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(A, n, col, act, rd);
 }
 
 // A vertex is ready once every active neighbour of larger key has a colour;
 // it then takes the smallest colour none of them has. Colours read while a
 // neighbour is being written are either unset (not ready yet) or final, so
 // the result does not depend on timing.
-__global__ void k_jp_step(Store st, const int* __restrict__ U, int n, int* __restrict__ U2, int* __restrict__ nU2,
-                          const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
+__global__ void k_jp_step(Store st, const int* __restrict__ U, const int* __restrict__ nU, int* __restrict__ U2,
+                          int* __restrict__ nU2, const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
   int i = gtid();
+  int n = *nU;
+  if (i == 0) ctr[C_PROF_JP] += n;
   if (i >= n) return;
   int v = U[i];
-  uint64_t kv = key_of(rd, v);
+  uint64_t kv = akey(rd, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
   bool big = false, ready = true;
   for (int j = 0; j < h.y; ++j) {
     int w = st.nn[h.x + j];
     if (!act[w]) continue;
-    if (key_of(rd, w) < kv) continue;
+    if (akey(rd, w) < kv) continue;
     int c = ((volatile const uint8_t*)col)[w];
     if (c == 0xFF) {
       ready = false;
@@ -115,7 +121,7 @@ __global__ void k_jp_step(Store st, const int* __restrict__ U, int n, int* __res
       bool taken = false;
       for (int j = 0; j < h.y && !taken; ++j) {
         int w = st.nn[h.x + j];
-        if (!act[w] || key_of(rd, w) < kv) continue;
+        if (!act[w] || akey(rd, w) < kv) continue;
         taken = ((volatile const uint8_t*)col)[w] == c;
       }
       if (!taken) break;
@@ -128,9 +134,9 @@ __global__ void k_jp_step(Store st, const int* __restrict__ U, int n, int* __res
   }
   ((volatile uint8_t*)col)[v] = (uint8_t)c;
 }
-void jp_step(const Store& st, const int* U, int n, int* U2, int* nU2, const uint8_t* act, uint8_t* col, Round rd,
-             int* ctr, hipStream_t s) {
-  if (n > 0) k_jp_step<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, U, n, U2, nU2, act, col, rd, ctr);
+void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
+             uint8_t* col, Round rd, int* ctr, hipStream_t s) {
+  if (nmax > 0) k_jp_step<<<(nmax + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, U, nU, U2, nU2, act, col, rd, ctr);
 }
 
 // class sizes (LDS histogram, one global atomic per colour per block)
@@ -213,11 +219,11 @@ __device__ __forceinline__ void queue_add(const Commit& cm, int x, int val, int 
 
 // a member is deferred when a same-class active neighbour has a larger key
 __device__ __forceinline__ bool beaten(const Store& st, int v, const OpArgs& a) {
-  uint64_t kv = key_of(a.rd, v);
+  uint64_t kv = akey(a.rd, v);
   Hdr h = st.hdr[v];
   for (int j = 0; j < h.y; ++j) {
     int w = st.nn[h.x + j];
-    if (a.act[w] && a.col[w] == a.cls && key_of(a.rd, w) > kv) return true;
+    if (a.act[w] && a.col[w] == a.cls && akey(a.rd, w) > kv) return true;
   }
   return false;
 }
@@ -423,7 +429,10 @@ __global__ void k_commit_alloc(Store st, Commit cm, int* ctr) {
 
 __global__ void k_commit_fill(Store st, Commit cm, int* ctr) {
   int n = min(ctr[C_REC], cm.rec_cap);
-  if (gtid() == 0) ctr[C_RECS] += n;
+  if (gtid() == 0) {
+    ctr[C_RECS] += n;
+    ctr[C_PROF_DIRTY] += ctr[C_DIRTY];
+  }
   for (int r = gtid(); r < n; r += gstride()) {
     int x = cm.rec_row[r];
     int base = cm.dbase[x];
@@ -476,7 +485,160 @@ __device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap
   return n;
 }
 
-__global__ void k_commit_merge(Store st, Commit cm, int* ctr) {
+// sorting network on a register array (all indices are compile-time constants)
+template <int N>
+__device__ __forceinline__ void bitonic(int (&a)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        int l = i ^ j;
+        if (l > i) {
+          int x = a[i], y = a[l];
+          int lo = min(x, y), hi = max(x, y);
+          bool up = (i & k) == 0;
+          a[i] = up ? lo : hi;
+          a[l] = up ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
+constexpr int kRegRow = 32;  // rows up to this many candidates are merged in registers
+
+// general path: candidates in the row's staging range, insertion sorts there
+__device__ void merge_row_staged(Store& st, const Commit& cm, int x, int base, Hdr h, int2 cp, int added, int* ctr) {
+  int* s = cm.stage + base;
+  for (int k = 0; k < h.w; ++k) s[k] = st.ne[h.z + k];
+  int m = 0, tot = h.w + added;
+  for (int k = 0; k < tot; ++k) {
+    int t = s[k];
+    Elem e = st.tri[t];
+    if (e.w && holds(e, x)) s[m++] = t;
+  }
+  sort_unique(s, m);
+  int* q = s + tot;
+  int nq = 0;
+  for (int k = 0; k < m; ++k) {
+    Elem e = st.tri[s[k]];
+    if (e.x != x) q[nq++] = e.x;
+    if (e.y != x) q[nq++] = e.y;
+    if (e.z != x) q[nq++] = e.z;
+  }
+  sort_unique(q, nq);
+  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
+  m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
+  nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
+  st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
+  st.cap[x] = make_int2(nn_cap, ne_cap);
+}
+
+// reserve a slot for n ids: in place when it fits, else fresh pool space
+__device__ bool row_slot(int64_t pool_cap, int* top, int& off, int& cap, int n, int err, int* ctr) {
+  if (n <= cap) return true;
+  int nc = max(8, (2 * n + 3) & ~3);
+  int o = atomicAdd(top, nc);
+  if ((int64_t)o + nc > pool_cap) {
+    atomicOr(&ctr[C_ERR], err);
+    return false;
+  }
+  off = o;
+  cap = nc;
+  atomicAdd(&ctr[C_RELOC], 1);
+  return true;
+}
+
+// register path: NE(x) = sorted live candidates holding x; NN(x) = the sorted
+// "next" vertices of those elements plus the one "previous" vertex that is
+// not a next (x on the boundary)
+__device__ void merge_row_regs(Store& st, const Commit& cm, int x, int base, Hdr h, int2 cp, int tot, int* ctr) {
+  constexpr int N = kRegRow;
+  int c[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int t = INT_MAX;
+    if (k < tot) {
+      t = k < h.w ? st.ne[h.z + k] : cm.stage[base + k];
+      Elem e = st.tri[t];
+      if (!(e.w && holds(e, x))) t = INT_MAX;
+    }
+    c[k] = t;
+  }
+  bitonic<N>(c);
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (c[k] != INT_MAX && (k == 0 || c[k] != c[k - 1])) ++m;
+  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
+  bool ok = row_slot(st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, m, E_NE_POOL, ctr);
+  if (!ok) m = min(m, ne_cap);
+  int nx[N], pv[N];
+  int j = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    nx[k] = INT_MAX;
+    pv[k] = INT_MAX;
+    int t = c[k];
+    if (t != INT_MAX && (k == 0 || t != c[k - 1])) {
+      if (j < m) st.ne[ne_off + j] = t;
+      ++j;
+      Elem e = st.tri[t];
+      int sl = slot_of(e, x);
+      nx[k] = at(e, sl == 2 ? 0 : sl + 1);
+      pv[k] = at(e, sl == 0 ? 2 : sl - 1);
+    }
+  }
+  bitonic<N>(nx);
+  // previous vertices missing from the nexts (one for a boundary vertex)
+  int extra = INT_MAX, nextra = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (pv[k] == INT_MAX) continue;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < N; ++q) found |= nx[q] == pv[k];
+    if (!found) {
+      extra = pv[k];
+      ++nextra;
+    }
+  }
+  if (nextra > 1) {
+    // not a disk or half-disk star: fall back to the general path
+    merge_row_staged(st, cm, x, base, h, cp, tot - h.w, ctr);
+    return;
+  }
+  int nq = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) nq += nx[k] != INT_MAX;
+  nq += nextra;
+  bool ok2 = row_slot(st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, nq, E_NN_POOL, ctr);
+  int lim = ok2 ? nq : min(nq, nn_cap);
+  int w = 0;
+  bool put = nextra == 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int v = nx[k];
+    if (v == INT_MAX) continue;
+    if (!put && extra < v) {
+      if (w < lim) st.nn[nn_off + w] = extra;
+      ++w;
+      put = true;
+    }
+    if (w < lim) st.nn[nn_off + w] = v;
+    ++w;
+  }
+  if (!put) {
+    if (w < lim) st.nn[nn_off + w] = extra;
+    ++w;
+  }
+  st.hdr[x] = make_int4(nn_off, lim, ne_off, m);
+  st.cap[x] = make_int2(nn_cap, ne_cap);
+}
+
+__global__ void __launch_bounds__(256) k_commit_merge(Store st, Commit cm, int* ctr) {
   int n = ctr[C_DIRTY];
   for (int i = gtid(); i < n; i += gstride()) {
     int x = cm.dlist[i];
@@ -488,29 +650,9 @@ __global__ void k_commit_merge(Store st, Commit cm, int* ctr) {
     cm.pend[x] = 0;
     cm.nxt[x] = 1;
     if (base < 0) continue;
-    int* s = cm.stage + base;
-    for (int k = 0; k < h.w; ++k) s[k] = st.ne[h.z + k];
-    int m = 0, tot = h.w + added;
-    for (int k = 0; k < tot; ++k) {
-      int t = s[k];
-      Elem e = st.tri[t];
-      if (e.w && holds(e, x)) s[m++] = t;
-    }
-    sort_unique(s, m);
-    int* q = s + tot;
-    int nq = 0;
-    for (int k = 0; k < m; ++k) {
-      Elem e = st.tri[s[k]];
-      if (e.x != x) q[nq++] = e.x;
-      if (e.y != x) q[nq++] = e.y;
-      if (e.z != x) q[nq++] = e.z;
-    }
-    sort_unique(q, nq);
-    int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
-    m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
-    nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
-    st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
-    st.cap[x] = make_int2(nn_cap, ne_cap);
+    int tot = h.w + added;
+    if (tot <= kRegRow) merge_row_regs(st, cm, x, base, h, cp, tot, ctr);
+    else merge_row_staged(st, cm, x, base, h, cp, added, ctr);
   }
 }
 

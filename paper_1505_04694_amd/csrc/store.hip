@@ -425,26 +425,25 @@ __global__ void k_refine_split(const double2* __restrict__ xy, const Met* __rest
   for (int t = gtid(); t < T; t += gstride()) {
     Elem e = tri[t];
     if (!e.w) continue;
-    int v[3] = {e.x, e.y, e.z};
-    int m[3];
-    int ns = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int p = v[k], q = v[k == 2 ? 0 : k + 1];
-      m[k] = elen2(xy, met, p, q) > L_up2 ? midpoint_of(hdr, nn, mid, p, q) : -1;
-      ns += m[k] >= 0;
-    }
+    int m0 = elen2(xy, met, e.x, e.y) > L_up2 ? midpoint_of(hdr, nn, mid, e.x, e.y) : -1;
+    int m1 = elen2(xy, met, e.y, e.z) > L_up2 ? midpoint_of(hdr, nn, mid, e.y, e.z) : -1;
+    int m2 = elen2(xy, met, e.z, e.x) > L_up2 ? midpoint_of(hdr, nn, mid, e.z, e.x) : -1;
+    int ns = (m0 >= 0) + (m1 >= 0) + (m2 >= 0);
     if (ns == 0) continue;
     Elem ch[4];
     if (ns == 1) {
-      int k = m[0] >= 0 ? 0 : (m[1] >= 0 ? 1 : 2);
-      int P = v[k], Q = v[(k + 1) % 3], R = v[(k + 2) % 3], M = m[k];
+      // the split edge k runs P -> Q with mid-point M, R opposite
+      int k = m0 >= 0 ? 0 : (m1 >= 0 ? 1 : 2);
+      int P = at(e, k), Q = at(e, k == 2 ? 0 : k + 1), R = at(e, k == 0 ? 2 : k - 1);
+      int M = k == 0 ? m0 : (k == 1 ? m1 : m2);
       ch[0] = mk(P, M, R);
       ch[1] = mk(M, Q, R);
     } else if (ns == 2) {
-      int k = m[0] < 0 ? 0 : (m[1] < 0 ? 1 : 2);
-      int P = v[k], Q = v[(k + 1) % 3], R = v[(k + 2) % 3];
-      int M1 = m[(k + 1) % 3], M2 = m[(k + 2) % 3];
+      // the unsplit edge k runs P -> Q; M1 on Q-R, M2 on R-P
+      int k = m0 < 0 ? 0 : (m1 < 0 ? 1 : 2);
+      int P = at(e, k), Q = at(e, k == 2 ? 0 : k + 1), R = at(e, k == 0 ? 2 : k - 1);
+      int M1 = k == 0 ? m1 : (k == 1 ? m2 : m0);
+      int M2 = k == 0 ? m2 : (k == 1 ? m0 : m1);
       ch[0] = mk(M1, R, M2);
       double dP = elen2(xy, met, P, M1), dQ = elen2(xy, met, Q, M2);
       if (dP <= dQ) {
@@ -455,14 +454,16 @@ __global__ void k_refine_split(const double2* __restrict__ xy, const Met* __rest
         ch[2] = mk(Q, M1, M2);
       }
     } else {
-      ch[0] = mk(v[0], m[0], m[2]);
-      ch[1] = mk(m[0], v[1], m[1]);
-      ch[2] = mk(m[2], m[1], v[2]);
-      ch[3] = mk(m[0], m[1], m[2]);
+      ch[0] = mk(e.x, m0, m2);
+      ch[1] = mk(m0, e.y, m1);
+      ch[2] = mk(m2, m1, e.z);
+      ch[3] = mk(m0, m1, m2);
     }
     tri[t] = ch[0];
     int base = T0 + eoff[t];
-    for (int i = 1; i <= ns; ++i) tri[base + i - 1] = ch[i];
+    tri[base] = ch[1];
+    if (ns >= 2) tri[base + 1] = ch[2];
+    if (ns == 3) tri[base + 2] = ch[3];
   }
 }
 void refine_split(const Store& st, double L_up2, const int* mid, const int* eoff, int T0, hipStream_t s) {

@@ -25,7 +25,8 @@ STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colou
 
 EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_export",
            "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
-           "pm_last_error", "pm_version", "pm_fp64_selfcheck"]
+           "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read"]
+KERNELS = ["jp", "collapse", "flip", "smooth", "commit", "adjoint", "quality", "select"]
 
 
 class PMError(RuntimeError):
@@ -90,6 +91,10 @@ def lib():
         L.pm_last_error.argtypes = [P]
         L.pm_version.restype = C.c_char_p
         L.pm_version.argtypes = []
+        L.pm_profile.restype = S
+        L.pm_profile.argtypes = [P, C.c_uint32]
+        L.pm_profile_read.restype = S
+        L.pm_profile_read.argtypes = [P, C.c_int32, P, P, P]
         L.pm_fp64_selfcheck.restype = S
         L.pm_fp64_selfcheck.argtypes = [P, P, C.c_int64, P, P]
         _lib = L
@@ -129,6 +134,16 @@ def pm_fp64_selfcheck(a, b):
     q = np.empty_like(a); r = np.empty_like(a)
     _check(None, lib().pm_fp64_selfcheck(_p(a), _p(b), a.size, _p(q), _p(r)))
     return q, r
+
+
+def pm_profile(h, mask: int):
+    _check(h, lib().pm_profile(h, mask))
+
+
+def pm_profile_read(h, kid: int):
+    ms, n, u = C.c_double(), C.c_int64(), C.c_int64()
+    _check(h, lib().pm_profile_read(h, kid, C.byref(ms), C.byref(n), C.byref(u)))
+    return dict(ms=ms.value, launches=n.value, units=u.value)
 
 
 def pm_version() -> str:
@@ -286,6 +301,12 @@ class Mesh:
 
     def quality(self, grad: bool = False):
         return pm_quality(self.h, grad)
+
+    def profile(self, mask: int):
+        pm_profile(self.h, mask)
+
+    def profile_read(self):
+        return {k: pm_profile_read(self.h, i) for i, k in enumerate(KERNELS)}
 
     def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1):
         return dict(coarsen=self.coarsen(sweep), refine=self.refine(), swap=self.swap(sweep),
