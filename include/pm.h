@@ -73,7 +73,9 @@ typedef struct {
   int32_t smooth_sweeps;  /* coloured sweeps of pm_smooth                       */
   double slack;           /* adjacency row capacity factor (>= 1)               */
   int32_t wg_size;        /* work-group size, 0 = library default               */
-  int32_t reserved;
+  int32_t variant;        /* kernel shapes: bit 0 = collapse, bit 1 = smoothing run
+                             on groups of 8 lanes per vertex instead of one thread;
+                             results are identical either way                    */
 } pm_options;
 
 /* Per-phase counters, all integers:

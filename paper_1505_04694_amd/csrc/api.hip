@@ -55,6 +55,7 @@ struct pm_mesh {
   DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
   DBuf<double> qpart;
   DBuf<uint64_t> key;
+  int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing
   int64_t peak_bytes = 0, cur_bytes = 0;
 };
 
@@ -441,12 +442,14 @@ pm_status compact(pm_mesh* m) {
 bool bad_opts(const pm_options* o) {
   return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
          o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
-         (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0);
+         (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0) ||
+         o->variant < 0 || o->variant > 3;
 }
 
 // rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1)
 pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   TRY(ensure_phase_scratch(m));
+  m->variant = o->variant;
   int mode = kind == 0 ? 1 : 2;
   int max_rounds = kind == 0 ? o->coarsen_rounds : o->swap_rounds;
   int phase = kind == 0 ? PH_COARSEN : PH_SWAP;
@@ -472,8 +475,9 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
       zero_ints(m->ctr + C_DIRTY, 3, m->s);  // dirty, records, staging
       OpArgs a{m->act.p, m->col.p, c, rd, o->L_low2, qmin2};
       if (kind == 0)
-        timed(m, PM_K_COLLAPSE, cl.size[c],
-              [&] { collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
+        timed(m, PM_K_COLLAPSE, cl.size[c], [&] {
+          collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->variant & 1, m->s);
+        });
       else
         timed(m, PM_K_FLIP, cl.size[c],
               [&] { flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
@@ -508,7 +512,7 @@ void fill_defaults(pm_options* o) {
   o->smooth_sweeps = 1;
   o->slack = 2.0;
   o->wg_size = 0;
-  o->reserved = 0;
+  o->variant = 0;
 }
 
 }  // namespace
@@ -736,6 +740,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
   TRY(ensure_phase_scratch(m));
+  m->variant = o->variant;
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
   select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
@@ -749,8 +754,9 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   st->v[12] = cl.jp_iters;
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
-      timed(m, PM_K_SMOOTH, cl.size[c],
-            [&] { smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, m->s); });
+      timed(m, PM_K_SMOOTH, cl.size[c], [&] {
+        smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant >> 1) & 1, m->s);
+      });
   set_flags(m->listA.p, n, m->act.p, 0, m->s);
   TRY(stats_read(m, st));
   st->v[0] = o->smooth_sweeps;

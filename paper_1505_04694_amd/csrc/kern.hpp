@@ -149,9 +149,11 @@ void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, in
 void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, hipStream_t s);
 void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s);
 
-void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
+// variant 0: one thread per member; 1: a group of 8 lanes per member
+void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
+                    hipStream_t s);
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
-void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, hipStream_t s);
+void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s);
 void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);

@@ -13,6 +13,8 @@
 
 namespace pm {
 
+constexpr int kG = 8;  // lanes per vertex in the lane-group kernels
+
 __device__ __forceinline__ uint64_t key_of(const Round& rd, int v) {
   return vkey(rd.sseed, (uint32_t)(rd.lid ? rd.lid[v] : v));
 }
@@ -84,13 +86,8 @@ void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStrea
 // it then takes the smallest colour none of them has. Colours read while a
 // neighbour is being written are either unset (not ready yet) or final, so
 // the result does not depend on timing.
-__global__ void k_jp_step(Store st, const int* __restrict__ U, const int* __restrict__ nU, int* __restrict__ U2,
-                          int* __restrict__ nU2, const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
-  int i = gtid();
-  int n = *nU;
-  if (i == 0) ctr[C_PROF_JP] += n;
-  if (i >= n) return;
-  int v = U[i];
+__device__ void jp_visit(const Store& st, int v, int* __restrict__ U2, int* __restrict__ nU2,
+                         const uint8_t* __restrict__ act, uint8_t* col, const Round& rd, int* ctr) {
   uint64_t kv = akey(rd, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
@@ -134,9 +131,20 @@ __global__ void k_jp_step(Store st, const int* __restrict__ U, const int* __rest
   }
   ((volatile uint8_t*)col)[v] = (uint8_t)c;
 }
+
+// grid-stride over the device-side count, so a launch past the end of the
+// work costs one empty pass of a capped grid
+__global__ void __launch_bounds__(256) k_jp_step(Store st, const int* __restrict__ U, const int* __restrict__ nU,
+                                                 int* __restrict__ U2, int* __restrict__ nU2,
+                                                 const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
+  int n = *nU;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_PROF_JP] += n;
+  for (int i = gtid(); i < n; i += gstride()) jp_visit(st, U[i], U2, nU2, act, col, rd, ctr);
+}
+
 void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
              uint8_t* col, Round rd, int* ctr, hipStream_t s) {
-  if (nmax > 0) k_jp_step<<<(nmax + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, U, nU, U2, nU2, act, col, rd, ctr);
+  if (nmax > 0) k_jp_step<<<grid_for(nmax, 2048), kBlock, 0, s>>>(st, U, nU, U2, nU2, act, col, rd, ctr);
 }
 
 // class sizes (LDS histogram, one global atomic per colour per block)
@@ -322,8 +330,15 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
   count_status(status, ctr);
 }
-void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
-  if (n > 0) k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+__global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
+                                                    Commit cm, int* ctr);
+void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  if (variant == 1)
+    k_collapse_g<<<(int)(((int64_t)n * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+  else
+    k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
 
 // ---- swapping (Sec. 2.4.3) ------------------------------------------------------------------
@@ -777,8 +792,371 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, hipStream_t s) {
-  if (n > 0) k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
+void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
+  if (n <= 0) return;
+  if (variant == 1)
+    k_smooth_g<<<(int)(((int64_t)n * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, kind, ctr);
+  else
+    k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+}
+
+// ---- lane groups: 8 lanes per vertex ----------------------------------------------------------
+// A vertex's 1-ring is spread over a group of kG lanes: lane j owns the j-th
+// neighbour and the j-th element of the vertex's sorted rows, loads them in
+// parallel and keeps its element's geometry in registers. Sums run over the
+// lanes in row order (one shuffle per term), so every FP64 sum has the same
+// rounding sequence as a serial loop over the row. Vertices with more than
+// kG neighbours or elements take the one-thread path on the group's lane 0.
+struct Grp {
+  int j;     // index in the group
+  int base;  // first lane of the group in the wavefront
+};
+__device__ __forceinline__ Grp grp() {
+  int l = __lane_id();
+  return Grp{l & (kG - 1), l & ~(kG - 1)};
+}
+__device__ __forceinline__ double gget(double v, int k, const Grp& g) { return __shfl(v, g.base + k); }
+__device__ __forceinline__ int gget(int v, int k, const Grp& g) { return __shfl(v, g.base + k); }
+// serial sum acc = ((init + v_0) + v_1) + ... over lanes 0..n-1
+__device__ __forceinline__ double gsum(double v, int n, const Grp& g) {
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kG; ++k) {
+    double t = gget(v, k, g);
+    if (k < n) acc = acc + t;
+  }
+  return acc;
+}
+// serial "first or smaller" minimum over lanes 0..n-1
+__device__ __forceinline__ double gmin(double v, int n, const Grp& g) {
+  double mn = 0.0;
+#pragma unroll
+  for (int k = 0; k < kG; ++k) {
+    double t = gget(v, k, g);
+    if (k < n && (k == 0 || t < mn)) mn = t;
+  }
+  return mn;
+}
+__device__ __forceinline__ bool gany(bool p, const Grp& g) {
+  uint64_t b = __ballot(p);
+  return ((b >> g.base) & 0xFFull) != 0;
+}
+__device__ __forceinline__ uint64_t gor64(uint64_t v, const Grp& g) {
+#pragma unroll
+  for (int d = 1; d < kG; d <<= 1) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo |= (uint32_t)__shfl_xor((int)lo, d);
+    hi |= (uint32_t)__shfl_xor((int)hi, d);
+    v = ((uint64_t)hi << 32) | lo;
+  }
+  return v;
+}
+
+// one element of a vertex's patch, in stored order; slot k holds the vertex
+struct PatchElem {
+  double x0, y0, x1, y1, x2, y2;
+  double a, b, c;  // mean tensor (stored order)
+  int k;
+};
+
+__device__ __forceinline__ PatchElem load_patch_elem(const Store& st, const Elem& e, int v) {
+  PatchElem pe;
+  double2 p0 = st.xy[e.x], p1 = st.xy[e.y], p2 = st.xy[e.z];
+  Met m0 = st.met[e.x], m1 = st.met[e.y], m2 = st.met[e.z];
+  pe.x0 = p0.x; pe.y0 = p0.y;
+  pe.x1 = p1.x; pe.y1 = p1.y;
+  pe.x2 = p2.x; pe.y2 = p2.y;
+  pe.a = ((m0.a + m1.a) + m2.a) / 3.0;
+  pe.b = ((m0.b + m1.b) + m2.b) / 3.0;
+  pe.c = ((m0.c + m1.c) + m2.c) / 3.0;
+  pe.k = slot_of(e, v);
+  return pe;
+}
+
+// the element's geometry with the patch vertex placed at p
+__device__ __forceinline__ Geo patch_geo(const PatchElem& pe, double2 p) {
+  Geo g;
+  g.x[0] = pe.k == 0 ? p.x : pe.x0;
+  g.y[0] = pe.k == 0 ? p.y : pe.y0;
+  g.x[1] = pe.k == 1 ? p.x : pe.x1;
+  g.y[1] = pe.k == 1 ? p.y : pe.y1;
+  g.x[2] = pe.k == 2 ? p.x : pe.x2;
+  g.y[2] = pe.k == 2 ? p.y : pe.y2;
+  g.a = pe.a;
+  g.b = pe.b;
+  g.c = pe.c;
+  return g;
+}
+
+// patch minimum of q^2 and validity with the vertex at p (lanes j < nw own elements)
+__device__ __forceinline__ double gpatch_min(const PatchElem& pe, bool own, double2 p, int nw, const Grp& g,
+                                             bool& valid) {
+  double q2 = 0.0;
+  bool bad = false;
+  if (own) {
+    Geo gg = patch_geo(pe, p);
+    bad = !(area2(gg) > 0.0);
+    q2 = qual2(gg);
+  }
+  valid = !gany(bad, g);
+  return gmin(q2, nw, g);
+}
+
+__device__ __forceinline__ double gpatch_q(const PatchElem& pe, bool own, double2 p, int nw, const Grp& g) {
+  double q = own ? qual(patch_geo(pe, p)) : 0.0;
+  return gsum(q, nw, g);
+}
+
+__device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  bool ownn = g.j < h.y, owne = g.j < h.w;
+  double2 pw = make_double2(0.0, 0.0);
+  Met mw{0.0, 0.0, 0.0};
+  if (ownn) {
+    int w = st.nn[h.x + g.j];
+    pw = st.xy[w];
+    mw = st.met[w];
+  }
+  PatchElem pe;
+  if (owne) pe = load_patch_elem(st, st.tri[st.ne[h.z + g.j]], v);
+  else pe = PatchElem{};
+  double2 p;
+  if (kind == 0) {
+    double ea = (mv.a + mw.a) * 0.5;
+    double eb = (mv.b + mw.b) * 0.5;
+    double ec = (mv.c + mw.c) * 0.5;
+    double dx = pw.x - pv.x, dy = pw.y - pv.y;
+    double Ga = gsum(ea, h.y, g), Gb = gsum(eb, h.y, g), Gc = gsum(ec, h.y, g);
+    double rx = gsum(ea * dx + eb * dy, h.y, g);
+    double ry = gsum(eb * dx + ec * dy, h.y, g);
+    double det = Ga * Gc - Gb * Gb;
+    p = make_double2(pv.x + (Gc * rx - Gb * ry) / det, pv.y + (Ga * ry - Gb * rx) / det);
+    bool vo, vn;
+    double oldmin = gpatch_min(pe, owne, pv, h.w, g, vo);
+    double newmin = gpatch_min(pe, owne, p, h.w, g, vn);
+    if (!(vn && newmin >= oldmin)) return false;
+  } else {
+    double ex = 0.0, ey = 0.0;
+    if (owne) qual_grad_x(patch_geo(pe, pv), pe.k, ex, ey);
+    double gx = gsum(ex, h.w, g), gy = gsum(ey, h.w, g);
+    if (gx == 0.0 && gy == 0.0) return false;
+    double ax = fabs(gx), ay = fabs(gy);
+    double nrm = ax < ay ? ay : ax;
+    double dx = gx / nrm, dy = gy / nrm;
+    double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
+    double hh = gmin(hx < hy ? hy : hx, h.y, g);
+    bool vo;
+    double oldmin = gpatch_min(pe, owne, pv, h.w, g, vo);
+    double Qold = gpatch_q(pe, owne, pv, h.w, g);
+    double step = hh;
+    bool ok = false;
+    for (int k = 1; k <= 4 && !ok; ++k) {
+      step = step * 0.5;
+      p = make_double2(pv.x + step * dx, pv.y + step * dy);
+      bool vn;
+      double newmin = gpatch_min(pe, owne, p, h.w, g, vn);
+      if (!vn || !(newmin >= oldmin)) continue;
+      if (!(gpatch_q(pe, owne, p, h.w, g) > Qold)) continue;
+      ok = true;
+    }
+    if (!ok) return false;
+  }
+  if (g.j == 0) st.xy[v] = p;
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+  Grp g = grp();
+  int gid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  int status = -1;
+  if (gid < n) {
+    int v = list[gid];
+    Hdr h = st.hdr[v];
+    if (h.y > kG || h.w > kG) {
+      if (g.j == 0) status = (kind == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v)) ? 2 : 1;
+    } else {
+      bool moved = smooth_group(st, v, h, kind, g);
+      if (g.j == 0) status = moved ? 2 : 1;
+    }
+  }
+  count_status(status, ctr);
+}
+
+// ---- collapse with lane groups -----------------------------------------------------------------
+__device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm, int* ctr, const Grp& g) {
+  bool ownn = g.j < h.y, owne = g.j < h.w;
+  uint64_t kv = a.rd.key[v];
+  int w = -1;
+  bool beat = false;
+  if (ownn) {
+    w = st.nn[h.x + g.j];
+    beat = a.act[w] && a.col[w] == a.cls && a.rd.key[w] > kv;
+  }
+  if (gany(beat, g)) {
+    if (g.j == 0) cm.nxt[v] = 1;
+    return 0;
+  }
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  uint8_t tv = st.tag[v];
+  double2 pw = make_double2(0.0, 0.0);
+  Met mw{0.0, 0.0, 0.0};
+  double L = INFINITY;
+  bool cand = false;
+  if (ownn) {
+    pw = st.xy[w];
+    mw = st.met[w];
+    if (!(tv & ~st.tag[w])) {
+      L = len2(pv, mv, pw, mw);
+      cand = L < a.L_low2;
+    }
+  }
+  // element lane: ids and data of the element's other two vertices
+  int t = -1;
+  Elem e = make_int4(0, 0, 0, 0);
+  double2 q0 = make_double2(0.0, 0.0), q1 = q0;
+  Met n0{0.0, 0.0, 0.0}, n1 = n0;
+  int o0 = -1, o1 = -1, k = 0;
+  if (owne) {
+    t = st.ne[h.z + g.j];
+    e = st.tri[t];
+    k = slot_of(e, v);
+    o0 = at(e, k == 2 ? 0 : k + 1);  // next after v
+    o1 = at(e, k == 0 ? 2 : k - 1);  // before v
+    q0 = st.xy[o0];
+    q1 = st.xy[o1];
+    n0 = st.met[o0];
+    n1 = st.met[o1];
+  }
+  double lastL = -INFINITY;
+  int lastU = -1, u = -1;
+  for (;;) {
+    // group minimum of (L, w) over candidates after (lastL, lastU)
+    bool after = cand && (L > lastL || (L == lastL && w > lastU));
+    double bL = after ? L : INFINITY;
+    int bU = after ? w : INT_MAX;
+    int bj = after ? g.j : -1;
+#pragma unroll
+    for (int d = 1; d < kG; d <<= 1) {
+      double oL = __shfl_xor(bL, d);
+      int oU = __shfl_xor(bU, d);
+      int oj = __shfl_xor(bj, d);
+      if (oL < bL || (oL == bL && oU < bU)) {
+        bL = oL;
+        bU = oU;
+        bj = oj;
+      }
+    }
+    if (bj < 0) break;
+    // the candidate's data from the lane that owns it
+    double2 pu = make_double2(gget(pw.x, bj, g), gget(pw.y, bj, g));
+    Met mu{gget(mw.a, bj, g), gget(mw.b, bj, g), gget(mw.c, bj, g)};
+    bool bad = false;
+    if (owne && o0 != bU && o1 != bU) {
+      // element (u, o0, o1) in cyclic order, rotated smallest id first
+      int r;  // rotation: which of (u, o0, o1) comes first
+      if (bU < o0 && bU < o1) r = 0;
+      else if (o0 < bU && o0 < o1) r = 1;
+      else r = 2;
+      double2 c0 = r == 0 ? pu : (r == 1 ? q0 : q1);
+      double2 c1 = r == 0 ? q0 : (r == 1 ? q1 : pu);
+      double2 c2 = r == 0 ? q1 : (r == 1 ? pu : q0);
+      Met d0 = r == 0 ? mu : (r == 1 ? n0 : n1);
+      Met d1 = r == 0 ? n0 : (r == 1 ? n1 : mu);
+      Met d2 = r == 0 ? n1 : (r == 1 ? mu : n0);
+      Geo gg = make_geo(c0, c1, c2, d0, d1, d2);
+      bad = !(area2(gg) > 0.0) || !(qual2(gg) >= a.qmin2);
+    }
+    if (!gany(bad, g)) {
+      u = bU;
+      break;
+    }
+    lastL = bL;
+    lastU = bU;
+  }
+  if (u < 0) return 1;
+  if (owne) {
+    Elem ne;
+    if (o0 == u || o1 == u) {
+      ne = e;
+      ne.w = 0;
+    } else {
+      int3 r3 = rot_min(u, o0, o1);
+      ne = make_int4(r3.x, r3.y, r3.z, 1);
+    }
+    st.tri[t] = ne;
+  }
+  if (ownn) mark_dirty(cm, w, ctr);
+  if (g.j == 0) {
+    st.valive[v] = 0;
+    queue_add(cm, u, v, h.w, ctr);
+  }
+  return 2;
+}
+
+__global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
+                                                    Commit cm, int* ctr) {
+  Grp g = grp();
+  int gid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  int status = -1;
+  if (gid < n) {
+    int v = list[gid];
+    Hdr h = st.hdr[v];
+    if (h.y > kG || h.w > kG) {
+      if (g.j == 0) status = collapse_one(st, v, a, cm, ctr);
+    } else {
+      int r = collapse_group(st, v, h, a, cm, ctr, g);
+      if (g.j == 0) status = r;
+    }
+  }
+  count_status(status, ctr);
+}
+
+// ---- adjoint with lane groups ---------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adjoint_g(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
+  Grp g = grp();
+  int v = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  if (v >= st.V) return;
+  Hdr h = st.hdr[v];
+  double gx = 0.0, gy = 0.0, ga = 0.0, gb = 0.0, gc = 0.0;
+  for (int c0 = 0; c0 < h.w; c0 += kG) {
+    int nw = min(kG, h.w - c0);
+    double ex = 0.0, ey = 0.0, da = 0.0, db = 0.0, dc = 0.0;
+    if (g.j < nw) {
+      Elem e = st.tri[st.ne[h.z + c0 + g.j]];
+      Geo gg = geo_of(st, e);
+      qual_grad_x(gg, slot_of(e, v), ex, ey);
+      qual_grad_m(gg, da, db, dc);
+      da = da / 3.0;
+      db = db / 3.0;
+      dc = dc / 3.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kG; ++k) {
+      double tx = gget(ex, k, g), ty = gget(ey, k, g), ta = gget(da, k, g), tb = gget(db, k, g),
+             tc = gget(dc, k, g);
+      if (k < nw) {
+        gx = gx + tx;
+        gy = gy + ty;
+        ga = ga + ta;
+        gb = gb + tb;
+        gc = gc + tc;
+      }
+    }
+  }
+  if (g.j == 0) {
+    if (dQdx) {
+      dQdx[2 * v] = gx;
+      dQdx[2 * v + 1] = gy;
+    }
+    if (dQdM) {
+      dQdM[3 * v] = ga;
+      dQdM[3 * v + 1] = gb;
+      dQdM[3 * v + 2] = gc;
+    }
+  }
 }
 
 // ---- quality functional and adjoint (Sec. 2.2) --------------------------------------------------
@@ -868,7 +1246,7 @@ __global__ void k_adjoint(Store st, double* __restrict__ dQdx, double* __restric
   }
 }
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s) {
-  k_adjoint<<<grid_for(st.V), kBlock, 0, s>>>(st, dQdx, dQdM);
+  k_adjoint_g<<<(int)(((int64_t)st.V * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, dQdx, dQdM);
 }
 
 __global__ void k_fp64_probe(const double* __restrict__ a, const double* __restrict__ b, int n,

@@ -39,7 +39,7 @@ class Options(C.Structure):
     _fields_ = [("L_low2", C.c_double), ("L_up2", C.c_double), ("q_min", C.c_double), ("seed", C.c_uint64),
                 ("sweep", C.c_int32), ("coarsen_rounds", C.c_int32), ("swap_rounds", C.c_int32),
                 ("refine_passes", C.c_int32), ("smooth_kind", C.c_int32), ("smooth_sweeps", C.c_int32),
-                ("slack", C.c_double), ("wg_size", C.c_int32), ("reserved", C.c_int32)]
+                ("slack", C.c_double), ("wg_size", C.c_int32), ("variant", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -260,7 +260,8 @@ def pm_quality(h, grad: bool = False):
 class Mesh:
     """Owning wrapper around a pm_mesh handle."""
 
-    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None):
+    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None, variant: int = 0):
+        self.variant = variant
         self.h = pm_mesh_create(xy, tri, metric, tags, pm_default_options(seed=seed, slack=slack), stream)
 
     @classmethod
@@ -288,16 +289,17 @@ class Mesh:
 
     def coarsen(self, sweep=0, L_low2=0.5, q_min=0.1, max_rounds=200):
         return pm_coarsen(self.h, pm_default_options(sweep=sweep, L_low2=L_low2, q_min=q_min,
-                                                     coarsen_rounds=max_rounds))
+                                                     coarsen_rounds=max_rounds, variant=self.variant))
 
     def refine(self, L_up2=2.0, max_passes=32):
         return pm_refine(self.h, pm_default_options(L_up2=L_up2, refine_passes=max_passes))
 
     def swap(self, sweep=0, max_rounds=100):
-        return pm_swap(self.h, pm_default_options(sweep=sweep, swap_rounds=max_rounds))
+        return pm_swap(self.h, pm_default_options(sweep=sweep, swap_rounds=max_rounds, variant=self.variant))
 
     def smooth(self, sweep=0, kind=0, sweeps=1):
-        return pm_smooth(self.h, pm_default_options(sweep=sweep, smooth_kind=kind, smooth_sweeps=sweeps))
+        return pm_smooth(self.h, pm_default_options(sweep=sweep, smooth_kind=kind, smooth_sweeps=sweeps,
+                                                    variant=self.variant))
 
     def quality(self, grad: bool = False):
         return pm_quality(self.h, grad)

@@ -76,10 +76,22 @@ def test_full_sweeps(name, make, seed):
     compare_quality(om, gm, "end")
 
 
+@pytest.mark.parametrize("name,make,seed", SMALL[2:4])
+def test_lane_group_variants_match(name, make, seed):
+    # collapse and smoothing on groups of 8 lanes per vertex give the same results
+    mi = make()
+    om, gm = both(mi, seed)
+    gm.variant = 3
+    run_sweeps(om, gm, 2, smooth_kinds=(0, 1))
+    compare_quality(om, gm, "end")
+
+
 @pytest.mark.parametrize("kind", [0, 1])
-def test_smoothing_sweeps_on_jittered_mesh(kind):
+@pytest.mark.parametrize("variant", [0, 2])
+def test_smoothing_sweeps_on_jittered_mesh(kind, variant):
     mi = inputs.config2(129)
     om, gm = both(mi, 1)
+    gm.variant = variant
     compare_stats(om.smooth(0, kind, 3), gm.smooth(0, kind, 3), "smooth")
     compare_mesh(om, gm, "smooth", rows=False)
     compare_quality(om, gm, "after smoothing")
