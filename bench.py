@@ -37,6 +37,10 @@ BYTES_PER_UNIT = {
 }
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def run_step(mesh, counts=None):
     """The step's phase sequence; works on pmesh.Mesh and on the oracle's mesh."""
     out = []
@@ -78,6 +82,52 @@ def topo_hash(export):
     return h.hexdigest()[:16]
 
 
+def batch_bench(count, torch, inputs, pmesh, sweeps=2, seed=2):
+    """Batched workload: `count` meshes with n log-uniform in [17, 513] and
+    per-mesh layer parameters, `sweeps` adaptation sweeps; one batched handle
+    against one plain handle per mesh, run one after the other. Mesh creation
+    is outside the timed regions; results are compared mesh by mesh."""
+    mis = inputs.config3(count, seed)
+
+    def sweep_all(objs):
+        ops = 0
+        for s in range(sweeps):
+            for o in objs:
+                tr = o.sweep(s)
+                ops += sum(st["coloured"] + st["evaluated"] + st["edges"] for st in tr.values())
+        return ops
+
+    log(f"batched workload: {count} meshes, {sum(mi.V for mi in mis)} vertices")
+    # warm-up on a small batch so first-launch costs stay out of the timing
+    w = pmesh.Batch.from_inputs(mis[:4], seed=seed)
+    sweep_all([w])
+    w.close()
+    gb = pmesh.Batch.from_inputs(mis, seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ops_b = sweep_all([gb])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"batched sweeps: {(t1 - t0) * 1e3:.1f} ms; now one handle per mesh")
+    plain = [pmesh.Mesh.from_input(mi, seed=seed) for mi in mis]
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ops_p = sweep_all(plain)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    equal = True
+    for i, pm_ in enumerate(plain):
+        e1, e2 = pm_.export(), gb.export_mesh(i)
+        equal &= bool((e1["tri"][e1["talive"]] == e2["tri"][e2["talive"]]).all()
+                      and (e1["xy"] == e2["xy"]).all() and e1["tri"].shape == e2["tri"].shape)
+        pm_.close()
+    gb.close()
+    vtot = sum(mi.V for mi in mis)
+    return {"meshes": count, "sweeps": sweeps, "vertices": vtot, "batched_ms": (t1 - t0) * 1e3,
+            "plain_ms": (t3 - t2) * 1e3, "speedup": (t3 - t2) / (t1 - t0), "ops_batched": ops_b,
+            "ops_plain": ops_p, "batched_ops_per_s": ops_b / (t1 - t0), "results_equal": equal}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,7 +135,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile-kernels", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path is single-device", file=sys.stderr)
@@ -111,6 +162,7 @@ def main():
         tr = run_step(m)
         return m, tr
 
+    log(f"inputs ready: {mi.V} vertices, {mi.T} triangles")
     # one profiled step finds the kernel with the most device time
     m, _ = gpu_step(mask=0xFF)
     prof_all = m.profile_read()
@@ -167,7 +219,12 @@ def main():
         "topology_hash": gpu_hash,
     }
 
+    if not a.no_batch:
+        result["batch"] = batch_bench(a.batch_count, torch, inputs, pmesh)
+
+    log(f"timed steps: {ms:.2f} ms/step")
     if not a.no_cpu:
+        log("oracle step (CPU baseline)")
         from oracle.orc import OracleMesh
         t2 = time.perf_counter()
         om = OracleMesh.from_input(mi, seed=PRIO_SEED)

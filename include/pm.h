@@ -171,6 +171,26 @@ pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* 
  * does; every threshold decision of the path relies on that. */
 pm_status pm_fp64_selfcheck(const double* a, const double* b, int64_t n, double* quot, double* root);
 
+/* Batches of independent meshes (Sec. 3: many small independent sets at
+ * once). pm_batch_create concatenates `count` meshes (host arrays only) into
+ * one store, each in its own vertex and element range with headroom for
+ * refinement. The phase calls (pm_coarsen, pm_refine, pm_swap, pm_smooth,
+ * pm_colour, pm_quality) then run every mesh of the batch in the same kernel
+ * launches; each mesh draws priorities from its own local vertex ids, so its
+ * result equals that of the same calls on a handle holding it alone. Rounds
+ * advance in lockstep; stats are summed over the meshes (rounds: the maximum;
+ * colours: per colouring of the whole batch). */
+pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_options* o, void* stream,
+                          pm_mesh** out);
+pm_status pm_batch_count(const pm_mesh* m, int32_t* count);
+/* slots of mesh i (its live mesh after pm_coarsen: all slots live) */
+pm_status pm_batch_sizes(const pm_mesh* m, int32_t i, int64_t* V, int64_t* T);
+/* host copies of mesh i with its own local ids; arrays sized by pm_batch_sizes */
+pm_status pm_batch_export(pm_mesh* m, int32_t i, double* xy, int32_t* tri, double* metric, uint8_t* tags,
+                          uint8_t* valive, uint8_t* talive);
+/* per-mesh quality functional and minimum quality (host arrays of count) */
+pm_status pm_batch_quality(pm_mesh* m, double* Q, double* qmin);
+
 /* Per-kernel timing. Kernel ids for pm_profile / pm_profile_read: */
 enum {
   PM_K_JP = 0,       /* Jones-Plassmann iteration; units: active vertices visited   */

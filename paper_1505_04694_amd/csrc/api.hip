@@ -50,11 +50,16 @@ struct pm_mesh {
   int* hctr = nullptr;  // pinned mirror
   double* hq = nullptr; // pinned doubles
   // scratch
-  DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, partial, mid;
+  DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
   DBuf<uint8_t> act, col, nxt, u8tmp;
   DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
   DBuf<double> qpart;
   DBuf<uint64_t> key;
+  // mesh ranges (host mirror of Store::vbase/vused/tbase/tused)
+  std::vector<int> vbase, vused, tbase, tused;
+  int* ranges = nullptr;  // device: vbase[B+1], vused[B], tbase[B+1], tused[B]
+  int* mdone = nullptr;   // device: per-mesh "refinement finished" flags
+  DBuf<int> rtmp;         // per-mesh scratch (sums, new bases)
   int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing
   int64_t peak_bytes = 0, cur_bytes = 0;
 };
@@ -248,6 +253,33 @@ pm_status grow_elements(pm_mesh* m, int need) {
   return PM_OK;
 }
 
+// copy the host range arrays to the device and point the store at them
+pm_status upload_ranges(pm_mesh* m) {
+  Store& st = m->st;
+  int B = st.B;
+  std::vector<int> all;
+  all.insert(all.end(), m->vbase.begin(), m->vbase.end());
+  all.insert(all.end(), m->vused.begin(), m->vused.end());
+  all.insert(all.end(), m->tbase.begin(), m->tbase.end());
+  all.insert(all.end(), m->tused.begin(), m->tused.end());
+  if (!m->ranges) TRY(dalloc(m, &m->ranges, all.size()));
+  HIPCHK(hipMemcpy(m->ranges, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+  st.vbase = m->ranges;
+  st.vused = st.vbase + B + 1;
+  st.tbase = st.vused + B;
+  st.tused = st.tbase + B + 1;
+  return PM_OK;
+}
+
+// ranges of a single mesh: everything in use
+pm_status single_ranges(pm_mesh* m) {
+  m->vbase = {0, m->st.V};
+  m->vused = {m->st.V};
+  m->tbase = {0, m->st.T};
+  m->tused = {m->st.T};
+  return upload_ranges(m);
+}
+
 // (Re)build every adjacency row from the element list into fresh pools.
 pm_status build_rows(pm_mesh* m) {
   Store& st = m->st;
@@ -351,7 +383,7 @@ constexpr int kJpBatch = 4;
 pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
-  jp_init(A, n, m->col.p, m->act.p, rd, m->s);
+  jp_init(m->st, A, n, m->col.p, m->act.p, rd, m->s);
   int* bufs[2] = {m->jpU0.p, m->jpU1.p};
   const int* cur = A;
   int known = n;  // upper bound of the current list length
@@ -399,43 +431,108 @@ pm_status stats_read(pm_mesh* m, pm_stats* st) {
   return PM_OK;
 }
 
-pm_status compact(pm_mesh* m) {
+// headroom a batched mesh keeps after its used slots (refinement grows into it)
+int headroom(int used) { return std::max(used / 2, 64); }
+
+// Stable renumbering of live vertices and elements. A single mesh is packed
+// densely; the meshes of a batch are packed into consecutive ranges with
+// headroom (extra_v / extra_t: further slots a mesh is known to need).
+pm_status compact(pm_mesh* m, const std::vector<int>* extra_v = nullptr, const std::vector<int>* extra_t = nullptr) {
   Store& st = m->st;
-  int V = st.V, T = st.T;
+  int V = st.V, T = st.T, B = st.B;
   TRY(ensure(m, m->vt0, V));
   TRY(ensure(m, m->vt1, V));
+  TRY(ensure(m, m->vt2, V));
   TRY(ensure(m, m->tt0, T));
   TRY(ensure(m, m->tt1, T));
+  TRY(ensure(m, m->tt2, T));
+  TRY(ensure(m, m->rtmp, 4 * (size_t)B + 4));
   TRY(ensure(m, m->partial, scan_partials_needed(std::max(V, T)) + 2));
   flag_live_vertices(st, m->vt0.p, m->s);
   scan_excl(m->vt0.p, m->vt1.p, V, m->ctr + C_TOTAL, m->partial.p, m->s);
   flag_live_elements(st, m->tt0.p, m->s);
   scan_excl(m->tt0.p, m->tt1.p, T, m->ctr + C_TOTAL2, m->partial.p, m->s);
-  TRY(read_ctr(m, C_TOTAL, 2));
-  int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
+  range_sums(m->vt1.p, m->vt0.p, st.vbase, st.vused, B, m->rtmp.p, m->s);
+  range_sums(m->tt1.p, m->tt0.p, st.tbase, st.tused, B, m->rtmp.p + B, m->s);
+  std::vector<int> live(2 * B);
+  HIPCHK(hipMemcpyAsync(live.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
+  TRY(sync(m));
+  std::vector<int> nvb(B + 1, 0), ntb(B + 1, 0);
+  for (int i = 0; i < B; ++i) {
+    int lv = live[i], lt = live[B + i];
+    int ev = extra_v ? (*extra_v)[i] : 0, et = extra_t ? (*extra_t)[i] : 0;
+    int cv = B == 1 ? lv : lv + ev + headroom(lv + ev);
+    int ct = B == 1 ? lt : lt + et + headroom(lt + et);
+    if ((int64_t)nvb[i] + cv > (1ll << 30) || (int64_t)ntb[i] + ct > (1ll << 30))
+      return fail(m, PM_E_NOMEM, "store beyond 2^30 slots");
+    nvb[i + 1] = nvb[i] + cv;
+    ntb[i + 1] = ntb[i] + ct;
+  }
+  int nV = nvb[B], nT = ntb[B];
+  HIPCHK(hipMemcpyAsync(m->rtmp.p, nvb.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, m->s));
+  HIPCHK(hipMemcpyAsync(m->rtmp.p + B + 1, ntb.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, m->s));
+  mesh_maps(m->vt0.p, m->vt1.p, st.vmesh, st.vbase, m->rtmp.p, V, m->vt2.p, m->s);
+  mesh_maps(m->tt0.p, m->tt1.p, st.tmesh, st.tbase, m->rtmp.p + B + 1, T, m->tt2.p, m->s);
+  int vcap = std::max(B == 1 ? st.Vcap : nV, 1), tcap = std::max(B == 1 ? st.Tcap : nT, 1);
   double2* xy2;
   Met* met2;
-  uint8_t* tag2;
+  uint8_t *tag2, *va2;
   Elem* tri2;
-  TRY(dalloc(m, &xy2, st.Vcap));
-  TRY(dalloc(m, &met2, st.Vcap));
-  TRY(dalloc(m, &tag2, st.Vcap));
-  TRY(dalloc(m, &tri2, st.Tcap));
-  compact_vertices(st, m->vt1.p, xy2, met2, tag2, m->s);
-  compact_elements(st, m->vt1.p, m->tt1.p, tri2, m->s);
+  TRY(dalloc(m, &xy2, vcap));
+  TRY(dalloc(m, &met2, vcap));
+  TRY(dalloc(m, &tag2, vcap));
+  TRY(dalloc(m, &va2, vcap));
+  TRY(dalloc(m, &tri2, tcap));
+  HIPCHK(hipMemsetAsync(va2, 0, vcap, m->s));
+  HIPCHK(hipMemsetAsync(tri2, 0, sizeof(Elem) * (size_t)tcap, m->s));
+  compact_vertices(st, m->vt2.p, xy2, met2, tag2, va2, m->s);
+  compact_elements(st, m->vt2.p, m->tt2.p, tri2, m->s);
+  int *vmesh2 = nullptr, *tmesh2 = nullptr;
+  if (B > 1) {
+    TRY(dalloc(m, &vmesh2, vcap));
+    TRY(dalloc(m, &tmesh2, tcap));
+    fill_mesh_ids(m->rtmp.p, B, nV, vmesh2, m->s);
+    fill_mesh_ids(m->rtmp.p + B + 1, B, nT, tmesh2, m->s);
+  }
   HIPCHK(hipStreamSynchronize(m->s));
+  if (B > 1) {
+    // headers and capacities follow the new slot count
+    Hdr* hdr2;
+    int2* cap2;
+    TRY(dalloc(m, &hdr2, vcap));
+    TRY(dalloc(m, &cap2, vcap));
+    HIPCHK(hipMemsetAsync(hdr2, 0, sizeof(Hdr) * (size_t)vcap, m->s));
+    HIPCHK(hipMemsetAsync(cap2, 0, sizeof(int2) * (size_t)vcap, m->s));
+    dfree(m, st.hdr, st.Vcap);
+    dfree(m, st.cap, st.Vcap);
+    st.hdr = hdr2;
+    st.cap = cap2;
+    dfree(m, st.vmesh, st.Vcap);
+    dfree(m, st.tmesh, st.Tcap);
+    st.vmesh = vmesh2;
+    st.tmesh = tmesh2;
+  }
   dfree(m, st.xy, st.Vcap);
   dfree(m, st.met, st.Vcap);
   dfree(m, st.tag, st.Vcap);
+  dfree(m, st.valive, st.Vcap);
   dfree(m, st.tri, st.Tcap);
   st.xy = xy2;
   st.met = met2;
   st.tag = tag2;
+  st.valive = va2;
   st.tri = tri2;
-  st.V = nv;
-  st.T = nt;
-  fill_u8(st.valive, st.Vcap, 0, m->s);
-  fill_u8(st.valive, nv, 1, m->s);
+  st.Vcap = vcap;
+  st.Tcap = tcap;
+  st.V = nV;
+  st.T = nT;
+  m->vbase = nvb;
+  m->tbase = ntb;
+  for (int i = 0; i < B; ++i) {
+    m->vused[i] = live[i];
+    m->tused[i] = live[B + i];
+  }
+  TRY(upload_ranges(m));
   return build_rows(m);
 }
 
@@ -464,7 +561,7 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   Commit cm = commit_of(m);
   while (nA > 0 && r < max_rounds) {
     TRY(maybe_repack(m));
-    Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), nullptr, m->key.p};
+    Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->key.p};
     Classes cl;
     TRY(colour_list(m, m->listA.p, nA, rd, cl));
     st->v[1] += nA;
@@ -545,9 +642,13 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, s.tri, s.Tcap);
   dfree(m, s.nn, s.nn_pool);
   dfree(m, s.ne, s.ne_pool);
+  dfree(m, s.vmesh, s.Vcap);
+  dfree(m, s.tmesh, s.Tcap);
+  dfree(m, m->ranges, 1);
+  dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
-                     &m->vt4, &m->tt0, &m->tt1, &m->partial, &m->mid, &m->dirty, &m->dlist, &m->pend, &m->dbase,
-                     &m->rec_row, &m->rec_val, &m->rec_off, &m->stage};
+                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->dirty, &m->dlist, &m->pend,
+                     &m->dbase, &m->rec_row, &m->rec_val, &m->rec_off, &m->stage, &m->rtmp};
   for (auto* b : ib) dfree(m, b->p, b->n);
   DBuf<uint8_t>* ub[] = {&m->act, &m->col, &m->nxt, &m->u8tmp};
   for (auto* b : ub) dfree(m, b->p, b->n);
@@ -615,6 +716,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   (void)hipStreamSynchronize(m->s);
   dfree(m, tri3, 3 * (size_t)T);
   dfree(m, xyraw, 2 * (size_t)V);
+  if (single_ranges(m) != PM_OK) return bail(PM_E_DEVICE);
   k_validate(st, m->ctr, m->s);
   pm_status r = check_err(m);
   if (r != PM_OK) return bail(r);
@@ -700,7 +802,7 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, ctx), nullptr, m->key.p}, cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, ctx), m->key.p}, cl));
   if (ncolours) *ncolours = cl.ncol;
   if (colour_out) {
     TRY(ensure(m, m->vt0, st.V));
@@ -747,8 +849,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), nullptr, m->key.p},
-                  cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), m->key.p}, cl));
   st->v[1] = n;
   st->v[5] = cl.ncol;
   st->v[12] = cl.jp_iters;
@@ -772,39 +873,96 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
   memset(st, 0, sizeof(*st));
   stats_zero(m);
   Store& s = m->st;
+  int B = s.B;
   int p = 0;
   bool done = false;
-  for (; p < o->refine_passes; ++p) {
+  int relayouts = 0;
+  // per-mesh flags: a mesh whose pass found nothing to split is finished
+  std::vector<int> mdone(B, 0);
+  if (B > 1) {
+    if (!m->mdone) TRY(dalloc(m, &m->mdone, B));
+    HIPCHK(hipMemcpy(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+    s.mdone = m->mdone;
+  }
+  while (p < o->refine_passes) {
     int V0 = s.V, T0 = s.T;
     TRY(ensure(m, m->vt0, V0));
     TRY(ensure(m, m->vt1, V0));
     TRY(ensure(m, m->tt0, T0));
     TRY(ensure(m, m->tt1, T0));
+    TRY(ensure(m, m->rtmp, 4 * (size_t)B + 4));
     TRY(ensure(m, m->partial, scan_partials_needed(std::max(V0, T0)) + 2));
+    zero_ints(m->ctr + C_EDGES, 1, m->s);
     refine_mark(s, o->L_up2, m->vt0.p, m->ctr, m->s);
     scan_excl(m->vt0.p, m->vt1.p, V0, m->ctr + C_TOTAL, m->partial.p, m->s);
     refine_count(s, o->L_up2, m->tt0.p, m->s);
     scan_excl(m->tt0.p, m->tt1.p, T0, m->ctr + C_TOTAL2, m->partial.p, m->s);
+    range_sums(m->vt1.p, m->vt0.p, s.vbase, s.vused, B, m->rtmp.p, m->s);
+    range_sums(m->tt1.p, m->tt0.p, s.tbase, s.tused, B, m->rtmp.p + B, m->s);
+    std::vector<int> need(2 * B);
+    HIPCHK(hipMemcpyAsync(need.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
     TRY(read_ctr(m, C_TOTAL, 2));
+    TRY(read_ctr(m, C_EDGES, 1));
     int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
+    int edges = m->hctr[C_EDGES];
     if (nv == 0) {
+      st->v[6] += edges;
       done = true;
       break;
     }
-    if ((int64_t)V0 + nv > (1ll << 30) || (int64_t)T0 + nt > (1ll << 30))
-      return fail(m, PM_E_NOMEM, "refinement beyond 2^30 vertices or elements");
-    TRY(grow_vertices(m, V0 + nv));
-    TRY(grow_elements(m, T0 + nt));
+
+    if (B == 1) {
+      if ((int64_t)V0 + nv > (1ll << 30) || (int64_t)T0 + nt > (1ll << 30))
+        return fail(m, PM_E_NOMEM, "refinement beyond 2^30 vertices or elements");
+      TRY(grow_vertices(m, V0 + nv));
+      TRY(grow_elements(m, T0 + nt));
+    } else {
+      bool fits = true;
+      for (int i = 0; i < B; ++i)
+        fits &= m->vused[i] + need[i] <= m->vbase[i + 1] - m->vbase[i] &&
+                m->tused[i] + need[B + i] <= m->tbase[i + 1] - m->tbase[i];
+      if (!fits) {
+        // a mesh outgrows its range: re-lay the batch out with room, then redo the pass
+        if (++relayouts > 1) return fail(m, PM_E_NOMEM, "refinement could not be given room");
+        std::vector<int> ev(need.begin(), need.begin() + B), et(need.begin() + B, need.end());
+        TRY(compact(m, &ev, &et));
+        continue;
+      }
+    }
+    st->v[6] += edges;
+    relayouts = 0;
+    // meshes whose pass found nothing to split are finished (checked after any relayout)
+    bool newly_done = false;
+    for (int i = 0; i < B && B > 1; ++i)
+      if (!mdone[i] && need[i] == 0) mdone[i] = 1, newly_done = true;
+    if (newly_done) HIPCHK(hipMemcpy(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice));
     TRY(ensure(m, m->mid, (size_t)s.nn_pool));
-    refine_mint(s, o->L_up2, m->vt1.p, m->mid.p, V0, m->s);
-    refine_split(s, o->L_up2, m->mid.p, m->tt1.p, T0, m->s);
-    s.V = V0 + nv;
-    s.T = T0 + nt;
+    if (B == 1) {
+      m->vused[0] = s.V;  // unchanged until the new slots are counted below
+      m->tused[0] = s.T;
+    }
+    refine_mint(s, o->L_up2, m->vt1.p, m->mid.p, m->s);
+    refine_split(s, o->L_up2, m->mid.p, m->tt1.p, m->s);
+    for (int i = 0; i < B; ++i) {
+      m->vused[i] += need[i];
+      m->tused[i] += need[B + i];
+    }
+    if (B == 1) {
+      s.V = V0 + nv;
+      s.T = T0 + nt;
+      m->vbase[1] = s.V;
+      m->tbase[1] = s.T;
+    }
+    TRY(sync(m));
+    TRY(upload_ranges(m));
     st->v[4] += nv;
     st->v[8] += nv;
     st->v[9] += nt;
+    ++p;
     TRY(build_rows(m));
   }
+  s.mdone = nullptr;
+  stats_zero(m);
   TRY(stats_read(m, st));
   st->v[0] = p;
   st->v[7] = done ? 1 : 0;
@@ -825,6 +983,179 @@ pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* 
   prof_flush(m);
   if (Q) *Q = m->hq[0];
   if (qmin) *qmin = m->hq[1];
+  return PM_OK;
+}
+
+pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_options* o, void* stream,
+                          pm_mesh** out) {
+  if (!out) return PM_E_ARG;
+  *out = nullptr;
+  if (!meshes || count < 1) return PM_E_ARG;
+  pm_options def;
+  fill_defaults(&def);
+  if (!o) o = &def;
+  if (bad_opts(o)) return PM_E_ARG;
+  std::vector<int> vb(count + 1, 0), tb(count + 1, 0), vu(count), tu(count);
+  for (int i = 0; i < count; ++i) {
+    const pm_mesh_desc& d = meshes[i];
+    if (!d.xy || !d.tri || !d.metric || d.mem_kind != PM_MEM_HOST || d.V < 3 || d.T < 1) return PM_E_ARG;
+    int64_t cv = d.V + headroom((int)std::min<int64_t>(d.V, 1 << 29));
+    int64_t ct = d.T + headroom((int)std::min<int64_t>(d.T, 1 << 29));
+    if (vb[i] + cv > (1ll << 30) || tb[i] + ct > (1ll << 30)) return PM_E_ARG;
+    vu[i] = (int)d.V;
+    tu[i] = (int)d.T;
+    vb[i + 1] = vb[i] + (int)cv;
+    tb[i + 1] = tb[i] + (int)ct;
+  }
+  int nV = vb[count], nT = tb[count];
+  // the concatenated store on the host: unused slots are dead (identity metric)
+  std::vector<double> xy(2 * (size_t)nV, 0.0), met(3 * (size_t)nV, 0.0);
+  std::vector<uint8_t> tag(nV, 0), va(nV, 0);
+  std::vector<Elem> tri(nT, make_int4(0, 0, 0, 0));
+  std::vector<int> vmesh(nV), tmesh(nT);
+  g_create_err.clear();
+  for (int i = 0; i < count; ++i) {
+    const pm_mesh_desc& d = meshes[i];
+    for (int v = vb[i]; v < vb[i + 1]; ++v) {
+      vmesh[v] = i;
+      met[3 * (size_t)v] = 1.0;
+      met[3 * (size_t)v + 2] = 1.0;
+    }
+    for (int t = tb[i]; t < tb[i + 1]; ++t) tmesh[t] = i;
+    for (int64_t v = 0; v < d.V; ++v) {
+      size_t g = (size_t)(vb[i] + v);
+      double x = d.xy[2 * v], y = d.xy[2 * v + 1];
+      xy[2 * g] = x;
+      xy[2 * g + 1] = y;
+      for (int k = 0; k < 3; ++k) met[3 * g + k] = d.metric[3 * v + k];
+      va[g] = 1;
+      if (d.tags) {
+        tag[g] = d.tags[v];
+      } else {
+        uint8_t tg = 0;
+        if (x == 0.0) tg |= 1;
+        if (x == 1.0) tg |= 2;
+        if (y == 0.0) tg |= 4;
+        if (y == 1.0) tg |= 8;
+        tag[g] = tg;
+      }
+    }
+    for (int64_t t = 0; t < d.T; ++t) {
+      int a = d.tri[3 * t], b = d.tri[3 * t + 1], c = d.tri[3 * t + 2];
+      if (a < 0 || b < 0 || c < 0 || a >= d.V || b >= d.V || c >= d.V) {
+        g_create_err = "mesh " + std::to_string(i) + ": element id out of range";
+        return PM_E_MESH;
+      }
+      a += vb[i];
+      b += vb[i];
+      c += vb[i];
+      Elem e;
+      if (a < b && a < c) e = make_int4(a, b, c, 1);
+      else if (b < a && b < c) e = make_int4(b, c, a, 1);
+      else e = make_int4(c, a, b, 1);
+      tri[tb[i] + t] = e;
+    }
+  }
+  pm_mesh* m = new (std::nothrow) pm_mesh();
+  if (!m) return PM_E_NOMEM;
+  m->s = (hipStream_t)stream;
+  m->seed = o->seed;
+  m->slack = o->slack;
+  auto bail = [&](pm_status st) {
+    g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
+    pm_mesh_destroy(m);
+    return st;
+  };
+  if (hipMalloc((void**)&m->ctr, C_COUNT * sizeof(int)) != hipSuccess) return bail(PM_E_NOMEM);
+  if (hipHostMalloc((void**)&m->hctr, C_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return bail(PM_E_NOMEM);
+  if (hipHostMalloc((void**)&m->hq, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return bail(PM_E_NOMEM);
+  zero_ints(m->ctr, C_COUNT, m->s);
+  Store& st = m->st;
+  st.B = count;
+  if (grow_vertices(m, nV) != PM_OK || grow_elements(m, nT) != PM_OK) return bail(PM_E_NOMEM);
+  st.V = nV;
+  st.T = nT;
+  if (dalloc(m, &st.vmesh, nV) != PM_OK || dalloc(m, &st.tmesh, nT) != PM_OK) return bail(PM_E_NOMEM);
+  double* xyraw = nullptr;
+  if (dalloc(m, &xyraw, 2 * (size_t)nV) != PM_OK) return bail(PM_E_NOMEM);
+  bool ok = hipMemcpy(xyraw, xy.data(), sizeof(double) * xy.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.met, met.data(), sizeof(double) * met.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.tag, tag.data(), tag.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.valive, va.data(), va.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.tri, tri.data(), sizeof(Elem) * tri.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.vmesh, vmesh.data(), sizeof(int) * vmesh.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.tmesh, tmesh.data(), sizeof(int) * tmesh.size(), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    dfree(m, xyraw, 2 * (size_t)nV);
+    return bail(PM_E_DEVICE);
+  }
+  xy_in(xyraw, nV, st.xy, m->s);
+  (void)hipStreamSynchronize(m->s);
+  dfree(m, xyraw, 2 * (size_t)nV);
+  m->vbase = vb;
+  m->tbase = tb;
+  m->vused = vu;
+  m->tused = tu;
+  if (upload_ranges(m) != PM_OK) return bail(PM_E_DEVICE);
+  k_validate(st, m->ctr, m->s);
+  pm_status r = check_err(m);
+  if (r != PM_OK) return bail(r);
+  r = build_rows(m);
+  if (r != PM_OK) return bail(r);
+  *out = m;
+  return PM_OK;
+}
+
+pm_status pm_batch_count(const pm_mesh* m, int32_t* count) {
+  if (!m || !count) return PM_E_ARG;
+  *count = m->st.B;
+  return PM_OK;
+}
+
+pm_status pm_batch_sizes(const pm_mesh* m, int32_t i, int64_t* V, int64_t* T) {
+  if (!m || i < 0 || i >= m->st.B) return PM_E_ARG;
+  if (V) *V = m->vused[i];
+  if (T) *T = m->tused[i];
+  return PM_OK;
+}
+
+pm_status pm_batch_export(pm_mesh* m, int32_t i, double* xy, int32_t* tri, double* metric, uint8_t* tags,
+                          uint8_t* valive, uint8_t* talive) {
+  if (!m || i < 0 || i >= m->st.B) return PM_E_ARG;
+  Store& st = m->st;
+  int v0 = m->vbase[i], nv = m->vused[i], t0 = m->tbase[i], nt = m->tused[i];
+  if (xy) HIPCHK(hipMemcpyAsync(xy, st.xy + v0, sizeof(double2) * nv, hipMemcpyDeviceToHost, m->s));
+  if (metric) HIPCHK(hipMemcpyAsync(metric, st.met + v0, sizeof(Met) * nv, hipMemcpyDeviceToHost, m->s));
+  if (tags) HIPCHK(hipMemcpyAsync(tags, st.tag + v0, nv, hipMemcpyDeviceToHost, m->s));
+  if (valive) HIPCHK(hipMemcpyAsync(valive, st.valive + v0, nv, hipMemcpyDeviceToHost, m->s));
+  std::vector<Elem> e(nt);
+  HIPCHK(hipMemcpyAsync(e.data(), st.tri + t0, sizeof(Elem) * nt, hipMemcpyDeviceToHost, m->s));
+  TRY(sync(m));
+  for (int t = 0; t < nt; ++t) {
+    if (tri) {
+      tri[3 * t] = e[t].w ? e[t].x - v0 : e[t].x;
+      tri[3 * t + 1] = e[t].w ? e[t].y - v0 : e[t].y;
+      tri[3 * t + 2] = e[t].w ? e[t].z - v0 : e[t].z;
+    }
+    if (talive) talive[t] = e[t].w ? 1 : 0;
+  }
+  return PM_OK;
+}
+
+pm_status pm_batch_quality(pm_mesh* m, double* Q, double* qmin) {
+  if (!m) return PM_E_ARG;
+  int B = m->st.B;
+  TRY(ensure(m, m->qpart, 2 * (size_t)B + 2));
+  quality_per_mesh(m->st, m->qpart.p, m->s);
+  std::vector<double> h(2 * (size_t)B);
+  HIPCHK(hipMemcpyAsync(h.data(), m->qpart.p, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, m->s));
+  TRY(sync(m));
+  for (int i = 0; i < B; ++i) {
+    if (Q) Q[i] = h[2 * i];
+    if (qmin) qmin[i] = h[2 * i + 1];
+  }
   return PM_OK;
 }
 

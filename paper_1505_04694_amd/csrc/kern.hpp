@@ -63,7 +63,24 @@ struct Store {
   int* nn = nullptr;
   int* ne = nullptr;
   int64_t nn_pool = 0, ne_pool = 0;  // pool capacities (entries)
+  // Several independent meshes may share one store, each in its own
+  // contiguous vertex range [vbase[i], vbase[i+1]) and element range
+  // [tbase[i], tbase[i+1]), of which the first vused[i] / tused[i] slots are
+  // in use. vmesh / tmesh give the mesh of a slot (null for a single mesh).
+  int B = 1;
+  int* vmesh = nullptr;
+  int* tmesh = nullptr;
+  int* vbase = nullptr;  // B + 1 entries (device)
+  int* vused = nullptr;  // B
+  int* tbase = nullptr;  // B + 1
+  int* tused = nullptr;  // B
+  int* mdone = nullptr;  // B flags: mesh finished refining (refinement skips it); may be null
 };
+
+// local id of a vertex within its mesh (priorities are drawn per mesh)
+__device__ __forceinline__ int local_id(const Store& st, int v) {
+  return st.vmesh ? v - st.vbase[st.vmesh[v]] : v;
+}
 
 // launch shape used by every grid-stride kernel
 constexpr int kBlock = 256;
@@ -98,22 +115,31 @@ void build_finish(const Store& st, int* ctr, hipStream_t s);
 // compaction
 void flag_live_vertices(const Store& st, int* flag, hipStream_t s);
 void flag_live_elements(const Store& st, int* flag, hipStream_t s);
-void compact_vertices(const Store& st, const int* vmap, double2* xy2, Met* met2, uint8_t* tag2, hipStream_t s);
+void compact_vertices(const Store& st, const int* vmap, double2* xy2, Met* met2, uint8_t* tag2, uint8_t* va2,
+                      hipStream_t s);
 void compact_elements(const Store& st, const int* vmap, const int* tmap, Elem* tri2, hipStream_t s);
 
 // refinement
 void refine_mark(const Store& st, double L_up2, int* cnt, int* ctr, hipStream_t s);
-void refine_mint(const Store& st, double L_up2, const int* off, int* mid, int V0, hipStream_t s);
+// new ids inside each mesh's range: base + used + (scan - scan at the range start)
+void refine_mint(const Store& st, double L_up2, const int* vscan, int* mid, hipStream_t s);
 void refine_count(const Store& st, double L_up2, int* ecnt, hipStream_t s);
-void refine_split(const Store& st, double L_up2, const int* mid, const int* eoff, int T0, hipStream_t s);
+void refine_split(const Store& st, double L_up2, const int* mid, const int* escan, hipStream_t s);
+
+// per-mesh sums of a 0/1 (or count) array over the used slots, from its exclusive scan
+void range_sums(const int* scan, const int* src, const int* base, const int* used, int B, int* out, hipStream_t s);
+// per-mesh renumbering maps: map[x] = nbase[mesh] + scan[x] - scan[base[mesh]] for flagged slots
+void mesh_maps(const int* flag, const int* scan, const int* mesh, const int* base, const int* nbase, int n, int* map,
+               hipStream_t s);
+// mesh index of every slot of the ranges given by base (B + 1 entries)
+void fill_mesh_ids(const int* base, int B, int n, int* mesh, hipStream_t s);
 
 void export_tri(const Store& st, int* tri3, uint8_t* talive, hipStream_t s);
 
 // ---- ops.hip ----
 struct Round {
   uint64_t sseed;      // stream seed of this round's priorities
-  const int* lid;      // local ids (batched meshes) or null
-  uint64_t* key;       // per vertex: (priority, id) of the active vertices
+  uint64_t* key;       // per vertex: (priority, local id) of the active vertices
 };
 
 struct Commit {
@@ -142,7 +168,7 @@ void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
                      int* n, hipStream_t s);
-void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s);
+void jp_init(const Store& st, const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s);
 // one JP iteration over *nU entries of U (grid sized for nmax >= *nU)
 void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
              uint8_t* col, Round rd, int* ctr, hipStream_t s);
@@ -158,6 +184,7 @@ void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);
+void quality_per_mesh(const Store& st, double* out, hipStream_t s);
 void fp64_probe(const double* a, const double* b, int n, double* q, double* r, hipStream_t s);
 
 }  // namespace pm

@@ -15,8 +15,8 @@ namespace pm {
 
 constexpr int kG = 8;  // lanes per vertex in the lane-group kernels
 
-__device__ __forceinline__ uint64_t key_of(const Round& rd, int v) {
-  return vkey(rd.sseed, (uint32_t)(rd.lid ? rd.lid[v] : v));
+__device__ __forceinline__ uint64_t key_of(const Store& st, const Round& rd, int v) {
+  return vkey(rd.sseed, (uint32_t)local_id(st, v));
 }
 // key of an active vertex, computed once per colouring by jp_init
 __device__ __forceinline__ uint64_t akey(const Round& rd, int v) { return rd.key[v]; }
@@ -69,17 +69,17 @@ void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* ac
 }
 
 // ---- Jones-Plassmann colouring (Sec. 3.2) ------------------------------------------------
-__global__ void k_jp_init(const int* __restrict__ A, int n, uint8_t* __restrict__ col, uint8_t* __restrict__ act,
-                          Round rd) {
+__global__ void k_jp_init(Store st, const int* __restrict__ A, int n, uint8_t* __restrict__ col,
+                          uint8_t* __restrict__ act, Round rd) {
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
     col[v] = 0xFF;
     act[v] = 1;
-    rd.key[v] = key_of(rd, v);
+    rd.key[v] = key_of(st, rd, v);
   }
 }
-void jp_init(const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s) {
-  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(A, n, col, act, rd);
+void jp_init(const Store& st, const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s) {
+  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(st, A, n, col, act, rd);
 }
 
 // A vertex is ready once every active neighbour of larger key has a colour;
@@ -1212,6 +1212,39 @@ __global__ void k_quality_final(const double* __restrict__ psum, const double* _
     out[1] = lm[0];
   }
 }
+// one block per mesh of a batch: Q and qmin of each mesh's element range
+__global__ void k_quality_mesh(Store st, double* __restrict__ out) {
+  __shared__ double ls[QB], lm[QB];
+  int i = blockIdx.x;
+  int lo = st.tbase[i], hi = st.tbase[i] + st.tused[i];
+  double s = 0.0, mn = INFINITY;
+  for (int t = lo + (int)threadIdx.x; t < hi; t += QB) {
+    Elem e = st.tri[t];
+    if (!e.w) continue;
+    double q = qual(geo_of(st, e));
+    s = s + q;
+    mn = q < mn ? q : mn;
+  }
+  ls[threadIdx.x] = s;
+  lm[threadIdx.x] = mn;
+  __syncthreads();
+  for (int d = QB / 2; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) {
+      ls[threadIdx.x] = ls[threadIdx.x] + ls[threadIdx.x + d];
+      double o = lm[threadIdx.x + d];
+      lm[threadIdx.x] = o < lm[threadIdx.x] ? o : lm[threadIdx.x];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * i] = ls[0];
+    out[2 * i + 1] = lm[0];
+  }
+}
+void quality_per_mesh(const Store& st, double* out, hipStream_t s) {
+  k_quality_mesh<<<st.B, QB, 0, s>>>(st, out);
+}
+
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s) {
   k_quality<<<nparts, QB, 0, s>>>(st, psum, pmin);
   k_quality_final<<<1, QB, 0, s>>>(psum, pmin, nparts, out2);

@@ -110,6 +110,7 @@ __global__ void k_validate_elems(const Elem* __restrict__ tri, int T, int V, con
                                  int* ctr) {
   for (int t = gtid(); t < T; t += gstride()) {
     Elem e = tri[t];
+    if (!e.w) continue;  // unused slot of a mesh's range
     if (e.x < 0 || e.y < 0 || e.z < 0 || e.x >= V || e.y >= V || e.z >= V || e.x == e.y || e.y == e.z ||
         e.x == e.z) {
       atomicOr(&ctr[C_ERR], E_MESH_ID);
@@ -121,8 +122,10 @@ __global__ void k_validate_elems(const Elem* __restrict__ tri, int T, int V, con
   }
 }
 
-__global__ void k_validate_verts(const double2* __restrict__ xy, const Met* __restrict__ met, int V, int* ctr) {
+__global__ void k_validate_verts(const double2* __restrict__ xy, const Met* __restrict__ met,
+                                 const uint8_t* __restrict__ valive, int V, int* ctr) {
   for (int v = gtid(); v < V; v += gstride()) {
+    if (!valive[v]) continue;
     Met m = met[v];
     double2 p = xy[v];
     bool ok = (m.a > 0.0) && (m.a * m.c - m.b * m.b > 0.0) && isfinite(m.a) && isfinite(m.b) &&
@@ -133,7 +136,7 @@ __global__ void k_validate_verts(const double2* __restrict__ xy, const Met* __re
 
 void k_validate(const Store& st, int* ctr, hipStream_t s) {
   k_validate_elems<<<grid_for(st.T), kBlock, 0, s>>>(st.tri, st.T, st.V, st.xy, ctr);
-  k_validate_verts<<<grid_for(st.V), kBlock, 0, s>>>(st.xy, st.met, st.V, ctr);
+  k_validate_verts<<<grid_for(st.V), kBlock, 0, s>>>(st.xy, st.met, st.valive, st.V, ctr);
 }
 
 // ---- row build ----------------------------------------------------------------------
@@ -293,17 +296,59 @@ void flag_live_elements(const Store& st, int* flag, hipStream_t s) {
 __global__ void k_compact_v(const double2* __restrict__ xy, const Met* __restrict__ met,
                             const uint8_t* __restrict__ tag, const uint8_t* __restrict__ valive, int V,
                             const int* __restrict__ vmap, double2* __restrict__ xy2, Met* __restrict__ met2,
-                            uint8_t* __restrict__ tag2) {
+                            uint8_t* __restrict__ tag2, uint8_t* __restrict__ va2) {
   for (int v = gtid(); v < V; v += gstride()) {
     if (!valive[v]) continue;
     int n = vmap[v];
     xy2[n] = xy[v];
     met2[n] = met[v];
     tag2[n] = tag[v];
+    va2[n] = 1;
   }
 }
-void compact_vertices(const Store& st, const int* vmap, double2* xy2, Met* met2, uint8_t* tag2, hipStream_t s) {
-  k_compact_v<<<grid_for(st.V), kBlock, 0, s>>>(st.xy, st.met, st.tag, st.valive, st.V, vmap, xy2, met2, tag2);
+void compact_vertices(const Store& st, const int* vmap, double2* xy2, Met* met2, uint8_t* tag2, uint8_t* va2,
+                      hipStream_t s) {
+  k_compact_v<<<grid_for(st.V), kBlock, 0, s>>>(st.xy, st.met, st.tag, st.valive, st.V, vmap, xy2, met2, tag2, va2);
+}
+
+__global__ void k_range_sums(const int* __restrict__ scan, const int* __restrict__ src, const int* __restrict__ base,
+                             const int* __restrict__ used, int B, int* __restrict__ out) {
+  for (int i = gtid(); i < B; i += gstride()) {
+    int lo = base[i], hi = base[i] + used[i];
+    // inclusive value at hi - 1 minus exclusive value at lo
+    out[i] = hi > lo ? scan[hi - 1] + src[hi - 1] - scan[lo] : 0;
+  }
+}
+void range_sums(const int* scan, const int* src, const int* base, const int* used, int B, int* out, hipStream_t s) {
+  k_range_sums<<<grid_for(B), kBlock, 0, s>>>(scan, src, base, used, B, out);
+}
+
+__global__ void k_mesh_maps(const int* __restrict__ flag, const int* __restrict__ scan, const int* __restrict__ mesh,
+                            const int* __restrict__ base, const int* __restrict__ nbase, int n, int* __restrict__ map) {
+  for (int x = gtid(); x < n; x += gstride()) {
+    if (!flag[x]) continue;
+    int i = mesh ? mesh[x] : 0;
+    map[x] = nbase[i] + scan[x] - scan[base[i]];
+  }
+}
+void mesh_maps(const int* flag, const int* scan, const int* mesh, const int* base, const int* nbase, int n, int* map,
+               hipStream_t s) {
+  k_mesh_maps<<<grid_for(n), kBlock, 0, s>>>(flag, scan, mesh, base, nbase, n, map);
+}
+
+__global__ void k_fill_mesh_ids(const int* __restrict__ base, int B, int n, int* __restrict__ mesh) {
+  for (int x = gtid(); x < n; x += gstride()) {
+    int lo = 0, hi = B;  // last i with base[i] <= x
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (base[mid] <= x) lo = mid;
+      else hi = mid;
+    }
+    mesh[x] = lo;
+  }
+}
+void fill_mesh_ids(const int* base, int B, int n, int* mesh, hipStream_t s) {
+  k_fill_mesh_ids<<<grid_for(n), kBlock, 0, s>>>(base, B, n, mesh);
 }
 
 __global__ void k_compact_t(const Elem* __restrict__ tri, int T, const int* __restrict__ vmap,
@@ -324,16 +369,21 @@ __device__ __forceinline__ double elen2(const double2* xy, const Met* met, int i
   return len2(xy[i], met[i], xy[j], met[j]);
 }
 
-// count long edges (a, b > a) per vertex; also counts tested edges
-__global__ void k_refine_mark(const double2* __restrict__ xy, const Met* __restrict__ met,
-                              const uint8_t* __restrict__ valive, const Hdr* __restrict__ hdr,
-                              const int* __restrict__ nn, int V, double L_up2, int* __restrict__ cnt, int* ctr) {
+// count long edges (a, b > a) per vertex; also counts tested edges. Meshes of
+// a batch that have finished refining are skipped.
+__global__ void k_refine_mark(Store st, double L_up2, int* __restrict__ cnt, int* ctr) {
+  const double2* xy = st.xy;
+  const Met* met = st.met;
+  const Hdr* hdr = st.hdr;
+  const int* nn = st.nn;
+  int V = st.V;
   int stride = gstride();
   for (int v0 = blockIdx.x * blockDim.x; v0 < V; v0 += stride) {
     int a = v0 + (int)threadIdx.x;
     int tested = 0, c = 0;
     if (a < V) {
-      if (valive[a]) {
+      bool skip = st.mdone && st.mdone[st.vmesh ? st.vmesh[a] : 0];
+      if (st.valive[a] && !skip) {
         Hdr h = hdr[a];
         for (int j = 0; j < h.y; ++j) {
           int b = nn[h.x + j];
@@ -348,39 +398,40 @@ __global__ void k_refine_mark(const double2* __restrict__ xy, const Met* __restr
   }
 }
 void refine_mark(const Store& st, double L_up2, int* cnt, int* ctr, hipStream_t s) {
-  k_refine_mark<<<grid_for(st.V), kBlock, 0, s>>>(st.xy, st.met, st.valive, st.hdr, st.nn, st.V, L_up2, cnt, ctr);
+  k_refine_mark<<<grid_for(st.V), kBlock, 0, s>>>(st, L_up2, cnt, ctr);
 }
 
-// new vertex ids: V0 + (exclusive count of long edges before a) + rank in a's row
-__global__ void k_refine_mint(double2* xy, Met* met, uint8_t* tag, uint8_t* valive, const Hdr* __restrict__ hdr,
-                              const int* __restrict__ nn, int V, double L_up2, const int* __restrict__ off,
-                              int* __restrict__ mid, int V0) {
-  for (int a = gtid(); a < V; a += gstride()) {
-    if (!valive[a]) continue;
-    Hdr h = hdr[a];
+// new vertex ids inside the vertex's mesh range: base + used + (long edges of
+// the mesh before a, in (a, b) order) + rank in a's row
+__global__ void k_refine_mint(Store st, double L_up2, const int* __restrict__ vscan, int* __restrict__ mid) {
+  for (int a = gtid(); a < st.V; a += gstride()) {
+    if (!st.valive[a]) continue;
+    int i = st.vmesh ? st.vmesh[a] : 0;
+    if (a >= st.vbase[i] + st.vused[i]) continue;  // minted in this pass
+    Hdr h = st.hdr[a];
+    int first = st.vbase[i] + st.vused[i] + vscan[a] - vscan[st.vbase[i]];
     int k = 0;
     for (int j = 0; j < h.y; ++j) {
-      int b = nn[h.x + j];
+      int b = st.nn[h.x + j];
       if (b <= a) continue;
-      if (!(elen2(xy, met, a, b) > L_up2)) continue;
-      int id = V0 + off[a] + k++;
+      if (!(elen2(st.xy, st.met, a, b) > L_up2)) continue;
+      int id = first + k++;
       mid[h.x + j] = id;
-      double2 pa = xy[a], pb = xy[b];
-      Met ma = met[a], mb = met[b];
-      xy[id] = make_double2((pa.x + pb.x) * 0.5, (pa.y + pb.y) * 0.5);
+      double2 pa = st.xy[a], pb = st.xy[b];
+      Met ma = st.met[a], mb = st.met[b];
+      st.xy[id] = make_double2((pa.x + pb.x) * 0.5, (pa.y + pb.y) * 0.5);
       Met mm;
       mm.a = (ma.a + mb.a) * 0.5;
       mm.b = (ma.b + mb.b) * 0.5;
       mm.c = (ma.c + mb.c) * 0.5;
-      met[id] = mm;
-      tag[id] = tag[a] & tag[b];
-      valive[id] = 1;
+      st.met[id] = mm;
+      st.tag[id] = st.tag[a] & st.tag[b];
+      st.valive[id] = 1;
     }
   }
 }
-void refine_mint(const Store& st, double L_up2, const int* off, int* mid, int V0, hipStream_t s) {
-  k_refine_mint<<<grid_for(V0), kBlock, 0, s>>>(st.xy, st.met, st.tag, st.valive, st.hdr, st.nn, V0, L_up2, off,
-                                               mid, V0);
+void refine_mint(const Store& st, double L_up2, const int* vscan, int* mid, hipStream_t s) {
+  k_refine_mint<<<grid_for(st.V), kBlock, 0, s>>>(st, L_up2, vscan, mid);
 }
 
 __global__ void k_refine_count(const double2* __restrict__ xy, const Met* __restrict__ met,
@@ -417,14 +468,21 @@ __device__ __forceinline__ Elem mk(int a, int b, int c) {
   return make_int4(r.x, r.y, r.z, 1);
 }
 
-// children by template; the first keeps the parent id, the others take
-// T0 + (exclusive count before t) + (child index - 1)
-__global__ void k_refine_split(const double2* __restrict__ xy, const Met* __restrict__ met, Elem* tri, int T,
-                               const Hdr* __restrict__ hdr, const int* __restrict__ nn, const int* __restrict__ mid,
-                               double L_up2, const int* __restrict__ eoff, int T0) {
+// children by template; the first keeps the parent id, the others take ids
+// inside the element's mesh range: base + used + (new children of the mesh
+// before t) + (child index - 1)
+__global__ void k_refine_split(Store st, double L_up2, const int* __restrict__ mid, const int* __restrict__ escan) {
+  const double2* xy = st.xy;
+  const Met* met = st.met;
+  Elem* tri = st.tri;
+  const Hdr* hdr = st.hdr;
+  const int* nn = st.nn;
+  int T = st.T;
   for (int t = gtid(); t < T; t += gstride()) {
     Elem e = tri[t];
     if (!e.w) continue;
+    int i = st.tmesh ? st.tmesh[t] : 0;
+    if (t >= st.tbase[i] + st.tused[i]) continue;  // a child written in this pass
     int m0 = elen2(xy, met, e.x, e.y) > L_up2 ? midpoint_of(hdr, nn, mid, e.x, e.y) : -1;
     int m1 = elen2(xy, met, e.y, e.z) > L_up2 ? midpoint_of(hdr, nn, mid, e.y, e.z) : -1;
     int m2 = elen2(xy, met, e.z, e.x) > L_up2 ? midpoint_of(hdr, nn, mid, e.z, e.x) : -1;
@@ -460,14 +518,14 @@ __global__ void k_refine_split(const double2* __restrict__ xy, const Met* __rest
       ch[3] = mk(m0, m1, m2);
     }
     tri[t] = ch[0];
-    int base = T0 + eoff[t];
+    int base = st.tbase[i] + st.tused[i] + escan[t] - escan[st.tbase[i]];
     tri[base] = ch[1];
     if (ns >= 2) tri[base + 1] = ch[2];
     if (ns == 3) tri[base + 2] = ch[3];
   }
 }
-void refine_split(const Store& st, double L_up2, const int* mid, const int* eoff, int T0, hipStream_t s) {
-  k_refine_split<<<grid_for(T0), kBlock, 0, s>>>(st.xy, st.met, st.tri, T0, st.hdr, st.nn, mid, L_up2, eoff, T0);
+void refine_split(const Store& st, double L_up2, const int* mid, const int* escan, hipStream_t s) {
+  k_refine_split<<<grid_for(st.T), kBlock, 0, s>>>(st, L_up2, mid, escan);
 }
 
 // ---- small utilities ---------------------------------------------------------------------------

@@ -25,7 +25,8 @@ STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colou
 
 EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_export",
            "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
-           "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read"]
+           "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read",
+           "pm_batch_create", "pm_batch_count", "pm_batch_sizes", "pm_batch_export", "pm_batch_quality"]
 KERNELS = ["jp", "collapse", "flip", "smooth", "commit", "adjoint", "quality", "select"]
 
 
@@ -95,6 +96,16 @@ def lib():
         L.pm_profile.argtypes = [P, C.c_uint32]
         L.pm_profile_read.restype = S
         L.pm_profile_read.argtypes = [P, C.c_int32, P, P, P]
+        L.pm_batch_create.restype = S
+        L.pm_batch_create.argtypes = [P, C.c_int32, C.POINTER(Options), P, C.POINTER(P)]
+        L.pm_batch_count.restype = S
+        L.pm_batch_count.argtypes = [P, P]
+        L.pm_batch_sizes.restype = S
+        L.pm_batch_sizes.argtypes = [P, C.c_int32, P, P]
+        L.pm_batch_export.restype = S
+        L.pm_batch_export.argtypes = [P, C.c_int32, P, P, P, P, P, P]
+        L.pm_batch_quality.restype = S
+        L.pm_batch_quality.argtypes = [P, P, P]
         L.pm_fp64_selfcheck.restype = S
         L.pm_fp64_selfcheck.argtypes = [P, P, C.c_int64, P, P]
         _lib = L
@@ -257,6 +268,57 @@ def pm_quality(h, grad: bool = False):
     return Q.value, qmin.value, gx, gm
 
 
+def pm_batch_create(meshes, options: Options | None = None, stream=None):
+    """meshes: list of (xy, tri, metric, tags-or-None) host arrays."""
+    n = len(meshes)
+    descs = (MeshDesc * n)()
+    keep = []
+    for i, (xy, tri, metric, tags) in enumerate(meshes):
+        xy = np.ascontiguousarray(xy, np.float64); tri = np.ascontiguousarray(tri, np.int32)
+        metric = np.ascontiguousarray(metric, np.float64)
+        tags = None if tags is None else np.ascontiguousarray(tags, np.uint8)
+        keep += [xy, tri, metric, tags]
+        descs[i].xy = _p(xy).value
+        descs[i].tri = _p(tri).value
+        descs[i].metric = _p(metric).value
+        descs[i].tags = _p(tags).value if tags is not None else None
+        descs[i].V, descs[i].T = xy.shape[0], tri.shape[0]
+        descs[i].mem_kind = PM_MEM_HOST
+    h = C.c_void_p()
+    o = options if options is not None else pm_default_options()
+    st = lib().pm_batch_create(descs, n, C.byref(o), stream if stream is not None else _stream(), C.byref(h))
+    if st != PM_OK:
+        raise PMError(st, "pm_batch_create: " + lib().pm_last_error(None).decode())
+    return h
+
+
+def pm_batch_count(h) -> int:
+    n = C.c_int32()
+    _check(h, lib().pm_batch_count(h, C.byref(n)))
+    return n.value
+
+
+def pm_batch_sizes(h, i: int):
+    V, T = C.c_int64(), C.c_int64()
+    _check(h, lib().pm_batch_sizes(h, i, C.byref(V), C.byref(T)))
+    return V.value, T.value
+
+
+def pm_batch_export(h, i: int):
+    V, T = pm_batch_sizes(h, i)
+    xy = np.empty((V, 2)); met = np.empty((V, 3)); tri = np.empty((max(T, 1), 3), np.int32)
+    tags = np.empty(V, np.uint8); va = np.empty(V, np.uint8); ta = np.empty(max(T, 1), np.uint8)
+    _check(h, lib().pm_batch_export(h, i, _p(xy), _p(tri), _p(met), _p(tags), _p(va), _p(ta)))
+    return dict(xy=xy, tri=tri[:T], metric=met, tags=tags, valive=va.astype(bool), talive=ta[:T].astype(bool))
+
+
+def pm_batch_quality(h):
+    n = pm_batch_count(h)
+    Q = np.empty(n); qm = np.empty(n)
+    _check(h, lib().pm_batch_quality(h, _p(Q), _p(qm)))
+    return Q, qm
+
+
 class Mesh:
     """Owning wrapper around a pm_mesh handle."""
 
@@ -313,3 +375,24 @@ class Mesh:
     def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1):
         return dict(coarsen=self.coarsen(sweep), refine=self.refine(), swap=self.swap(sweep),
                     smooth=self.smooth(sweep, smooth_kind, smooth_sweeps))
+
+
+class Batch(Mesh):
+    """A batch of independent meshes adapted by the same kernel launches."""
+
+    def __init__(self, meshes, seed: int = 0, slack: float = 2.0, stream=None, variant: int = 0):
+        self.variant = variant
+        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack), stream)
+
+    @classmethod
+    def from_inputs(cls, mis, seed: int = 0, **kw):
+        return cls([(mi.xy, mi.tri, mi.metric, mi.tags) for mi in mis], seed=seed, **kw)
+
+    def count(self):
+        return pm_batch_count(self.h)
+
+    def export_mesh(self, i: int):
+        return pm_batch_export(self.h, i)
+
+    def quality_per_mesh(self):
+        return pm_batch_quality(self.h)
