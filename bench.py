@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a device copy of 1 GiB (a kernel of known traffic for counter scaling)")
     ap.add_argument("--batch-count", type=int, default=256)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -163,6 +165,12 @@ def main():
         return m, tr
 
     log(f"inputs ready: {mi.V} vertices, {mi.T} triangles")
+    if a.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     # one profiled step finds the kernel with the most device time
     m, _ = gpu_step(mask=0xFF)
     prof_all = m.profile_read()

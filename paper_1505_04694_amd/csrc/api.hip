@@ -52,6 +52,8 @@ struct pm_mesh {
   // scratch
   DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
   DBuf<uint8_t> act, col, nxt, u8tmp;
+  DBuf<Met> emet;   // smoothing: per-element mean tensors
+  DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
   DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
   DBuf<double> qpart;
   DBuf<uint64_t> key;
@@ -342,6 +344,9 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->pend, V, true));
   TRY(ensure(m, m->dlist, V));
   TRY(ensure(m, m->dbase, V));
+  TRY(ensure(m, m->sflag, V));
+  TRY(ensure(m, m->spos, V));
+  TRY(ensure(m, m->spart, scan_partials_needed(V) + 2));
   int rec = 2 * V + 64;
   TRY(ensure(m, m->rec_row, rec));
   TRY(ensure(m, m->rec_val, rec));
@@ -406,7 +411,11 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   }
   out.jp_iters = it;
   zero_ints(m->ctr + C_HIST, 256, m->s);
-  class_lists(A, n, m->col.p, m->ctr, m->cls.p, m->s);
+  int nb = (n + kBlock - 1) / kBlock;
+  TRY(ensure(m, m->ctab, 256 * (size_t)nb + 256));
+  TRY(ensure(m, m->ctabs, 256 * (size_t)nb + 256));
+  TRY(ensure(m, m->spart, scan_partials_needed(256 * nb) + 2));
+  class_lists(A, n, m->col.p, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
   TRY(read_ctr(m, C_HIST, C_NCOL + 1 - C_HIST));
   TRY(check_err(m));
   out.ncol = m->hctr[C_NCOL];
@@ -554,7 +563,8 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
   timed(m, PM_K_SELECT, m->st.V,
-        [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s); });
+        [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p,
+                          m->spos.p, m->spart.p, m->s); });
   TRY(read_ctr(m, C_LIST_B, 1));
   int nA = m->hctr[C_LIST_B];
   int r = 0;
@@ -583,7 +593,8 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
     set_flags(m->listA.p, nA, m->act.p, 0, m->s);
     set_int(m->ctr + C_LIST_B, 0, m->s);
     timed(m, PM_K_SELECT, m->st.V,
-          [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->s); });
+          [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
+                          m->spos.p, m->spart.p, m->s); });
     TRY(read_ctr(m, C_LIST_B, 1));
     TRY(check_err(m));
     nA = m->hctr[C_LIST_B];
@@ -648,9 +659,11 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
                      &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->dirty, &m->dlist, &m->pend,
-                     &m->dbase, &m->rec_row, &m->rec_val, &m->rec_off, &m->stage, &m->rtmp};
+                     &m->dbase, &m->rec_row, &m->rec_val, &m->rec_off, &m->stage, &m->rtmp, &m->sflag, &m->spos,
+                     &m->ctab, &m->ctabs, &m->spart};
   for (auto* b : ib) dfree(m, b->p, b->n);
   DBuf<uint8_t>* ub[] = {&m->act, &m->col, &m->nxt, &m->u8tmp};
+  dfree(m, m->emet.p, m->emet.n);
   for (auto* b : ub) dfree(m, b->p, b->n);
   dfree(m, m->qpart.p, m->qpart.n);
   dfree(m, m->key.p, m->key.n);
@@ -798,7 +811,8 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
     act_in = m->u8tmp.p;
   }
   set_int(m->ctr + C_LIST_B, 0, m->s);
-  select_vertices(st, 0, 0.0, act_in, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  select_vertices(st, 0, 0.0, act_in, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p, m->spos.p, m->spart.p,
+                  m->s);
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
@@ -845,7 +859,8 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   m->variant = o->variant;
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
-  select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->s);
+  select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p, m->spos.p,
+                  m->spart.p, m->s);
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
@@ -853,11 +868,16 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   st->v[1] = n;
   st->v[5] = cl.ncol;
   st->v[12] = cl.jp_iters;
+  // topology and metrics stay fixed while smoothing: element tensors once
+  TRY(ensure(m, m->emet, (size_t)std::max(m->st.T, 1)));
+  element_metrics(m->st, m->emet.p, m->s);
+  m->st.emet = m->emet.p;
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
       timed(m, PM_K_SMOOTH, cl.size[c], [&] {
         smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant >> 1) & 1, m->s);
       });
+  m->st.emet = nullptr;
   set_flags(m->listA.p, n, m->act.p, 0, m->s);
   TRY(stats_read(m, st));
   st->v[0] = o->smooth_sweeps;

@@ -203,6 +203,19 @@ __device__ __forceinline__ int wave_add_full(int* counter, int amount) {
   return base + incl - amount;
 }
 
+// XCD-aware block order. Work-groups are dealt to the 8 XCDs in turn (block b
+// runs on XCD b % 8), and each XCD has its own L2. Renumbering blocks so that
+// every XCD receives one contiguous eighth of the grid keeps neighbouring work
+// items (neighbouring vertices, when lists are in vertex order) in one L2.
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_block() {
+  int nb = gridDim.x, b = blockIdx.x;
+  int per = nb / kXcd, rem = nb % kXcd;
+  int x = b % kXcd, k = b / kXcd;
+  return x * per + min(x, rem) + k;
+}
+__device__ __forceinline__ int xtid() { return xcd_block() * blockDim.x + threadIdx.x; }
+
 // grid-stride helpers
 __device__ __forceinline__ int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gstride() { return gridDim.x * blockDim.x; }

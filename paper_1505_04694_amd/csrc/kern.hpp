@@ -75,6 +75,8 @@ struct Store {
   int* tbase = nullptr;  // B + 1
   int* tused = nullptr;  // B
   int* mdone = nullptr;  // B flags: mesh finished refining (refinement skips it); may be null
+  // per-element mean tensor, valid while topology and metrics are fixed (smoothing); may be null
+  Met* emet = nullptr;
 };
 
 // local id of a vertex within its mesh (priorities are drawn per mesh)
@@ -166,13 +168,16 @@ struct OpArgs {
 
 void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s);
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
+// selected vertices in ascending order; flag/pos: V ints, partial: scan scratch
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
-                     int* n, hipStream_t s);
+                     int* n, int* flag, int* pos, int* partial, hipStream_t s);
 void jp_init(const Store& st, const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s);
 // one JP iteration over *nU entries of U (grid sized for nmax >= *nU)
 void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
              uint8_t* col, Round rd, int* ctr, hipStream_t s);
-void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, hipStream_t s);
+// stable class lists; tab/tabscan: 256 * ceil(n/256) ints each
+void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, int* tab, int* tabscan, int* partial,
+                 hipStream_t s);
 void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s);
 
 // variant 0: one thread per member; 1: a group of 8 lanes per member
@@ -185,6 +190,7 @@ void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s);
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);
 void quality_per_mesh(const Store& st, double* out, hipStream_t s);
+void element_metrics(const Store& st, Met* out, hipStream_t s);
 void fp64_probe(const double* a, const double* b, int n, double* q, double* r, hipStream_t s);
 
 }  // namespace pm

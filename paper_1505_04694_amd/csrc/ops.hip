@@ -54,18 +54,27 @@ __device__ __forceinline__ bool want(const Store& st, int v, int mode, double L_
   }
 }
 
-// every vertex v with (nxt == null or nxt[v]) and want(v); clears nxt
-__global__ void k_select(Store st, int mode, double L_low2, const uint8_t* __restrict__ active,
-                         uint8_t* __restrict__ nxt, int* __restrict__ out, int* __restrict__ n) {
-  for (int v = gtid(); v < st.V; v += gstride()) {
+// flag[v] = 1 for every vertex v with (nxt == null or nxt[v]) and want(v); clears nxt
+__global__ void k_select_flags(Store st, int mode, double L_low2, const uint8_t* __restrict__ active,
+                               uint8_t* __restrict__ nxt, int* __restrict__ flag) {
+  for (int v = xtid(); v < st.V; v += gstride()) {
     bool on = nxt ? nxt[v] != 0 : true;
     if (nxt && on) nxt[v] = 0;
-    if (on && want(st, v, mode, L_low2, active)) out[wave_append_slot(n)] = v;
+    flag[v] = (on && want(st, v, mode, L_low2, active)) ? 1 : 0;
   }
 }
+__global__ void k_select_scatter(int V, const int* __restrict__ flag, const int* __restrict__ pos,
+                                 int* __restrict__ out) {
+  for (int v = gtid(); v < V; v += gstride())
+    if (flag[v]) out[pos[v]] = v;
+}
+// the selected vertices in ascending id order (an ordered compaction), so
+// that lists and the colour classes cut from them follow the mesh's layout
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
-                     int* n, hipStream_t s) {
-  k_select<<<grid_for(st.V), kBlock, 0, s>>>(st, mode, L_low2, active, nxt, out, n);
+                     int* n, int* flag, int* pos, int* partial, hipStream_t s) {
+  k_select_flags<<<grid_for(st.V), kBlock, 0, s>>>(st, mode, L_low2, active, nxt, flag);
+  scan_excl(flag, pos, st.V, n, partial, s);
+  k_select_scatter<<<grid_for(st.V), kBlock, 0, s>>>(st.V, flag, pos, out);
 }
 
 // ---- Jones-Plassmann colouring (Sec. 3.2) ------------------------------------------------
@@ -139,7 +148,7 @@ __global__ void __launch_bounds__(256) k_jp_step(Store st, const int* __restrict
                                                  const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
   int n = *nU;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_PROF_JP] += n;
-  for (int i = gtid(); i < n; i += gstride()) jp_visit(st, U[i], U2, nU2, act, col, rd, ctr);
+  for (int i = xtid(); i < n; i += gstride()) jp_visit(st, U[i], U2, nU2, act, col, rd, ctr);
 }
 
 void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
@@ -147,56 +156,82 @@ void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, in
   if (nmax > 0) k_jp_step<<<grid_for(nmax, 2048), kBlock, 0, s>>>(st, U, nU, U2, nU2, act, col, rd, ctr);
 }
 
-// class sizes (LDS histogram, one global atomic per colour per block)
-__global__ void k_class_hist(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int* ctr) {
+// Class lists by a stable counting sort on the colour: per block (256 list
+// entries) the number of each colour, an exclusive scan over (colour, block),
+// then every entry goes to its colour's range at the position of its rank
+// among equal colours in the block. Class lists keep the order of A.
+__global__ void k_class_count(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int nb,
+                              int* __restrict__ tab) {
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  int i = gtid();
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) atomicAdd(&h[col[A[i]]], 1);
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&ctr[C_HIST + threadIdx.x], h[threadIdx.x]);
+  tab[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
-__global__ void k_class_offsets(int* ctr) {
-  __shared__ int lds[256];
+
+// rank of each lane among the lanes of its block holding the same colour, in lane order
+__device__ int block_rank(int c, bool valid, int* wcnt /* 4 waves x 256 */) {
+  int lane = __lane_id(), w = threadIdx.x / kWave;
+  uint64_t lt = (1ull << lane) - 1ull;
+  int rank = 0, mine = 0;
+  uint64_t left = __ballot(valid);
+  while (left) {
+    int lead = __ffsll((unsigned long long)left) - 1;
+    int cc = __shfl(c, lead);
+    uint64_t mask = __ballot(valid && c == cc);
+    if (valid && c == cc) {
+      rank = __popcll(mask & lt);
+      mine = __popcll(mask);
+    }
+    if (lane == lead) wcnt[w * 256 + cc] = __popcll(mask);
+    left &= ~mask;
+  }
+  __syncthreads();
+  if (valid)
+    for (int k = 0; k < w; ++k) rank += wcnt[k * 256 + c];
+  (void)mine;
+  return rank;
+}
+
+__global__ void k_class_place(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int nb,
+                              const int* __restrict__ tabscan, int* __restrict__ out) {
+  __shared__ int wcnt[4 * 256];
+  for (int k = threadIdx.x; k < 4 * 256; k += blockDim.x) wcnt[k] = 0;
+  __syncthreads();
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool valid = i < n;
+  int v = valid ? A[i] : -1;
+  int c = valid ? (int)col[v] : 0;
+  int r = block_rank(c, valid, wcnt);
+  if (valid) out[tabscan[(int64_t)c * nb + blockIdx.x] + r] = v;
+}
+
+__global__ void k_class_sizes(const int* __restrict__ tabscan, int nb, int n, int* ctr) {
   int c = threadIdx.x;
-  lds[c] = ctr[C_HIST + c];
+  int lo = tabscan[(int64_t)c * nb];
+  int hi = c < 255 ? tabscan[(int64_t)(c + 1) * nb] : n;
+  ctr[C_HIST + c] = hi - lo;
+  ctr[C_OFF + c] = lo;
   __syncthreads();
   if (c == 0) {
-    int acc = 0, ncol = 0;
-    for (int k = 0; k < 256; ++k) {
-      ctr[C_OFF + k] = acc;
-      ctr[C_CUR + k] = 0;
-      acc += lds[k];
-      if (lds[k]) ncol = k + 1;
-    }
+    int ncol = 0;
+    for (int k = 0; k < 256; ++k)
+      if (ctr[C_HIST + k]) ncol = k + 1;
     ctr[C_NCOL] = ncol;
   }
 }
-__global__ void k_class_scatter(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int* ctr,
-                                int* __restrict__ out) {
-  __shared__ int cnt[256], base[256];
-  cnt[threadIdx.x] = 0;
-  __syncthreads();
-  int i = gtid();
-  int v = -1, c = 0, r = 0;
-  if (i < n) {
-    v = A[i];
-    c = col[v];
-    r = atomicAdd(&cnt[c], 1);
-  }
-  __syncthreads();
-  if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr[C_CUR + threadIdx.x], cnt[threadIdx.x]);
-  __syncthreads();
-  if (v >= 0) out[ctr[C_OFF + c] + base[c] + r] = v;
-}
-void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, hipStream_t s) {
+
+void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, int* tab, int* tabscan, int* partial,
+                 hipStream_t s) {
   static_assert(kBlock == 256, "class kernels use one LDS slot per colour and thread");
-  int g = (n + kBlock - 1) / kBlock;
-  if (g < 1) g = 1;
-  k_class_hist<<<g, kBlock, 0, s>>>(A, n, col, ctr);
-  k_class_offsets<<<1, 256, 0, s>>>(ctr);
-  k_class_scatter<<<g, kBlock, 0, s>>>(A, n, col, ctr, out);
+  int nb = (n + kBlock - 1) / kBlock;
+  if (nb < 1) nb = 1;
+  k_class_count<<<nb, kBlock, 0, s>>>(A, n, col, nb, tab);
+  scan_excl(tab, tabscan, 256 * nb, ctr + C_TOTAL, partial, s);
+  k_class_place<<<nb, kBlock, 0, s>>>(A, n, col, nb, tabscan, out);
+  k_class_sizes<<<1, 256, 0, s>>>(tabscan, nb, n, ctr);
 }
 
 __global__ void k_colour_out(int V, const uint8_t* __restrict__ act, const uint8_t* __restrict__ col,
@@ -261,21 +296,36 @@ __device__ __forceinline__ void count_status(int status, int* ctr) {
 // tried in ascending (L^2, u); the first whose re-pointed elements all keep
 // area > 0 and q^2 >= q_min^2 is taken.
 __device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
-  if (beaten(st, v, a)) {
-    cm.nxt[v] = 1;
-    return 0;
-  }
   Hdr h = st.hdr[v];
   double2 pv = st.xy[v];
   Met mv = st.met[v];
   uint8_t tv = st.tag[v];
+  uint64_t kv = akey(a.rd, v);
+  // one pass over the 1-ring: re-validation and the first candidate together
+  double bL = INFINITY;
+  int bU = -1;
+  for (int j = 0; j < h.y; ++j) {
+    int w = st.nn[h.x + j];
+    if (a.act[w] && a.col[w] == a.cls && akey(a.rd, w) > kv) {
+      cm.nxt[v] = 1;
+      return 0;
+    }
+    if (tv & ~st.tag[w]) continue;
+    double L = len2(pv, mv, st.xy[w], st.met[w]);
+    if (!(L < a.L_low2)) continue;
+    if (bU < 0 || L < bL || (L == bL && w < bU)) {
+      bL = L;
+      bU = w;
+    }
+  }
   double lastL = -INFINITY;
   int lastU = -1;
   int u = -1;
-  for (;;) {
-    double bL = INFINITY;
-    int bU = -1;
-    for (int j = 0; j < h.y; ++j) {
+  for (bool first = true;; first = false) {
+    if (!first) {
+      bL = INFINITY;
+      bU = -1;
+      for (int j = 0; j < h.y; ++j) {
       int w = st.nn[h.x + j];
       if (tv & ~st.tag[w]) continue;
       double L = len2(pv, mv, st.xy[w], st.met[w]);
@@ -285,6 +335,7 @@ __device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, 
       if (after && better) {
         bL = L;
         bU = w;
+      }
       }
     }
     if (bU < 0) break;
@@ -325,7 +376,7 @@ __device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, 
 }
 
 __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
-  int i = gtid();
+  int i = xtid();
   int status = -1;
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
   count_status(status, ctr);
@@ -406,7 +457,7 @@ __device__ int flip_one(Store st, int v, const OpArgs& a, const Commit& cm, int*
 }
 
 __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
-  int i = gtid();
+  int i = xtid();
   int status = -1;
   if (i < n) status = flip_one(st, list[i], a, cm, ctr);
   count_status(status, ctr);
@@ -679,17 +730,51 @@ void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s) 
 }
 
 // ---- smoothing (Sec. 2.4.4) ---------------------------------------------------------------------
+__global__ void k_elem_metric(Store st, Met* __restrict__ out) {
+  for (int t = gtid(); t < st.T; t += gstride()) {
+    Elem e = st.tri[t];
+    if (!e.w) continue;
+    Met m0 = st.met[e.x], m1 = st.met[e.y], m2 = st.met[e.z];
+    Met r;
+    r.a = ((m0.a + m1.a) + m2.a) / 3.0;
+    r.b = ((m0.b + m1.b) + m2.b) / 3.0;
+    r.c = ((m0.c + m1.c) + m2.c) / 3.0;
+    out[t] = r;
+  }
+}
+void element_metrics(const Store& st, Met* out, hipStream_t s) {
+  k_elem_metric<<<grid_for(st.T), kBlock, 0, s>>>(st, out);
+}
+
+// element t's geometry with vertex v at p; the mean tensor comes from the
+// per-element array when present (the same value, computed once)
+__device__ __forceinline__ Geo patch_elem_geo(const Store& st, int t, const Elem& e, int v, double2 p) {
+  double2 p0 = e.x == v ? p : st.xy[e.x];
+  double2 p1 = e.y == v ? p : st.xy[e.y];
+  double2 p2 = e.z == v ? p : st.xy[e.z];
+  if (st.emet) {
+    Geo g;
+    g.x[0] = p0.x; g.y[0] = p0.y;
+    g.x[1] = p1.x; g.y[1] = p1.y;
+    g.x[2] = p2.x; g.y[2] = p2.y;
+    Met m = st.emet[t];
+    g.a = m.a;
+    g.b = m.b;
+    g.c = m.c;
+    return g;
+  }
+  return make_geo(p0, p1, p2, st.met[e.x], st.met[e.y], st.met[e.z]);
+}
+
 // smallest q^2 over v's elements with v placed at p; valid = all areas positive
 __device__ double patch_min_q2(const Store& st, int v, Hdr h, double2 p, bool& valid) {
   valid = true;
   double mn = 0.0;
   bool first = true;
   for (int i = 0; i < h.w; ++i) {
-    Elem e = st.tri[st.ne[h.z + i]];
-    double2 p0 = e.x == v ? p : st.xy[e.x];
-    double2 p1 = e.y == v ? p : st.xy[e.y];
-    double2 p2 = e.z == v ? p : st.xy[e.z];
-    Geo g = make_geo(p0, p1, p2, st.met[e.x], st.met[e.y], st.met[e.z]);
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    Geo g = patch_elem_geo(st, t, e, v, p);
     if (!(area2(g) > 0.0)) valid = false;
     double q2 = qual2(g);
     if (first || q2 < mn) mn = q2;
@@ -701,13 +786,16 @@ __device__ double patch_min_q2(const Store& st, int v, Hdr h, double2 p, bool& v
 __device__ double patch_q(const Store& st, int v, Hdr h, double2 p) {
   double s = 0.0;
   for (int i = 0; i < h.w; ++i) {
-    Elem e = st.tri[st.ne[h.z + i]];
-    double2 p0 = e.x == v ? p : st.xy[e.x];
-    double2 p1 = e.y == v ? p : st.xy[e.y];
-    double2 p2 = e.z == v ? p : st.xy[e.z];
-    s = s + qual(make_geo(p0, p1, p2, st.met[e.x], st.met[e.y], st.met[e.z]));
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    s = s + qual(patch_elem_geo(st, t, e, v, p));
   }
   return s;
+}
+
+// "first or smaller" running minimum, as in a serial loop over the row
+__device__ __forceinline__ void run_min(double q, bool first, double& mn) {
+  if (first || q < mn) mn = q;
 }
 
 __device__ bool smooth_laplace(Store st, int v) {
@@ -731,9 +819,25 @@ __device__ bool smooth_laplace(Store st, int v) {
   }
   double det = Ga * Gc - Gb * Gb;
   double2 p = make_double2(pv.x + (Gc * rx - Gb * ry) / det, pv.y + (Ga * ry - Gb * rx) / det);
-  bool vo, vn;
-  double oldmin = patch_min_q2(st, v, h, pv, vo);
-  double newmin = patch_min_q2(st, v, h, p, vn);
+  // one pass over the patch: minimum q^2 at the old and at the new position
+  double oldmin = 0.0, newmin = 0.0;
+  bool vn = true;
+  for (int i = 0; i < h.w; ++i) {
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    Geo go = patch_elem_geo(st, t, e, v, pv);
+    Geo gn = go;
+    int k = slot_of(e, v);
+    gn.x[0] = k == 0 ? p.x : go.x[0];
+    gn.y[0] = k == 0 ? p.y : go.y[0];
+    gn.x[1] = k == 1 ? p.x : go.x[1];
+    gn.y[1] = k == 1 ? p.y : go.y[1];
+    gn.x[2] = k == 2 ? p.x : go.x[2];
+    gn.y[2] = k == 2 ? p.y : go.y[2];
+    run_min(qual2(go), i == 0, oldmin);
+    if (!(area2(gn) > 0.0)) vn = false;
+    run_min(qual2(gn), i == 0, newmin);
+  }
   if (vn && newmin >= oldmin) {
     st.xy[v] = p;
     return true;
@@ -741,49 +845,82 @@ __device__ bool smooth_laplace(Store st, int v) {
   return false;
 }
 
+// geometry with slot k moved to p
+__device__ __forceinline__ Geo moved(const Geo& g, int k, double2 p) {
+  Geo r = g;
+  r.x[0] = k == 0 ? p.x : g.x[0];
+  r.y[0] = k == 0 ? p.y : g.y[0];
+  r.x[1] = k == 1 ? p.x : g.x[1];
+  r.y[1] = k == 1 ? p.y : g.y[1];
+  r.x[2] = k == 2 ? p.x : g.x[2];
+  r.y[2] = k == 2 ? p.y : g.y[2];
+  return r;
+}
+
 __device__ bool smooth_gradient(Store st, int v) {
   Hdr h = st.hdr[v];
   double2 pv = st.xy[v];
-  double gx = 0.0, gy = 0.0;
+  // pass 1: gradient of Q_v, Q_v and the minimum q^2 at the current position
+  double gx = 0.0, gy = 0.0, Qold = 0.0, oldmin = 0.0;
   for (int i = 0; i < h.w; ++i) {
-    Elem e = st.tri[st.ne[h.z + i]];
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    Geo g = patch_elem_geo(st, t, e, v, pv);
     double ex, ey;
-    qual_grad_x(geo_of(st, e), slot_of(e, v), ex, ey);
+    qual_grad_x(g, slot_of(e, v), ex, ey);
     gx = gx + ex;
     gy = gy + ey;
+    Qold = Qold + qual(g);
+    run_min(qual2(g), i == 0, oldmin);
   }
   if (gx == 0.0 && gy == 0.0) return false;
   double ax = fabs(gx), ay = fabs(gy);
   double nrm = ax < ay ? ay : ax;
   double dx = gx / nrm, dy = gy / nrm;
   double hh = 0.0;
-  bool first = true;
   for (int j = 0; j < h.y; ++j) {
     double2 pw = st.xy[st.nn[h.x + j]];
     double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
     double hj = hx < hy ? hy : hx;
-    if (first || hj < hh) hh = hj;
-    first = false;
+    if (j == 0 || hj < hh) hh = hj;
   }
-  bool vo;
-  double oldmin = patch_min_q2(st, v, h, pv, vo);
-  double Qold = patch_q(st, v, h, pv);
+  // pass 2: the four trial steps h/2 .. h/16 together; the first acceptable wins
+  double2 p[4];
   double step = hh;
-  for (int k = 1; k <= 4; ++k) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
     step = step * 0.5;
-    double2 p = make_double2(pv.x + step * dx, pv.y + step * dy);
-    bool vn;
-    double newmin = patch_min_q2(st, v, h, p, vn);
-    if (!vn || !(newmin >= oldmin)) continue;
-    if (!(patch_q(st, v, h, p) > Qold)) continue;
-    st.xy[v] = p;
-    return true;
+    p[k] = make_double2(pv.x + step * dx, pv.y + step * dy);
   }
-  return false;
+  double mn[4] = {0.0, 0.0, 0.0, 0.0}, Q[4] = {0.0, 0.0, 0.0, 0.0};
+  bool ok[4] = {true, true, true, true};
+  for (int i = 0; i < h.w; ++i) {
+    int t = st.ne[h.z + i];
+    Elem e = st.tri[t];
+    Geo g = patch_elem_geo(st, t, e, v, pv);
+    int sl = slot_of(e, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Geo gk = moved(g, sl, p[k]);
+      if (!(area2(gk) > 0.0)) ok[k] = false;
+      run_min(qual2(gk), i == 0, mn[k]);
+      Q[k] = Q[k] + qual(gk);
+    }
+  }
+  int pick = -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (pick < 0 && ok[k] && mn[k] >= oldmin && Q[k] > Qold) pick = k;
+  if (pick < 0) return false;
+  // recompute the chosen point rather than index the trial array
+  double sp = hh;
+  for (int k = 0; k <= pick; ++k) sp = sp * 0.5;
+  st.xy[v] = make_double2(pv.x + sp * dx, pv.y + sp * dy);
+  return true;
 }
 
 __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
-  int i = gtid();
+  int i = xtid();
   int status = -1;
   if (i < n) {
     int v = list[i];
@@ -969,7 +1106,7 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
 
 __global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
   Grp g = grp();
-  int gid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
   if (gid < n) {
     int v = list[gid];
@@ -1099,7 +1236,7 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
 __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
   Grp g = grp();
-  int gid = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
   if (gid < n) {
     int v = list[gid];
@@ -1117,7 +1254,7 @@ __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restr
 // ---- adjoint with lane groups ---------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_adjoint_g(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
   Grp g = grp();
-  int v = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kG);
+  int v = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   if (v >= st.V) return;
   Hdr h = st.hdr[v];
   double gx = 0.0, gy = 0.0, ga = 0.0, gb = 0.0, gc = 0.0;
@@ -1252,7 +1389,7 @@ void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double
 
 // per vertex, summed over NE(v) in ascending element id: no floating-point atomics
 __global__ void k_adjoint(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
-  for (int v = gtid(); v < st.V; v += gstride()) {
+  for (int v = xtid(); v < st.V; v += gstride()) {
     Hdr h = st.hdr[v];
     double gx = 0.0, gy = 0.0, ga = 0.0, gb = 0.0, gc = 0.0;
     for (int i = 0; i < h.w; ++i) {
