@@ -63,6 +63,22 @@ def op_count(trace):
     return ops
 
 
+def measured_traffic(name):
+    """HBM bytes per launch of kernel `name` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import glob
+    path = os.path.join(ROOT, "profiles", "traffic_2049.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1505_04694_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    if h.hexdigest() != d.get("sources_sha256") or name not in d.get("kernels", {}):
+        return None
+    return d["kernels"][name]["traffic_bytes_per_launch"]
+
+
 def roofline(name, dom):
     """Achieved algorithmic bandwidth of the dominant kernel over the timed steps."""
     launches = max(dom["launches"], 1)
@@ -70,7 +86,7 @@ def roofline(name, dom):
     avg_s = dom["ms"] * 1e-3 / launches
     achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(name),
             "bytes_per_unit": BYTES_PER_UNIT[name], "units_per_launch": round(dom["units"] / launches, 1),
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"]}
 
