@@ -51,12 +51,15 @@ struct pm_mesh {
   double* hq = nullptr; // pinned doubles
   // scratch
   DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
-  DBuf<uint8_t> act, col, nxt, u8tmp;
+  DBuf<uint8_t> nxt, u8tmp;
   DBuf<Met> emet;   // smoothing: per-element mean tensors
   DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
-  DBuf<int> dirty, dlist, pend, dbase, rec_row, rec_val, rec_off, stage;
+  DBuf<int> oep, stage;  // commit: operation stamps, fallback staging
+  DBuf<int2> orec;       // commit: operation records
+  DBuf<uint64_t> own;    // commit: row owner keys
+  int epoch = 0;         // commit epoch, one per class
   DBuf<double> qpart;
-  DBuf<uint64_t> key;
+  DBuf<uint64_t> rw;  // round words (priority, active, colour) per vertex
   // mesh ranges (host mirror of Store::vbase/vused/tbase/tused)
   std::vector<int> vbase, vused, tbase, tused;
   int* ranges = nullptr;  // device: vbase[B+1], vused[B], tbase[B+1], tused[B]
@@ -188,7 +191,6 @@ pm_status check_err(pm_mesh* m) {
   if (e & E_MESH_METRIC) msg += " metric not SPD or non-finite coordinates;";
   if (e & (E_NN_POOL | E_NE_POOL)) msg += " adjacency pool exhausted;";
   if (e & E_STAGE) msg += " commit staging exhausted;";
-  if (e & E_REC) msg += " record buffer exhausted;";
   if (e & E_COLOURS) msg += " more than 254 colours;";
   set_int(m->ctr + C_ERR, 0, m->s);
   pm_status st = (e & (E_MESH_ID | E_MESH_ORIENT | E_MESH_MANIFOLD | E_MESH_METRIC)) ? PM_E_MESH : PM_E_NOMEM;
@@ -333,40 +335,30 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   int V = std::max(m->st.V, 1), T = std::max(m->st.T, 1);
   TRY(ensure(m, m->listA, V));
   TRY(ensure(m, m->listB, V));
-  TRY(ensure(m, m->jpU0, V));
-  TRY(ensure(m, m->jpU1, V));
+  TRY(ensure(m, m->jpU0, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
+  TRY(ensure(m, m->jpU1, (size_t)V / kJpChunk + 1));
   TRY(ensure(m, m->cls, V));
-  TRY(ensure(m, m->key, V));
-  TRY(ensure(m, m->act, V, true));
-  TRY(ensure(m, m->col, V));
+  TRY(ensure(m, m->rw, V, true));
   TRY(ensure(m, m->nxt, V, true));
-  TRY(ensure(m, m->dirty, V, true));
-  TRY(ensure(m, m->pend, V, true));
-  TRY(ensure(m, m->dlist, V));
-  TRY(ensure(m, m->dbase, V));
+  TRY(ensure(m, m->oep, V, true));
+  TRY(ensure(m, m->orec, V));
+  TRY(ensure(m, m->own, V, true));
   TRY(ensure(m, m->sflag, V));
   TRY(ensure(m, m->spos, V));
   TRY(ensure(m, m->spart, scan_partials_needed(V) + 2));
-  int rec = 2 * V + 64;
-  TRY(ensure(m, m->rec_row, rec));
-  TRY(ensure(m, m->rec_val, rec));
-  TRY(ensure(m, m->rec_off, rec));
-  // staging bound: 3 (|NE(x)| + additions) + 4 per dirty row, summed
-  size_t stage = 12 * (size_t)T + 10 * (size_t)V + 1024;
+  // staging for the rows past the register path (more than 32 candidates):
+  // 4 ids per candidate; running out fails the phase with E_STAGE
+  size_t stage = 4 * (size_t)T + 4 * (size_t)V + 65536;
   TRY(ensure(m, m->stage, stage));
   return PM_OK;
 }
 
 Commit commit_of(pm_mesh* m) {
   Commit c;
-  c.dirty = m->dirty.p;
-  c.dlist = m->dlist.p;
-  c.pend = m->pend.p;
-  c.dbase = m->dbase.p;
-  c.rec_row = m->rec_row.p;
-  c.rec_val = m->rec_val.p;
-  c.rec_off = m->rec_off.p;
-  c.rec_cap = (int)std::min<size_t>(m->rec_row.n, INT32_MAX);
+  c.epoch = m->epoch;
+  c.oep = m->oep.p;
+  c.orec = m->orec.p;
+  c.own = m->own.p;
   c.stage = m->stage.p;
   c.stage_cap = (int64_t)m->stage.n;
   c.nxt = m->nxt.p;
@@ -379,35 +371,26 @@ struct Classes {
   int jp_iters = 0;
 };
 
-// Jones-Plassmann on list A (n entries): colours in m->col, keys in m->key,
-// act flags set, class lists in m->cls. The caller clears the act flags.
-// Iterations are launched in batches between count read-backs; a launch past
-// the end of the work finds an empty list and returns at once.
+// Jones-Plassmann on list A (n entries): round words in rd.rw (the caller
+// clears them), class lists in m->cls. Iterations run on a chunked copy of A
+// and are launched in batches between read-backs of the count still waiting;
+// a launch past the end of the work finds only empty chunks.
 constexpr int kJpBatch = 4;
 
 pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
-  jp_init(m->st, A, n, m->col.p, m->act.p, rd, m->s);
-  int* bufs[2] = {m->jpU0.p, m->jpU1.p};
-  const int* cur = A;
-  int known = n;  // upper bound of the current list length
+  jp_init(m->st, A, n, rd, m->s);
+  stripe_zero(m->ctr, S_JPL, 8, m->s);
   int it = 0;
-  set_int(m->ctr + C_JP, n, m->s);
   for (;;) {
-    for (int b = 0; b < kJpBatch; ++b, ++it) {
-      int* nxt = bufs[it & 1];
-      int* cin = m->ctr + C_JP + (it % 32);
-      int* cout = m->ctr + C_JP + ((it + 1) % 32);
-      set_int(cout, 0, m->s);
-      timed(m, PM_K_JP, 0, [&] { jp_step(m->st, cur, cin, known, nxt, cout, m->act.p, m->col.p, rd, m->ctr, m->s); });
-      cur = nxt;
-    }
-    TRY(read_ctr(m, C_JP + (it % 32), 1));
-    int left = m->hctr[C_JP + (it % 32)];
+    for (int b = 0; b < kJpBatch; ++b, ++it)
+      timed(m, PM_K_JP, 0, [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
+    stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
+    TRY(read_ctr(m, C_JP, 1));
+    int left = m->hctr[C_JP];
     if (left == 0) break;
     if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
-    known = left;
   }
   out.jp_iters = it;
   zero_ints(m->ctr + C_HIST, 256, m->s);
@@ -415,7 +398,7 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   TRY(ensure(m, m->ctab, 256 * (size_t)nb + 256));
   TRY(ensure(m, m->ctabs, 256 * (size_t)nb + 256));
   TRY(ensure(m, m->spart, scan_partials_needed(256 * nb) + 2));
-  class_lists(A, n, m->col.p, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
+  class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
   TRY(read_ctr(m, C_HIST, C_NCOL + 1 - C_HIST));
   TRY(check_err(m));
   out.ncol = m->hctr[C_NCOL];
@@ -424,9 +407,10 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   return PM_OK;
 }
 
-void stats_zero(pm_mesh* m) { zero_ints(m->ctr + C_EVAL, 6, m->s); }
+void stats_zero(pm_mesh* m) { stripe_zero(m->ctr, S_EVAL, 6, m->s); }
 
 pm_status stats_read(pm_mesh* m, pm_stats* st) {
+  stripe_sum(m->ctr, S_EVAL, 6, C_EVAL, m->s);
   TRY(read_ctr(m, C_EVAL, 6));
   prof_flush(m);
   if (st) {
@@ -434,7 +418,7 @@ pm_status stats_read(pm_mesh* m, pm_stats* st) {
     st->v[3] += m->hctr[C_DEFER];
     st->v[4] += m->hctr[C_COMMIT];
     st->v[11] += m->hctr[C_RELOC];
-    st->v[10] += m->hctr[C_RECS];
+    st->v[10] += m->hctr[C_ROWS];
     st->v[6] += m->hctr[C_EDGES];
   }
   return PM_OK;
@@ -571,7 +555,7 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   Commit cm = commit_of(m);
   while (nA > 0 && r < max_rounds) {
     TRY(maybe_repack(m));
-    Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->key.p};
+    Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->rw.p};
     Classes cl;
     TRY(colour_list(m, m->listA.p, nA, rd, cl));
     st->v[1] += nA;
@@ -579,8 +563,8 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
     st->v[12] += cl.jp_iters;
     for (int c = 0; c < cl.ncol; ++c) {
       if (cl.size[c] == 0) continue;
-      zero_ints(m->ctr + C_DIRTY, 3, m->s);  // dirty, records, staging
-      OpArgs a{m->act.p, m->col.p, c, rd, o->L_low2, qmin2};
+      cm.epoch = ++m->epoch;
+      OpArgs a{m->rw.p, c, rd, o->L_low2, qmin2};
       if (kind == 0)
         timed(m, PM_K_COLLAPSE, cl.size[c], [&] {
           collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->variant & 1, m->s);
@@ -588,9 +572,11 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
       else
         timed(m, PM_K_FLIP, cl.size[c],
               [&] { flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
-      timed(m, PM_K_COMMIT, 0, [&] { commit_rows(m->st, cm, m->ctr, m->st.V, m->s); });
+      timed(m, PM_K_COMMIT, 0, [&] {
+        commit_rows(m->st, m->cls.p + cl.off[c], cl.size[c], cm, kind != 0, m->ctr, m->s);
+      });
     }
-    set_flags(m->listA.p, nA, m->act.p, 0, m->s);
+    clear_round(m->listA.p, nA, m->rw.p, m->s);
     set_int(m->ctr + C_LIST_B, 0, m->s);
     timed(m, PM_K_SELECT, m->st.V,
           [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
@@ -658,15 +644,17 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->ranges, 1);
   dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
-                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->dirty, &m->dlist, &m->pend,
-                     &m->dbase, &m->rec_row, &m->rec_val, &m->rec_off, &m->stage, &m->rtmp, &m->sflag, &m->spos,
+                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->oep, &m->stage, &m->rtmp,
+                     &m->sflag, &m->spos,
                      &m->ctab, &m->ctabs, &m->spart};
   for (auto* b : ib) dfree(m, b->p, b->n);
-  DBuf<uint8_t>* ub[] = {&m->act, &m->col, &m->nxt, &m->u8tmp};
+  DBuf<uint8_t>* ub[] = {&m->nxt, &m->u8tmp};
   dfree(m, m->emet.p, m->emet.n);
   for (auto* b : ub) dfree(m, b->p, b->n);
   dfree(m, m->qpart.p, m->qpart.n);
-  dfree(m, m->key.p, m->key.n);
+  dfree(m, m->rw.p, m->rw.n);
+  dfree(m, m->own.p, m->own.n);
+  dfree(m, m->orec.p, m->orec.n);
   prof_flush(m);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
   if (m->ctr) (void)hipFree(m->ctr);
@@ -816,15 +804,15 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, ctx), m->key.p}, cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, ctx), m->rw.p}, cl));
   if (ncolours) *ncolours = cl.ncol;
   if (colour_out) {
     TRY(ensure(m, m->vt0, st.V));
-    pm::colour_out(st, m->act.p, m->col.p, m->vt0.p, m->s);
+    pm::colour_out(st, m->rw.p, m->vt0.p, m->s);
     HIPCHK(hipMemcpyAsync(colour_out, m->vt0.p, sizeof(int) * st.V,
                           mem_kind == PM_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, m->s));
   }
-  set_flags(m->listA.p, n, m->act.p, 0, m->s);
+  clear_round(m->listA.p, n, m->rw.p, m->s);
   return sync(m);
 }
 
@@ -864,7 +852,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
   Classes cl;
-  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), m->key.p}, cl));
+  TRY(colour_list(m, m->listA.p, n, Round{stream_seed(m->seed, make_ctx(o->sweep, PH_SMOOTH, 0)), m->rw.p}, cl));
   st->v[1] = n;
   st->v[5] = cl.ncol;
   st->v[12] = cl.jp_iters;
@@ -878,7 +866,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
         smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant >> 1) & 1, m->s);
       });
   m->st.emet = nullptr;
-  set_flags(m->listA.p, n, m->act.p, 0, m->s);
+  clear_round(m->listA.p, n, m->rw.p, m->s);
   TRY(stats_read(m, st));
   st->v[0] = o->smooth_sweeps;
   st->v[7] = 1;
@@ -912,7 +900,7 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     TRY(ensure(m, m->tt1, T0));
     TRY(ensure(m, m->rtmp, 4 * (size_t)B + 4));
     TRY(ensure(m, m->partial, scan_partials_needed(std::max(V0, T0)) + 2));
-    zero_ints(m->ctr + C_EDGES, 1, m->s);
+    stripe_zero(m->ctr, S_EDGES, 1, m->s);
     refine_mark(s, o->L_up2, m->vt0.p, m->ctr, m->s);
     scan_excl(m->vt0.p, m->vt1.p, V0, m->ctr + C_TOTAL, m->partial.p, m->s);
     refine_count(s, o->L_up2, m->tt0.p, m->s);
@@ -921,6 +909,7 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     range_sums(m->tt1.p, m->tt0.p, s.tbase, s.tused, B, m->rtmp.p + B, m->s);
     std::vector<int> need(2 * B);
     HIPCHK(hipMemcpyAsync(need.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
+    stripe_sum(m->ctr, S_EDGES, 1, C_EDGES, m->s);
     TRY(read_ctr(m, C_TOTAL, 2));
     TRY(read_ctr(m, C_EDGES, 1));
     int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
@@ -1188,7 +1177,7 @@ pm_status pm_profile(pm_mesh* m, uint32_t mask) {
     m->prof.ms[k] = 0.0;
     m->prof.launches[k] = m->prof.units[k] = 0;
   }
-  zero_ints(m->ctr + C_PROF_JP, 2, m->s);
+  stripe_zero(m->ctr, S_PJP, 2, m->s);
   return sync(m);
 }
 
@@ -1196,13 +1185,14 @@ pm_status pm_profile_read(pm_mesh* m, int32_t id, double* ms, int64_t* launches,
   if (!m || id < 0 || id >= PM_K_COUNT) return PM_E_ARG;
   TRY(sync(m));
   prof_flush(m);
+  stripe_sum(m->ctr, S_PJP, 2, C_PROF_JP, m->s);
   TRY(read_ctr(m, C_PROF_JP, 2));
   if (ms) *ms = m->prof.ms[id];
   if (launches) *launches = m->prof.launches[id];
   if (units) {
     *units = m->prof.units[id];
     if (id == PM_K_JP) *units = m->hctr[C_PROF_JP];
-    if (id == PM_K_COMMIT) *units = m->hctr[C_PROF_DIRTY];
+    if (id == PM_K_COMMIT) *units = m->hctr[C_PROF_ROWS];
   }
   return PM_OK;
 }

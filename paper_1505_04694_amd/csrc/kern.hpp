@@ -16,32 +16,46 @@ enum Ctr {
   C_ERR = 2,        // error bits (see Err)
   C_LIST_A = 3,     // generic list counters
   C_LIST_B = 4,
-  C_DIRTY = 5,      // dirty rows of the current class
-  C_REC = 6,        // records of the current class
-  C_STAGE = 7,      // staging space handed out by the commit
-  C_EVAL = 8,       // stats accumulated on the device
+  C_STAGE = 7,      // fallback staging space handed out by the commit
+  C_EVAL = 8,       // 8..13: stats, summed from the stripes (same order as the S_ slots)
   C_DEFER = 9,
   C_COMMIT = 10,
   C_RELOC = 11,
-  C_RECS = 12,
+  C_ROWS = 12,
   C_EDGES = 13,
   C_TOTAL = 14,     // scan totals
   C_TOTAL2 = 15,
-  C_JP = 16,        // 16..63: JP iteration list counters
+  C_JP = 16,        // JP: vertices still waiting after the last iteration (summed)
   C_HIST = 64,      // 64..319: colour histogram (class sizes)
   C_OFF = 320,      // 320..575: class offsets
   C_CUR = 576,      // 576..831: class cursors
   C_NCOL = 832,     // number of colours
-  C_PROF_JP = 833,  // profiling: active vertices visited by JP iterations
-  C_PROF_DIRTY = 834,  // profiling: dirty rows committed
-  C_COUNT = 896
+  C_PROF_JP = 833,  // profiling: active vertices visited by JP iterations (summed)
+  C_PROF_ROWS = 834,  // profiling: rows rebuilt by the commit (summed)
+  C_STRIPE = 1024,  // kStripes stripes of kStripeW ints, one 128-byte line each
+  C_COUNT = 1024 + 64 * 32
 };
+// Counters that many wavefronts bump are striped: a wavefront adds to the
+// stripe of its index modulo kStripes, so concurrent atomics spread over 64
+// cache lines instead of queueing on one; the host sums a slot over stripes.
+constexpr int kStripes = 64, kStripeW = 32;
+enum Slot {
+  S_EVAL = 0, S_DEFER = 1, S_COMMIT = 2, S_RELOC = 3, S_ROWS = 4, S_EDGES = 5,  // stats
+  S_PJP = 6, S_PROWS = 7,  // profiling units
+  S_JPL = 8                // 8..15: JP vertices left, by iteration modulo 8
+};
+__device__ __forceinline__ int* stripe_ptr(int* ctr, int slot) {
+  int w = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kStripes - 1));
+  return ctr + C_STRIPE + w * kStripeW + slot;
+}
+void stripe_zero(int* ctr, int slot, int nslots, hipStream_t s);
+// ctr[dst + k] = sum over stripes of slot + k, k < nslots
+void stripe_sum(int* ctr, int slot, int nslots, int dst, hipStream_t s);
 constexpr int kMaxColours = 255;  // colour 0xFF marks "uncoloured"
 enum Err {
   E_NN_POOL = 1,
   E_NE_POOL = 2,
   E_STAGE = 4,
-  E_REC = 8,
   E_MESH_ORIENT = 16,
   E_MESH_MANIFOLD = 32,
   E_MESH_ID = 64,
@@ -139,53 +153,72 @@ void fill_mesh_ids(const int* base, int B, int n, int* mesh, hipStream_t s);
 void export_tri(const Store& st, int* tri3, uint8_t* talive, hipStream_t s);
 
 // ---- ops.hip ----
+// Round word of a vertex (one 64-bit load answers every question a neighbour
+// asks during a round): priority in bits 63..32, bit 8 set while the vertex is
+// active, colour in bits 7..0 (0xFF: not coloured yet). Zero = inactive.
+// Keys are (priority, id); within a mesh the global id order is the local id
+// order, so ties are broken by the vertex ids themselves.
+constexpr uint64_t kRwAct = 1ull << 8;
+__host__ __device__ __forceinline__ bool rw_beats(uint64_t rw_w, int w, uint64_t rw_v, int v) {
+  uint32_t pw = (uint32_t)(rw_w >> 32), pv = (uint32_t)(rw_v >> 32);
+  return pw != pv ? pw > pv : w > v;
+}
+
 struct Round {
   uint64_t sseed;      // stream seed of this round's priorities
-  uint64_t* key;       // per vertex: (priority, local id) of the active vertices
+  uint64_t* rw;        // round words
 };
 
+// Deferred update by pull: a committing member stamps its operation and
+// claims the rows it changes; the commit then rebuilds every claimed row once,
+// by its owner, from the row's old NE set plus what its committed neighbours
+// hand over. Epochs grow by one per class, so stale stamps never match.
 struct Commit {
-  int* dirty;      // V ints, 0 when clean
-  int* dlist;      // dirty rows of the class
-  int* pend;       // V ints: queued addition weight per row
-  int* dbase;      // V ints: staging base per row
-  int* rec_row;    // queued additions
-  int* rec_val;
-  int* rec_off;
-  int rec_cap;
-  int* stage;
+  int epoch;
+  int* oep;        // V: epoch of the vertex's last committed operation
+  int2* orec;      // V: that operation: (-(u+1), 0) collapse onto u, (t1, t2) flip's elements
+  uint64_t* own;   // V: row owner key, maximised: (epoch << 32) | ~member
+  int* stage;      // staging for rows past the register path
   int64_t stage_cap;
   uint8_t* nxt;    // next-round flags
 };
+__device__ __forceinline__ uint64_t own_key(int epoch, int v) {
+  return ((uint64_t)(uint32_t)epoch << 32) | (uint64_t)(uint32_t)(~v);
+}
 
 struct OpArgs {
-  const uint8_t* act;
-  const uint8_t* col;
+  const uint64_t* rw;
   int cls;
   Round rd;
   double L_low2, qmin2;
 };
 
 void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s);
+void clear_round(const int* list, int n, uint64_t* rw, hipStream_t s);
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
 // selected vertices in ascending order; flag/pos: V ints, partial: scan scratch
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
                      int* n, int* flag, int* pos, int* partial, hipStream_t s);
-void jp_init(const Store& st, const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s);
-// one JP iteration over *nU entries of U (grid sized for nmax >= *nU)
-void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
-             uint8_t* col, Round rd, int* ctr, hipStream_t s);
+void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s);
+// One JP iteration over a chunked list: chunk k of kJpChunk slots holds cnt[k]
+// vertices at W[k * kJpChunk ...]; the first iteration reads the n entries of
+// A instead. Waiting vertices are compacted in place, in order, per chunk.
+constexpr int kJpChunk = 1024;
+void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,
+              hipStream_t s);
 // stable class lists; tab/tabscan: 256 * ceil(n/256) ints each
-void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, int* tab, int* tabscan, int* partial,
+void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
                  hipStream_t s);
-void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s);
+void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s);
 
 // variant 0: one thread per member; 1: a group of 8 lanes per member
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
                     hipStream_t s);
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s);
-void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s);
+// rebuild the rows claimed by the committed members of list[0..n) (the class
+// just processed, launched in the same shape); flips: members' own rows too
+void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);

@@ -18,8 +18,15 @@ constexpr int kG = 8;  // lanes per vertex in the lane-group kernels
 __device__ __forceinline__ uint64_t key_of(const Store& st, const Round& rd, int v) {
   return vkey(rd.sseed, (uint32_t)local_id(st, v));
 }
-// key of an active vertex, computed once per colouring by jp_init
-__device__ __forceinline__ uint64_t akey(const Round& rd, int v) { return rd.key[v]; }
+__device__ __forceinline__ uint64_t rw_get(const uint64_t* rw, int v) { return ((volatile const uint64_t*)rw)[v]; }
+__device__ __forceinline__ void rw_put(uint64_t* rw, int v, uint64_t x) { ((volatile uint64_t*)rw)[v] = x; }
+
+__global__ void k_clear_round(const int* __restrict__ list, int n, uint64_t* __restrict__ rw) {
+  for (int i = gtid(); i < n; i += gstride()) rw[list[i]] = 0;
+}
+void clear_round(const int* list, int n, uint64_t* rw, hipStream_t s) {
+  if (n > 0) k_clear_round<<<grid_for(n), kBlock, 0, s>>>(list, n, rw);
+}
 
 // ---- flags and lists -----------------------------------------------------------------
 __global__ void k_set_flags(const int* __restrict__ list, int n, uint8_t* __restrict__ flag, uint8_t val) {
@@ -78,44 +85,34 @@ void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* ac
 }
 
 // ---- Jones-Plassmann colouring (Sec. 3.2) ------------------------------------------------
-__global__ void k_jp_init(Store st, const int* __restrict__ A, int n, uint8_t* __restrict__ col,
-                          uint8_t* __restrict__ act, Round rd) {
+__global__ void k_jp_init(Store st, const int* __restrict__ A, int n, Round rd) {
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
-    col[v] = 0xFF;
-    act[v] = 1;
-    rd.key[v] = key_of(st, rd, v);
+    uint64_t prio = key_of(st, rd, v) >> 32;
+    rd.rw[v] = (prio << 32) | kRwAct | 0xFFull;
   }
 }
-void jp_init(const Store& st, const int* A, int n, uint8_t* col, uint8_t* act, Round rd, hipStream_t s) {
-  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(st, A, n, col, act, rd);
+void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
+  if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(st, A, n, rd);
 }
 
 // A vertex is ready once every active neighbour of larger key has a colour;
 // it then takes the smallest colour none of them has. Colours read while a
 // neighbour is being written are either unset (not ready yet) or final, so
-// the result does not depend on timing.
-__device__ void jp_visit(const Store& st, int v, int* __restrict__ U2, int* __restrict__ nU2,
-                         const uint8_t* __restrict__ act, uint8_t* col, const Round& rd, int* ctr) {
-  uint64_t kv = akey(rd, v);
+// the result does not depend on timing. Returns false while v must wait.
+__device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
+  uint64_t rv = rw_get(rd.rw, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
-  bool big = false, ready = true;
+  bool big = false;
   for (int j = 0; j < h.y; ++j) {
     int w = st.nn[h.x + j];
-    if (!act[w]) continue;
-    if (akey(rd, w) < kv) continue;
-    int c = ((volatile const uint8_t*)col)[w];
-    if (c == 0xFF) {
-      ready = false;
-      break;
-    }
+    uint64_t x = rw_get(rd.rw, w);
+    if (!(x & kRwAct) || !rw_beats(x, w, rv, v)) continue;
+    int c = (int)(x & 0xFF);
+    if (c == 0xFF) return false;
     if (c < 64) used |= 1ull << c;
     else big = true;
-  }
-  if (!ready) {
-    U2[wave_append_slot(nU2)] = v;
-    return;
   }
   int c;
   if (~used != 0ull && !big) {
@@ -127,8 +124,9 @@ __device__ void jp_visit(const Store& st, int v, int* __restrict__ U2, int* __re
       bool taken = false;
       for (int j = 0; j < h.y && !taken; ++j) {
         int w = st.nn[h.x + j];
-        if (!act[w] || akey(rd, w) < kv) continue;
-        taken = ((volatile const uint8_t*)col)[w] == c;
+        uint64_t x = rw_get(rd.rw, w);
+        if (!(x & kRwAct) || !rw_beats(x, w, rv, v)) continue;
+        taken = (int)(x & 0xFF) == c;
       }
       if (!taken) break;
       ++c;
@@ -138,35 +136,112 @@ __device__ void jp_visit(const Store& st, int v, int* __restrict__ U2, int* __re
     atomicOr(&ctr[C_ERR], E_COLOURS);
     c = kMaxColours - 1;
   }
-  ((volatile uint8_t*)col)[v] = (uint8_t)c;
+  rw_put(rd.rw, v, (rv & ~0xFFull) | (uint64_t)c);
+  return true;
 }
 
-// grid-stride over the device-side count, so a launch past the end of the
-// work costs one empty pass of a capped grid
-__global__ void __launch_bounds__(256) k_jp_step(Store st, const int* __restrict__ U, const int* __restrict__ nU,
-                                                 int* __restrict__ U2, int* __restrict__ nU2,
-                                                 const uint8_t* __restrict__ act, uint8_t* col, Round rd, int* ctr) {
-  int n = *nU;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_PROF_JP] += n;
-  for (int i = xtid(); i < n; i += gstride()) jp_visit(st, U[i], U2, nU2, act, col, rd, ctr);
+// One block per chunk; each thread takes kJpItems entries (item r of thread
+// t is entry r * kBlock + t). The waiting vertices are packed to the front of
+// the chunk in their old order: every read happens before the block barrier,
+// every write after it, so the compaction can run in place. One atomic per
+// chunk (on a stripe) counts what is left.
+constexpr int kJpItems = kJpChunk / kBlock;
+__global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restrict__ A, int n, int* W,
+                                                  int* __restrict__ cnt, int first, Round rd, int* ctr, int slot,
+                                                  int next_slot) {
+  __shared__ int wtot[kJpItems][kBlock / kWave];
+  int kb = xcd_block();
+  if (blockIdx.x == 0 && threadIdx.x < kStripes) ctr[C_STRIPE + threadIdx.x * kStripeW + next_slot] = 0;
+  int m = first ? min(kJpChunk, n - kb * kJpChunk) : cnt[kb];
+  if (m <= 0) {
+    if (first && threadIdx.x == 0) cnt[kb] = 0;
+    return;
+  }
+  const int* in = (first ? A : W) + (size_t)kb * kJpChunk;
+  int vv[kJpItems];
+#pragma unroll
+  for (int r = 0; r < kJpItems; ++r) {
+    int i = r * kBlock + (int)threadIdx.x;
+    vv[r] = i < m ? in[i] : -1;
+  }
+  bool keep[kJpItems];
+#pragma unroll
+  for (int r = 0; r < kJpItems; ++r) keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr);
+  int lane = __lane_id(), wv = (int)threadIdx.x / kWave;
+  uint64_t bal[kJpItems];
+#pragma unroll
+  for (int r = 0; r < kJpItems; ++r) {
+    bal[r] = __ballot(keep[r]);
+    if (lane == 0) wtot[r][wv] = __popcll(bal[r]);
+  }
+  __syncthreads();
+  int base = 0, pos[kJpItems];
+  uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < kJpItems; ++r) {
+    int before = 0, row = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / kWave; ++q) {
+      int c = wtot[r][q];
+      row += c;
+      if (q < wv) before += c;
+    }
+    pos[r] = base + before + __popcll(bal[r] & below);
+    base += row;
+  }
+  int* out = W + (size_t)kb * kJpChunk;
+#pragma unroll
+  for (int r = 0; r < kJpItems; ++r)
+    if (keep[r]) out[pos[r]] = vv[r];
+  if (threadIdx.x == 0) {
+    cnt[kb] = base;
+    int* sp = ctr + C_STRIPE + (kb & (kStripes - 1)) * kStripeW;
+    if (base) atomicAdd(sp + slot, base);
+    atomicAdd(sp + S_PJP, m);
+  }
 }
 
-void jp_step(const Store& st, const int* U, const int* nU, int nmax, int* U2, int* nU2, const uint8_t* act,
-             uint8_t* col, Round rd, int* ctr, hipStream_t s) {
-  if (nmax > 0) k_jp_step<<<grid_for(nmax, 2048), kBlock, 0, s>>>(st, U, nU, U2, nU2, act, col, rd, ctr);
+void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,
+              hipStream_t s) {
+  int nch = (n + kJpChunk - 1) / kJpChunk;
+  if (nch > 0)
+    k_jp_chunk<<<nch, kBlock, 0, s>>>(st, A, n, W, cnt, first ? 1 : 0, rd, ctr, S_JPL + (it & 7),
+                                       S_JPL + ((it + 1) & 7));
+}
+
+// ---- striped counters --------------------------------------------------------------------------
+__global__ void k_stripe_zero(int* ctr, int slot, int nslots) {
+  int w = (int)threadIdx.x;
+  for (int k = 0; k < nslots; ++k) ctr[C_STRIPE + w * kStripeW + slot + k] = 0;
+}
+void stripe_zero(int* ctr, int slot, int nslots, hipStream_t s) {
+  k_stripe_zero<<<1, kStripes, 0, s>>>(ctr, slot, nslots);
+}
+__global__ void k_stripe_sum(int* ctr, int slot, int nslots, int dst) {
+  int w = (int)threadIdx.x;
+  for (int k = 0; k < nslots; ++k) {
+    int x = ctr[C_STRIPE + w * kStripeW + slot + k];
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d);
+    if (w == 0) ctr[dst + k] = x;
+  }
+}
+void stripe_sum(int* ctr, int slot, int nslots, int dst, hipStream_t s) {
+  static_assert(kStripes == kWave, "one lane per stripe");
+  k_stripe_sum<<<1, kStripes, 0, s>>>(ctr, slot, nslots, dst);
 }
 
 // Class lists by a stable counting sort on the colour: per block (256 list
 // entries) the number of each colour, an exclusive scan over (colour, block),
 // then every entry goes to its colour's range at the position of its rank
 // among equal colours in the block. Class lists keep the order of A.
-__global__ void k_class_count(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int nb,
+__global__ void k_class_count(const int* __restrict__ A, int n, const uint64_t* __restrict__ rw, int nb,
                               int* __restrict__ tab) {
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&h[col[A[i]]], 1);
+  if (i < n) atomicAdd(&h[(int)(rw[A[i]] & 0xFF)], 1);
   __syncthreads();
   tab[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
@@ -195,7 +270,7 @@ __device__ int block_rank(int c, bool valid, int* wcnt /* 4 waves x 256 */) {
   return rank;
 }
 
-__global__ void k_class_place(const int* __restrict__ A, int n, const uint8_t* __restrict__ col, int nb,
+__global__ void k_class_place(const int* __restrict__ A, int n, const uint64_t* __restrict__ rw, int nb,
                               const int* __restrict__ tabscan, int* __restrict__ out) {
   __shared__ int wcnt[4 * 256];
   for (int k = threadIdx.x; k < 4 * 256; k += blockDim.x) wcnt[k] = 0;
@@ -203,7 +278,7 @@ __global__ void k_class_place(const int* __restrict__ A, int n, const uint8_t* _
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool valid = i < n;
   int v = valid ? A[i] : -1;
-  int c = valid ? (int)col[v] : 0;
+  int c = valid ? (int)(rw[v] & 0xFF) : 0;
   int r = block_rank(c, valid, wcnt);
   if (valid) out[tabscan[(int64_t)c * nb + blockIdx.x] + r] = v;
 }
@@ -223,51 +298,45 @@ __global__ void k_class_sizes(const int* __restrict__ tabscan, int nb, int n, in
   }
 }
 
-void class_lists(const int* A, int n, const uint8_t* col, int* ctr, int* out, int* tab, int* tabscan, int* partial,
+void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
                  hipStream_t s) {
   static_assert(kBlock == 256, "class kernels use one LDS slot per colour and thread");
   int nb = (n + kBlock - 1) / kBlock;
   if (nb < 1) nb = 1;
-  k_class_count<<<nb, kBlock, 0, s>>>(A, n, col, nb, tab);
+  k_class_count<<<nb, kBlock, 0, s>>>(A, n, rw, nb, tab);
   scan_excl(tab, tabscan, 256 * nb, ctr + C_TOTAL, partial, s);
-  k_class_place<<<nb, kBlock, 0, s>>>(A, n, col, nb, tabscan, out);
+  k_class_place<<<nb, kBlock, 0, s>>>(A, n, rw, nb, tabscan, out);
   k_class_sizes<<<1, 256, 0, s>>>(tabscan, nb, n, ctr);
 }
 
-__global__ void k_colour_out(int V, const uint8_t* __restrict__ act, const uint8_t* __restrict__ col,
-                             int* __restrict__ out) {
-  for (int v = gtid(); v < V; v += gstride()) out[v] = act[v] ? (int)col[v] : -1;
+__global__ void k_colour_out(int V, const uint64_t* __restrict__ rw, int* __restrict__ out) {
+  for (int v = gtid(); v < V; v += gstride()) out[v] = (rw[v] & kRwAct) ? (int)(rw[v] & 0xFF) : -1;
 }
-void colour_out(const Store& st, const uint8_t* act, const uint8_t* col, int* out, hipStream_t s) {
-  k_colour_out<<<grid_for(st.V), kBlock, 0, s>>>(st.V, act, col, out);
+void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s) {
+  k_colour_out<<<grid_for(st.V), kBlock, 0, s>>>(st.V, rw, out);
 }
 
-// ---- deferred update: queueing (Sec. 3.3) -----------------------------------------------
-__device__ __forceinline__ void mark_dirty(const Commit& cm, int x, int* ctr) {
-  if (atomicExch(&cm.dirty[x], 1) == 0) cm.dlist[wave_append_slot(&ctr[C_DIRTY])] = x;
+// ---- deferred update: stamps and claims (Sec. 3.3) -------------------------------------------
+// A committed member stamps its operation and claims every row it changes;
+// the claim with the largest key (the smallest member id) wins the row.
+__device__ __forceinline__ void claim_row(const Commit& cm, int x, int v) {
+  atomicMax((unsigned long long*)&cm.own[x], (unsigned long long)own_key(cm.epoch, v));
 }
-// queue an addition to NE(x): val >= 0 absorbs NE(val) (a collapsed vertex),
-// val < 0 adds element -val-1; weight = number of ids it may add
-__device__ __forceinline__ void queue_add(const Commit& cm, int x, int val, int weight, int* ctr) {
-  int off = atomicAdd(&cm.pend[x], weight);
-  int r = wave_append_slot(&ctr[C_REC]);
-  if (r < cm.rec_cap) {
-    cm.rec_row[r] = x;
-    cm.rec_val[r] = val;
-    cm.rec_off[r] = off;
-  } else {
-    atomicOr(&ctr[C_ERR], E_REC);
-  }
+__device__ __forceinline__ void stamp(const Commit& cm, int v, int2 rec) {
+  cm.orec[v] = rec;
+  cm.oep[v] = cm.epoch;
 }
 
 // a member is deferred when a same-class active neighbour has a larger key
+__device__ __forceinline__ bool same_class_beats(const OpArgs& a, int w, uint64_t rv, int v) {
+  uint64_t x = a.rw[w];
+  return (x & kRwAct) && (int)(x & 0xFF) == a.cls && rw_beats(x, w, rv, v);
+}
 __device__ __forceinline__ bool beaten(const Store& st, int v, const OpArgs& a) {
-  uint64_t kv = akey(a.rd, v);
+  uint64_t rv = a.rw[v];
   Hdr h = st.hdr[v];
-  for (int j = 0; j < h.y; ++j) {
-    int w = st.nn[h.x + j];
-    if (a.act[w] && a.col[w] == a.cls && akey(a.rd, w) > kv) return true;
-  }
+  for (int j = 0; j < h.y; ++j)
+    if (same_class_beats(a, st.nn[h.x + j], rv, v)) return true;
   return false;
 }
 
@@ -285,9 +354,10 @@ __device__ __forceinline__ void count_status(int status, int* ctr) {
   uint64_t e = __ballot(status >= 1);
   uint64_t c = __ballot(status == 2);
   if (__lane_id() == 0) {
-    if (d) atomicAdd(&ctr[C_DEFER], __popcll(d));
-    if (e) atomicAdd(&ctr[C_EVAL], __popcll(e));
-    if (c) atomicAdd(&ctr[C_COMMIT], __popcll(c));
+    int* sp = stripe_ptr(ctr, 0);
+    if (d) atomicAdd(sp + S_DEFER, __popcll(d));
+    if (e) atomicAdd(sp + S_EVAL, __popcll(e));
+    if (c) atomicAdd(sp + S_COMMIT, __popcll(c));
   }
 }
 
@@ -300,13 +370,13 @@ __device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, 
   double2 pv = st.xy[v];
   Met mv = st.met[v];
   uint8_t tv = st.tag[v];
-  uint64_t kv = akey(a.rd, v);
+  uint64_t rv = a.rw[v];
   // one pass over the 1-ring: re-validation and the first candidate together
   double bL = INFINITY;
   int bU = -1;
   for (int j = 0; j < h.y; ++j) {
     int w = st.nn[h.x + j];
-    if (a.act[w] && a.col[w] == a.cls && akey(a.rd, w) > kv) {
+    if (same_class_beats(a, w, rv, v)) {
       cm.nxt[v] = 1;
       return 0;
     }
@@ -370,12 +440,13 @@ __device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, 
     st.tri[t] = e;
   }
   st.valive[v] = 0;
-  for (int j = 0; j < h.y; ++j) mark_dirty(cm, st.nn[h.x + j], ctr);
-  queue_add(cm, u, v, h.w, ctr);
+  stamp(cm, v, make_int2(-(u + 1), 0));
+  for (int j = 0; j < h.y; ++j) claim_row(cm, st.nn[h.x + j], v);
   return 2;
 }
 
 __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
   int status = -1;
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
@@ -447,16 +518,16 @@ __device__ int flip_one(Store st, int v, const OpArgs& a, const Commit& cm, int*
   int3 tv = rot_min(v, bb, ba), tw = rot_min(bw, ba, bb);
   st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
   st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
-  mark_dirty(cm, v, ctr);
-  mark_dirty(cm, bw, ctr);
-  mark_dirty(cm, ba, ctr);
-  mark_dirty(cm, bb, ctr);
-  queue_add(cm, ba, -bT2 - 1, 1, ctr);
-  queue_add(cm, bb, -bT1 - 1, 1, ctr);
+  stamp(cm, v, make_int2(lo, hi));
+  claim_row(cm, v, v);
+  claim_row(cm, bw, v);
+  claim_row(cm, ba, v);
+  claim_row(cm, bb, v);
   return 2;
 }
 
 __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
   int status = -1;
   if (i < n) status = flip_one(st, list[i], a, cm, ctr);
@@ -467,51 +538,44 @@ void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, in
 }
 
 // ---- deferred update: commit ------------------------------------------------------------------
-// Every dirty row gets a private staging range. Its owner copies the old NE
-// row and the queued additions there, keeps the elements that are live and
-// still hold the row's vertex, sorts them (the canonical order), and derives
-// NN from them: NN(x) is the set of other vertices of x's elements.
-__global__ void k_commit_alloc(Store st, Commit cm, int* ctr) {
-  int n = ctr[C_DIRTY];
-  int stride = gstride();
-  for (int i0 = blockIdx.x * blockDim.x; i0 < n; i0 += stride) {
-    int i = i0 + (int)threadIdx.x;
-    int need = 0, x = -1;
-    if (i < n) {
-      x = cm.dlist[i];
-      need = 3 * (st.hdr[x].w + cm.pend[x]) + 4;
-    }
-    int base = wave_add_full(&ctr[C_STAGE], need);
-    if (x >= 0) {
-      if ((int64_t)base + need > cm.stage_cap) {
-        atomicOr(&ctr[C_ERR], E_STAGE);
-        cm.dbase[x] = -1;
-      } else {
-        cm.dbase[x] = base;
-      }
-    }
-  }
-}
+// Each claimed row is rebuilt once, by the owner's thread, from its candidate
+// elements: the old NE(x), all of NE(w) for a neighbour w collapsed onto x,
+// and the two elements of every committed flip around x. NE(x) becomes the
+// sorted candidates that are live and hold x (the canonical order); NN(x) is
+// then the set of the other vertices of those elements.
 
-__global__ void k_commit_fill(Store st, Commit cm, int* ctr) {
-  int n = min(ctr[C_REC], cm.rec_cap);
-  if (gtid() == 0) {
-    ctr[C_RECS] += n;
-    ctr[C_PROF_DIRTY] += ctr[C_DIRTY];
-  }
-  for (int r = gtid(); r < n; r += gstride()) {
-    int x = cm.rec_row[r];
-    int base = cm.dbase[x];
-    if (base < 0) continue;
-    int* dst = cm.stage + base + st.hdr[x].w + cm.rec_off[r];
-    int val = cm.rec_val[r];
-    if (val >= 0) {
-      Hdr hv = st.hdr[val];
-      for (int k = 0; k < hv.w; ++k) dst[k] = st.ne[hv.z + k];
+// the candidates of row x, written to dst[k * stride] for k < lim; returns
+// how many there are
+__device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm, int x, Hdr h, int* dst, int stride, int lim) {
+  int n = 0;
+  for (int k = 0; k < h.w; ++k, ++n)
+    if (n < lim) dst[n * stride] = st.ne[h.z + k];
+  for (int j = 0; j < h.y; ++j) {
+    int w = st.nn[h.x + j];
+    if (cm.oep[w] != cm.epoch) continue;
+    int2 r = cm.orec[w];
+    if (r.x < 0) {
+      if (-r.x - 1 != x) continue;
+      Hdr hw = st.hdr[w];
+      for (int k = 0; k < hw.w; ++k, ++n)
+        if (n < lim) dst[n * stride] = st.ne[hw.z + k];
     } else {
-      dst[0] = -val - 1;
+      if (n < lim) dst[n * stride] = r.x;
+      ++n;
+      if (n < lim) dst[n * stride] = r.y;
+      ++n;
     }
   }
+  if (cm.oep[x] == cm.epoch) {
+    int2 r = cm.orec[x];
+    if (r.x >= 0) {
+      if (n < lim) dst[n * stride] = r.x;
+      ++n;
+      if (n < lim) dst[n * stride] = r.y;
+      ++n;
+    }
+  }
+  return n;
 }
 
 __device__ void sort_unique(int* a, int& n) {
@@ -530,13 +594,15 @@ __device__ void sort_unique(int* a, int& n) {
   n = m;
 }
 
+__device__ __forceinline__ int grown_cap(int n) { return max(8, (2 * n + 3) & ~3); }
+
 // write a sorted row, in place when it fits, else in fresh pool space; on
 // pool exhaustion the row keeps its slot and is cut to its capacity (the
 // error bit fails the phase), so no later read leaves the pool
 __device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap, const int* src, int n, int err,
                        int* ctr) {
   if (n > cap) {
-    int nc = max(8, (2 * n + 3) & ~3);
+    int nc = grown_cap(n);
     int o = atomicAdd(top, nc);
     if ((int64_t)o + nc > pool_cap) {
       atomicOr(&ctr[C_ERR], err);
@@ -544,11 +610,47 @@ __device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap
     } else {
       off = o;
       cap = nc;
-      atomicAdd(&ctr[C_RELOC], 1);
+      atomicAdd(stripe_ptr(ctr, S_RELOC), 1);
     }
   }
   for (int k = 0; k < n; ++k) pool[off + k] = src[k];
   return n;
+}
+
+// general path: candidates in a private staging range, insertion sorts there
+__device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm, int x, int* ctr) {
+  Hdr h = st.hdr[x];
+  int2 cp = st.cap[x];
+  int tot = row_candidates(st, cm, x, h, nullptr, 0, 0);
+  int64_t need = 4 * (int64_t)tot + 4;
+  int base = atomicAdd(&ctr[C_STAGE], (int)need);
+  if ((int64_t)base + need > cm.stage_cap) {
+    atomicOr(&ctr[C_ERR], E_STAGE);
+    return;
+  }
+  int* s = cm.stage + base;
+  row_candidates(st, cm, x, h, s, 1, tot);
+  int m = 0;
+  for (int k = 0; k < tot; ++k) {
+    int t = s[k];
+    Elem e = st.tri[t];
+    if (e.w && holds(e, x)) s[m++] = t;
+  }
+  sort_unique(s, m);
+  int* q = s + tot;
+  int nq = 0;
+  for (int k = 0; k < m; ++k) {
+    Elem e = st.tri[s[k]];
+    if (e.x != x) q[nq++] = e.x;
+    if (e.y != x) q[nq++] = e.y;
+    if (e.z != x) q[nq++] = e.z;
+  }
+  sort_unique(q, nq);
+  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
+  m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
+  nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
+  st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
+  st.cap[x] = make_int2(nn_cap, ne_cap);
 }
 
 // sorting network on a register array (all indices are compile-time constants)
@@ -573,160 +675,238 @@ __device__ __forceinline__ void bitonic(int (&a)[N]) {
   }
 }
 
-constexpr int kRegRow = 32;  // rows up to this many candidates are merged in registers
+constexpr int kRegRow = 32;  // rows up to this many candidates are rebuilt in registers
 
-// general path: candidates in the row's staging range, insertion sorts there
-__device__ void merge_row_staged(Store& st, const Commit& cm, int x, int base, Hdr h, int2 cp, int added, int* ctr) {
-  int* s = cm.stage + base;
-  for (int k = 0; k < h.w; ++k) s[k] = st.ne[h.z + k];
-  int m = 0, tot = h.w + added;
-  for (int k = 0; k < tot; ++k) {
-    int t = s[k];
-    Elem e = st.tri[t];
-    if (e.w && holds(e, x)) s[m++] = t;
-  }
-  sort_unique(s, m);
-  int* q = s + tot;
-  int nq = 0;
-  for (int k = 0; k < m; ++k) {
-    Elem e = st.tri[s[k]];
-    if (e.x != x) q[nq++] = e.x;
-    if (e.y != x) q[nq++] = e.y;
-    if (e.z != x) q[nq++] = e.z;
-  }
-  sort_unique(q, nq);
-  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
-  m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
-  nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
-  st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
-  st.cap[x] = make_int2(nn_cap, ne_cap);
-}
-
-// reserve a slot for n ids: in place when it fits, else fresh pool space
-__device__ bool row_slot(int64_t pool_cap, int* top, int& off, int& cap, int n, int err, int* ctr) {
-  if (n <= cap) return true;
-  int nc = max(8, (2 * n + 3) & ~3);
-  int o = atomicAdd(top, nc);
-  if ((int64_t)o + nc > pool_cap) {
-    atomicOr(&ctr[C_ERR], err);
-    return false;
-  }
-  off = o;
-  cap = nc;
-  atomicAdd(&ctr[C_RELOC], 1);
-  return true;
-}
-
-// register path: NE(x) = sorted live candidates holding x; NN(x) = the sorted
-// "next" vertices of those elements plus the one "previous" vertex that is
-// not a next (x on the boundary)
-__device__ void merge_row_regs(Store& st, const Commit& cm, int x, int base, Hdr h, int2 cp, int tot, int* ctr) {
-  constexpr int N = kRegRow;
-  int c[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    int t = INT_MAX;
-    if (k < tot) {
-      t = k < h.w ? st.ne[h.z + k] : cm.stage[base + k];
-      Elem e = st.tri[t];
-      if (!(e.w && holds(e, x))) t = INT_MAX;
-    }
-    c[k] = t;
-  }
-  bitonic<N>(c);
+// Register path for rows of at most N candidates, staged in this thread's
+// LDS column (x < 0: idle lane). Every lane of the wavefront makes this call
+// together, so fresh pool space is handed out with one atomic per wavefront
+// and pool. NE(x) = the sorted, distinct candidates that are live and hold
+// x, written back to the column; NN(x) = the sorted "next" vertices of those
+// elements plus the one "previous" vertex that is no "next" (x on the
+// boundary). Returns true for a row whose elements do not form a disk or a
+// half-disk around x; such a row is left to the general path.
+template <int N>
+__device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, int x, int tot, int* col, int* ctr) {
+  bool act = x >= 0;
   int m = 0;
+  {
+    int c[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k)
-    if (c[k] != INT_MAX && (k == 0 || c[k] != c[k - 1])) ++m;
-  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
-  bool ok = row_slot(st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, m, E_NE_POOL, ctr);
-  if (!ok) m = min(m, ne_cap);
+    for (int k = 0; k < N; ++k) {
+      int t = INT_MAX;
+      if (act && k < tot) {
+        t = col[k * kBlock];
+        Elem e = st.tri[t];
+        if (!(e.w && holds(e, x))) t = INT_MAX;
+      }
+      c[k] = t;
+    }
+    bitonic<N>(c);
+    int prev = INT_MAX;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      int t = c[k];
+      if (t != INT_MAX && t != prev) col[(m++) * kBlock] = t;
+      prev = t;
+    }
+  }
   int nx[N], pv[N];
-  int j = 0;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     nx[k] = INT_MAX;
     pv[k] = INT_MAX;
-    int t = c[k];
-    if (t != INT_MAX && (k == 0 || t != c[k - 1])) {
-      if (j < m) st.ne[ne_off + j] = t;
-      ++j;
-      Elem e = st.tri[t];
+    if (k < m) {
+      Elem e = st.tri[col[k * kBlock]];
       int sl = slot_of(e, x);
       nx[k] = at(e, sl == 2 ? 0 : sl + 1);
       pv[k] = at(e, sl == 0 ? 2 : sl - 1);
     }
   }
   bitonic<N>(nx);
-  // previous vertices missing from the nexts (one for a boundary vertex)
+  bitonic<N>(pv);
+  // In a disk the sorted nexts and previouses agree; in a half-disk they
+  // differ by one element each, so shared values sit at most one place
+  // apart. A previous not found within one place is counted as extra (more
+  // than one extra: neither, and the general path decides).
   int extra = INT_MAX, nextra = 0;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    if (pv[k] == INT_MAX) continue;
-    bool found = false;
-#pragma unroll
-    for (int q = 0; q < N; ++q) found |= nx[q] == pv[k];
+    int b = pv[k];
+    if (b == INT_MAX) continue;
+    bool found = b == nx[k];
+    if (k > 0) found |= b == nx[k - 1];
+    if (k + 1 < N) found |= b == nx[k + 1];
     if (!found) {
-      extra = pv[k];
+      extra = b;
       ++nextra;
     }
   }
-  if (nextra > 1) {
-    // not a disk or half-disk star: fall back to the general path
-    merge_row_staged(st, cm, x, base, h, cp, tot - h.w, ctr);
-    return;
-  }
-  int nq = 0;
+  bool odd = act && nextra > 1;
+  bool reg = act && !odd;
+  int nq = nextra;
 #pragma unroll
   for (int k = 0; k < N; ++k) nq += nx[k] != INT_MAX;
-  nq += nextra;
-  bool ok2 = row_slot(st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, nq, E_NN_POOL, ctr);
-  int lim = ok2 ? nq : min(nq, nn_cap);
-  int w = 0;
-  bool put = nextra == 0;
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    int v = nx[k];
-    if (v == INT_MAX) continue;
-    if (!put && extra < v) {
-      if (w < lim) st.nn[nn_off + w] = extra;
-      ++w;
-      put = true;
+  // slots: in place when the row fits, else fresh pool space
+  Hdr h = make_int4(0, 0, 0, 0);
+  int2 cp = make_int2(0, 0);
+  if (reg) {
+    h = st.hdr[x];
+    cp = st.cap[x];
+  }
+  int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
+  int ne_need = reg && m > ne_cap ? grown_cap(m) : 0;
+  int nn_need = reg && nq > nn_cap ? grown_cap(nq) : 0;
+  int ne_at = wave_add_full(&ctr[C_NE_TOP], ne_need);
+  int nn_at = wave_add_full(&ctr[C_NN_TOP], nn_need);
+  int lim_ne = m, lim_nn = nq;
+  if (ne_need) {
+    if ((int64_t)ne_at + ne_need > st.ne_pool) {
+      atomicOr(&ctr[C_ERR], E_NE_POOL);
+      lim_ne = min(m, ne_cap);
+    } else {
+      ne_off = ne_at;
+      ne_cap = ne_need;
     }
-    if (w < lim) st.nn[nn_off + w] = v;
-    ++w;
   }
-  if (!put) {
-    if (w < lim) st.nn[nn_off + w] = extra;
-    ++w;
+  if (nn_need) {
+    if ((int64_t)nn_at + nn_need > st.nn_pool) {
+      atomicOr(&ctr[C_ERR], E_NN_POOL);
+      lim_nn = min(nq, nn_cap);
+    } else {
+      nn_off = nn_at;
+      nn_cap = nn_need;
+    }
   }
-  st.hdr[x] = make_int4(nn_off, lim, ne_off, m);
-  st.cap[x] = make_int2(nn_cap, ne_cap);
+  uint64_t rel = __ballot(ne_need > 0), rel2 = __ballot(nn_need > 0);
+  if (__lane_id() == 0 && (rel | rel2)) atomicAdd(stripe_ptr(ctr, S_RELOC), __popcll(rel) + __popcll(rel2));
+  if (reg) {
+    for (int k = 0; k < lim_ne; ++k) st.ne[ne_off + k] = col[k * kBlock];
+    int w = 0;
+    bool put = nextra == 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      int v = nx[k];
+      if (v == INT_MAX) continue;
+      if (!put && extra < v) {
+        if (w < lim_nn) st.nn[nn_off + w] = extra;
+        ++w;
+        put = true;
+      }
+      if (w < lim_nn) st.nn[nn_off + w] = v;
+      ++w;
+    }
+    if (!put) {
+      if (w < lim_nn) st.nn[nn_off + w] = extra;
+      ++w;
+    }
+    st.hdr[x] = make_int4(nn_off, lim_nn, ne_off, lim_ne);
+    st.cap[x] = make_int2(nn_cap, ne_cap);
+  }
+  return odd;
 }
 
-__global__ void __launch_bounds__(256) k_commit_merge(Store st, Commit cm, int* ctr) {
-  int n = ctr[C_DIRTY];
-  for (int i = gtid(); i < n; i += gstride()) {
-    int x = cm.dlist[i];
-    int base = cm.dbase[x];
-    Hdr h = st.hdr[x];
-    int2 cp = st.cap[x];
-    int added = cm.pend[x];
-    cm.dirty[x] = 0;
-    cm.pend[x] = 0;
-    cm.nxt[x] = 1;
-    if (base < 0) continue;
-    int tot = h.w + added;
-    if (tot <= kRegRow) merge_row_regs(st, cm, x, base, h, cp, tot, ctr);
-    else merge_row_staged(st, cm, x, base, h, cp, added, ctr);
+// Rebuild row x (x < 0: idle lane); every lane of the wavefront makes this
+// call together. Rows of up to 16 candidates take the small register path,
+// up to kRegRow the large one (a wavefront runs a path only when one of its
+// lanes needs it), the rest the general path.
+__device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, int x, int* col, int* ctr) {
+  bool act = x >= 0;
+  int tot = 0;
+  if (act) tot = row_candidates(st, cm, x, st.hdr[x], col, kBlock, kRegRow);
+  bool small = act && tot <= 16, large = act && tot > 16 && tot <= kRegRow;
+  bool general = act && tot > kRegRow;
+  if (__ballot(small)) general |= rebuild_reg<16>(st, cm, small ? x : -1, tot, col, ctr);
+  if (__ballot(large)) general |= rebuild_reg<kRegRow>(st, cm, large ? x : -1, tot, col, ctr);
+  if (general) rebuild_staged(st, cm, x, ctr);
+  if (act) cm.nxt[x] = 1;
+  uint64_t rows = __ballot(act);
+  if (__lane_id() == 0 && rows) {
+    int* sp = stripe_ptr(ctr, 0);
+    atomicAdd(sp + S_ROWS, __popcll(rows));
+    atomicAdd(sp + S_PROWS, __popcll(rows));
   }
 }
 
-void commit_rows(const Store& st, Commit cm, int* ctr, int vmax, hipStream_t s) {
-  int g = grid_for(vmax, 4096);
-  k_commit_alloc<<<g, kBlock, 0, s>>>(st, cm, ctr);
-  k_commit_fill<<<g, kBlock, 0, s>>>(st, cm, ctr);
-  k_commit_merge<<<g, kBlock, 0, s>>>(st, cm, ctr);
+// block-wide exclusive scan of one int per thread; returns the block total
+__device__ __forceinline__ int block_scan(int x, int& excl, int* wsum) {
+  int lane = __lane_id(), wv = (int)threadIdx.x / kWave;
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int o = __shfl_up(incl, d);
+    if (lane >= d) incl += o;
+  }
+  if (lane == kWave - 1) wsum[wv] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < kBlock / kWave; ++q) {
+    int c = wsum[q];
+    total += c;
+    if (q < wv) before += c;
+  }
+  excl = before + incl - x;
+  return total;
+}
+
+// One block per 256 class members, in the class kernel's block order (the
+// rows a block rebuilds are those its class block just touched, in the same
+// XCD's L2). The (member, neighbour) pairs of the block's committed members
+// are spread over its threads; a pair rebuilds the neighbour's row when the
+// member owns it. Flip members' own rows follow after a barrier, since the
+// pairs read the members' rows.
+__global__ void __launch_bounds__(256) k_commit(Store st, const int* __restrict__ list, int n, Commit cm, int flips,
+                                                int* ctr) {
+  __shared__ int col[kRegRow * kBlock];
+  __shared__ int pre[kBlock + 1];
+  __shared__ int moff[kBlock];
+  __shared__ int mid[kBlock];
+  __shared__ int wsum[kBlock / kWave];
+  int i = xtid();
+  int v = -1, deg = 0, off = 0;
+  bool flip_self = false;
+  if (i < n) {
+    v = list[i];
+    if (cm.oep[v] == cm.epoch) {
+      Hdr h = st.hdr[v];
+      deg = h.y;
+      off = h.x;
+      flip_self = flips != 0;
+    }
+  }
+  int excl;
+  int P = block_scan(deg, excl, wsum);
+  pre[threadIdx.x] = excl;
+  moff[threadIdx.x] = off;
+  mid[threadIdx.x] = v;
+  if (threadIdx.x == 0) pre[kBlock] = P;
+  __syncthreads();
+  int* mycol = col + threadIdx.x;
+  for (int p0 = 0; p0 < P; p0 += kBlock) {
+    int p = p0 + (int)threadIdx.x;
+    int x = -1;
+    if (p < P) {
+      // the member s with pre[s] <= p < pre[s + 1] (members without pairs
+      // have pre[s] == pre[s + 1]; take the last s with pre[s] <= p)
+      int lo = 0, hi = kBlock - 1;
+      while (lo < hi) {
+        int mdl = (lo + hi + 1) >> 1;
+        if (pre[mdl] <= p) lo = mdl;
+        else hi = mdl - 1;
+      }
+      int y = st.nn[moff[lo] + (p - pre[lo])];
+      if (cm.own[y] == own_key(cm.epoch, mid[lo])) x = y;
+    }
+    rebuild_row(st, cm, x, mycol, ctr);
+  }
+  if (!flips) return;
+  __syncthreads();
+  int x = (flip_self && cm.own[v] == own_key(cm.epoch, v)) ? v : -1;
+  rebuild_row(st, cm, x, mycol, ctr);
+}
+
+void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s) {
+  if (n > 0) k_commit<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, cm, flips ? 1 : 0, ctr);
 }
 
 // ---- smoothing (Sec. 2.4.4) ---------------------------------------------------------------------
@@ -1124,12 +1304,12 @@ __global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restric
 // ---- collapse with lane groups -----------------------------------------------------------------
 __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm, int* ctr, const Grp& g) {
   bool ownn = g.j < h.y, owne = g.j < h.w;
-  uint64_t kv = a.rd.key[v];
+  uint64_t rv = a.rw[v];
   int w = -1;
   bool beat = false;
   if (ownn) {
     w = st.nn[h.x + g.j];
-    beat = a.act[w] && a.col[w] == a.cls && a.rd.key[w] > kv;
+    beat = same_class_beats(a, w, rv, v);
   }
   if (gany(beat, g)) {
     if (g.j == 0) cm.nxt[v] = 1;
@@ -1225,10 +1405,10 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
     }
     st.tri[t] = ne;
   }
-  if (ownn) mark_dirty(cm, w, ctr);
+  if (ownn) claim_row(cm, w, v);
   if (g.j == 0) {
     st.valive[v] = 0;
-    queue_add(cm, u, v, h.w, ctr);
+    stamp(cm, v, make_int2(-(u + 1), 0));
   }
   return 2;
 }
@@ -1236,6 +1416,7 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
 __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
   Grp g = grp();
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
   if (gid < n) {

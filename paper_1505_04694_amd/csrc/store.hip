@@ -394,7 +394,7 @@ __global__ void k_refine_mark(Store st, double L_up2, int* __restrict__ cnt, int
       }
       cnt[a] = c;
     }
-    wave_add_full(&ctr[C_EDGES], tested);
+    wave_add_full(stripe_ptr(ctr, S_EDGES), tested);
   }
 }
 void refine_mark(const Store& st, double L_up2, int* cnt, int* ctr, hipStream_t s) {
