@@ -75,7 +75,10 @@ typedef struct {
   int32_t wg_size;        /* work-group size, 0 = library default               */
   int32_t variant;        /* kernel shapes: bit 0 = collapse, bit 1 = smoothing run
                              on groups of 8 lanes per vertex instead of one thread;
-                             results are identical either way                    */
+                             0 = automatic (groups for small collapse classes,
+                             one-block kernels for small lists and classes),
+                             bit 2 = one thread per vertex and the multi-block
+                             kernels throughout; results are identical          */
 } pm_options;
 
 /* Per-phase counters, all integers:

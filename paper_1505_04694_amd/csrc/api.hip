@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -65,8 +66,10 @@ struct pm_mesh {
   int* ranges = nullptr;  // device: vbase[B+1], vused[B], tbase[B+1], tused[B]
   int* mdone = nullptr;   // device: per-mesh "refinement finished" flags
   DBuf<int> rtmp;         // per-mesh scratch (sums, new bases)
-  int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing
+  int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing, bit 2: no automatic shapes
   int64_t peak_bytes = 0, cur_bytes = 0;
+  bool pool = false;  // device memory from the stream-ordered pool
+  int jp_last = 8;    // JP iterations the last colouring took
 };
 
 namespace {
@@ -92,11 +95,27 @@ pm_status fail(pm_mesh* m, pm_status st, const std::string& msg) {
     if (r_ != PM_OK) return r_;     \
   } while (0)
 
+// Device memory comes from the device's stream-ordered pool where there is
+// one: blocks freed by a phase or a handle stay in the pool (up to a release
+// threshold) for the next request, instead of a driver call each time.
+void init_pool(pm_mesh* m) {
+  int dev = 0, sup = 0;
+  hipMemPool_t p;
+  m->pool = hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&sup, hipDeviceAttributeMemoryPoolsSupported, dev) == hipSuccess && sup &&
+            hipDeviceGetDefaultMemPool(&p, dev) == hipSuccess;
+  if (m->pool) {
+    uint64_t keep = 16ull << 30;
+    (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+  (void)hipGetLastError();
+}
+
 template <class T>
 pm_status dalloc(pm_mesh* m, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  hipError_t e = m->pool ? hipMallocAsync((void**)p, n * sizeof(T), m->s) : hipMalloc((void**)p, n * sizeof(T));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
@@ -105,10 +124,40 @@ pm_status dalloc(pm_mesh* m, T** p, size_t n) {
   m->peak_bytes = std::max(m->peak_bytes, m->cur_bytes);
   return PM_OK;
 }
+// Pinned host blocks (the counter mirror and the quality read-back) are kept
+// in a process-wide free list: pinning memory is a slow driver call.
+constexpr size_t kPinnedBytes = C_COUNT * sizeof(int) + 64 * sizeof(double);
+std::mutex g_pinned_mu;
+std::vector<void*> g_pinned_free;
+bool pinned_get(pm_mesh* m) {
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+    }
+  }
+  if (!p && hipHostMalloc(&p, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  m->hctr = (int*)p;
+  m->hq = (double*)((char*)p + C_COUNT * sizeof(int));
+  return true;
+}
+void pinned_put(pm_mesh* m) {
+  if (!m->hctr) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  g_pinned_free.push_back(m->hctr);
+  m->hctr = nullptr;
+  m->hq = nullptr;
+}
+
 template <class T>
 void dfree(pm_mesh* m, T*& p, size_t n) {
   if (p) {
-    (void)hipFree(p);
+    (void)(m->pool ? hipFreeAsync(p, m->s) : hipFree(p));
     m->cur_bytes -= (int64_t)(std::max<size_t>(n, 1) * sizeof(T));
   }
   p = nullptr;
@@ -180,8 +229,9 @@ pm_status read_ctr(pm_mesh* m, int lo, int n) {
   return PM_OK;
 }
 
-pm_status check_err(pm_mesh* m) {
-  TRY(read_ctr(m, C_ERR, 1));
+// fresh: the host copy of the counters was read after the last kernel
+pm_status check_err(pm_mesh* m, bool fresh = false) {
+  if (!fresh) TRY(read_ctr(m, C_ERR, 1));
   int e = m->hctr[C_ERR];
   if (!e) return PM_OK;
   std::string msg = "device error bits " + std::to_string(e) + ":";
@@ -324,8 +374,8 @@ pm_status build_rows(pm_mesh* m) {
 
 // free pool space check between rounds: rebuild (repack) when a round could
 // plausibly exhaust it
-pm_status maybe_repack(pm_mesh* m) {
-  TRY(read_ctr(m, C_NN_TOP, 2));
+pm_status maybe_repack(pm_mesh* m, bool fresh = false) {
+  if (!fresh) TRY(read_ctr(m, C_NN_TOP, 2));
   int64_t nn_top = m->hctr[C_NN_TOP], ne_top = m->hctr[C_NE_TOP];
   if (nn_top * 3 > m->st.nn_pool * 2 || ne_top * 3 > m->st.ne_pool * 2) return build_rows(m);
   return PM_OK;
@@ -336,7 +386,8 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->listA, V));
   TRY(ensure(m, m->listB, V));
   TRY(ensure(m, m->jpU0, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
-  TRY(ensure(m, m->jpU1, (size_t)V / kJpChunk + 1));
+  // chunk counts of the chunked JP, or the second waiting list of the small colouring
+  TRY(ensure(m, m->jpU1, std::max((size_t)V / kJpChunk + 1, (size_t)std::min(V, kSmallColour))));
   TRY(ensure(m, m->cls, V));
   TRY(ensure(m, m->rw, V, true));
   TRY(ensure(m, m->nxt, V, true));
@@ -380,11 +431,24 @@ constexpr int kJpBatch = 4;
 pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
+  if (n <= kSmallColour && !(m->variant & 4)) {
+    timed(m, PM_K_JP, 0, [&] { colour_small(m->st, A, n, rd, m->jpU0.p, m->jpU1.p, m->cls.p, m->ctr, m->s); });
+    TRY(read_ctr(m, 0, C_NCOL + 1));
+    TRY(check_err(m, true));
+    out.jp_iters = m->hctr[C_TOTAL];
+    out.ncol = m->hctr[C_NCOL];
+    out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
+    out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
+    return PM_OK;
+  }
   jp_init(m->st, A, n, rd, m->s);
   stripe_zero(m->ctr, S_JPL, 8, m->s);
   int it = 0;
   for (;;) {
-    for (int b = 0; b < kJpBatch; ++b, ++it)
+    // first batch: as many iterations as the last colouring needed, so that
+    // most colourings need one read-back
+    int batch = it == 0 ? std::min(std::max(m->jp_last, kJpBatch), 64) : kJpBatch;
+    for (int b = 0; b < batch; ++b, ++it)
       timed(m, PM_K_JP, 0, [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
     stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
     TRY(read_ctr(m, C_JP, 1));
@@ -393,14 +457,15 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
     if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
   }
   out.jp_iters = it;
+  m->jp_last = it;
   zero_ints(m->ctr + C_HIST, 256, m->s);
   int nb = (n + kBlock - 1) / kBlock;
   TRY(ensure(m, m->ctab, 256 * (size_t)nb + 256));
   TRY(ensure(m, m->ctabs, 256 * (size_t)nb + 256));
   TRY(ensure(m, m->spart, scan_partials_needed(256 * nb) + 2));
   class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
-  TRY(read_ctr(m, C_HIST, C_NCOL + 1 - C_HIST));
-  TRY(check_err(m));
+  TRY(read_ctr(m, 0, C_NCOL + 1));
+  TRY(check_err(m, true));
   out.ncol = m->hctr[C_NCOL];
   out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
   out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
@@ -533,10 +598,20 @@ bool bad_opts(const pm_options* o) {
   return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
          o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
          (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0) ||
-         o->variant < 0 || o->variant > 3;
+         o->variant < 0 || o->variant > 7;
 }
 
 // rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1)
+// Small classes are latency bound: one thread per member walks its rows and
+// elements one dependent load after another. Groups of 8 lanes per member
+// take those loads side by side, so below this size they are used.
+constexpr int kGroupBelow = 16384;
+int collapse_shape(const pm_mesh* m, int n) {
+  if (m->variant & 1) return 1;
+  if (m->variant & 4) return 0;
+  return n < kGroupBelow ? 1 : 0;
+}
+
 pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   TRY(ensure_phase_scratch(m));
   m->variant = o->variant;
@@ -549,12 +624,13 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   timed(m, PM_K_SELECT, m->st.V,
         [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p,
                           m->spos.p, m->spart.p, m->s); });
-  TRY(read_ctr(m, C_LIST_B, 1));
+  TRY(read_ctr(m, 0, C_EVAL));  // pool tops, error bits and the list length at once
+  TRY(check_err(m, true));
   int nA = m->hctr[C_LIST_B];
   int r = 0;
   Commit cm = commit_of(m);
   while (nA > 0 && r < max_rounds) {
-    TRY(maybe_repack(m));
+    TRY(maybe_repack(m, true));
     Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->rw.p};
     Classes cl;
     TRY(colour_list(m, m->listA.p, nA, rd, cl));
@@ -565,9 +641,15 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
       if (cl.size[c] == 0) continue;
       cm.epoch = ++m->epoch;
       OpArgs a{m->rw.p, c, rd, o->L_low2, qmin2};
+      if (cl.size[c] <= kSmallClass && !(m->variant & 4)) {
+        // a small class: operation and commit in one block, one launch
+        timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, cl.size[c],
+              [&] { class_small(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, kind, m->ctr, m->s); });
+        continue;
+      }
       if (kind == 0)
         timed(m, PM_K_COLLAPSE, cl.size[c], [&] {
-          collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->variant & 1, m->s);
+          collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, collapse_shape(m, cl.size[c]), m->s);
         });
       else
         timed(m, PM_K_FLIP, cl.size[c],
@@ -581,8 +663,8 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
     timed(m, PM_K_SELECT, m->st.V,
           [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
                           m->spos.p, m->spart.p, m->s); });
-    TRY(read_ctr(m, C_LIST_B, 1));
-    TRY(check_err(m));
+    TRY(read_ctr(m, 0, C_EVAL));
+    TRY(check_err(m, true));
     nA = m->hctr[C_LIST_B];
     std::swap(m->listA, m->listB);
     ++r;
@@ -657,9 +739,8 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->orec.p, m->orec.n);
   prof_flush(m);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
-  if (m->ctr) (void)hipFree(m->ctr);
-  if (m->hctr) (void)hipHostFree(m->hctr);
-  if (m->hq) (void)hipHostFree(m->hq);
+  dfree(m, m->ctr, C_COUNT);
+  pinned_put(m);
   delete m;
   return PM_OK;
 }
@@ -679,17 +760,14 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
+  init_pool(m);
   g_create_err.clear();
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
     pm_mesh_destroy(m);
     return st;
   };
-  if (hipMalloc((void**)&m->ctr, C_COUNT * sizeof(int)) != hipSuccess) return bail(PM_E_NOMEM);
-  if (hipHostMalloc((void**)&m->hctr, C_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
-    return bail(PM_E_NOMEM);
-  if (hipHostMalloc((void**)&m->hq, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return bail(PM_E_NOMEM);
+  if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
   zero_ints(m->ctr, C_COUNT, m->s);
   int V = (int)d->V, T = (int)d->T;
   if (grow_vertices(m, V) != PM_OK || grow_elements(m, T) != PM_OK) return bail(PM_E_NOMEM);
@@ -1070,16 +1148,13 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
+  init_pool(m);
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
     pm_mesh_destroy(m);
     return st;
   };
-  if (hipMalloc((void**)&m->ctr, C_COUNT * sizeof(int)) != hipSuccess) return bail(PM_E_NOMEM);
-  if (hipHostMalloc((void**)&m->hctr, C_COUNT * sizeof(int), hipHostMallocDefault) != hipSuccess)
-    return bail(PM_E_NOMEM);
-  if (hipHostMalloc((void**)&m->hq, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-    return bail(PM_E_NOMEM);
+  if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
   zero_ints(m->ctr, C_COUNT, m->s);
   Store& st = m->st;
   st.B = count;

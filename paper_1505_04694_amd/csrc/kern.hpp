@@ -210,6 +210,11 @@ void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first
 void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
                  hipStream_t s);
 void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s);
+// lists up to kSmallColour entries: colouring and class lists in one block;
+// writes class sizes, offsets and count like class_lists, iterations to C_TOTAL
+constexpr int kSmallColour = 8192;
+void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* out, int* ctr,
+                  hipStream_t s);
 
 // variant 0: one thread per member; 1: a group of 8 lanes per member
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
@@ -219,6 +224,10 @@ void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, i
 // rebuild the rows claimed by the committed members of list[0..n) (the class
 // just processed, launched in the same shape); flips: members' own rows too
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s);
+// a class of at most kSmallClass members: operation and commit in one block
+// (kind 0 collapse, 1 flip)
+constexpr int kSmallClass = 32;
+void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);

@@ -13,7 +13,8 @@
 
 namespace pm {
 
-constexpr int kG = 8;  // lanes per vertex in the lane-group kernels
+constexpr int kG = 8;    // lanes per vertex in the lane-group kernels
+constexpr int kGC = 16;  // lanes per vertex in the lane-group collapse
 
 __device__ __forceinline__ uint64_t key_of(const Store& st, const Round& rd, int v) {
   return vkey(rd.sseed, (uint32_t)local_id(st, v));
@@ -309,6 +310,70 @@ void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, in
   k_class_sizes<<<1, 256, 0, s>>>(tabscan, nb, n, ctr);
 }
 
+// Small lists: one block runs the whole colouring (JP iterations separated
+// by block barriers until no vertex waits) and cuts the class lists, in one
+// launch. Classes come out in no particular order; the members of a class
+// are an independent set, so their order does not change any result.
+constexpr int kSmallThreads = 1024;
+__global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const int* __restrict__ A, int n, Round rd,
+                                                              int* W0, int* W1, int* __restrict__ out, int* ctr) {
+  __shared__ int nwait, hist[256], cur[256];
+  int tid = (int)threadIdx.x;
+  for (int i = tid; i < n; i += kSmallThreads) {
+    int v = A[i];
+    uint64_t prio = key_of(st, rd, v) >> 32;
+    rd.rw[v] = (prio << 32) | kRwAct | 0xFFull;
+  }
+  if (tid < 256) hist[tid] = 0;
+  __syncthreads();
+  const int* in = A;
+  int nw = n, it = 0, visited = 0;
+  while (nw > 0) {
+    if (tid == 0) nwait = 0;
+    __syncthreads();
+    int* wout = (it & 1) ? W1 : W0;
+    for (int i = tid; i < nw; i += kSmallThreads) {
+      int v = in[i];
+      if (!jp_try(st, v, rd, ctr)) wout[atomicAdd(&nwait, 1)] = v;
+    }
+    __syncthreads();
+    visited += nw;
+    nw = nwait;
+    in = wout;
+    ++it;
+    __syncthreads();
+    if (it > 4 * kMaxColours + n) {  // cannot happen: the largest waiting key is always ready
+      if (tid == 0) atomicOr(&ctr[C_ERR], E_COLOURS);
+      return;
+    }
+  }
+  for (int i = tid; i < n; i += kSmallThreads) atomicAdd(&hist[(int)(rd.rw[A[i]] & 0xFF)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int o = 0, ncol = 0;
+    for (int c = 0; c < 256; ++c) {
+      cur[c] = o;
+      ctr[C_OFF + c] = o;
+      ctr[C_HIST + c] = hist[c];
+      o += hist[c];
+      if (hist[c]) ncol = c + 1;
+    }
+    ctr[C_NCOL] = ncol;
+    ctr[C_JP] = 0;
+    ctr[C_TOTAL] = it;
+    atomicAdd(ctr + C_STRIPE + S_PJP, visited);
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += kSmallThreads) {
+    int v = A[i];
+    out[atomicAdd(&cur[(int)(rd.rw[v] & 0xFF)], 1)] = v;
+  }
+}
+void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* out, int* ctr,
+                  hipStream_t s) {
+  k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, rd, W0, W1, out, ctr);
+}
+
 __global__ void k_colour_out(int V, const uint64_t* __restrict__ rw, int* __restrict__ out) {
   for (int v = gtid(); v < V; v += gstride()) out[v] = (rw[v] & kRwAct) ? (int)(rw[v] & 0xFF) : -1;
 }
@@ -365,7 +430,7 @@ __device__ __forceinline__ void count_status(int status, int* ctr) {
 // Candidates u: neighbours on every boundary side v lies on, with L^2 < L_low2,
 // tried in ascending (L^2, u); the first whose re-pointed elements all keep
 // area > 0 and q^2 >= q_min^2 is taken.
-__device__ int collapse_one(Store st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
+__device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
   Hdr h = st.hdr[v];
   double2 pv = st.xy[v];
   Met mv = st.met[v];
@@ -458,7 +523,7 @@ void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm
                     hipStream_t s) {
   if (n <= 0) return;
   if (variant == 1)
-    k_collapse_g<<<(int)(((int64_t)n * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    k_collapse_g<<<(int)(((int64_t)n * kGC + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
   else
     k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
@@ -468,7 +533,7 @@ void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm
 // when both areas stay positive and the smaller q^2 rises strictly; the best
 // new minimum wins, ties to the smaller w; the element holding v keeps the
 // smaller id.
-__device__ int flip_one(Store st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
+__device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a, const Commit& cm, int* ctr) {
   if (beaten(st, v, a)) {
     cm.nxt[v] = 1;
     return 0;
@@ -545,25 +610,44 @@ void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, in
 // then the set of the other vertices of those elements.
 
 // the candidates of row x, written to dst[k * stride] for k < lim; returns
-// how many there are
-__device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm, int x, Hdr h, int* dst, int stride, int lim) {
+// how many there are. Row entries and stamps are fetched eight at a time,
+// so a row costs a few dependent loads rather than one per neighbour.
+__device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm, int x, Hdr h, int* dst, int stride,
+                                              int lim) {
+  constexpr int B = 8;
   int n = 0;
-  for (int k = 0; k < h.w; ++k, ++n)
-    if (n < lim) dst[n * stride] = st.ne[h.z + k];
-  for (int j = 0; j < h.y; ++j) {
-    int w = st.nn[h.x + j];
-    if (cm.oep[w] != cm.epoch) continue;
-    int2 r = cm.orec[w];
-    if (r.x < 0) {
-      if (-r.x - 1 != x) continue;
-      Hdr hw = st.hdr[w];
-      for (int k = 0; k < hw.w; ++k, ++n)
-        if (n < lim) dst[n * stride] = st.ne[hw.z + k];
-    } else {
-      if (n < lim) dst[n * stride] = r.x;
-      ++n;
-      if (n < lim) dst[n * stride] = r.y;
-      ++n;
+  for (int k0 = 0; k0 < h.w; k0 += B) {
+    int t[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) t[q] = k0 + q < h.w ? st.ne[h.z + k0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q)
+      if (t[q] >= 0) {
+        if (n < lim) dst[n * stride] = t[q];
+        ++n;
+      }
+  }
+  for (int j0 = 0; j0 < h.y; j0 += B) {
+    int w[B], ep[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q) ep[q] = w[q] >= 0 ? cm.oep[w[q]] : 0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (w[q] < 0 || ep[q] != cm.epoch) continue;
+      int2 r = cm.orec[w[q]];
+      if (r.x < 0) {
+        if (-r.x - 1 != x) continue;
+        Hdr hw = st.hdr[w[q]];
+        for (int k = 0; k < hw.w; ++k, ++n)
+          if (n < lim) dst[n * stride] = st.ne[hw.z + k];
+      } else {
+        if (n < lim) dst[n * stride] = r.x;
+        ++n;
+        if (n < lim) dst[n * stride] = r.y;
+        ++n;
+      }
     }
   }
   if (cm.oep[x] == cm.epoch) {
@@ -849,24 +933,29 @@ __device__ __forceinline__ int block_scan(int x, int& excl, int* wsum) {
   return total;
 }
 
-// One block per 256 class members, in the class kernel's block order (the
-// rows a block rebuilds are those its class block just touched, in the same
-// XCD's L2). The (member, neighbour) pairs of the block's committed members
-// are spread over its threads; a pair rebuilds the neighbour's row when the
-// member owns it. Flip members' own rows follow after a barrier, since the
-// pairs read the members' rows.
-__global__ void __launch_bounds__(256) k_commit(Store st, const int* __restrict__ list, int n, Commit cm, int flips,
-                                                int* ctr) {
-  __shared__ int col[kRegRow * kBlock];
-  __shared__ int pre[kBlock + 1];
-  __shared__ int moff[kBlock];
-  __shared__ int mid[kBlock];
-  __shared__ int wsum[kBlock / kWave];
-  int i = xtid();
+// LDS of one commit block
+struct CommitLds {
+  int col[kRegRow * kBlock];  // candidate staging, one column per thread
+  int pre[kBlock];            // pair prefix per member
+  int moff[kBlock];           // member's NN row offset
+  int mid[kBlock];            // member id
+  int q[2 * kBlock];          // queued rows
+  int wsum[kBlock / kWave];
+};
+
+// Rebuild the rows claimed by the committed members list[base .. base + cnt)
+// (cnt <= kBlock), with all kBlock threads of the block. The (member,
+// neighbour) pairs are spread over the threads; a pair whose member owns the
+// neighbour's row queues that row in LDS, and every time 256 rows are queued
+// all threads rebuild one each. Flip members' own rows follow after a
+// barrier, since the pairs read the members' rows.
+__device__ __forceinline__ void commit_chunk(const Store& st, const int* __restrict__ list, int base, int cnt, const Commit& cm,
+                             int flips, int* ctr, CommitLds& L) {
+  int tid = (int)threadIdx.x;
   int v = -1, deg = 0, off = 0;
   bool flip_self = false;
-  if (i < n) {
-    v = list[i];
+  if (tid < cnt) {
+    v = list[base + tid];
     if (cm.oep[v] == cm.epoch) {
       Hdr h = st.hdr[v];
       deg = h.y;
@@ -875,38 +964,64 @@ __global__ void __launch_bounds__(256) k_commit(Store st, const int* __restrict_
     }
   }
   int excl;
-  int P = block_scan(deg, excl, wsum);
-  pre[threadIdx.x] = excl;
-  moff[threadIdx.x] = off;
-  mid[threadIdx.x] = v;
-  if (threadIdx.x == 0) pre[kBlock] = P;
+  int P = block_scan(deg, excl, L.wsum);
+  L.pre[tid] = excl;
+  L.moff[tid] = off;
+  L.mid[tid] = v;
   __syncthreads();
-  int* mycol = col + threadIdx.x;
+  int* mycol = L.col + tid;
+  int qn = 0;
   for (int p0 = 0; p0 < P; p0 += kBlock) {
-    int p = p0 + (int)threadIdx.x;
+    int p = p0 + tid;
     int x = -1;
     if (p < P) {
-      // the member s with pre[s] <= p < pre[s + 1] (members without pairs
-      // have pre[s] == pre[s + 1]; take the last s with pre[s] <= p)
+      // the member s with pre[s] <= p < pre[s + 1]: the last s with pre[s] <= p
       int lo = 0, hi = kBlock - 1;
       while (lo < hi) {
-        int mdl = (lo + hi + 1) >> 1;
-        if (pre[mdl] <= p) lo = mdl;
-        else hi = mdl - 1;
+        int md = (lo + hi + 1) >> 1;
+        if (L.pre[md] <= p) lo = md;
+        else hi = md - 1;
       }
-      int y = st.nn[moff[lo] + (p - pre[lo])];
-      if (cm.own[y] == own_key(cm.epoch, mid[lo])) x = y;
+      int y = st.nn[L.moff[lo] + (p - L.pre[lo])];
+      if (cm.own[y] == own_key(cm.epoch, L.mid[lo])) x = y;
     }
+    int rank;
+    int got = block_scan(x >= 0 ? 1 : 0, rank, L.wsum);
+    if (x >= 0) L.q[qn + rank] = x;
+    qn += got;
+    __syncthreads();
+    if (qn >= kBlock) {
+      rebuild_row(st, cm, L.q[tid], mycol, ctr);
+      qn -= kBlock;
+      int keep = tid < qn ? L.q[kBlock + tid] : -1;
+      __syncthreads();
+      if (tid < qn) L.q[tid] = keep;
+      __syncthreads();
+    }
+  }
+  if (qn > 0) rebuild_row(st, cm, tid < qn ? L.q[tid] : -1, mycol, ctr);
+  if (flips) {
+    __syncthreads();
+    int x = (flip_self && cm.own[v] == own_key(cm.epoch, v)) ? v : -1;
     rebuild_row(st, cm, x, mycol, ctr);
   }
-  if (!flips) return;
-  __syncthreads();
-  int x = (flip_self && cm.own[v] == own_key(cm.epoch, v)) ? v : -1;
-  rebuild_row(st, cm, x, mycol, ctr);
+  __syncthreads();  // the LDS is reused by the next chunk
+}
+
+// One block per mpb class members (256, or fewer for small classes, so that
+// more blocks share the latency-bound work), in XCD-aware block order.
+__global__ void __launch_bounds__(256) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
+                                                int flips, int* ctr) {
+  __shared__ CommitLds L;
+  int base = xcd_block() * mpb;
+  commit_chunk(st, list, base, min(mpb, n - base), cm, flips, ctr, L);
 }
 
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s) {
-  if (n > 0) k_commit<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, cm, flips ? 1 : 0, ctr);
+  if (n <= 0) return;
+  int mpb = n >= 256 * 1024 ? 256 : (n >= 64 * 1024 ? 64 : 16);
+  int nb = (n + mpb - 1) / mpb;
+  k_commit<<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, flips ? 1 : 0, ctr);
 }
 
 // ---- smoothing (Sec. 2.4.4) ---------------------------------------------------------------------
@@ -1302,7 +1417,20 @@ __global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restric
 }
 
 // ---- collapse with lane groups -----------------------------------------------------------------
-__device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm, int* ctr, const Grp& g) {
+// G lanes per member (G = kGC): small classes are made of the vertices that
+// earlier rounds left, often of high degree, so the groups are wider here.
+template <int G>
+__device__ __forceinline__ Grp grp_of() {
+  int l = __lane_id();
+  return Grp{l & (G - 1), l & ~(G - 1)};
+}
+template <int G>
+__device__ __forceinline__ bool gany_of(bool p, const Grp& g) {
+  uint64_t b = __ballot(p);
+  return ((b >> g.base) & ((1ull << G) - 1ull)) != 0;
+}
+template <int G>
+__device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm, int* ctr, const Grp& g) {
   bool ownn = g.j < h.y, owne = g.j < h.w;
   uint64_t rv = a.rw[v];
   int w = -1;
@@ -1311,7 +1439,7 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
     w = st.nn[h.x + g.j];
     beat = same_class_beats(a, w, rv, v);
   }
-  if (gany(beat, g)) {
+  if (gany_of<G>(beat, g)) {
     if (g.j == 0) cm.nxt[v] = 1;
     return 0;
   }
@@ -1356,7 +1484,7 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
     int bU = after ? w : INT_MAX;
     int bj = after ? g.j : -1;
 #pragma unroll
-    for (int d = 1; d < kG; d <<= 1) {
+    for (int d = 1; d < G; d <<= 1) {
       double oL = __shfl_xor(bL, d);
       int oU = __shfl_xor(bU, d);
       int oj = __shfl_xor(bj, d);
@@ -1386,7 +1514,7 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
       Geo gg = make_geo(c0, c1, c2, d0, d1, d2);
       bad = !(area2(gg) > 0.0) || !(qual2(gg) >= a.qmin2);
     }
-    if (!gany(bad, g)) {
+    if (!gany_of<G>(bad, g)) {
       u = bU;
       break;
     }
@@ -1415,21 +1543,60 @@ __device__ int collapse_group(Store& st, int v, Hdr h, const OpArgs& a, const Co
 
 __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
-  Grp g = grp();
+  Grp g = grp_of<kGC>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
-  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
+  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kGC);
   int status = -1;
   if (gid < n) {
     int v = list[gid];
     Hdr h = st.hdr[v];
-    if (h.y > kG || h.w > kG) {
+    if (h.y > kGC || h.w > kGC) {
       if (g.j == 0) status = collapse_one(st, v, a, cm, ctr);
     } else {
-      int r = collapse_group(st, v, h, a, cm, ctr, g);
+      int r = collapse_group<kGC>(st, v, h, a, cm, ctr, g);
       if (g.j == 0) status = r;
     }
   }
   count_status(status, ctr);
+}
+
+// A small class in one block: the operation (collapse on groups of kGC lanes,
+// or flips one per thread), a block barrier, then the commit of the same
+// members; one launch instead of two. Every thread reaches every barrier.
+__global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
+                                                     Commit cm, int kind, int* ctr) {
+  __shared__ CommitLds L;
+  int tid = (int)threadIdx.x;
+  if (tid == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
+  if (kind == 0) {
+    Grp g = grp_of<kGC>();
+    for (int p0 = 0; p0 < n; p0 += kBlock / kGC) {
+      int gid = p0 + tid / kGC;
+      int status = -1;
+      if (gid < n) {
+        int v = list[gid];
+        Hdr h = st.hdr[v];
+        if (h.y > kGC || h.w > kGC) {
+          if (g.j == 0) status = collapse_one(st, v, a, cm, ctr);
+        } else {
+          int r = collapse_group<kGC>(st, v, h, a, cm, ctr, g);
+          if (g.j == 0) status = r;
+        }
+      }
+      count_status(status, ctr);
+    }
+  } else {
+    for (int i0 = 0; i0 < n; i0 += kBlock) {
+      int i = i0 + tid;
+      int status = i < n ? flip_one(st, list[i], a, cm, ctr) : -1;
+      count_status(status, ctr);
+    }
+  }
+  __syncthreads();
+  for (int base = 0; base < n; base += kBlock) commit_chunk(st, list, base, min(kBlock, n - base), cm, kind, ctr, L);
+}
+void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
+  if (n > 0) k_class_small<<<1, kBlock, 0, s>>>(st, list, n, a, cm, kind, ctr);
 }
 
 // ---- adjoint with lane groups ---------------------------------------------------------------------

@@ -76,12 +76,14 @@ def test_full_sweeps(name, make, seed):
     compare_quality(om, gm, "end")
 
 
+@pytest.mark.parametrize("variant", [3, 4])
 @pytest.mark.parametrize("name,make,seed", SMALL[2:4])
-def test_lane_group_variants_match(name, make, seed):
-    # collapse and smoothing on groups of 8 lanes per vertex give the same results
+def test_kernel_shapes_match(name, make, seed, variant):
+    # collapse and smoothing on groups of 8 lanes per vertex throughout (3), or
+    # on one thread per vertex throughout (4), give the same results
     mi = make()
     om, gm = both(mi, seed)
-    gm.variant = 3
+    gm.variant = variant
     run_sweeps(om, gm, 2, smooth_kinds=(0, 1))
     compare_quality(om, gm, "end")
 
