@@ -216,6 +216,28 @@ __device__ __forceinline__ int xcd_block() {
 }
 __device__ __forceinline__ int xtid() { return xcd_block() * blockDim.x + threadIdx.x; }
 
+// sorting network on a register array (all indices are compile-time constants)
+template <int N>
+__device__ __forceinline__ void bitonic(int (&a)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        int l = i ^ j;
+        if (l > i) {
+          int x = a[i], y = a[l];
+          int lo = min(x, y), hi = max(x, y);
+          bool up = (i & k) == 0;
+          a[i] = up ? lo : hi;
+          a[l] = up ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
 // grid-stride helpers
 __device__ __forceinline__ int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ int gstride() { return gridDim.x * blockDim.x; }

@@ -737,28 +737,6 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
   st.cap[x] = make_int2(nn_cap, ne_cap);
 }
 
-// sorting network on a register array (all indices are compile-time constants)
-template <int N>
-__device__ __forceinline__ void bitonic(int (&a)[N]) {
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        int l = i ^ j;
-        if (l > i) {
-          int x = a[i], y = a[l];
-          int lo = min(x, y), hi = max(x, y);
-          bool up = (i & k) == 0;
-          a[i] = up ? lo : hi;
-          a[l] = up ? hi : lo;
-        }
-      }
-    }
-  }
-}
-
 constexpr int kRegRow = 32;  // rows up to this many candidates are rebuilt in registers
 
 // Register path for rows of at most N candidates, staged in this thread's

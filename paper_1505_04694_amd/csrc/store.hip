@@ -225,12 +225,81 @@ __device__ void isort(int* a, int n) {
 // "previous" vertex that is not a next (boundary vertices). A repeated next
 // means a directed edge is used twice: inconsistent orientation or a
 // non-manifold edge; more than one unmatched previous is a pinched vertex.
+// Rows of up to 16 elements are finished in registers: sorting networks,
+// and every previous looked up among all nexts.
+constexpr int kFinishReg = 16;
+__device__ __forceinline__ void row_finish_reg(const Elem* __restrict__ tri, Hdr* __restrict__ hdr, int ncap,
+                                               int* __restrict__ nn, int* __restrict__ ne, int v, Hdr h,
+                                               int* ctr) {
+  constexpr int N = kFinishReg;
+  int c = h.w;
+  int r[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) r[k] = k < c ? ne[h.z + k] : INT_MAX;
+  bitonic<N>(r);
+  int nx[N], pv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    nx[k] = INT_MAX;
+    pv[k] = INT_MAX;
+    if (k < c) {
+      ne[h.z + k] = r[k];
+      Elem e = tri[r[k]];
+      int s = slot_of(e, v);
+      nx[k] = at(e, s == 2 ? 0 : s + 1);
+      pv[k] = at(e, s == 0 ? 2 : s - 1);
+    }
+  }
+  bitonic<N>(nx);
+  bool bad = false;
+#pragma unroll
+  for (int k = 1; k < N; ++k) bad |= nx[k] != INT_MAX && nx[k] == nx[k - 1];
+  int extra = INT_MAX, nextra = 0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (pv[k] == INT_MAX) continue;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < N; ++q) found |= nx[q] == pv[k];
+    if (!found) {
+      extra = pv[k];
+      ++nextra;
+    }
+  }
+  int n = c + nextra;
+  if (nextra > 1 || n > ncap) bad = true;
+  if (bad) {
+    atomicOr(&ctr[C_ERR], E_MESH_MANIFOLD);
+    n = c;
+    nextra = 0;
+  }
+  int w = 0;
+  bool put = nextra == 0;
+  int* out = nn + h.x;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    int x = nx[k];
+    if (x == INT_MAX) continue;
+    if (!put && extra < x) {
+      out[w++] = extra;
+      put = true;
+    }
+    out[w++] = x;
+  }
+  if (!put) out[w++] = extra;
+  reinterpret_cast<int*>(&hdr[v])[1] = n;
+}
+
 __global__ void k_row_finish(const Elem* __restrict__ tri, Hdr* __restrict__ hdr, const int2* __restrict__ cap,
                              int* __restrict__ nn, int* __restrict__ ne, int V, int* ctr) {
   for (int v = gtid(); v < V; v += gstride()) {
     Hdr h = hdr[v];
     int c = h.w;
     if (c == 0) continue;
+    if (c <= kFinishReg) {
+      row_finish_reg(tri, hdr, cap[v].x, nn, ne, v, h, ctr);
+      continue;
+    }
     int* row = ne + h.z;
     isort(row, c);
     int* out = nn + h.x;
