@@ -55,8 +55,8 @@ struct pm_mesh {
   DBuf<uint8_t> nxt, u8tmp;
   DBuf<Met> emet;   // smoothing: per-element mean tensors
   DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
-  DBuf<int> oep, stage;  // commit: operation stamps, fallback staging
-  DBuf<int2> orec;       // commit: operation records
+  DBuf<int> stage;       // commit: fallback staging
+  DBuf<int4> ops;        // commit: operation records
   DBuf<uint64_t> own;    // commit: row owner keys
   int epoch = 0;         // commit epoch, one per class
   DBuf<double> qpart;
@@ -391,8 +391,7 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->cls, V));
   TRY(ensure(m, m->rw, V, true));
   TRY(ensure(m, m->nxt, V, true));
-  TRY(ensure(m, m->oep, V, true));
-  TRY(ensure(m, m->orec, V));
+  TRY(ensure(m, m->ops, V, true));
   TRY(ensure(m, m->own, V, true));
   TRY(ensure(m, m->sflag, V));
   TRY(ensure(m, m->spos, V));
@@ -407,8 +406,7 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
 Commit commit_of(pm_mesh* m) {
   Commit c;
   c.epoch = m->epoch;
-  c.oep = m->oep.p;
-  c.orec = m->orec.p;
+  c.ops = m->ops.p;
   c.own = m->own.p;
   c.stage = m->stage.p;
   c.stage_cap = (int64_t)m->stage.n;
@@ -726,7 +724,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->ranges, 1);
   dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
-                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->oep, &m->stage, &m->rtmp,
+                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->stage, &m->rtmp,
                      &m->sflag, &m->spos,
                      &m->ctab, &m->ctabs, &m->spart};
   for (auto* b : ib) dfree(m, b->p, b->n);
@@ -736,7 +734,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->qpart.p, m->qpart.n);
   dfree(m, m->rw.p, m->rw.n);
   dfree(m, m->own.p, m->own.n);
-  dfree(m, m->orec.p, m->orec.n);
+  dfree(m, m->ops.p, m->ops.n);
   prof_flush(m);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
   dfree(m, m->ctr, C_COUNT);

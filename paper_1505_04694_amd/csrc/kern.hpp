@@ -175,10 +175,12 @@ struct Round {
 // hand over. Epochs grow by one per class, so stale stamps never match.
 struct Commit {
   int epoch;
-  int* oep;        // V: epoch of the vertex's last committed operation
-  int2* orec;      // V: that operation: (-(u+1), 0) collapse onto u, (t1, t2) flip's elements
+  // V: the vertex's last committed operation, (epoch, a, b, c): a collapse
+  // onto u is (epoch, -(u+1), ne_off, ne_cnt) with the member's NE row, a
+  // flip (epoch, t1, t2, 0) with its two elements
+  int4* ops;
   uint64_t* own;   // V: row owner key, maximised: (epoch << 32) | ~member
-  int* stage;      // staging for rows past the register path
+  int* stage;      // staging for rows past the register paths
   int64_t stage_cap;
   uint8_t* nxt;    // next-round flags
 };

@@ -387,9 +387,8 @@ void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s) {
 __device__ __forceinline__ void claim_row(const Commit& cm, int x, int v) {
   atomicMax((unsigned long long*)&cm.own[x], (unsigned long long)own_key(cm.epoch, v));
 }
-__device__ __forceinline__ void stamp(const Commit& cm, int v, int2 rec) {
-  cm.orec[v] = rec;
-  cm.oep[v] = cm.epoch;
+__device__ __forceinline__ void stamp(const Commit& cm, int v, int a, int b, int c) {
+  cm.ops[v] = make_int4(cm.epoch, a, b, c);
 }
 
 // a member is deferred when a same-class active neighbour has a larger key
@@ -505,7 +504,7 @@ __device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs
     st.tri[t] = e;
   }
   st.valive[v] = 0;
-  stamp(cm, v, make_int2(-(u + 1), 0));
+  stamp(cm, v, -(u + 1), h.z, h.w);
   for (int j = 0; j < h.y; ++j) claim_row(cm, st.nn[h.x + j], v);
   return 2;
 }
@@ -583,7 +582,7 @@ __device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a,
   int3 tv = rot_min(v, bb, ba), tw = rot_min(bw, ba, bb);
   st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
   st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
-  stamp(cm, v, make_int2(lo, hi));
+  stamp(cm, v, lo, hi, 0);
   claim_row(cm, v, v);
   claim_row(cm, bw, v);
   claim_row(cm, ba, v);
@@ -609,55 +608,88 @@ void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, in
 // sorted candidates that are live and hold x (the canonical order); NN(x) is
 // then the set of the other vertices of those elements.
 
-// the candidates of row x, written to dst[k * stride] for k < lim; returns
-// how many there are. Row entries and stamps are fetched eight at a time,
-// so a row costs a few dependent loads rather than one per neighbour.
+// the candidates of row x that are live and hold x (possibly repeated),
+// written to dst[k * stride] for k < lim; returns how many there are. Row
+// entries, operation records and elements are fetched eight at a time, so a
+// row costs a few dependent loads rather than one per neighbour; a collapse
+// record carries the member's NE row range. Filtering here keeps the
+// candidate count at the new row's size (a collapse target's old row and the
+// absorbed row share only the two elements that die).
+__device__ __forceinline__ bool keeps(const Store& st, int t, int x) {
+  Elem e = st.tri[t];
+  return e.w && holds(e, x);
+}
 __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm, int x, Hdr h, int* dst, int stride,
                                               int lim) {
   constexpr int B = 8;
   int n = 0;
+  auto put = [&](int t) {
+    if (n < lim) dst[n * stride] = t;
+    ++n;
+  };
   for (int k0 = 0; k0 < h.w; k0 += B) {
     int t[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) t[q] = k0 + q < h.w ? st.ne[h.z + k0 + q] : -1;
+    bool ok[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) ok[q] = t[q] >= 0 && keeps(st, t[q], x);
 #pragma unroll
     for (int q = 0; q < B; ++q)
-      if (t[q] >= 0) {
-        if (n < lim) dst[n * stride] = t[q];
-        ++n;
-      }
+      if (ok[q]) put(t[q]);
   }
+  // a neighbour w collapsed onto x hands over NE(w); the first such range is
+  // noted in the batched scan, any further ones (several members collapsing
+  // onto one vertex) are found by a second, plain scan
+  int az = 0, aw = 0, targets = 0;
   for (int j0 = 0; j0 < h.y; j0 += B) {
-    int w[B], ep[B];
+    int w[B];
+    int4 r[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
 #pragma unroll
-    for (int q = 0; q < B; ++q) ep[q] = w[q] >= 0 ? cm.oep[w[q]] : 0;
+    for (int q = 0; q < B; ++q) r[q] = w[q] >= 0 ? cm.ops[w[q]] : make_int4(0, 0, 0, 0);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      if (w[q] < 0 || ep[q] != cm.epoch) continue;
-      int2 r = cm.orec[w[q]];
-      if (r.x < 0) {
-        if (-r.x - 1 != x) continue;
-        Hdr hw = st.hdr[w[q]];
-        for (int k = 0; k < hw.w; ++k, ++n)
-          if (n < lim) dst[n * stride] = st.ne[hw.z + k];
+      if (w[q] < 0 || r[q].x != cm.epoch) continue;
+      if (r[q].y < 0) {
+        if (-r[q].y - 1 != x) continue;
+        if (targets++ == 0) {
+          az = r[q].z;
+          aw = r[q].w;
+        }
       } else {
-        if (n < lim) dst[n * stride] = r.x;
-        ++n;
-        if (n < lim) dst[n * stride] = r.y;
-        ++n;
+        if (keeps(st, r[q].y, x)) put(r[q].y);
+        if (keeps(st, r[q].z, x)) put(r[q].z);
       }
     }
   }
-  if (cm.oep[x] == cm.epoch) {
-    int2 r = cm.orec[x];
-    if (r.x >= 0) {
-      if (n < lim) dst[n * stride] = r.x;
-      ++n;
-      if (n < lim) dst[n * stride] = r.y;
-      ++n;
+  auto absorb = [&](int z, int cnt) {
+    for (int k0 = 0; k0 < cnt; k0 += B) {
+      int t[B];
+#pragma unroll
+      for (int p = 0; p < B; ++p) t[p] = k0 + p < cnt ? st.ne[z + k0 + p] : -1;
+      bool ok[B];
+#pragma unroll
+      for (int p = 0; p < B; ++p) ok[p] = t[p] >= 0 && keeps(st, t[p], x);
+#pragma unroll
+      for (int p = 0; p < B; ++p)
+        if (ok[p]) put(t[p]);
     }
+  };
+  if (targets > 0) absorb(az, aw);
+  if (targets > 1) {
+    int seen = 0;
+    for (int j = 0; j < h.y; ++j) {
+      int4 r = cm.ops[st.nn[h.x + j]];
+      if (r.x != cm.epoch || r.y >= 0 || -r.y - 1 != x) continue;
+      if (seen++ > 0) absorb(r.z, r.w);
+    }
+  }
+  int4 r = cm.ops[x];
+  if (r.x == cm.epoch && r.y >= 0) {
+    if (keeps(st, r.y, x)) put(r.y);
+    if (keeps(st, r.z, x)) put(r.z);
   }
   return n;
 }
@@ -737,7 +769,8 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
   st.cap[x] = make_int2(nn_cap, ne_cap);
 }
 
-constexpr int kRegRow = 32;  // rows up to this many candidates are rebuilt in registers
+constexpr int kRegSmall = 16;  // rows up to this many candidates: the small register path
+constexpr int kRegRow = 32;    // up to this many: the large register path
 
 // Register path for rows of at most N candidates, staged in this thread's
 // LDS column (x < 0: idle lane). Every lane of the wavefront makes this call
@@ -747,8 +780,9 @@ constexpr int kRegRow = 32;  // rows up to this many candidates are rebuilt in r
 // elements plus the one "previous" vertex that is no "next" (x on the
 // boundary). Returns true for a row whose elements do not form a disk or a
 // half-disk around x; such a row is left to the general path.
-template <int N>
-__device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, int x, int tot, int* col, int* ctr) {
+template <int N, int S>
+__device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, int x, Hdr h, int2 cp, int tot, int* col,
+                                            int* ctr) {
   bool act = x >= 0;
   int m = 0;
   {
@@ -756,11 +790,7 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       int t = INT_MAX;
-      if (act && k < tot) {
-        t = col[k * kBlock];
-        Elem e = st.tri[t];
-        if (!(e.w && holds(e, x))) t = INT_MAX;
-      }
+      if (act && k < tot) t = col[k * S];
       c[k] = t;
     }
     bitonic<N>(c);
@@ -768,36 +798,31 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       int t = c[k];
-      if (t != INT_MAX && t != prev) col[(m++) * kBlock] = t;
+      if (t != INT_MAX && t != prev) col[(m++) * S] = t;
       prev = t;
     }
   }
-  int nx[N], pv[N];
+  int nx[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     nx[k] = INT_MAX;
-    pv[k] = INT_MAX;
     if (k < m) {
-      Elem e = st.tri[col[k * kBlock]];
+      Elem e = st.tri[col[k * S]];
       int sl = slot_of(e, x);
       nx[k] = at(e, sl == 2 ? 0 : sl + 1);
-      pv[k] = at(e, sl == 0 ? 2 : sl - 1);
     }
   }
   bitonic<N>(nx);
-  bitonic<N>(pv);
-  // In a disk the sorted nexts and previouses agree; in a half-disk they
-  // differ by one element each, so shared values sit at most one place
-  // apart. A previous not found within one place is counted as extra (more
-  // than one extra: neither, and the general path decides).
+  // previous vertices that are no next (one for a boundary vertex; more:
+  // the elements form no disk or half-disk, and the general path decides)
   int extra = INT_MAX, nextra = 0;
+  for (int k = 0; k < m; ++k) {
+    Elem e = st.tri[col[k * S]];
+    int sl = slot_of(e, x);
+    int b = at(e, sl == 0 ? 2 : sl - 1);
+    bool found = false;
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    int b = pv[k];
-    if (b == INT_MAX) continue;
-    bool found = b == nx[k];
-    if (k > 0) found |= b == nx[k - 1];
-    if (k + 1 < N) found |= b == nx[k + 1];
+    for (int q = 0; q < N; ++q) found |= nx[q] == b;
     if (!found) {
       extra = b;
       ++nextra;
@@ -809,12 +834,6 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
 #pragma unroll
   for (int k = 0; k < N; ++k) nq += nx[k] != INT_MAX;
   // slots: in place when the row fits, else fresh pool space
-  Hdr h = make_int4(0, 0, 0, 0);
-  int2 cp = make_int2(0, 0);
-  if (reg) {
-    h = st.hdr[x];
-    cp = st.cap[x];
-  }
   int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
   int ne_need = reg && m > ne_cap ? grown_cap(m) : 0;
   int nn_need = reg && nq > nn_cap ? grown_cap(nq) : 0;
@@ -842,7 +861,7 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   uint64_t rel = __ballot(ne_need > 0), rel2 = __ballot(nn_need > 0);
   if (__lane_id() == 0 && (rel | rel2)) atomicAdd(stripe_ptr(ctr, S_RELOC), __popcll(rel) + __popcll(rel2));
   if (reg) {
-    for (int k = 0; k < lim_ne; ++k) st.ne[ne_off + k] = col[k * kBlock];
+    for (int k = 0; k < lim_ne; ++k) st.ne[ne_off + k] = col[k * S];
     int w = 0;
     bool put = nextra == 0;
 #pragma unroll
@@ -868,20 +887,38 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
 }
 
 // Rebuild row x (x < 0: idle lane); every lane of the wavefront makes this
-// call together. Rows of up to 16 candidates take the small register path,
-// up to kRegRow the large one (a wavefront runs a path only when one of its
-// lanes needs it), the rest the general path.
-__device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, int x, int* col, int* ctr) {
+// call together. Rows of up to N candidates (staged in this thread's LDS
+// column: N slots, stride S) take the register path. Rows with more are
+// queued in the block's LDS queue bq when one is given (for the larger
+// register path after the small rows), else they and rows that are no disk
+// take the general path.
+template <int N, int S>
+__device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, int x, int* col, int* ctr, int* bq,
+                                            int* bqn) {
   bool act = x >= 0;
   int tot = 0;
-  if (act) tot = row_candidates(st, cm, x, st.hdr[x], col, kBlock, kRegRow);
-  bool small = act && tot <= 16, large = act && tot > 16 && tot <= kRegRow;
-  bool general = act && tot > kRegRow;
-  if (__ballot(small)) general |= rebuild_reg<16>(st, cm, small ? x : -1, tot, col, ctr);
-  if (__ballot(large)) general |= rebuild_reg<kRegRow>(st, cm, large ? x : -1, tot, col, ctr);
+  Hdr h = make_int4(0, 0, 0, 0);
+  int2 cp = make_int2(0, 0);
+  if (act) {
+    h = st.hdr[x];
+    cp = st.cap[x];
+    tot = row_candidates(st, cm, x, h, col, S, N);
+  }
+  bool reg = act && tot <= N;
+  bool later = false;
+  if (bq && act && !reg) {
+    int slot = atomicAdd(bqn, 1);
+    if (slot < kBlock) {
+      bq[slot] = x;
+      later = true;
+    }
+  }
+  bool general = act && !reg && !later;
+  if (__ballot(reg)) general |= rebuild_reg<N, S>(st, cm, reg ? x : -1, h, cp, tot, col, ctr);
   if (general) rebuild_staged(st, cm, x, ctr);
-  if (act) cm.nxt[x] = 1;
-  uint64_t rows = __ballot(act);
+  bool done = act && !later;  // a queued row is counted when it is rebuilt
+  if (done) cm.nxt[x] = 1;
+  uint64_t rows = __ballot(done);
   if (__lane_id() == 0 && rows) {
     int* sp = stripe_ptr(ctr, 0);
     atomicAdd(sp + S_ROWS, __popcll(rows));
@@ -912,76 +949,70 @@ __device__ __forceinline__ int block_scan(int x, int& excl, int* wsum) {
 }
 
 // LDS of one commit block
+constexpr int kPairB = 8;  // neighbours per member taken per pair round
 struct CommitLds {
-  int col[kRegRow * kBlock];  // candidate staging, one column per thread
-  int pre[kBlock];            // pair prefix per member
-  int moff[kBlock];           // member's NN row offset
-  int mid[kBlock];            // member id
-  int q[2 * kBlock];          // queued rows
+  int col[kRegSmall * kBlock];  // candidate staging: kRegSmall per thread, or kRegRow for half the threads
+  int q[kPairB * kBlock];       // rows queued in a pair round
+  int bq[kBlock];               // rows of more than kRegSmall candidates
+  int bqn;
   int wsum[kBlock / kWave];
 };
+static_assert(kRegSmall * kBlock == kRegRow * (kBlock / 2), "the large path stages in the same LDS");
 
 // Rebuild the rows claimed by the committed members list[base .. base + cnt)
-// (cnt <= kBlock), with all kBlock threads of the block. The (member,
-// neighbour) pairs are spread over the threads; a pair whose member owns the
-// neighbour's row queues that row in LDS, and every time 256 rows are queued
-// all threads rebuild one each. Flip members' own rows follow after a
-// barrier, since the pairs read the members' rows.
-__device__ __forceinline__ void commit_chunk(const Store& st, const int* __restrict__ list, int base, int cnt, const Commit& cm,
-                             int flips, int* ctr, CommitLds& L) {
+// (cnt <= kBlock), with all kBlock threads of the block. Each thread takes
+// its member's neighbours kPairB at a time (row entries, then owner keys,
+// loaded side by side); the rows the member owns are queued in LDS in block
+// order and rebuilt 256 at a time. Flip members' own rows follow after the
+// last round, since the rounds read the members' rows.
+__device__ __forceinline__ void commit_chunk(const Store& st, const int* __restrict__ list, int base, int cnt,
+                                             const Commit& cm, int flips, int* ctr, CommitLds& L) {
   int tid = (int)threadIdx.x;
   int v = -1, deg = 0, off = 0;
-  bool flip_self = false;
+  bool com = false;
   if (tid < cnt) {
     v = list[base + tid];
-    if (cm.oep[v] == cm.epoch) {
+    com = cm.ops[v].x == cm.epoch;
+    if (com) {
       Hdr h = st.hdr[v];
       deg = h.y;
       off = h.x;
-      flip_self = flips != 0;
     }
   }
-  int excl;
-  int P = block_scan(deg, excl, L.wsum);
-  L.pre[tid] = excl;
-  L.moff[tid] = off;
-  L.mid[tid] = v;
-  __syncthreads();
+  uint64_t key = own_key(cm.epoch, v);
   int* mycol = L.col + tid;
-  int qn = 0;
-  for (int p0 = 0; p0 < P; p0 += kBlock) {
-    int p = p0 + tid;
-    int x = -1;
-    if (p < P) {
-      // the member s with pre[s] <= p < pre[s + 1]: the last s with pre[s] <= p
-      int lo = 0, hi = kBlock - 1;
-      while (lo < hi) {
-        int md = (lo + hi + 1) >> 1;
-        if (L.pre[md] <= p) lo = md;
-        else hi = md - 1;
-      }
-      int y = st.nn[L.moff[lo] + (p - L.pre[lo])];
-      if (cm.own[y] == own_key(cm.epoch, L.mid[lo])) x = y;
-    }
-    int rank;
-    int got = block_scan(x >= 0 ? 1 : 0, rank, L.wsum);
-    if (x >= 0) L.q[qn + rank] = x;
-    qn += got;
+  if (tid == 0) L.bqn = 0;
+  for (int j0 = 0; __syncthreads_or(j0 < deg); j0 += kPairB) {
+    int y[kPairB];
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q) y[q] = j0 + q < deg ? st.nn[off + j0 + q] : -1;
+    uint64_t k[kPairB];
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q) k[q] = y[q] >= 0 ? cm.own[y[q]] : 0ull;
+    int mine = 0;
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q) mine += (y[q] >= 0 && k[q] == key) ? 1 : 0;
+    int at;
+    int tot = block_scan(mine, at, L.wsum);
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q)
+      if (y[q] >= 0 && k[q] == key) L.q[at++] = y[q];
     __syncthreads();
-    if (qn >= kBlock) {
-      rebuild_row(st, cm, L.q[tid], mycol, ctr);
-      qn -= kBlock;
-      int keep = tid < qn ? L.q[kBlock + tid] : -1;
-      __syncthreads();
-      if (tid < qn) L.q[tid] = keep;
-      __syncthreads();
-    }
+    for (int r0 = 0; r0 < tot; r0 += kBlock)
+      rebuild_row<kRegSmall, kBlock>(st, cm, r0 + tid < tot ? L.q[r0 + tid] : -1, mycol, ctr, L.bq, &L.bqn);
   }
-  if (qn > 0) rebuild_row(st, cm, tid < qn ? L.q[tid] : -1, mycol, ctr);
   if (flips) {
     __syncthreads();
-    int x = (flip_self && cm.own[v] == own_key(cm.epoch, v)) ? v : -1;
-    rebuild_row(st, cm, x, mycol, ctr);
+    int x = (com && cm.own[v] == key) ? v : -1;
+    rebuild_row<kRegSmall, kBlock>(st, cm, x, mycol, ctr, L.bq, &L.bqn);
+  }
+  // rows of more than kRegSmall candidates, half the block at a time
+  __syncthreads();
+  int nbig = min(L.bqn, kBlock);
+  constexpr int H = kBlock / 2;
+  for (int b0 = 0; b0 < nbig; b0 += H) {
+    int x = (tid < H && b0 + tid < nbig) ? L.bq[b0 + tid] : -1;
+    rebuild_row<kRegRow, H>(st, cm, x, L.col + (tid & (H - 1)), ctr, nullptr, nullptr);
   }
   __syncthreads();  // the LDS is reused by the next chunk
 }
@@ -1001,6 +1032,7 @@ void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips,
   int nb = (n + mpb - 1) / mpb;
   k_commit<<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, flips ? 1 : 0, ctr);
 }
+
 
 // ---- smoothing (Sec. 2.4.4) ---------------------------------------------------------------------
 __global__ void k_elem_metric(Store st, Met* __restrict__ out) {
@@ -1514,7 +1546,7 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
   if (ownn) claim_row(cm, w, v);
   if (g.j == 0) {
     st.valive[v] = 0;
-    stamp(cm, v, make_int2(-(u + 1), 0));
+    stamp(cm, v, -(u + 1), h.z, h.w);
   }
   return 2;
 }
