@@ -91,6 +91,19 @@ def roofline(name, dom):
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"]}
 
 
+def kernel_roofline(prof):
+    """Achieved algorithmic bandwidth of every timed kernel over one profiled step."""
+    out = {}
+    for name, p in prof.items():
+        if p["ms"] <= 0 or p["units"] <= 0:
+            continue
+        gbs = BYTES_PER_UNIT[name] * p["units"] / (p["ms"] * 1e-3) / 1e9
+        out[name] = {"ms": round(p["ms"], 3), "launches": p["launches"], "units": p["units"],
+                     "bytes_per_unit": BYTES_PER_UNIT[name], "achieved": round(gbs, 2),
+                     "frac": round(gbs / HBM_PEAK_GBS, 5)}
+    return out
+
+
 def topo_hash(export):
     h = hashlib.sha256()
     h.update(export["tri"][export["talive"]].tobytes())
@@ -144,6 +157,46 @@ def batch_bench(count, torch, inputs, pmesh, sweeps=2, seed=2):
             "ops_plain": ops_p, "batched_ops_per_s": ops_b / (t1 - t0), "results_equal": equal}
 
 
+def config4_run(n=4097, sweeps=2, seed=3):
+    """4097^2 grid, two-layer metric, jitter from seed 3: create, then two
+    adaptation sweeps (coarsen -> refine -> swap -> gradient smoothing); the
+    handle's peak device memory against the 288 GB of one MI355X."""
+    import torch
+    from paper_1505_04694_amd import inputs, pmesh
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"building the {n}x{n} input")
+    mi = inputs.config4(n)
+    xy = torch.from_numpy(mi.xy).to(dev)
+    tri = torch.from_numpy(mi.tri).to(dev)
+    met = torch.from_numpy(mi.metric).to(dev)
+    tags = torch.from_numpy(mi.tags).to(dev)
+    torch.cuda.synchronize()
+    log(f"inputs ready: {mi.V} vertices, {mi.T} triangles")
+    t0 = time.perf_counter()
+    m = pmesh.Mesh(xy, tri, met, tags, seed=seed)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ops, phases = 0, []
+    for s in range(sweeps):
+        tr = m.sweep(s, smooth_kind=1)
+        ops += sum(st["coloured"] + st["evaluated"] + st["edges"] for st in tr.values())
+        phases.append(tr)
+        log(f"sweep {s} done")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cur, peak = m.memory()
+    V, T = m.sizes()
+    q = m.quality()
+    m.close()
+    print(json.dumps({"workload": f"{n}x{n} grid, interior jitter 0.2h (seed 3), two-layer metric, priority seed 3; "
+                                  f"{sweeps} sweeps coarsen->refine->swap->gradient smoothing",
+                      "vertices": mi.V, "triangles": mi.T, "create_ms": (t1 - t0) * 1e3,
+                      "sweeps_ms": (t2 - t1) * 1e3, "ops": ops, "ops_per_s": ops / (t2 - t1),
+                      "peak_device_bytes": peak, "peak_fraction_of_288GB": peak / 288e9,
+                      "final": {"vertices": V, "triangles": T, "quality": q}, "phases": phases}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,10 +208,15 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a device copy of 1 GiB (a kernel of known traffic for counter scaling)")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--config4", action="store_true",
+                    help="instead: the 4097x4097 workload, two sweeps with gradient smoothing, peak device memory")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path is single-device", file=sys.stderr)
         sys.exit(2)
+    if a.config4:
+        config4_run()
+        return
 
     import numpy as np
     import torch
@@ -239,6 +297,7 @@ def main():
                    "ops_per_step": ops},
         "roofline": roofline(dominant, dom),
         "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in prof_all.items()},
+        "kernel_roofline": kernel_roofline(prof_all),
         "phases": {name: st for name, st in traces[-1] if isinstance(st, dict)},
         "topology_hash": gpu_hash,
     }

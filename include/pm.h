@@ -118,6 +118,11 @@ pm_status pm_mesh_destroy(pm_mesh* m);
  * with a stable renumbering); otherwise dead slots may be included. */
 pm_status pm_mesh_sizes(const pm_mesh* m, int64_t* V, int64_t* T);
 
+/* Device memory held by the handle: now, and the most at any time since it
+ * was created (store, adjacency pools and phase scratch; the inputs and
+ * outputs the caller owns are not counted). Either output may be NULL. */
+pm_status pm_mesh_memory(const pm_mesh* m, int64_t* current_bytes, int64_t* peak_bytes);
+
 /* Copies the live mesh out (V x 2, T x 3, V x 3, V) in slot order, which is
  * the live order after pm_coarsen. Any output may be NULL. mem_kind says
  * whether the outputs are host or device pointers; they must hold the sizes

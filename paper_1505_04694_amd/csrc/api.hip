@@ -56,6 +56,8 @@ struct pm_mesh {
   DBuf<Met> emet;   // smoothing: per-element mean tensors
   DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
   DBuf<int> stage;       // commit: fallback staging
+  DBuf<int> touch, seen; // small rounds: rows rebuilt, selection stamps
+  int sel_mark = 0;      // selection stamp, one per small round
   DBuf<int4> ops;        // commit: operation records
   DBuf<uint64_t> own;    // commit: row owner keys
   int epoch = 0;         // commit epoch, one per class
@@ -392,6 +394,8 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->rw, V, true));
   TRY(ensure(m, m->nxt, V, true));
   TRY(ensure(m, m->ops, V, true));
+  TRY(ensure(m, m->touch, std::max(V, 65536)));
+  TRY(ensure(m, m->seen, V, true));
   TRY(ensure(m, m->own, V, true));
   TRY(ensure(m, m->sflag, V));
   TRY(ensure(m, m->spos, V));
@@ -407,6 +411,8 @@ Commit commit_of(pm_mesh* m) {
   Commit c;
   c.epoch = m->epoch;
   c.ops = m->ops.p;
+  c.touched = nullptr;
+  c.touched_cap = (int)std::min<size_t>(m->touch.n, INT32_MAX);
   c.own = m->own.p;
   c.stage = m->stage.p;
   c.stage_cap = (int64_t)m->stage.n;
@@ -632,6 +638,10 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
     Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->rw.p};
     Classes cl;
     TRY(colour_list(m, m->listA.p, nA, rd, cl));
+    // a small round (coloured by one block) records the rows it rebuilds, so
+    // the next round's list comes from its own lists, not from every slot
+    bool small = nA <= kSmallColour && !(m->variant & 4);
+    cm.touched = small ? m->touch.p : nullptr;
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
@@ -657,11 +667,23 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
       });
     }
     clear_round(m->listA.p, nA, m->rw.p, m->s);
-    set_int(m->ctr + C_LIST_B, 0, m->s);
-    timed(m, PM_K_SELECT, m->st.V,
-          [&] { select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
-                          m->spos.p, m->spart.p, m->s); });
-    TRY(read_ctr(m, 0, C_EVAL));
+    bool listed = false;
+    if (small) {
+      timed(m, PM_K_SELECT, nA, [&] {
+        select_small(m->st, mode, o->L_low2, m->listA.p, nA, m->touch.p, cm.touched_cap, m->nxt.p, m->seen.p,
+                     ++m->sel_mark, m->listB.p, m->ctr, m->s);
+      });
+      TRY(read_ctr(m, 0, C_EVAL));
+      listed = m->hctr[C_LIST_B] >= 0;
+    }
+    if (!listed) {
+      set_int(m->ctr + C_LIST_B, 0, m->s);
+      timed(m, PM_K_SELECT, m->st.V, [&] {
+        select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
+                        m->spos.p, m->spart.p, m->s);
+      });
+      TRY(read_ctr(m, 0, C_EVAL));
+    }
     TRY(check_err(m, true));
     nA = m->hctr[C_LIST_B];
     std::swap(m->listA, m->listB);
@@ -724,7 +746,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->ranges, 1);
   dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
-                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->stage, &m->rtmp,
+                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->stage, &m->touch, &m->seen, &m->rtmp,
                      &m->sflag, &m->spos,
                      &m->ctab, &m->ctabs, &m->spart};
   for (auto* b : ib) dfree(m, b->p, b->n);
@@ -807,6 +829,13 @@ pm_status pm_mesh_sizes(const pm_mesh* m, int64_t* V, int64_t* T) {
   if (!m) return PM_E_ARG;
   if (V) *V = m->st.V;
   if (T) *T = m->st.T;
+  return PM_OK;
+}
+
+pm_status pm_mesh_memory(const pm_mesh* m, int64_t* current_bytes, int64_t* peak_bytes) {
+  if (!m) return PM_E_ARG;
+  if (current_bytes) *current_bytes = m->cur_bytes;
+  if (peak_bytes) *peak_bytes = m->peak_bytes;
   return PM_OK;
 }
 

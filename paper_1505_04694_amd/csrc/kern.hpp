@@ -16,6 +16,7 @@ enum Ctr {
   C_ERR = 2,        // error bits (see Err)
   C_LIST_A = 3,     // generic list counters
   C_LIST_B = 4,
+  C_TOUCH = 5,      // rows rebuilt in the current round (small rounds)
   C_STAGE = 7,      // fallback staging space handed out by the commit
   C_EVAL = 8,       // 8..13: stats, summed from the stripes (same order as the S_ slots)
   C_DEFER = 9,
@@ -182,6 +183,8 @@ struct Commit {
   uint64_t* own;   // V: row owner key, maximised: (epoch << 32) | ~member
   int* stage;      // staging for rows past the register paths
   int64_t stage_cap;
+  int* touched;    // small rounds: every row rebuilt, for the list-based selection (else null)
+  int touched_cap;
   uint8_t* nxt;    // next-round flags
 };
 __device__ __forceinline__ uint64_t own_key(int epoch, int v) {
@@ -212,6 +215,12 @@ void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first
 void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
                  hipStream_t s);
 void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s);
+// next-round list of a small round from its own lists: the members A (the
+// deferred ones carry the next-round flag) and the rows rebuilt, each vertex
+// once (stamp array `seen`, marker `mark`); writes the count to C_LIST_B, or
+// -1 when the rebuilt rows overflowed their list (then select over all slots)
+void select_small(const Store& st, int mode, double L_low2, const int* A, int nA, const int* touched, int cap,
+                  uint8_t* nxt, int* seen, int mark, int* out, int* ctr, hipStream_t s);
 // lists up to kSmallColour entries: colouring and class lists in one block;
 // writes class sizes, offsets and count like class_lists, iterations to C_TOTAL
 constexpr int kSmallColour = 8192;

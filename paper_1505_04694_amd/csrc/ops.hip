@@ -360,6 +360,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     }
     ctr[C_NCOL] = ncol;
     ctr[C_JP] = 0;
+    ctr[C_TOUCH] = 0;
     ctr[C_TOTAL] = it;
     atomicAdd(ctr + C_STRIPE + S_PJP, visited);
   }
@@ -372,6 +373,33 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
 void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* out, int* ctr,
                   hipStream_t s) {
   k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, rd, W0, W1, out, ctr);
+}
+
+__global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mode, double L_low2,
+                                                               const int* __restrict__ A, int nA,
+                                                               const int* __restrict__ touched, int cap,
+                                                               uint8_t* __restrict__ nxt, int* __restrict__ seen,
+                                                               int mark, int* __restrict__ out, int* ctr) {
+  __shared__ int cnt;
+  int nt = ctr[C_TOUCH];
+  if (nt > cap) {
+    if (threadIdx.x == 0) ctr[C_LIST_B] = -1;
+    return;
+  }
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int i = (int)threadIdx.x; i < nA + nt; i += kSmallThreads) {
+    int x = i < nA ? A[i] : touched[i - nA];
+    if (!nxt[x] || atomicMax(&seen[x], mark) >= mark) continue;
+    nxt[x] = 0;
+    if (want(st, x, mode, L_low2, nullptr)) out[atomicAdd(&cnt, 1)] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ctr[C_LIST_B] = cnt;
+}
+void select_small(const Store& st, int mode, double L_low2, const int* A, int nA, const int* touched, int cap,
+                  uint8_t* nxt, int* seen, int mark, int* out, int* ctr, hipStream_t s) {
+  k_select_small<<<1, kSmallThreads, 0, s>>>(st, mode, L_low2, A, nA, touched, cap, nxt, seen, mark, out, ctr);
 }
 
 __global__ void k_colour_out(int V, const uint64_t* __restrict__ rw, int* __restrict__ out) {
@@ -918,6 +946,10 @@ __device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, i
   if (general) rebuild_staged(st, cm, x, ctr);
   bool done = act && !later;  // a queued row is counted when it is rebuilt
   if (done) cm.nxt[x] = 1;
+  if (cm.touched) {
+    int slot = wave_add_full(&ctr[C_TOUCH], done ? 1 : 0);
+    if (done && slot < cm.touched_cap) cm.touched[slot] = x;
+  }
   uint64_t rows = __ballot(done);
   if (__lane_id() == 0 && rows) {
     int* sp = stripe_ptr(ctr, 0);

@@ -23,7 +23,7 @@ STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_D
 STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colours", "edges", "converged",
               "new_vertices", "new_elements", "records", "relocated", "jp_iterations"]
 
-EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_export",
+EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_memory", "pm_mesh_export",
            "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
            "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read",
            "pm_batch_create", "pm_batch_count", "pm_batch_sizes", "pm_batch_export", "pm_batch_quality"]
@@ -77,6 +77,8 @@ def lib():
         L.pm_mesh_destroy.argtypes = [P]
         L.pm_mesh_sizes.restype = S
         L.pm_mesh_sizes.argtypes = [P, P, P]
+        L.pm_mesh_memory.restype = S
+        L.pm_mesh_memory.argtypes = [P, P, P]
         L.pm_mesh_export.restype = S
         L.pm_mesh_export.argtypes = [P, P, P, P, P, P, P, C.c_int32]
         L.pm_mesh_rows.restype = S
@@ -200,6 +202,13 @@ def pm_mesh_sizes(h):
     V, T = C.c_int64(), C.c_int64()
     _check(h, lib().pm_mesh_sizes(h, C.byref(V), C.byref(T)))
     return V.value, T.value
+
+
+def pm_mesh_memory(h):
+    """(current, peak) device bytes held by the handle."""
+    cur, peak = C.c_int64(), C.c_int64()
+    _check(h, lib().pm_mesh_memory(h, C.byref(cur), C.byref(peak)))
+    return cur.value, peak.value
 
 
 def pm_mesh_export(h):
@@ -339,6 +348,9 @@ class Mesh:
 
     def sizes(self):
         return pm_mesh_sizes(self.h)
+
+    def memory(self):
+        return pm_mesh_memory(self.h)
 
     def export(self):
         return pm_mesh_export(self.h)
