@@ -147,6 +147,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
 // every write after it, so the compaction can run in place. One atomic per
 // chunk (on a stripe) counts what is left.
 constexpr int kJpItems = kJpChunk / kBlock;
+constexpr int kJpLocal = 3;  // passes per launch over a chunk that makes progress
 __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restrict__ A, int n, int* W,
                                                   int* __restrict__ cnt, int first, Round rd, int* ctr, int slot,
                                                   int next_slot) {
@@ -166,8 +167,32 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     vv[r] = i < m ? in[i] : -1;
   }
   bool keep[kJpItems];
+  int tries = 0;  // this thread's vertex visits, for the profile's unit count
+  bool moved = false;
 #pragma unroll
-  for (int r = 0; r < kJpItems; ++r) keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr);
+  for (int r = 0; r < kJpItems; ++r) {
+    keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr);
+    moved |= vv[r] >= 0 && !keep[r];
+    tries += vv[r] >= 0 ? 1 : 0;
+  }
+  // more passes over the chunk's waiting vertices while the chunk makes
+  // progress: chains of neighbours inside the chunk resolve in one launch
+  for (int pass = 1; pass < kJpLocal; ++pass) {
+    bool waiting = false;
+#pragma unroll
+    for (int r = 0; r < kJpItems; ++r) waiting |= keep[r];
+    if (!__syncthreads_or(moved && waiting)) break;
+    moved = false;
+#pragma unroll
+    for (int r = 0; r < kJpItems; ++r)
+      if (keep[r]) {
+        ++tries;
+        keep[r] = !jp_try(st, vv[r], rd, ctr);
+        moved |= !keep[r];
+      }
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) tries += __shfl_xor(tries, d);
   int lane = __lane_id(), wv = (int)threadIdx.x / kWave;
   uint64_t bal[kJpItems];
 #pragma unroll
@@ -198,8 +223,8 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     cnt[kb] = base;
     int* sp = ctr + C_STRIPE + (kb & (kStripes - 1)) * kStripeW;
     if (base) atomicAdd(sp + slot, base);
-    atomicAdd(sp + S_PJP, m);
   }
+  if (lane == 0 && tries) atomicAdd(stripe_ptr(ctr, S_PJP), tries);
 }
 
 void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,

@@ -226,12 +226,13 @@ __device__ void isort(int* a, int n) {
 // means a directed edge is used twice: inconsistent orientation or a
 // non-manifold edge; more than one unmatched previous is a pinched vertex.
 // Rows of up to 16 elements are finished in registers: sorting networks,
-// and every previous looked up among all nexts.
+// and every previous looked up among all nexts (8-wide when a wavefront's
+// rows all fit, 16-wide otherwise).
 constexpr int kFinishReg = 16;
+template <int N>
 __device__ __forceinline__ void row_finish_reg(const Elem* __restrict__ tri, Hdr* __restrict__ hdr, int ncap,
                                                int* __restrict__ nn, int* __restrict__ ne, int v, Hdr h,
                                                int* ctr) {
-  constexpr int N = kFinishReg;
   int c = h.w;
   int r[N];
 #pragma unroll
@@ -297,7 +298,8 @@ __global__ void k_row_finish(const Elem* __restrict__ tri, Hdr* __restrict__ hdr
     int c = h.w;
     if (c == 0) continue;
     if (c <= kFinishReg) {
-      row_finish_reg(tri, hdr, cap[v].x, nn, ne, v, h, ctr);
+      if (__all(c <= 8)) row_finish_reg<8>(tri, hdr, cap[v].x, nn, ne, v, h, ctr);
+      else row_finish_reg<kFinishReg>(tri, hdr, cap[v].x, nn, ne, v, h, ctr);
       continue;
     }
     int* row = ne + h.z;
