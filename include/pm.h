@@ -73,12 +73,13 @@ typedef struct {
   int32_t smooth_sweeps;  /* coloured sweeps of pm_smooth                       */
   double slack;           /* adjacency row capacity factor (>= 1)               */
   int32_t wg_size;        /* work-group size, 0 = library default               */
-  int32_t variant;        /* kernel shapes: bit 0 = collapse, bit 1 = smoothing run
-                             on groups of 8 lanes per vertex instead of one thread;
-                             0 = automatic (groups for small collapse classes,
-                             one-block kernels for small lists and classes),
-                             bit 2 = one thread per vertex and the multi-block
-                             kernels throughout; results are identical          */
+  int32_t variant;        /* kernel shapes, results identical for all: 0 =
+                             defaults (collapse on 16 lanes per vertex,
+                             smoothing on 8, one-block kernels for small lists
+                             and classes); bit 2 = one thread per vertex and
+                             the multi-block kernels throughout; bit 3 =
+                             collapse on 8 lanes; bits 0, 1 = the lane-group
+                             defaults, kept for older callers                   */
 } pm_options;
 
 /* Per-phase counters, all integers:

@@ -602,18 +602,21 @@ bool bad_opts(const pm_options* o) {
   return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
          o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
          (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0) ||
-         o->variant < 0 || o->variant > 7;
+         o->variant < 0 || o->variant > 15;
 }
 
 // rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1)
-// Small classes are latency bound: one thread per member walks its rows and
-// elements one dependent load after another. Groups of 8 lanes per member
-// take those loads side by side, so below this size they are used.
-constexpr int kGroupBelow = 16384;
+// Collapse runs on groups of lanes per member by default: each lane loads
+// one neighbour and one element of the member's 1-ring side by side and
+// keeps it in registers, so a member costs a few dependent loads and no
+// re-reads (one thread per member walks the ring serially and, with tens of
+// thousands of members in flight per XCD, re-fetches it from HBM). 16 lanes
+// by default, 8 on request; one thread per member on request.
 int collapse_shape(const pm_mesh* m, int n) {
-  if (m->variant & 1) return 1;
+  (void)n;
   if (m->variant & 4) return 0;
-  return n < kGroupBelow ? 1 : 0;
+  if (m->variant & 8) return 2;
+  return 1;
 }
 
 pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
@@ -968,7 +971,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
       timed(m, PM_K_SMOOTH, cl.size[c], [&] {
-        smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant >> 1) & 1, m->s);
+        smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant & 4) ? 0 : 1, m->s);
       });
   m->st.emet = nullptr;
   clear_round(m->listA.p, n, m->rw.p, m->s);

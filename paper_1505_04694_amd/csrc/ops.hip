@@ -569,13 +569,16 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
   count_status(status, ctr);
 }
+template <int G>
 __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr);
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
                     hipStream_t s) {
   if (n <= 0) return;
   if (variant == 1)
-    k_collapse_g<<<(int)(((int64_t)n * kGC + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    k_collapse_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+  else if (variant == 2)
+    k_collapse_g<8><<<(int)(((int64_t)n * 8 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
   else
     k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
@@ -1608,24 +1611,27 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
   return 2;
 }
 
+template <int G>
 __global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
-  Grp g = grp_of<kGC>();
+  Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
-  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kGC);
+  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G);
   int status = -1;
   if (gid < n) {
     int v = list[gid];
     Hdr h = st.hdr[v];
-    if (h.y > kGC || h.w > kGC) {
+    if (h.y > G || h.w > G) {
       if (g.j == 0) status = collapse_one(st, v, a, cm, ctr);
     } else {
-      int r = collapse_group<kGC>(st, v, h, a, cm, ctr, g);
+      int r = collapse_group<G>(st, v, h, a, cm, ctr, g);
       if (g.j == 0) status = r;
     }
   }
   count_status(status, ctr);
 }
+template __global__ void k_collapse_g<8>(Store, const int*, int, OpArgs, Commit, int*);
+template __global__ void k_collapse_g<16>(Store, const int*, int, OpArgs, Commit, int*);
 
 // A small class in one block: the operation (collapse on groups of kGC lanes,
 // or flips one per thread), a block barrier, then the commit of the same
