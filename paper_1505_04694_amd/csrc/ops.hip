@@ -102,18 +102,28 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // neighbour is being written are either unset (not ready yet) or final, so
 // the result does not depend on timing. Returns false while v must wait.
 __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
+  constexpr int B = 8;  // neighbours fetched side by side
   uint64_t rv = rw_get(rd.rw, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
   bool big = false;
-  for (int j = 0; j < h.y; ++j) {
-    int w = st.nn[h.x + j];
-    uint64_t x = rw_get(rd.rw, w);
-    if (!(x & kRwAct) || !rw_beats(x, w, rv, v)) continue;
-    int c = (int)(x & 0xFF);
-    if (c == 0xFF) return false;
-    if (c < 64) used |= 1ull << c;
-    else big = true;
+  for (int j0 = 0; j0 < h.y; j0 += B) {
+    int w[B];
+    uint64_t x[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_get(rd.rw, w[q]) : 0ull;
+    bool wait = false;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (!(x[q] & kRwAct) || !rw_beats(x[q], w[q], rv, v)) continue;
+      int c = (int)(x[q] & 0xFF);
+      if (c == 0xFF) wait = true;
+      else if (c < 64) used |= 1ull << c;
+      else big = true;
+    }
+    if (wait) return false;
   }
   int c;
   if (~used != 0ull && !big) {
