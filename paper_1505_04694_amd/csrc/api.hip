@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -70,7 +71,6 @@ struct pm_mesh {
   DBuf<int> rtmp;         // per-mesh scratch (sums, new bases)
   int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing, bit 2: no automatic shapes
   int64_t peak_bytes = 0, cur_bytes = 0;
-  bool pool = false;  // device memory from the stream-ordered pool
   int jp_last = 8;    // JP iterations the last colouring took
 };
 
@@ -97,27 +97,84 @@ pm_status fail(pm_mesh* m, pm_status st, const std::string& msg) {
     if (r_ != PM_OK) return r_;     \
   } while (0)
 
-// Device memory comes from the device's stream-ordered pool where there is
-// one: blocks freed by a phase or a handle stay in the pool (up to a release
-// threshold) for the next request, instead of a driver call each time.
-void init_pool(pm_mesh* m) {
-  int dev = 0, sup = 0;
-  hipMemPool_t p;
-  m->pool = hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&sup, hipDeviceAttributeMemoryPoolsSupported, dev) == hipSuccess && sup &&
-            hipDeviceGetDefaultMemPool(&p, dev) == hipSuccess;
-  if (m->pool) {
-    uint64_t keep = 16ull << 30;
-    (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+// Device blocks are recycled through a process-wide cache keyed by device,
+// stream and size. A block freed on a stream is handed out again only on the
+// same stream, whose order makes the reuse safe without a wait, so handles
+// and phase scratch that come and go skip the driver's allocation and free
+// (each a synchronising call of tens of microseconds or more). Blocks up to
+// twice the request are reused; past kCacheMax cached bytes a freed block is
+// returned to the driver, and a failed allocation first empties the cache.
+struct CacheKey {
+  int dev;
+  uintptr_t stream;
+  size_t bytes;
+  bool operator<(const CacheKey& o) const {
+    if (dev != o.dev) return dev < o.dev;
+    if (stream != o.stream) return stream < o.stream;
+    return bytes < o.bytes;
   }
-  (void)hipGetLastError();
+};
+constexpr size_t kCacheMax = 32ull << 30;
+std::mutex g_cache_mu;
+std::multimap<CacheKey, void*> g_cache_free;
+std::map<void*, CacheKey> g_cache_live;
+size_t g_cache_bytes = 0;
+
+void cache_drop_all() {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  for (auto& kv : g_cache_free) (void)hipFree(kv.second);
+  g_cache_free.clear();
+  g_cache_bytes = 0;
+}
+
+hipError_t cache_get(hipStream_t s, void** p, size_t bytes) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  CacheKey want{dev, (uintptr_t)s, bytes};
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache_free.lower_bound(want);
+    if (it != g_cache_free.end() && it->first.dev == dev && it->first.stream == want.stream &&
+        it->first.bytes <= 2 * bytes) {
+      *p = it->second;
+      g_cache_bytes -= it->first.bytes;
+      g_cache_live[*p] = it->first;
+      g_cache_free.erase(it);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cache_drop_all();
+    e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return e;
+  }
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache_live[*p] = want;
+  return hipSuccess;
+}
+
+void cache_put(void* p) {
+  std::unique_lock<std::mutex> lk(g_cache_mu);
+  auto it = g_cache_live.find(p);
+  if (it == g_cache_live.end()) return;
+  CacheKey k = it->second;
+  g_cache_live.erase(it);
+  if (g_cache_bytes + k.bytes > kCacheMax) {
+    lk.unlock();
+    (void)hipFree(p);
+    return;
+  }
+  g_cache_free.insert({k, p});
+  g_cache_bytes += k.bytes;
 }
 
 template <class T>
 pm_status dalloc(pm_mesh* m, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  hipError_t e = m->pool ? hipMallocAsync((void**)p, n * sizeof(T), m->s) : hipMalloc((void**)p, n * sizeof(T));
+  hipError_t e = cache_get(m->s, (void**)p, n * sizeof(T));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
@@ -159,7 +216,7 @@ void pinned_put(pm_mesh* m) {
 template <class T>
 void dfree(pm_mesh* m, T*& p, size_t n) {
   if (p) {
-    (void)(m->pool ? hipFreeAsync(p, m->s) : hipFree(p));
+    cache_put(p);
     m->cur_bytes -= (int64_t)(std::max<size_t>(n, 1) * sizeof(T));
   }
   p = nullptr;
@@ -783,7 +840,6 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
-  init_pool(m);
   g_create_err.clear();
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
@@ -1178,7 +1234,6 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
-  init_pool(m);
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
     pm_mesh_destroy(m);
