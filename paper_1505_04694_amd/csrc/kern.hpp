@@ -208,7 +208,7 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s);
 // One JP iteration over a chunked list: chunk k of kJpChunk slots holds cnt[k]
 // vertices at W[k * kJpChunk ...]; the first iteration reads the n entries of
 // A instead. Waiting vertices are compacted in place, in order, per chunk.
-constexpr int kJpChunk = 1024;
+constexpr int kJpChunk = 512;
 void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,
               hipStream_t s);
 // stable class lists; tab/tabscan: 256 * ceil(n/256) ints each
