@@ -709,24 +709,24 @@ __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm,
   // onto one vertex) are found by a second, plain scan
   int az = 0, aw = 0, targets = 0;
   for (int j0 = 0; j0 < h.y; j0 += B) {
-    int w[B];
-    int4 r[B];
+    int w[B], ep[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
 #pragma unroll
-    for (int q = 0; q < B; ++q) r[q] = w[q] >= 0 ? cm.ops[w[q]] : make_int4(0, 0, 0, 0);
+    for (int q = 0; q < B; ++q) ep[q] = w[q] >= 0 ? cm.ops[w[q]].x : 0;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      if (w[q] < 0 || r[q].x != cm.epoch) continue;
-      if (r[q].y < 0) {
-        if (-r[q].y - 1 != x) continue;
+      if (w[q] < 0 || ep[q] != cm.epoch) continue;
+      int4 r = cm.ops[w[q]];  // the line the stamp came from
+      if (r.y < 0) {
+        if (-r.y - 1 != x) continue;
         if (targets++ == 0) {
-          az = r[q].z;
-          aw = r[q].w;
+          az = r.z;
+          aw = r.w;
         }
       } else {
-        if (keeps(st, r[q].y, x)) put(r[q].y);
-        if (keeps(st, r[q].z, x)) put(r[q].z);
+        if (keeps(st, r.y, x)) put(r.y);
+        if (keeps(st, r.z, x)) put(r.z);
       }
     }
   }
@@ -1089,7 +1089,7 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
 
 // One block per mpb class members (256, or fewer for small classes, so that
 // more blocks share the latency-bound work), in XCD-aware block order.
-__global__ void __launch_bounds__(256) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
+__global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
                                                 int flips, int* ctr) {
   __shared__ CommitLds L;
   int base = xcd_block() * mpb;
