@@ -580,7 +580,7 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
   count_status(status, ctr);
 }
 template <int G>
-__global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
+__global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr);
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
                     hipStream_t s) {
@@ -1304,7 +1304,7 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
   if (n <= 0) return;
   if (variant == 1)
@@ -1479,7 +1479,7 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   return true;
 }
 
-__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
   Grp g = grp();
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
@@ -1622,7 +1622,7 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
 }
 
 template <int G>
-__global__ void __launch_bounds__(256) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
+__global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
   Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
