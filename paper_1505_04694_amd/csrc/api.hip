@@ -58,6 +58,7 @@ struct pm_mesh {
   DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
   DBuf<int> stage;       // commit: fallback staging
   DBuf<int> touch, seen; // small rounds: rows rebuilt, selection stamps
+  DBuf<int> jpB;         // JP: the neighbour each waiting vertex waits for
   int sel_mark = 0;      // selection stamp, one per small round
   DBuf<int4> ops;        // commit: operation records
   DBuf<uint64_t> own;    // commit: row owner keys
@@ -445,6 +446,7 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->listA, V));
   TRY(ensure(m, m->listB, V));
   TRY(ensure(m, m->jpU0, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
+  TRY(ensure(m, m->jpB, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
   // chunk counts of the chunked JP, or the second waiting list of the small colouring
   TRY(ensure(m, m->jpU1, std::max((size_t)V / kJpChunk + 1, (size_t)std::min(V, kSmallColour))));
   TRY(ensure(m, m->cls, V));
@@ -510,7 +512,8 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
     // most colourings need one read-back
     int batch = it == 0 ? std::min(std::max(m->jp_last, kJpBatch), 64) : kJpBatch;
     for (int b = 0; b < batch; ++b, ++it)
-      timed(m, PM_K_JP, 0, [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
+      timed(m, PM_K_JP, 0,
+            [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpB.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
     stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
     TRY(read_ctr(m, C_JP, 1));
     int left = m->hctr[C_JP];
@@ -806,7 +809,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->ranges, 1);
   dfree(m, m->mdone, 1);
   DBuf<int>* ib[] = {&m->listA, &m->listB, &m->jpU0, &m->jpU1, &m->cls, &m->vt0, &m->vt1, &m->vt2, &m->vt3,
-                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->stage, &m->touch, &m->seen, &m->rtmp,
+                     &m->vt4, &m->tt0, &m->tt1, &m->tt2, &m->partial, &m->mid, &m->stage, &m->touch, &m->seen, &m->jpB, &m->rtmp,
                      &m->sflag, &m->spos,
                      &m->ctab, &m->ctabs, &m->spart};
   for (auto* b : ib) dfree(m, b->p, b->n);

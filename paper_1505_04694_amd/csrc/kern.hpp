@@ -209,8 +209,9 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s);
 // vertices at W[k * kJpChunk ...]; the first iteration reads the n entries of
 // A instead. Waiting vertices are compacted in place, in order, per chunk.
 constexpr int kJpChunk = 512;
-void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,
-              hipStream_t s);
+// WB holds, beside each waiting vertex, the neighbour that blocked it
+void jp_chunk(const Store& st, const int* A, int n, int* W, int* WB, int* cnt, bool first, Round rd, int* ctr,
+              int it, hipStream_t s);
 // stable class lists; tab/tabscan: 256 * ceil(n/256) ints each
 void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
                  hipStream_t s);

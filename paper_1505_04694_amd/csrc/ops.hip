@@ -101,8 +101,12 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // it then takes the smallest colour none of them has. Colours read while a
 // neighbour is being written are either unset (not ready yet) or final, so
 // the result does not depend on timing. Returns false while v must wait.
-__device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
+// blocker: in, a neighbour that kept v waiting before (or -1); out, the
+// neighbour that keeps it waiting now. While that neighbour has no colour, v
+// cannot be ready, and one load settles the visit.
+__device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& blocker) {
   constexpr int B = 8;  // neighbours fetched side by side
+  if (blocker >= 0 && (rw_get(rd.rw, blocker) & 0xFF) == 0xFF) return false;
   uint64_t rv = rw_get(rd.rw, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
@@ -114,16 +118,19 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
     for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
 #pragma unroll
     for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_get(rd.rw, w[q]) : 0ull;
-    bool wait = false;
+    int wait = -1;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       if (!(x[q] & kRwAct) || !rw_beats(x[q], w[q], rv, v)) continue;
       int c = (int)(x[q] & 0xFF);
-      if (c == 0xFF) wait = true;
+      if (c == 0xFF) wait = wait < 0 ? w[q] : wait;
       else if (c < 64) used |= 1ull << c;
       else big = true;
     }
-    if (wait) return false;
+    if (wait >= 0) {
+      blocker = wait;
+      return false;
+    }
   }
   int c;
   if (~used != 0ull && !big) {
@@ -158,7 +165,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr) {
 // chunk (on a stripe) counts what is left.
 constexpr int kJpItems = kJpChunk / kBlock;
 constexpr int kJpLocal = 3;  // passes per launch over a chunk that makes progress
-__global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restrict__ A, int n, int* W,
+__global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restrict__ A, int n, int* W, int* WB,
                                                   int* __restrict__ cnt, int first, Round rd, int* ctr, int slot,
                                                   int next_slot) {
   __shared__ int wtot[kJpItems][kBlock / kWave];
@@ -170,18 +177,20 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     return;
   }
   const int* in = (first ? A : W) + (size_t)kb * kJpChunk;
-  int vv[kJpItems];
+  const int* inb = WB + (size_t)kb * kJpChunk;
+  int vv[kJpItems], bl[kJpItems];
 #pragma unroll
   for (int r = 0; r < kJpItems; ++r) {
     int i = r * kBlock + (int)threadIdx.x;
     vv[r] = i < m ? in[i] : -1;
+    bl[r] = (i < m && !first) ? inb[i] : -1;
   }
   bool keep[kJpItems];
   int tries = 0;  // this thread's vertex visits, for the profile's unit count
   bool moved = false;
 #pragma unroll
   for (int r = 0; r < kJpItems; ++r) {
-    keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr);
+    keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr, bl[r]);
     moved |= vv[r] >= 0 && !keep[r];
     tries += vv[r] >= 0 ? 1 : 0;
   }
@@ -197,7 +206,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     for (int r = 0; r < kJpItems; ++r)
       if (keep[r]) {
         ++tries;
-        keep[r] = !jp_try(st, vv[r], rd, ctr);
+        keep[r] = !jp_try(st, vv[r], rd, ctr, bl[r]);
         moved |= !keep[r];
       }
   }
@@ -226,9 +235,13 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     base += row;
   }
   int* out = W + (size_t)kb * kJpChunk;
+  int* outb = WB + (size_t)kb * kJpChunk;
 #pragma unroll
   for (int r = 0; r < kJpItems; ++r)
-    if (keep[r]) out[pos[r]] = vv[r];
+    if (keep[r]) {
+      out[pos[r]] = vv[r];
+      outb[pos[r]] = bl[r];
+    }
   if (threadIdx.x == 0) {
     cnt[kb] = base;
     int* sp = ctr + C_STRIPE + (kb & (kStripes - 1)) * kStripeW;
@@ -237,11 +250,11 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
   if (lane == 0 && tries) atomicAdd(stripe_ptr(ctr, S_PJP), tries);
 }
 
-void jp_chunk(const Store& st, const int* A, int n, int* W, int* cnt, bool first, Round rd, int* ctr, int it,
-              hipStream_t s) {
+void jp_chunk(const Store& st, const int* A, int n, int* W, int* WB, int* cnt, bool first, Round rd, int* ctr,
+              int it, hipStream_t s) {
   int nch = (n + kJpChunk - 1) / kJpChunk;
   if (nch > 0)
-    k_jp_chunk<<<nch, kBlock, 0, s>>>(st, A, n, W, cnt, first ? 1 : 0, rd, ctr, S_JPL + (it & 7),
+    k_jp_chunk<<<nch, kBlock, 0, s>>>(st, A, n, W, WB, cnt, first ? 1 : 0, rd, ctr, S_JPL + (it & 7),
                                        S_JPL + ((it + 1) & 7));
 }
 
@@ -369,7 +382,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     int* wout = (it & 1) ? W1 : W0;
     for (int i = tid; i < nw; i += kSmallThreads) {
       int v = in[i];
-      if (!jp_try(st, v, rd, ctr)) wout[atomicAdd(&nwait, 1)] = v;
+      int bl = -1;
+      if (!jp_try(st, v, rd, ctr, bl)) wout[atomicAdd(&nwait, 1)] = v;
     }
     __syncthreads();
     visited += nw;
