@@ -896,16 +896,19 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   // previous vertices that are no next (one for a boundary vertex; more:
   // the elements form no disk or half-disk, and the general path decides)
   int extra = INT_MAX, nextra = 0;
-  for (int k = 0; k < m; ++k) {
-    Elem e = st.tri[col[k * S]];
-    int sl = slot_of(e, x);
-    int b = at(e, sl == 0 ? 2 : sl - 1);
-    bool found = false;
 #pragma unroll
-    for (int q = 0; q < N; ++q) found |= nx[q] == b;
-    if (!found) {
-      extra = b;
-      ++nextra;
+  for (int k = 0; k < N; ++k) {
+    if (k < m) {  // unrolled, so the element loads go out together
+      Elem e = st.tri[col[k * S]];
+      int sl = slot_of(e, x);
+      int b = at(e, sl == 0 ? 2 : sl - 1);
+      bool found = false;
+#pragma unroll
+      for (int q = 0; q < N; ++q) found |= nx[q] == b;
+      if (!found) {
+        extra = b;
+        ++nextra;
+      }
     }
   }
   bool odd = act && nextra > 1;
@@ -1101,7 +1104,7 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
   __syncthreads();  // the LDS is reused by the next chunk
 }
 
-// One block per mpb class members (256, or fewer for small classes, so that
+// One block per mpb class members (128, or fewer for small classes, so that
 // more blocks share the latency-bound work), in XCD-aware block order.
 __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
                                                 int flips, int* ctr) {
@@ -1112,7 +1115,7 @@ __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restri
 
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s) {
   if (n <= 0) return;
-  int mpb = n >= 256 * 1024 ? 256 : (n >= 64 * 1024 ? 64 : 16);
+  int mpb = n >= 256 * 1024 ? 128 : (n >= 64 * 1024 ? 64 : 16);
   int nb = (n + mpb - 1) / mpb;
   k_commit<<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, flips ? 1 : 0, ctr);
 }
