@@ -1321,7 +1321,7 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
+__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
   if (n <= 0) return;
   if (variant == 1)
@@ -1496,7 +1496,7 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   return true;
 }
 
-__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
   Grp g = grp();
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
