@@ -446,7 +446,7 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->listA, V));
   TRY(ensure(m, m->listB, V));
   TRY(ensure(m, m->jpU0, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
-  TRY(ensure(m, m->jpB, ((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk));
+  TRY(ensure(m, m->jpB, std::max(((size_t)V + kJpChunk - 1) / kJpChunk * kJpChunk, 2 * (size_t)kSmallColour)));
   // chunk counts of the chunked JP, or the second waiting list of the small colouring
   TRY(ensure(m, m->jpU1, std::max((size_t)V / kJpChunk + 1, (size_t)std::min(V, kSmallColour))));
   TRY(ensure(m, m->cls, V));
@@ -495,7 +495,8 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
   if (n <= kSmallColour && !(m->variant & 4)) {
-    timed(m, PM_K_JP, 0, [&] { colour_small(m->st, A, n, rd, m->jpU0.p, m->jpU1.p, m->cls.p, m->ctr, m->s); });
+    timed(m, PM_K_JP, 0,
+          [&] { colour_small(m->st, A, n, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, m->s); });
     TRY(read_ctr(m, 0, C_NCOL + 1));
     TRY(check_err(m, true));
     out.jp_iters = m->hctr[C_TOTAL];

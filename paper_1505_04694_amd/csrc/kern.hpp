@@ -225,7 +225,8 @@ void select_small(const Store& st, int mode, double L_low2, const int* A, int nA
 // lists up to kSmallColour entries: colouring and class lists in one block;
 // writes class sizes, offsets and count like class_lists, iterations to C_TOTAL
 constexpr int kSmallColour = 8192;
-void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* out, int* ctr,
+// WB: 2 * kSmallColour ints for the blockers of the waiting lists
+void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* WB, int* out, int* ctr,
                   hipStream_t s);
 
 // variant 0: one thread per member; 1: a group of 8 lanes per member

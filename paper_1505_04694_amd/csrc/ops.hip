@@ -364,7 +364,8 @@ void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, in
 // are an independent set, so their order does not change any result.
 constexpr int kSmallThreads = 1024;
 __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const int* __restrict__ A, int n, Round rd,
-                                                              int* W0, int* W1, int* __restrict__ out, int* ctr) {
+                                                              int* W0, int* W1, int* WB, int* __restrict__ out,
+                                                              int* ctr) {
   __shared__ int nwait, hist[256], cur[256];
   int tid = (int)threadIdx.x;
   for (int i = tid; i < n; i += kSmallThreads) {
@@ -380,10 +381,16 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     if (tid == 0) nwait = 0;
     __syncthreads();
     int* wout = (it & 1) ? W1 : W0;
+    const int* bin = WB + ((it & 1) ? 0 : kSmallColour);  // blockers beside the entries read
+    int* bout = WB + ((it & 1) ? kSmallColour : 0);
     for (int i = tid; i < nw; i += kSmallThreads) {
       int v = in[i];
-      int bl = -1;
-      if (!jp_try(st, v, rd, ctr, bl)) wout[atomicAdd(&nwait, 1)] = v;
+      int bl = it > 0 ? bin[i] : -1;
+      if (!jp_try(st, v, rd, ctr, bl)) {
+        int k = atomicAdd(&nwait, 1);
+        wout[k] = v;
+        bout[k] = bl;
+      }
     }
     __syncthreads();
     visited += nw;
@@ -419,9 +426,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     out[atomicAdd(&cur[(int)(rd.rw[v] & 0xFF)], 1)] = v;
   }
 }
-void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* out, int* ctr,
+void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* WB, int* out, int* ctr,
                   hipStream_t s) {
-  k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, rd, W0, W1, out, ctr);
+  k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, rd, W0, W1, WB, out, ctr);
 }
 
 __global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mode, double L_low2,
