@@ -725,7 +725,10 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
         });
       else
         timed(m, PM_K_FLIP, cl.size[c],
-              [&] { flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s); });
+              [&] {
+                if (m->variant & 4) flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
+                else flip_class_g(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
+              });
       timed(m, PM_K_COMMIT, 0, [&] {
         commit_rows(m->st, m->cls.p + cl.off[c], cl.size[c], cm, kind != 0, m->ctr, m->s);
       });

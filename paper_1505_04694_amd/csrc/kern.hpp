@@ -233,6 +233,8 @@ void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* 
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
                     hipStream_t s);
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
+// flips on groups of 16 lanes per member
+void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s);
 // rebuild the rows claimed by the committed members of list[0..n) (the class
 // just processed, launched in the same shape); flips: members' own rows too

@@ -1667,8 +1667,147 @@ __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __re
 template __global__ void k_collapse_g<8>(Store, const int*, int, OpArgs, Commit, int*);
 template __global__ void k_collapse_g<16>(Store, const int*, int, OpArgs, Commit, int*);
 
-// A small class in one block: the operation (collapse on groups of kGC lanes,
-// or flips one per thread), a block barrier, then the commit of the same
+// ---- flips with lane groups -----------------------------------------------------------------------
+// Lane j owns the member's j-th element T1 = (v, w, a) (cyclic from v): the
+// edge (v, w) and its data. The element across that edge, T2, is the one
+// whose vertex before v is w; the lane holding it hands over its id, its
+// other vertex b and its quality. Each lane then evaluates the flip of its
+// edge; the group keeps the largest new minimum quality, ties to the smaller
+// w, as the one-thread scan does.
+template <int G>
+__device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm,
+                                          const Grp& g) {
+  bool ownn = g.j < h.y, owne = g.j < h.w;
+  uint64_t rv = a.rw[v];
+  bool beat = ownn && same_class_beats(a, st.nn[h.x + g.j], rv, v);
+  if (gany_of<G>(beat, g)) {
+    if (g.j == 0) cm.nxt[v] = 1;
+    return 0;
+  }
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  int T1 = -1, k1 = 0, w = -1, av = -1;
+  double2 pw = make_double2(0.0, 0.0), pa = pw;
+  Met mw{0.0, 0.0, 0.0}, ma = mw;
+  if (owne) {
+    T1 = st.ne[h.z + g.j];
+    Elem e1 = st.tri[T1];
+    k1 = slot_of(e1, v);
+    w = at(e1, k1 == 2 ? 0 : k1 + 1);
+    av = at(e1, k1 == 0 ? 2 : k1 - 1);
+    pw = st.xy[w];
+    mw = st.met[w];
+    pa = st.xy[av];
+    ma = st.met[av];
+  }
+  // quality of T1 in its stored order (slot k1 holds v, then w, then a)
+  double q1 = 0.0;
+  if (owne) {
+    double2 s0 = k1 == 0 ? pv : (k1 == 1 ? pa : pw);
+    double2 s1 = k1 == 1 ? pv : (k1 == 2 ? pa : pw);
+    double2 s2 = k1 == 2 ? pv : (k1 == 0 ? pa : pw);
+    Met n0 = k1 == 0 ? mv : (k1 == 1 ? ma : mw);
+    Met n1 = k1 == 1 ? mv : (k1 == 2 ? ma : mw);
+    Met n2 = k1 == 2 ? mv : (k1 == 0 ? ma : mw);
+    q1 = qual2(make_geo(s0, s1, s2, n0, n1, n2));
+  }
+  // the lane whose element has w before v holds T2
+  int j2 = -1;
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    int pq = gget(av, q, g);
+    if (j2 < 0 && owne && q < h.w && pq == w) j2 = q;
+  }
+  int src = g.base + (j2 >= 0 ? j2 : 0);
+  int T2 = __shfl(T1, src);
+  int bv = __shfl(w, src);
+  double2 pb = make_double2(__shfl(pw.x, src), __shfl(pw.y, src));
+  Met mb{__shfl(mw.a, src), __shfl(mw.b, src), __shfl(mw.c, src)};
+  double q2 = __shfl(q1, src);
+  bool cand = owne && j2 >= 0;
+  double nmin = 0.0;
+  if (cand) {
+    // (v, b, a) and (w, a, b), each rotated smallest id first
+    int r1 = (v < bv && v < av) ? 0 : ((bv < v && bv < av) ? 1 : 2);
+    double2 c0 = r1 == 0 ? pv : (r1 == 1 ? pb : pa);
+    double2 c1 = r1 == 0 ? pb : (r1 == 1 ? pa : pv);
+    double2 c2 = r1 == 0 ? pa : (r1 == 1 ? pv : pb);
+    Met d0 = r1 == 0 ? mv : (r1 == 1 ? mb : ma);
+    Met d1 = r1 == 0 ? mb : (r1 == 1 ? ma : mv);
+    Met d2 = r1 == 0 ? ma : (r1 == 1 ? mv : mb);
+    Geo gv = make_geo(c0, c1, c2, d0, d1, d2);
+    int r2 = (w < av && w < bv) ? 0 : ((av < w && av < bv) ? 1 : 2);
+    double2 e0 = r2 == 0 ? pw : (r2 == 1 ? pa : pb);
+    double2 e1p = r2 == 0 ? pa : (r2 == 1 ? pb : pw);
+    double2 e2 = r2 == 0 ? pb : (r2 == 1 ? pw : pa);
+    Met f0 = r2 == 0 ? mw : (r2 == 1 ? ma : mb);
+    Met f1 = r2 == 0 ? ma : (r2 == 1 ? mb : mw);
+    Met f2 = r2 == 0 ? mb : (r2 == 1 ? mw : ma);
+    Geo gw = make_geo(e0, e1p, e2, f0, f1, f2);
+    if (!(area2(gv) > 0.0) || !(area2(gw) > 0.0)) {
+      cand = false;
+    } else {
+      double qv = qual2(gv), qw = qual2(gw);
+      nmin = qw < qv ? qw : qv;
+      double omin = q2 < q1 ? q2 : q1;
+      cand = nmin > omin;
+    }
+  }
+  // the best candidate: largest new minimum, ties to the smaller w
+  double bq = cand ? nmin : -INFINITY;
+  int bw = cand ? w : INT_MAX;
+  int bj = cand ? g.j : -1;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    double oq = __shfl_xor(bq, d);
+    int ow = __shfl_xor(bw, d);
+    int oj = __shfl_xor(bj, d);
+    if (oj >= 0 && (bj < 0 || oq > bq || (oq == bq && ow < bw))) {
+      bq = oq;
+      bw = ow;
+      bj = oj;
+    }
+  }
+  if (bj < 0) return 1;
+  if (g.j == bj) {
+    int lo = min(T1, T2), hi = max(T1, T2);
+    int3 tv = rot_min(v, bv, av), tw = rot_min(w, av, bv);
+    st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
+    st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
+    stamp(cm, v, lo, hi, 0);
+    claim_row(cm, v, v);
+    claim_row(cm, w, v);
+    claim_row(cm, av, v);
+    claim_row(cm, bv, v);
+  }
+  return 2;
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_flip_g(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm,
+                                                int* ctr) {
+  Grp g = grp_of<G>();
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
+  int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G);
+  int status = -1;
+  if (gid < n) {
+    int v = list[gid];
+    Hdr h = st.hdr[v];
+    if (h.y > G || h.w > G) {
+      if (g.j == 0) status = flip_one(st, v, a, cm, ctr);
+    } else {
+      int r = flip_group<G>(st, v, h, a, cm, g);
+      if (g.j == 0) status = r;
+    }
+  }
+  count_status(status, ctr);
+}
+void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
+  if (n > 0) k_flip_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+}
+
+// A small class in one block: the operation (collapse or flips on groups of
+// kGC lanes per member), a block barrier, then the commit of the same
 // members; one launch instead of two. Every thread reaches every barrier.
 __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                      Commit cm, int kind, int* ctr) {
@@ -1693,9 +1832,20 @@ __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __rest
       count_status(status, ctr);
     }
   } else {
-    for (int i0 = 0; i0 < n; i0 += kBlock) {
-      int i = i0 + tid;
-      int status = i < n ? flip_one(st, list[i], a, cm, ctr) : -1;
+    Grp g = grp_of<kGC>();
+    for (int p0 = 0; p0 < n; p0 += kBlock / kGC) {
+      int gid = p0 + tid / kGC;
+      int status = -1;
+      if (gid < n) {
+        int v = list[gid];
+        Hdr h = st.hdr[v];
+        if (h.y > kGC || h.w > kGC) {
+          if (g.j == 0) status = flip_one(st, v, a, cm, ctr);
+        } else {
+          int r = flip_group<kGC>(st, v, h, a, cm, g);
+          if (g.j == 0) status = r;
+        }
+      }
       count_status(status, ctr);
     }
   }
