@@ -140,18 +140,78 @@ void k_validate(const Store& st, int* ctr, hipStream_t s) {
 }
 
 // ---- row build ----------------------------------------------------------------------
-__global__ void k_ne_count(const Elem* __restrict__ tri, int T, int* __restrict__ cnt) {
-  for (int t = gtid(); t < T; t += gstride()) {
+// Element-to-vertex incidence counts and fills. A block takes a contiguous
+// chunk of kIncChunk elements; when the chunk's vertices span at most
+// kIncSpan ids (meshes numbered with locality), it counts in LDS and makes
+// one global atomic per vertex it touches instead of one per incidence.
+constexpr int kIncPer = 4;
+constexpr int kIncChunk = kBlock * kIncPer;
+constexpr int kIncSpan = 4096;
+__device__ __forceinline__ void chunk_span(const Elem* __restrict__ tri, int t0, int t1, int& vmin, int& vmax,
+                                           int* red) {
+  int lo = INT_MAX, hi = -1;
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
     Elem e = tri[t];
     if (!e.w) continue;
-    atomicAdd(&cnt[e.x], 1);
-    atomicAdd(&cnt[e.y], 1);
-    atomicAdd(&cnt[e.z], 1);
+    lo = min(lo, min(e.x, min(e.y, e.z)));
+    hi = max(hi, max(e.x, max(e.y, e.z)));
   }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    lo = min(lo, __shfl_xor(lo, d));
+    hi = max(hi, __shfl_xor(hi, d));
+  }
+  int wv = (int)threadIdx.x / kWave;
+  if (__lane_id() == 0) {
+    red[2 * wv] = lo;
+    red[2 * wv + 1] = hi;
+  }
+  __syncthreads();
+  vmin = INT_MAX;
+  vmax = -1;
+#pragma unroll
+  for (int q = 0; q < kBlock / kWave; ++q) {
+    vmin = min(vmin, red[2 * q]);
+    vmax = max(vmax, red[2 * q + 1]);
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_ne_count(const Elem* __restrict__ tri, int T, int* __restrict__ cnt) {
+  __shared__ int loc[kIncSpan];
+  __shared__ int red[2 * kBlock / kWave];
+  int t0 = blockIdx.x * kIncChunk, t1 = min(T, t0 + kIncChunk);
+  int vmin, vmax;
+  chunk_span(tri, t0, t1, vmin, vmax, red);
+  if (vmax < 0) return;
+  int span = vmax - vmin + 1;
+  if (span > kIncSpan) {
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+      Elem e = tri[t];
+      if (!e.w) continue;
+      atomicAdd(&cnt[e.x], 1);
+      atomicAdd(&cnt[e.y], 1);
+      atomicAdd(&cnt[e.z], 1);
+    }
+    return;
+  }
+  for (int i = (int)threadIdx.x; i < span; i += kBlock) loc[i] = 0;
+  __syncthreads();
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+    Elem e = tri[t];
+    if (!e.w) continue;
+    atomicAdd(&loc[e.x - vmin], 1);
+    atomicAdd(&loc[e.y - vmin], 1);
+    atomicAdd(&loc[e.z - vmin], 1);
+  }
+  __syncthreads();
+  for (int i = (int)threadIdx.x; i < span; i += kBlock)
+    if (loc[i]) atomicAdd(&cnt[vmin + i], loc[i]);
 }
 
 void build_count(const Store& st, int* ne_cnt, hipStream_t s) {
-  k_ne_count<<<grid_for(st.T), kBlock, 0, s>>>(st.tri, st.T, ne_cnt);
+  int nb = (st.T + kIncChunk - 1) / kIncChunk;
+  if (nb > 0) k_ne_count<<<nb, kBlock, 0, s>>>(st.tri, st.T, ne_cnt);
 }
 
 __device__ __forceinline__ int round4(int x) { return (x + 3) & ~3; }
@@ -190,23 +250,68 @@ void set_headers(const Store& st, const int* nn_off, const int* ne_off, const in
   k_set_headers<<<grid_for(st.V), kBlock, 0, s>>>(st.hdr, st.cap, st.V, nn_off, ne_off, nn_cap, ne_cap);
 }
 
-__global__ void k_ne_fill(const Elem* __restrict__ tri, int T, Hdr* hdr, int* __restrict__ ne) {
-  for (int t = gtid(); t < T; t += gstride()) {
-    Elem e = tri[t];
-    if (!e.w) continue;
-    int vs[3] = {e.x, e.y, e.z};
+// Fill: each incidence takes a slot of its vertex's NE row (rows are sorted
+// by the row finish, so the order of filling does not matter). In the LDS
+// path an incidence takes its rank among the chunk's incidences of that
+// vertex, and one global atomic per vertex reserves the chunk's slots.
+__global__ void __launch_bounds__(256) k_ne_fill(const Elem* __restrict__ tri, int T, Hdr* hdr, int* __restrict__ ne) {
+  __shared__ int loc[kIncSpan];
+  __shared__ int red[2 * kBlock / kWave];
+  int t0 = blockIdx.x * kIncChunk, t1 = min(T, t0 + kIncChunk);
+  int vmin, vmax;
+  chunk_span(tri, t0, t1, vmin, vmax, red);
+  if (vmax < 0) return;
+  int span = vmax - vmin + 1;
+  if (span > kIncSpan) {
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) {
+      Elem e = tri[t];
+      if (!e.w) continue;
+      int vs[3] = {e.x, e.y, e.z};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      int* cnt = reinterpret_cast<int*>(&hdr[vs[k]]) + 3;
-      int pos = atomicAdd(cnt, 1);
-      ne[hdr[vs[k]].z + pos] = t;
+      for (int k = 0; k < 3; ++k) {
+        int* c = reinterpret_cast<int*>(&hdr[vs[k]]) + 3;
+        int pos = atomicAdd(c, 1);
+        ne[hdr[vs[k]].z + pos] = t;
+      }
     }
+    return;
+  }
+  for (int i = (int)threadIdx.x; i < span; i += kBlock) loc[i] = 0;
+  __syncthreads();
+  int rank[kIncPer][3];
+#pragma unroll
+  for (int r = 0; r < kIncPer; ++r) {
+    int t = t0 + r * kBlock + (int)threadIdx.x;
+    Elem e = t < t1 ? tri[t] : make_int4(0, 0, 0, 0);
+    rank[r][0] = rank[r][1] = rank[r][2] = -1;
+    if (t < t1 && e.w) {
+      rank[r][0] = atomicAdd(&loc[e.x - vmin], 1);
+      rank[r][1] = atomicAdd(&loc[e.y - vmin], 1);
+      rank[r][2] = atomicAdd(&loc[e.z - vmin], 1);
+    }
+  }
+  __syncthreads();
+  // reserve the chunk's slots: loc[i] becomes the first slot of the chunk in row vmin + i
+  for (int i = (int)threadIdx.x; i < span; i += kBlock) {
+    int c = loc[i];
+    if (c) loc[i] = hdr[vmin + i].z + atomicAdd(reinterpret_cast<int*>(&hdr[vmin + i]) + 3, c);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kIncPer; ++r) {
+    int t = t0 + r * kBlock + (int)threadIdx.x;
+    if (rank[r][0] < 0) continue;
+    Elem e = tri[t];
+    ne[loc[e.x - vmin] + rank[r][0]] = t;
+    ne[loc[e.y - vmin] + rank[r][1]] = t;
+    ne[loc[e.z - vmin] + rank[r][2]] = t;
   }
 }
 
 void build_fill(const Store& st, int* fill, hipStream_t s) {
   (void)fill;
-  k_ne_fill<<<grid_for(st.T), kBlock, 0, s>>>(st.tri, st.T, st.hdr, st.ne);
+  int nb = (st.T + kIncChunk - 1) / kIncChunk;
+  if (nb > 0) k_ne_fill<<<nb, kBlock, 0, s>>>(st.tri, st.T, st.hdr, st.ne);
 }
 
 __device__ void isort(int* a, int n) {
