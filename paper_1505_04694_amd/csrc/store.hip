@@ -96,7 +96,31 @@ __global__ void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, 
 
 int scan_partials_needed(int n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
 
+// short arrays: one block of 1024 threads, each scanning a contiguous piece
+constexpr int kScanSingle = 65536;
+__global__ void __launch_bounds__(1024) k_scan_single(const int* __restrict__ in, int* __restrict__ out, int n,
+                                                      int* __restrict__ total) {
+  __shared__ int lds[1024 / kWave + 1];
+  int per = (n + 1023) / 1024;
+  int lo = (int)threadIdx.x * per;
+  int hi = min(n, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += in[i];
+  int tot;
+  int acc = block_excl(s, lds, &tot);
+  for (int i = lo; i < hi; ++i) {
+    int t = in[i];
+    out[i] = acc;
+    acc += t;
+  }
+  if (threadIdx.x == 0) *total = tot;
+}
+
 void scan_excl(const int* in, int* out, int n, int* total, int* partial, hipStream_t s) {
+  if (n <= kScanSingle) {
+    k_scan_single<<<1, 1024, 0, s>>>(in, out, n, total);
+    return;
+  }
   int nb = (n + SCAN_B - 1) / SCAN_B;
   if (nb < 1) nb = 1;
   k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, partial);
