@@ -51,6 +51,7 @@ struct pm_mesh {
   int* ctr = nullptr;   // device counters
   int* hctr = nullptr;  // pinned mirror
   double* hq = nullptr; // pinned doubles
+  int* haux = nullptr;   // pinned ints for small read-backs
   // scratch
   DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
   DBuf<uint8_t> nxt, u8tmp;
@@ -186,7 +187,8 @@ pm_status dalloc(pm_mesh* m, T** p, size_t n) {
 }
 // Pinned host blocks (the counter mirror and the quality read-back) are kept
 // in a process-wide free list: pinning memory is a slow driver call.
-constexpr size_t kPinnedBytes = C_COUNT * sizeof(int) + 64 * sizeof(double);
+constexpr int kAuxInts = 16384;  // pinned room for small read-backs beside the counters
+constexpr size_t kPinnedBytes = C_COUNT * sizeof(int) + 64 * sizeof(double) + kAuxInts * sizeof(int);
 std::mutex g_pinned_mu;
 std::vector<void*> g_pinned_free;
 bool pinned_get(pm_mesh* m) {
@@ -204,6 +206,7 @@ bool pinned_get(pm_mesh* m) {
   }
   m->hctr = (int*)p;
   m->hq = (double*)((char*)p + C_COUNT * sizeof(int));
+  m->haux = (int*)((char*)p + C_COUNT * sizeof(int) + 64 * sizeof(double));
   return true;
 }
 void pinned_put(pm_mesh* m) {
@@ -212,6 +215,7 @@ void pinned_put(pm_mesh* m) {
   g_pinned_free.push_back(m->hctr);
   m->hctr = nullptr;
   m->hq = nullptr;
+  m->haux = nullptr;
 }
 
 template <class T>
@@ -1078,11 +1082,13 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     scan_excl(m->tt0.p, m->tt1.p, T0, m->ctr + C_TOTAL2, m->partial.p, m->s);
     range_sums(m->vt1.p, m->vt0.p, s.vbase, s.vused, B, m->rtmp.p, m->s);
     range_sums(m->tt1.p, m->tt0.p, s.tbase, s.tused, B, m->rtmp.p + B, m->s);
+    // per-mesh needs, totals and tested edges come back in one wait
     std::vector<int> need(2 * B);
-    HIPCHK(hipMemcpyAsync(need.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
+    bool aux = 2 * B <= kAuxInts;
+    HIPCHK(hipMemcpyAsync(aux ? m->haux : need.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
     stripe_sum(m->ctr, S_EDGES, 1, C_EDGES, m->s);
-    TRY(read_ctr(m, C_TOTAL, 2));
-    TRY(read_ctr(m, C_EDGES, 1));
+    TRY(read_ctr(m, 0, C_JP));
+    if (aux) std::copy(m->haux, m->haux + 2 * B, need.begin());
     int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
     int edges = m->hctr[C_EDGES];
     if (nv == 0) {
