@@ -696,87 +696,131 @@ void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, in
 // then the set of the other vertices of those elements.
 
 // the candidates of row x that are live and hold x (possibly repeated),
-// written to dst[k * stride] for k < lim; returns how many there are. Row
-// entries, operation records and elements are fetched eight at a time, so a
-// row costs a few dependent loads rather than one per neighbour; a collapse
-// record carries the member's NE row range. Filtering here keeps the
-// candidate count at the new row's size (a collapse target's old row and the
-// absorbed row share only the two elements that die).
-__device__ __forceinline__ bool keeps(const Store& st, int t, int x) {
-  Elem e = st.tri[t];
-  return e.w && holds(e, x);
-}
+// written to dst[k * stride] for k < lim; returns how many there are. A class
+// holds one kind of operation: F, flips (records (epoch, t1, t2, 0)), else
+// collapses (records (epoch, -(u+1), ne_off, ne_cnt), the member's NE row).
+// Rows of up to kCandB entries are gathered level by level, each level's
+// loads issued together: NE(x), NN(x) and x's own record; then the elements
+// of NE(x) and the neighbours' records; then what those records name (an
+// absorbed NE row, then its elements; or each flip's two elements). Element
+// and record loads take index 0 for an empty slot, so that no load waits on
+// a branch. Longer rows go through the same steps B entries at a time.
+// Filtering here keeps the candidate count at the new row's size (a collapse
+// target's old row and the absorbed row share only the two elements that die).
+constexpr int kCandB = 8;
+__device__ __forceinline__ bool keeps(const Elem& e, int x) { return e.w && holds(e, x); }
+
+template <bool F>
 __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm, int x, Hdr h, int* dst, int stride,
                                               int lim) {
-  constexpr int B = 8;
+  constexpr int B = kCandB;
   int n = 0;
   auto put = [&](int t) {
     if (n < lim) dst[n * stride] = t;
     ++n;
   };
-  for (int k0 = 0; k0 < h.w; k0 += B) {
-    int t[B];
+  // the elements t[0 .. B) (t < 0: none) that are live and hold x
+  auto put_live = [&](const int (&t)[B]) {
+    Elem e[B];
 #pragma unroll
-    for (int q = 0; q < B; ++q) t[q] = k0 + q < h.w ? st.ne[h.z + k0 + q] : -1;
-    bool ok[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) ok[q] = t[q] >= 0 && keeps(st, t[q], x);
+    for (int q = 0; q < B; ++q) e[q] = st.tri[max(t[q], 0)];
 #pragma unroll
     for (int q = 0; q < B; ++q)
-      if (ok[q]) put(t[q]);
-  }
-  // a neighbour w collapsed onto x hands over NE(w); the first such range is
-  // noted in the batched scan, any further ones (several members collapsing
-  // onto one vertex) are found by a second, plain scan
-  int az = 0, aw = 0, targets = 0;
-  for (int j0 = 0; j0 < h.y; j0 += B) {
-    int w[B], ep[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
-#pragma unroll
-    for (int q = 0; q < B; ++q) ep[q] = w[q] >= 0 ? cm.ops[w[q]].x : 0;
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-      if (w[q] < 0 || ep[q] != cm.epoch) continue;
-      int4 r = cm.ops[w[q]];  // the line the stamp came from
-      if (r.y < 0) {
-        if (-r.y - 1 != x) continue;
-        if (targets++ == 0) {
-          az = r.z;
-          aw = r.w;
-        }
-      } else {
-        if (keeps(st, r.y, x)) put(r.y);
-        if (keeps(st, r.z, x)) put(r.z);
-      }
-    }
-  }
+      if (t[q] >= 0 && keeps(e[q], x)) put(t[q]);
+  };
+  // NE(w) of a neighbour w collapsed onto x
   auto absorb = [&](int z, int cnt) {
     for (int k0 = 0; k0 < cnt; k0 += B) {
       int t[B];
 #pragma unroll
-      for (int p = 0; p < B; ++p) t[p] = k0 + p < cnt ? st.ne[z + k0 + p] : -1;
-      bool ok[B];
-#pragma unroll
-      for (int p = 0; p < B; ++p) ok[p] = t[p] >= 0 && keeps(st, t[p], x);
-#pragma unroll
-      for (int p = 0; p < B; ++p)
-        if (ok[p]) put(t[p]);
+      for (int q = 0; q < B; ++q) t[q] = k0 + q < cnt ? st.ne[z + k0 + q] : -1;
+      put_live(t);
     }
   };
-  if (targets > 0) absorb(az, aw);
-  if (targets > 1) {
-    int seen = 0;
-    for (int j = 0; j < h.y; ++j) {
-      int4 r = cm.ops[st.nn[h.x + j]];
-      if (r.x != cm.epoch || r.y >= 0 || -r.y - 1 != x) continue;
-      if (seen++ > 0) absorb(r.z, r.w);
+  // the records of neighbours w[0 .. B) (w < 0: none), loaded side by side:
+  // flips hand over their two elements (taken four records at a time);
+  // collapses onto x are counted, and the first one's NE range is fetched
+  int targets = 0, tw = -1;
+  auto scan_records = [&](const int (&w)[B]) {
+    if (F) {
+#pragma unroll
+      for (int q0 = 0; q0 < B; q0 += B / 2) {
+        int4 r[B / 2];
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) r[q] = cm.ops[max(w[q0 + q], 0)];
+        int f0[B / 2], f1[B / 2];
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) {
+          bool c = w[q0 + q] >= 0 && r[q].x == cm.epoch && r[q].y >= 0;
+          f0[q] = c ? r[q].y : -1;
+          f1[q] = c ? r[q].z : -1;
+        }
+        Elem e0[B / 2], e1[B / 2];
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) e0[q] = st.tri[max(f0[q], 0)];
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) e1[q] = st.tri[max(f1[q], 0)];
+#pragma unroll
+        for (int q = 0; q < B / 2; ++q) {
+          if (f0[q] >= 0 && keeps(e0[q], x)) put(f0[q]);
+          if (f1[q] >= 0 && keeps(e1[q], x)) put(f1[q]);
+        }
+      }
+    } else {
+      int2 r[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) r[q] = *(const int2*)&cm.ops[max(w[q], 0)];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        if (w[q] >= 0 && r[q].x == cm.epoch && r[q].y == -x - 1) {
+          if (targets == 0) tw = w[q];
+          ++targets;
+        }
+      }
+    }
+  };
+  int4 rx = F ? cm.ops[x] : make_int4(0, 0, 0, 0);
+  if (h.w <= B && h.y <= B) {
+    int t[B], w[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) t[q] = q < h.w ? st.ne[h.z + q] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q) w[q] = q < h.y ? st.nn[h.x + q] : -1;
+    put_live(t);
+    scan_records(w);
+  } else {
+    for (int k0 = 0; k0 < h.w; k0 += B) {
+      int t[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) t[q] = k0 + q < h.w ? st.ne[h.z + k0 + q] : -1;
+      put_live(t);
+    }
+    for (int j0 = 0; j0 < h.y; j0 += B) {
+      int w[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+      scan_records(w);
     }
   }
-  int4 r = cm.ops[x];
-  if (r.x == cm.epoch && r.y >= 0) {
-    if (keeps(st, r.y, x)) put(r.y);
-    if (keeps(st, r.z, x)) put(r.z);
+  if (!F) {
+    if (targets > 0) {
+      int4 r = cm.ops[tw];
+      absorb(r.z, r.w);
+    }
+    // several members collapsed onto x: the further ranges, by a plain scan
+    if (targets > 1) {
+      int seen = 0;
+      for (int j = 0; j < h.y; ++j) {
+        int4 r = cm.ops[st.nn[h.x + j]];
+        if (r.x != cm.epoch || r.y != -x - 1) continue;
+        if (seen++ > 0) absorb(r.z, r.w);
+      }
+    }
+  } else if (rx.x == cm.epoch && rx.y >= 0) {
+    // x's own flip
+    Elem a = st.tri[rx.y], b = st.tri[rx.z];
+    if (keeps(a, x)) put(rx.y);
+    if (keeps(b, x)) put(rx.z);
   }
   return n;
 }
@@ -821,10 +865,11 @@ __device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap
 }
 
 // general path: candidates in a private staging range, insertion sorts there
+template <bool F>
 __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm, int x, int* ctr) {
   Hdr h = st.hdr[x];
   int2 cp = st.cap[x];
-  int tot = row_candidates(st, cm, x, h, nullptr, 0, 0);
+  int tot = row_candidates<F>(st, cm, x, h, nullptr, 0, 0);
   int64_t need = 4 * (int64_t)tot + 4;
   int base = atomicAdd(&ctr[C_STAGE], (int)need);
   if ((int64_t)base + need > cm.stage_cap) {
@@ -832,13 +877,8 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
     return;
   }
   int* s = cm.stage + base;
-  row_candidates(st, cm, x, h, s, 1, tot);
-  int m = 0;
-  for (int k = 0; k < tot; ++k) {
-    int t = s[k];
-    Elem e = st.tri[t];
-    if (e.w && holds(e, x)) s[m++] = t;
-  }
+  row_candidates<F>(st, cm, x, h, s, 1, tot);
+  int m = tot;
   sort_unique(s, m);
   int* q = s + tot;
   int nq = 0;
@@ -856,8 +896,36 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
   st.cap[x] = make_int2(nn_cap, ne_cap);
 }
 
+// the three vertex ids of element t (its live flag not loaded)
+__device__ __forceinline__ Elem tri_ids(const Store& st, int t) {
+  const int* p = (const int*)(st.tri + t);
+  return make_int4(p[0], p[1], p[2], 1);
+}
+
 constexpr int kRegSmall = 16;  // rows up to this many candidates: the small register path
 constexpr int kRegRow = 32;    // up to this many: the large register path
+
+// wave-wide exclusive offsets into two counters, both atomics in flight together
+__device__ __forceinline__ int2 wave_add2(int* c0, int a0, int* c1, int a1) {
+  int lane = __lane_id();
+  int i0 = a0, i1 = a1;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int o0 = __shfl_up(i0, d), o1 = __shfl_up(i1, d);
+    if (lane >= d) {
+      i0 += o0;
+      i1 += o1;
+    }
+  }
+  int b0 = 0, b1 = 0;
+  if (lane == kWave - 1) {
+    if (i0 > 0) b0 = atomicAdd(c0, i0);
+    if (i1 > 0) b1 = atomicAdd(c1, i1);
+  }
+  b0 = __shfl(b0, kWave - 1);
+  b1 = __shfl(b1, kWave - 1);
+  return make_int2(b0 + i0 - a0, b1 + i1 - a1);
+}
 
 // Register path for rows of at most N candidates, staged in this thread's
 // LDS column (x < 0: idle lane). Every lane of the wavefront makes this call
@@ -889,15 +957,21 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
       prev = t;
     }
   }
-  int nx[N];
+  // next vertex of x in each element (and, for the small path, the previous
+  // one from the same load; the large path loads the elements again rather
+  // than hold both arrays)
+  constexpr bool kBoth = N <= kRegSmall;
+  int nx[N], pv[kBoth ? N : 1];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    nx[k] = INT_MAX;
-    if (k < m) {
-      Elem e = st.tri[col[k * S]];
-      int sl = slot_of(e, x);
-      nx[k] = at(e, sl == 2 ? 0 : sl + 1);
-    }
+    int t = k < m ? col[k * S] : -1;
+    Elem e = tri_ids(st, max(t, 0));
+    int sl = slot_of(e, x);
+    nx[k] = t >= 0 ? at(e, sl == 2 ? 0 : sl + 1) : INT_MAX;
+    if constexpr (kBoth) pv[k] = t >= 0 ? at(e, sl == 0 ? 2 : sl - 1) : -1;
+    // the large path keeps at most eight element loads in flight
+    if constexpr (!kBoth)
+      if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
   }
   bitonic<N>(nx);
   // previous vertices that are no next (one for a boundary vertex; more:
@@ -905,10 +979,15 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   int extra = INT_MAX, nextra = 0;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    if (k < m) {  // unrolled, so the element loads go out together
-      Elem e = st.tri[col[k * S]];
-      int sl = slot_of(e, x);
-      int b = at(e, sl == 0 ? 2 : sl - 1);
+    if (k < m) {
+      int b;
+      if constexpr (kBoth) {
+        b = pv[k];
+      } else {
+        Elem e = tri_ids(st, col[k * S]);
+        int sl = slot_of(e, x);
+        b = at(e, sl == 0 ? 2 : sl - 1);
+      }
       bool found = false;
 #pragma unroll
       for (int q = 0; q < N; ++q) found |= nx[q] == b;
@@ -927,24 +1006,23 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
   int ne_need = reg && m > ne_cap ? grown_cap(m) : 0;
   int nn_need = reg && nq > nn_cap ? grown_cap(nq) : 0;
-  int ne_at = wave_add_full(&ctr[C_NE_TOP], ne_need);
-  int nn_at = wave_add_full(&ctr[C_NN_TOP], nn_need);
+  int2 at2 = wave_add2(&ctr[C_NE_TOP], ne_need, &ctr[C_NN_TOP], nn_need);
   int lim_ne = m, lim_nn = nq;
   if (ne_need) {
-    if ((int64_t)ne_at + ne_need > st.ne_pool) {
+    if ((int64_t)at2.x + ne_need > st.ne_pool) {
       atomicOr(&ctr[C_ERR], E_NE_POOL);
       lim_ne = min(m, ne_cap);
     } else {
-      ne_off = ne_at;
+      ne_off = at2.x;
       ne_cap = ne_need;
     }
   }
   if (nn_need) {
-    if ((int64_t)nn_at + nn_need > st.nn_pool) {
+    if ((int64_t)at2.y + nn_need > st.nn_pool) {
       atomicOr(&ctr[C_ERR], E_NN_POOL);
       lim_nn = min(nq, nn_cap);
     } else {
-      nn_off = nn_at;
+      nn_off = at2.y;
       nn_cap = nn_need;
     }
   }
@@ -981,22 +1059,36 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
 // column: N slots, stride S) take the register path. Rows with more are
 // queued in the block's LDS queue bq when one is given (for the larger
 // register path after the small rows), else they and rows that are no disk
-// take the general path.
-template <int N, int S>
+// take the general path. A row's first visit (bq given) flags it for the
+// next round and, in small rounds, appends it to the list of rebuilt rows;
+// that append's atomic is in flight while the row is gathered.
+template <bool F, int N, int S>
 __device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, int x, int* col, int* ctr, int* bq,
                                             int* bqn) {
   bool act = x >= 0;
+  bool first = bq != nullptr;
+  int tbase = 0, tincl = 0;
+  if (first && cm.touched) {
+    int lane = __lane_id();
+    tincl = act ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      int o = __shfl_up(tincl, d);
+      if (lane >= d) tincl += o;
+    }
+    if (lane == kWave - 1 && tincl > 0) tbase = atomicAdd(&ctr[C_TOUCH], tincl);
+  }
   int tot = 0;
   Hdr h = make_int4(0, 0, 0, 0);
   int2 cp = make_int2(0, 0);
   if (act) {
     h = st.hdr[x];
     cp = st.cap[x];
-    tot = row_candidates(st, cm, x, h, col, S, N);
+    tot = row_candidates<F>(st, cm, x, h, col, S, N);
   }
   bool reg = act && tot <= N;
   bool later = false;
-  if (bq && act && !reg) {
+  if (first && act && !reg) {
     int slot = atomicAdd(bqn, 1);
     if (slot < kBlock) {
       bq[slot] = x;
@@ -1005,13 +1097,15 @@ __device__ __forceinline__ void rebuild_row(const Store& st, const Commit& cm, i
   }
   bool general = act && !reg && !later;
   if (__ballot(reg)) general |= rebuild_reg<N, S>(st, cm, reg ? x : -1, h, cp, tot, col, ctr);
-  if (general) rebuild_staged(st, cm, x, ctr);
-  bool done = act && !later;  // a queued row is counted when it is rebuilt
-  if (done) cm.nxt[x] = 1;
-  if (cm.touched) {
-    int slot = wave_add_full(&ctr[C_TOUCH], done ? 1 : 0);
-    if (done && slot < cm.touched_cap) cm.touched[slot] = x;
+  if (general) rebuild_staged<F>(st, cm, x, ctr);
+  if (first) {
+    if (act) cm.nxt[x] = 1;
+    if (cm.touched) {
+      int slot = __shfl(tbase, kWave - 1) + tincl - 1;
+      if (act && slot < cm.touched_cap) cm.touched[slot] = x;
+    }
   }
+  bool done = act && !later;  // a queued row is counted when it is rebuilt
   uint64_t rows = __ballot(done);
   if (__lane_id() == 0 && rows) {
     int* sp = stripe_ptr(ctr, 0);
@@ -1057,18 +1151,20 @@ static_assert(kRegSmall * kBlock == kRegRow * (kBlock / 2), "the large path stag
 // (cnt <= kBlock), with all kBlock threads of the block. Each thread takes
 // its member's neighbours kPairB at a time (row entries, then owner keys,
 // loaded side by side); the rows the member owns are queued in LDS in block
-// order and rebuilt 256 at a time. Flip members' own rows follow after the
-// last round, since the rounds read the members' rows.
+// order and rebuilt 256 at a time. For flips one more round queues the
+// members' own rows, after the rounds that read the members' rows.
+template <bool F>
 __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restrict__ list, int base, int cnt,
-                                             const Commit& cm, int flips, int* ctr, CommitLds& L) {
+                                             const Commit& cm, int* ctr, CommitLds& L) {
   int tid = (int)threadIdx.x;
   int v = -1, deg = 0, off = 0;
   bool com = false;
   if (tid < cnt) {
     v = list[base + tid];
-    com = cm.ops[v].x == cm.epoch;
+    int ep = cm.ops[v].x;
+    Hdr h = st.hdr[v];
+    com = ep == cm.epoch;
     if (com) {
-      Hdr h = st.hdr[v];
       deg = h.y;
       off = h.x;
     }
@@ -1076,13 +1172,26 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
   uint64_t key = own_key(cm.epoch, v);
   int* mycol = L.col + tid;
   if (tid == 0) L.bqn = 0;
-  for (int j0 = 0; __syncthreads_or(j0 < deg); j0 += kPairB) {
+  bool own_round = F;
+  for (int j0 = 0;; j0 += kPairB) {
+    bool pairs = __syncthreads_or(j0 < deg);
+    if (!pairs && !own_round) break;
     int y[kPairB];
-#pragma unroll
-    for (int q = 0; q < kPairB; ++q) y[q] = j0 + q < deg ? st.nn[off + j0 + q] : -1;
     uint64_t k[kPairB];
+    if (pairs) {
 #pragma unroll
-    for (int q = 0; q < kPairB; ++q) k[q] = y[q] >= 0 ? cm.own[y[q]] : 0ull;
+      for (int q = 0; q < kPairB; ++q) y[q] = j0 + q < deg ? st.nn[off + j0 + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kPairB; ++q) k[q] = y[q] >= 0 ? cm.own[y[q]] : 0ull;
+    } else {
+      own_round = false;
+#pragma unroll
+      for (int q = 0; q < kPairB; ++q) y[q] = -1;
+      if (com) y[0] = v;
+      k[0] = com ? cm.own[v] : 0ull;
+#pragma unroll
+      for (int q = 1; q < kPairB; ++q) k[q] = 0ull;
+    }
     int mine = 0;
 #pragma unroll
     for (int q = 0; q < kPairB; ++q) mine += (y[q] >= 0 && k[q] == key) ? 1 : 0;
@@ -1093,12 +1202,7 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
       if (y[q] >= 0 && k[q] == key) L.q[at++] = y[q];
     __syncthreads();
     for (int r0 = 0; r0 < tot; r0 += kBlock)
-      rebuild_row<kRegSmall, kBlock>(st, cm, r0 + tid < tot ? L.q[r0 + tid] : -1, mycol, ctr, L.bq, &L.bqn);
-  }
-  if (flips) {
-    __syncthreads();
-    int x = (com && cm.own[v] == key) ? v : -1;
-    rebuild_row<kRegSmall, kBlock>(st, cm, x, mycol, ctr, L.bq, &L.bqn);
+      rebuild_row<F, kRegSmall, kBlock>(st, cm, r0 + tid < tot ? L.q[r0 + tid] : -1, mycol, ctr, L.bq, &L.bqn);
   }
   // rows of more than kRegSmall candidates, half the block at a time
   __syncthreads();
@@ -1106,25 +1210,30 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
   constexpr int H = kBlock / 2;
   for (int b0 = 0; b0 < nbig; b0 += H) {
     int x = (tid < H && b0 + tid < nbig) ? L.bq[b0 + tid] : -1;
-    rebuild_row<kRegRow, H>(st, cm, x, L.col + (tid & (H - 1)), ctr, nullptr, nullptr);
+    rebuild_row<F, kRegRow, H>(st, cm, x, L.col + (tid & (H - 1)), ctr, nullptr, nullptr);
   }
   __syncthreads();  // the LDS is reused by the next chunk
 }
 
 // One block per mpb class members (128, or fewer for small classes, so that
-// more blocks share the latency-bound work), in XCD-aware block order.
+// more blocks share the latency-bound work), in XCD-aware block order; one
+// kernel per kind of operation.
+template <bool F>
 __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
-                                                int flips, int* ctr) {
+                                                int* ctr) {
   __shared__ CommitLds L;
   int base = xcd_block() * mpb;
-  commit_chunk(st, list, base, min(mpb, n - base), cm, flips, ctr, L);
+  commit_chunk<F>(st, list, base, min(mpb, n - base), cm, ctr, L);
 }
 
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s) {
   if (n <= 0) return;
   int mpb = n >= 256 * 1024 ? 128 : (n >= 64 * 1024 ? 64 : 16);
   int nb = (n + mpb - 1) / mpb;
-  k_commit<<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, flips ? 1 : 0, ctr);
+  if (flips)
+    k_commit<true><<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, ctr);
+  else
+    k_commit<false><<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, ctr);
 }
 
 
@@ -1809,51 +1918,37 @@ void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, 
 // A small class in one block: the operation (collapse or flips on groups of
 // kGC lanes per member), a block barrier, then the commit of the same
 // members; one launch instead of two. Every thread reaches every barrier.
+template <bool F>
 __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
-                                                     Commit cm, int kind, int* ctr) {
+                                                     Commit cm, int* ctr) {
   __shared__ CommitLds L;
   int tid = (int)threadIdx.x;
   if (tid == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
-  if (kind == 0) {
-    Grp g = grp_of<kGC>();
-    for (int p0 = 0; p0 < n; p0 += kBlock / kGC) {
-      int gid = p0 + tid / kGC;
-      int status = -1;
-      if (gid < n) {
-        int v = list[gid];
-        Hdr h = st.hdr[v];
-        if (h.y > kGC || h.w > kGC) {
-          if (g.j == 0) status = collapse_one(st, v, a, cm, ctr);
-        } else {
-          int r = collapse_group<kGC>(st, v, h, a, cm, ctr, g);
-          if (g.j == 0) status = r;
-        }
+  Grp g = grp_of<kGC>();
+  for (int p0 = 0; p0 < n; p0 += kBlock / kGC) {
+    int gid = p0 + tid / kGC;
+    int status = -1;
+    if (gid < n) {
+      int v = list[gid];
+      Hdr h = st.hdr[v];
+      if (h.y > kGC || h.w > kGC) {
+        if (g.j == 0) status = F ? flip_one(st, v, a, cm, ctr) : collapse_one(st, v, a, cm, ctr);
+      } else {
+        int r = F ? flip_group<kGC>(st, v, h, a, cm, g) : collapse_group<kGC>(st, v, h, a, cm, ctr, g);
+        if (g.j == 0) status = r;
       }
-      count_status(status, ctr);
     }
-  } else {
-    Grp g = grp_of<kGC>();
-    for (int p0 = 0; p0 < n; p0 += kBlock / kGC) {
-      int gid = p0 + tid / kGC;
-      int status = -1;
-      if (gid < n) {
-        int v = list[gid];
-        Hdr h = st.hdr[v];
-        if (h.y > kGC || h.w > kGC) {
-          if (g.j == 0) status = flip_one(st, v, a, cm, ctr);
-        } else {
-          int r = flip_group<kGC>(st, v, h, a, cm, g);
-          if (g.j == 0) status = r;
-        }
-      }
-      count_status(status, ctr);
-    }
+    count_status(status, ctr);
   }
   __syncthreads();
-  for (int base = 0; base < n; base += kBlock) commit_chunk(st, list, base, min(kBlock, n - base), cm, kind, ctr, L);
+  for (int base = 0; base < n; base += kBlock) commit_chunk<F>(st, list, base, min(kBlock, n - base), cm, ctr, L);
 }
 void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
-  if (n > 0) k_class_small<<<1, kBlock, 0, s>>>(st, list, n, a, cm, kind, ctr);
+  if (n <= 0) return;
+  if (kind)
+    k_class_small<true><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+  else
+    k_class_small<false><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
 
 // ---- adjoint with lane groups ---------------------------------------------------------------------
