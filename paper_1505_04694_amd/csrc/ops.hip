@@ -1557,16 +1557,19 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   double2 pv = st.xy[v];
   Met mv = st.met[v];
   bool ownn = g.j < h.y, owne = g.j < h.w;
-  double2 pw = make_double2(0.0, 0.0);
-  Met mw{0.0, 0.0, 0.0};
-  if (ownn) {
-    int w = st.nn[h.x + g.j];
-    pw = st.xy[w];
-    mw = st.met[w];
+  // row entries, then neighbour data and elements, then the elements'
+  // vertex data, each level issued together (index 0 for an empty lane)
+  int w = ownn ? st.nn[h.x + g.j] : -1;
+  int t = owne ? st.ne[h.z + g.j] : -1;
+  double2 pw = st.xy[max(w, 0)];
+  Met mw = st.met[max(w, 0)];
+  Elem e = st.tri[max(t, 0)];
+  if (!ownn) {
+    pw = make_double2(0.0, 0.0);
+    mw = Met{0.0, 0.0, 0.0};
   }
-  PatchElem pe;
-  if (owne) pe = load_patch_elem(st, st.tri[st.ne[h.z + g.j]], v);
-  else pe = PatchElem{};
+  PatchElem pe = load_patch_elem(st, e, v);
+  if (!owne) pe = PatchElem{};
   double2 p;
   if (kind == 0) {
     double ea = (mv.a + mw.a) * 0.5;
@@ -1645,41 +1648,44 @@ __device__ __forceinline__ bool gany_of(bool p, const Grp& g) {
 template <int G>
 __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm, int* ctr, const Grp& g) {
   bool ownn = g.j < h.y, owne = g.j < h.w;
+  // loads by dependency level, each level issued together (index 0 stands
+  // in for a lane with no neighbour or element): the member's own data and
+  // its rows' entries; then each neighbour's round word and data and each
+  // element; the deferral test comes after them
   uint64_t rv = a.rw[v];
-  int w = -1;
-  bool beat = false;
-  if (ownn) {
-    w = st.nn[h.x + g.j];
-    beat = same_class_beats(a, w, rv, v);
-  }
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  uint8_t tv = st.tag[v];
+  int w = ownn ? st.nn[h.x + g.j] : -1;
+  int t = owne ? st.ne[h.z + g.j] : -1;
+  int ws = max(w, 0);
+  uint64_t xw = a.rw[ws];
+  double2 pw = st.xy[ws];
+  Met mw = st.met[ws];
+  uint8_t tw = st.tag[ws];
+  Elem e = st.tri[max(t, 0)];
+  bool beat = ownn && (xw & kRwAct) && (int)(xw & 0xFF) == a.cls && rw_beats(xw, w, rv, v);
   if (gany_of<G>(beat, g)) {
     if (g.j == 0) cm.nxt[v] = 1;
     return 0;
   }
-  double2 pv = st.xy[v];
-  Met mv = st.met[v];
-  uint8_t tv = st.tag[v];
-  double2 pw = make_double2(0.0, 0.0);
-  Met mw{0.0, 0.0, 0.0};
   double L = INFINITY;
   bool cand = false;
   if (ownn) {
-    pw = st.xy[w];
-    mw = st.met[w];
-    if (!(tv & ~st.tag[w])) {
+    if (!(tv & ~tw)) {
       L = len2(pv, mv, pw, mw);
       cand = L < a.L_low2;
     }
+  } else {
+    pw = make_double2(0.0, 0.0);
+    mw = Met{0.0, 0.0, 0.0};
   }
   // element lane: ids and data of the element's other two vertices
-  int t = -1;
-  Elem e = make_int4(0, 0, 0, 0);
   double2 q0 = make_double2(0.0, 0.0), q1 = q0;
   Met n0{0.0, 0.0, 0.0}, n1 = n0;
   int o0 = -1, o1 = -1, k = 0;
+  if (!owne) e = make_int4(0, 0, 0, 0);
   if (owne) {
-    t = st.ne[h.z + g.j];
-    e = st.tri[t];
     k = slot_of(e, v);
     o0 = at(e, k == 2 ? 0 : k + 1);  // next after v
     o1 = at(e, k == 0 ? 2 : k - 1);  // before v
@@ -1787,20 +1793,25 @@ template <int G>
 __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const OpArgs& a, const Commit& cm,
                                           const Grp& g) {
   bool ownn = g.j < h.y, owne = g.j < h.w;
+  // loads by dependency level, each level issued together: the member's
+  // data and its rows' entries, then the neighbours' round words and the
+  // elements; the deferral test comes after them
   uint64_t rv = a.rw[v];
-  bool beat = ownn && same_class_beats(a, st.nn[h.x + g.j], rv, v);
+  double2 pv = st.xy[v];
+  Met mv = st.met[v];
+  int y = ownn ? st.nn[h.x + g.j] : -1;
+  int T1 = owne ? st.ne[h.z + g.j] : -1;
+  uint64_t ry = a.rw[max(y, 0)];
+  Elem e1 = st.tri[max(T1, 0)];
+  bool beat = ownn && (ry & kRwAct) && (int)(ry & 0xFF) == a.cls && rw_beats(ry, y, rv, v);
   if (gany_of<G>(beat, g)) {
     if (g.j == 0) cm.nxt[v] = 1;
     return 0;
   }
-  double2 pv = st.xy[v];
-  Met mv = st.met[v];
-  int T1 = -1, k1 = 0, w = -1, av = -1;
+  int k1 = 0, w = -1, av = -1;
   double2 pw = make_double2(0.0, 0.0), pa = pw;
   Met mw{0.0, 0.0, 0.0}, ma = mw;
   if (owne) {
-    T1 = st.ne[h.z + g.j];
-    Elem e1 = st.tri[T1];
     k1 = slot_of(e1, v);
     w = at(e1, k1 == 2 ? 0 : k1 + 1);
     av = at(e1, k1 == 0 ? 2 : k1 - 1);
