@@ -934,12 +934,21 @@ pm_status pm_mesh_rows(pm_mesh* m, int64_t* nn_total, int64_t* ne_total, int64_t
   if (!m || !nn_total || !ne_total) return PM_E_ARG;
   Store& st = m->st;
   std::vector<Hdr> hdr(st.V);
+  std::vector<int2> cap(st.V);
   HIPCHK(hipMemcpyAsync(hdr.data(), st.hdr, sizeof(Hdr) * st.V, hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipMemcpyAsync(cap.data(), st.cap, sizeof(int2) * st.V, hipMemcpyDeviceToHost, m->s));
   TRY(sync(m));
   int64_t a = 0, b = 0;
   for (int v = 0; v < st.V; ++v) {
     a += hdr[v].y;
     b += hdr[v].w;
+    // the row layout the kernels rely on: slots start at multiples of four
+    // entries, hold a multiple of four, and hold their row
+    const Hdr& h = hdr[v];
+    const int2& c = cap[v];
+    bool ok = h.x % 4 == 0 && h.z % 4 == 0 && c.x % 4 == 0 && c.y % 4 == 0 && h.y <= c.x && h.w <= c.y &&
+              (int64_t)h.x + c.x <= st.nn_pool && (int64_t)h.z + c.y <= st.ne_pool;
+    if (!ok) return fail(m, PM_E_DEVICE, "row slot of vertex " + std::to_string(v) + " breaks the layout");
   }
   *nn_total = a;
   *ne_total = b;

@@ -203,6 +203,26 @@ __device__ __forceinline__ int wave_add_full(int* counter, int amount) {
   return base + incl - amount;
 }
 
+// Entries [off, off + 8) of a row slot holding cnt entries there (-1 past
+// them), as two 16-byte loads: slots start at multiples of four entries and
+// hold a multiple of four, so neither load leaves the slot.
+__device__ __forceinline__ void row8(const int* pool, int off, int cnt, int (&t)[8]) {
+  int4 a = make_int4(-1, -1, -1, -1), b = a;
+  if (cnt > 0) a = *(const int4*)(pool + off);
+  if (cnt > 4) b = *(const int4*)(pool + off + 4);
+  t[0] = a.x;
+  t[1] = a.y;
+  t[2] = a.z;
+  t[3] = a.w;
+  t[4] = b.x;
+  t[5] = b.y;
+  t[6] = b.z;
+  t[7] = b.w;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    if (q >= cnt) t[q] = -1;
+}
+
 // XCD-aware block order. Work-groups are dealt to the 8 XCDs in turn (block b
 // runs on XCD b % 8), and each XCD has its own L2. Renumbering blocks so that
 // every XCD receives one contiguous eighth of the grid keeps neighbouring work

@@ -114,8 +114,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& b
   for (int j0 = 0; j0 < h.y; j0 += B) {
     int w[B];
     uint64_t x[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+    row8(st.nn, h.x + j0, h.y - j0, w);
 #pragma unroll
     for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_get(rd.rw, w[q]) : 0ull;
     int wait = -1;
@@ -707,7 +706,7 @@ void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, in
 // a branch. Longer rows go through the same steps B entries at a time.
 // Filtering here keeps the candidate count at the new row's size (a collapse
 // target's old row and the absorbed row share only the two elements that die).
-constexpr int kCandB = 8;
+constexpr int kCandB = 8;  // row entries per batch (two 16-byte loads)
 __device__ __forceinline__ bool keeps(const Elem& e, int x) { return e.w && holds(e, x); }
 
 template <bool F>
@@ -732,8 +731,7 @@ __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm,
   auto absorb = [&](int z, int cnt) {
     for (int k0 = 0; k0 < cnt; k0 += B) {
       int t[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) t[q] = k0 + q < cnt ? st.ne[z + k0 + q] : -1;
+      row8(st.ne, z + k0, cnt - k0, t);
       put_live(t);
     }
   };
@@ -782,23 +780,19 @@ __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm,
   int4 rx = F ? cm.ops[x] : make_int4(0, 0, 0, 0);
   if (h.w <= B && h.y <= B) {
     int t[B], w[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) t[q] = q < h.w ? st.ne[h.z + q] : -1;
-#pragma unroll
-    for (int q = 0; q < B; ++q) w[q] = q < h.y ? st.nn[h.x + q] : -1;
+    row8(st.ne, h.z, h.w, t);
+    row8(st.nn, h.x, h.y, w);
     put_live(t);
     scan_records(w);
   } else {
     for (int k0 = 0; k0 < h.w; k0 += B) {
       int t[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) t[q] = k0 + q < h.w ? st.ne[h.z + k0 + q] : -1;
+      row8(st.ne, h.z + k0, h.w - k0, t);
       put_live(t);
     }
     for (int j0 = 0; j0 < h.y; j0 += B) {
       int w[B];
-#pragma unroll
-      for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+      row8(st.nn, h.x + j0, h.y - j0, w);
       scan_records(w);
     }
   }
@@ -1029,7 +1023,10 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   uint64_t rel = __ballot(ne_need > 0), rel2 = __ballot(nn_need > 0);
   if (__lane_id() == 0 && (rel | rel2)) atomicAdd(stripe_ptr(ctr, S_RELOC), __popcll(rel) + __popcll(rel2));
   if (reg) {
-    for (int k = 0; k < lim_ne; ++k) st.ne[ne_off + k] = col[k * S];
+    // NE(x) four entries per store (the slot holds a multiple of four; the
+    // entries past the row are padding)
+    for (int k = 0; k < lim_ne; k += 4)
+      *(int4*)(st.ne + ne_off + k) = make_int4(col[k * S], col[(k + 1) * S], col[(k + 2) * S], col[(k + 3) * S]);
     int w = 0;
     bool put = nextra == 0;
 #pragma unroll
@@ -1137,7 +1134,7 @@ __device__ __forceinline__ int block_scan(int x, int& excl, int* wsum) {
 }
 
 // LDS of one commit block
-constexpr int kPairB = 8;  // neighbours per member taken per pair round
+constexpr int kPairB = 8;  // neighbours per member taken per pair round (two 16-byte loads)
 struct CommitLds {
   int col[kRegSmall * kBlock];  // candidate staging: kRegSmall per thread, or kRegRow for half the threads
   int q[kPairB * kBlock];       // rows queued in a pair round
@@ -1179,8 +1176,7 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
     int y[kPairB];
     uint64_t k[kPairB];
     if (pairs) {
-#pragma unroll
-      for (int q = 0; q < kPairB; ++q) y[q] = j0 + q < deg ? st.nn[off + j0 + q] : -1;
+      row8(st.nn, off + j0, deg - j0, y);
 #pragma unroll
       for (int q = 0; q < kPairB; ++q) k[q] = y[q] >= 0 ? cm.own[y[q]] : 0ull;
     } else {
