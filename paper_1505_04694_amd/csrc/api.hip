@@ -63,6 +63,8 @@ struct pm_mesh {
   int sel_mark = 0;      // selection stamp, one per small round
   DBuf<int4> ops;        // commit: operation records
   DBuf<uint64_t> own;    // commit: row owner keys
+  DBuf<uint64_t> tk;     // commit: collapse-target counts
+  DBuf<int4> tgt;        // commit: collapse-target records
   int epoch = 0;         // commit epoch, one per class
   DBuf<double> qpart;
   DBuf<uint64_t> rw;  // round words (priority, active, colour) per vertex
@@ -460,6 +462,8 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->touch, std::max(V, 65536)));
   TRY(ensure(m, m->seen, V, true));
   TRY(ensure(m, m->own, V, true));
+  TRY(ensure(m, m->tk, V, true));
+  TRY(ensure(m, m->tgt, V));
   TRY(ensure(m, m->sflag, V));
   TRY(ensure(m, m->spos, V));
   TRY(ensure(m, m->spart, scan_partials_needed(V) + 2));
@@ -477,6 +481,8 @@ Commit commit_of(pm_mesh* m) {
   c.touched = nullptr;
   c.touched_cap = (int)std::min<size_t>(m->touch.n, INT32_MAX);
   c.own = m->own.p;
+  c.tk = m->tk.p;
+  c.tgt = m->tgt.p;
   c.stage = m->stage.p;
   c.stage_cap = (int64_t)m->stage.n;
   c.nxt = m->nxt.p;
@@ -827,6 +833,8 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->qpart.p, m->qpart.n);
   dfree(m, m->rw.p, m->rw.n);
   dfree(m, m->own.p, m->own.n);
+  dfree(m, m->tk.p, m->tk.n);
+  dfree(m, m->tgt.p, m->tgt.n);
   dfree(m, m->ops.p, m->ops.n);
   prof_flush(m);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);

@@ -181,6 +181,11 @@ struct Commit {
   // flip (epoch, t1, t2, 0) with its two elements
   int4* ops;
   uint64_t* own;   // V: row owner key, maximised: (epoch << 32) | ~member
+  // V: collapses onto the vertex, (epoch << 32) | count, and the last one's
+  // (member, ne_off, ne_cnt, epoch): a collapse target finds the row it
+  // absorbs without reading its neighbours' records
+  uint64_t* tk;
+  int4* tgt;
   int* stage;      // staging for rows past the register paths
   int64_t stage_cap;
   int* touched;    // small rounds: every row rebuilt, for the list-based selection (else null)

@@ -473,6 +473,14 @@ __device__ __forceinline__ void claim_row(const Commit& cm, int x, int v) {
 __device__ __forceinline__ void stamp(const Commit& cm, int v, int a, int b, int c) {
   cm.ops[v] = make_int4(cm.epoch, a, b, c);
 }
+// member v collapses onto u, handing over its NE row (ne_off, ne_cnt): the
+// count's epoch is raised first (a count of an older epoch restarts at zero)
+__device__ __forceinline__ void mark_target(const Commit& cm, int u, int v, int ne_off, int ne_cnt) {
+  cm.tgt[u] = make_int4(v, ne_off, ne_cnt, cm.epoch);
+  unsigned long long e = (unsigned long long)(uint32_t)cm.epoch << 32;
+  atomicMax((unsigned long long*)&cm.tk[u], e);
+  atomicAdd((unsigned long long*)&cm.tk[u], 1ull);
+}
 
 // a member is deferred when a same-class active neighbour has a larger key
 __device__ __forceinline__ bool same_class_beats(const OpArgs& a, int w, uint64_t rv, int v) {
@@ -588,6 +596,7 @@ __device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs
   }
   st.valive[v] = 0;
   stamp(cm, v, -(u + 1), h.z, h.w);
+  mark_target(cm, u, v, h.z, h.w);
   for (int j = 0; j < h.y; ++j) claim_row(cm, st.nn[h.x + j], v);
   return 2;
 }
@@ -735,83 +744,77 @@ __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm,
       put_live(t);
     }
   };
-  // the records of neighbours w[0 .. B) (w < 0: none), loaded side by side:
-  // flips hand over their two elements (taken four records at a time);
-  // collapses onto x are counted, and the first one's NE range is fetched
-  int targets = 0, tw = -1;
-  auto scan_records = [&](const int (&w)[B]) {
-    if (F) {
-#pragma unroll
-      for (int q0 = 0; q0 < B; q0 += B / 2) {
-        int4 r[B / 2];
-#pragma unroll
-        for (int q = 0; q < B / 2; ++q) r[q] = cm.ops[max(w[q0 + q], 0)];
-        int f0[B / 2], f1[B / 2];
-#pragma unroll
-        for (int q = 0; q < B / 2; ++q) {
-          bool c = w[q0 + q] >= 0 && r[q].x == cm.epoch && r[q].y >= 0;
-          f0[q] = c ? r[q].y : -1;
-          f1[q] = c ? r[q].z : -1;
-        }
-        Elem e0[B / 2], e1[B / 2];
-#pragma unroll
-        for (int q = 0; q < B / 2; ++q) e0[q] = st.tri[max(f0[q], 0)];
-#pragma unroll
-        for (int q = 0; q < B / 2; ++q) e1[q] = st.tri[max(f1[q], 0)];
-#pragma unroll
-        for (int q = 0; q < B / 2; ++q) {
-          if (f0[q] >= 0 && keeps(e0[q], x)) put(f0[q]);
-          if (f1[q] >= 0 && keeps(e1[q], x)) put(f1[q]);
-        }
+  if (!F) {
+    // collapses onto x: their count (this epoch's, else none) and the last
+    // one's NE range
+    uint64_t tk = cm.tk[x];
+    int4 tg = cm.tgt[x];
+    int nt = (uint32_t)(tk >> 32) == (uint32_t)cm.epoch ? (int)(uint32_t)tk : 0;
+    if (h.w <= B && (nt == 0 || (nt == 1 && tg.z <= B))) {
+      // the entries of NE(x) and of the absorbed row side by side, then the
+      // elements of each
+      int t[B], u[B];
+      row8(st.ne, h.z, h.w, t);
+      row8(st.ne, tg.y, nt == 1 ? tg.z : 0, u);
+      put_live(t);
+      if (nt == 1) put_live(u);
+      return n;
+    }
+    absorb(h.z, h.w);
+    if (nt == 1) {
+      absorb(tg.y, tg.z);
+    } else if (nt > 1) {
+      // several members collapsed onto x: their ranges, from their records
+      for (int j = 0; j < h.y; ++j) {
+        int4 r = cm.ops[st.nn[h.x + j]];
+        if (r.x == cm.epoch && r.y == -x - 1) absorb(r.z, r.w);
       }
-    } else {
-      int2 r[B];
+    }
+    return n;
+  }
+  // flips: NE(x), and the two elements of every committed flip around x
+  // (x's own and its neighbours'), four neighbour records at a time
+  int4 rx = cm.ops[x];
+  auto scan_flips = [&](const int (&w)[B]) {
 #pragma unroll
-      for (int q = 0; q < B; ++q) r[q] = *(const int2*)&cm.ops[max(w[q], 0)];
+    for (int q0 = 0; q0 < B; q0 += B / 2) {
+      int4 r[B / 2];
 #pragma unroll
-      for (int q = 0; q < B; ++q) {
-        if (w[q] >= 0 && r[q].x == cm.epoch && r[q].y == -x - 1) {
-          if (targets == 0) tw = w[q];
-          ++targets;
-        }
+      for (int q = 0; q < B / 2; ++q) r[q] = cm.ops[max(w[q0 + q], 0)];
+      int f0[B / 2], f1[B / 2];
+#pragma unroll
+      for (int q = 0; q < B / 2; ++q) {
+        bool c = w[q0 + q] >= 0 && r[q].x == cm.epoch && r[q].y >= 0;
+        f0[q] = c ? r[q].y : -1;
+        f1[q] = c ? r[q].z : -1;
+      }
+      Elem e0[B / 2], e1[B / 2];
+#pragma unroll
+      for (int q = 0; q < B / 2; ++q) e0[q] = st.tri[max(f0[q], 0)];
+#pragma unroll
+      for (int q = 0; q < B / 2; ++q) e1[q] = st.tri[max(f1[q], 0)];
+#pragma unroll
+      for (int q = 0; q < B / 2; ++q) {
+        if (f0[q] >= 0 && keeps(e0[q], x)) put(f0[q]);
+        if (f1[q] >= 0 && keeps(e1[q], x)) put(f1[q]);
       }
     }
   };
-  int4 rx = F ? cm.ops[x] : make_int4(0, 0, 0, 0);
   if (h.w <= B && h.y <= B) {
     int t[B], w[B];
     row8(st.ne, h.z, h.w, t);
     row8(st.nn, h.x, h.y, w);
     put_live(t);
-    scan_records(w);
+    scan_flips(w);
   } else {
-    for (int k0 = 0; k0 < h.w; k0 += B) {
-      int t[B];
-      row8(st.ne, h.z + k0, h.w - k0, t);
-      put_live(t);
-    }
+    absorb(h.z, h.w);
     for (int j0 = 0; j0 < h.y; j0 += B) {
       int w[B];
       row8(st.nn, h.x + j0, h.y - j0, w);
-      scan_records(w);
+      scan_flips(w);
     }
   }
-  if (!F) {
-    if (targets > 0) {
-      int4 r = cm.ops[tw];
-      absorb(r.z, r.w);
-    }
-    // several members collapsed onto x: the further ranges, by a plain scan
-    if (targets > 1) {
-      int seen = 0;
-      for (int j = 0; j < h.y; ++j) {
-        int4 r = cm.ops[st.nn[h.x + j]];
-        if (r.x != cm.epoch || r.y != -x - 1) continue;
-        if (seen++ > 0) absorb(r.z, r.w);
-      }
-    }
-  } else if (rx.x == cm.epoch && rx.y >= 0) {
-    // x's own flip
+  if (rx.x == cm.epoch && rx.y >= 0) {
     Elem a = st.tri[rx.y], b = st.tri[rx.z];
     if (keeps(a, x)) put(rx.y);
     if (keeps(b, x)) put(rx.z);
@@ -1752,6 +1755,7 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
   if (g.j == 0) {
     st.valive[v] = 0;
     stamp(cm, v, -(u + 1), h.z, h.w);
+    mark_target(cm, u, v, h.z, h.w);
   }
   return 2;
 }
