@@ -1436,7 +1436,7 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
   if (n <= 0) return;
   if (variant == 1)
@@ -1504,16 +1504,26 @@ struct PatchElem {
   int k;
 };
 
-__device__ __forceinline__ PatchElem load_patch_elem(const Store& st, const Elem& e, int v) {
+// element t = e of v's patch; the mean tensor from the per-element array
+// when present (the same value, computed once per phase), else from the
+// three vertices
+__device__ __forceinline__ PatchElem load_patch_elem(const Store& st, int t, const Elem& e, int v) {
   PatchElem pe;
   double2 p0 = st.xy[e.x], p1 = st.xy[e.y], p2 = st.xy[e.z];
-  Met m0 = st.met[e.x], m1 = st.met[e.y], m2 = st.met[e.z];
   pe.x0 = p0.x; pe.y0 = p0.y;
   pe.x1 = p1.x; pe.y1 = p1.y;
   pe.x2 = p2.x; pe.y2 = p2.y;
-  pe.a = ((m0.a + m1.a) + m2.a) / 3.0;
-  pe.b = ((m0.b + m1.b) + m2.b) / 3.0;
-  pe.c = ((m0.c + m1.c) + m2.c) / 3.0;
+  if (st.emet) {
+    Met m = st.emet[t];
+    pe.a = m.a;
+    pe.b = m.b;
+    pe.c = m.c;
+  } else {
+    Met m0 = st.met[e.x], m1 = st.met[e.y], m2 = st.met[e.z];
+    pe.a = ((m0.a + m1.a) + m2.a) / 3.0;
+    pe.b = ((m0.b + m1.b) + m2.b) / 3.0;
+    pe.c = ((m0.c + m1.c) + m2.c) / 3.0;
+  }
   pe.k = slot_of(e, v);
   return pe;
 }
@@ -1567,7 +1577,7 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
     pw = make_double2(0.0, 0.0);
     mw = Met{0.0, 0.0, 0.0};
   }
-  PatchElem pe = load_patch_elem(st, e, v);
+  PatchElem pe = load_patch_elem(st, max(t, 0), e, v);
   if (!owne) pe = PatchElem{};
   double2 p;
   if (kind == 0) {
@@ -1614,7 +1624,7 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   return true;
 }
 
-__global__ void __launch_bounds__(256) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
   Grp g = grp();
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
