@@ -56,6 +56,7 @@ struct pm_mesh {
   DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
   DBuf<uint8_t> nxt, u8tmp;
   DBuf<Met> emet;   // smoothing: per-element mean tensors
+  DBuf<VRec> vr;    // coarsening and swapping: vertex records
   DBuf<int> sflag, spos, ctab, ctabs, spart;  // ordered selection and stable class lists
   DBuf<int> stage;       // commit: fallback staging
   DBuf<int> touch, seen; // small rounds: rows rebuilt, selection stamps
@@ -676,7 +677,6 @@ bool bad_opts(const pm_options* o) {
          o->variant < 0 || o->variant > 15;
 }
 
-// rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1)
 // Collapse runs on groups of lanes per member by default: each lane loads
 // one neighbour and one element of the member's 1-ring side by side and
 // keeps it in registers, so a member costs a few dependent loads and no
@@ -690,7 +690,20 @@ int collapse_shape(const pm_mesh* m, int n) {
   return 1;
 }
 
+pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind);
+
+// rounds of colour -> classes -> op + commit (coarsen: kind 0, swap: kind 1);
+// vertices stay fixed through the rounds, so their records are built once
 pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
+  TRY(ensure(m, m->vr, (size_t)std::max(m->st.V, 1)));
+  vertex_records(m->st, m->vr.p, m->s);
+  m->st.vr = m->vr.p;
+  pm_status r = run_rounds_in(m, o, st, kind);
+  m->st.vr = nullptr;
+  return r;
+}
+
+pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   TRY(ensure_phase_scratch(m));
   m->variant = o->variant;
   int mode = kind == 0 ? 1 : 2;
@@ -829,6 +842,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   for (auto* b : ib) dfree(m, b->p, b->n);
   DBuf<uint8_t>* ub[] = {&m->nxt, &m->u8tmp};
   dfree(m, m->emet.p, m->emet.n);
+  dfree(m, m->vr.p, m->vr.n);
   for (auto* b : ub) dfree(m, b->p, b->n);
   dfree(m, m->qpart.p, m->qpart.n);
   dfree(m, m->rw.p, m->rw.n);

@@ -16,6 +16,16 @@ struct Met {
   double a, b, c;  // [[a, b], [b, c]]
 };
 
+// a vertex's coordinates, metric and boundary tag in one 64-byte line, for
+// the kernels that gather them for many neighbours at once
+struct alignas(64) VRec {
+  double x, y;
+  double a, b, c;
+  int tag;
+  int pad0;
+  double pad1, pad2;
+};
+
 // element: three vertex ids, counter-clockwise, smallest id first; w = 1 live
 typedef int4 Elem;
 

@@ -92,6 +92,9 @@ struct Store {
   int* mdone = nullptr;  // B flags: mesh finished refining (refinement skips it); may be null
   // per-element mean tensor, valid while topology and metrics are fixed (smoothing); may be null
   Met* emet = nullptr;
+  // V: coordinates, metric and tag per vertex in one line, valid while
+  // vertices stay fixed (coarsening and swapping rounds); may be null
+  VRec* vr = nullptr;
 };
 
 // local id of a vertex within its mesh (priorities are drawn per mesh)
@@ -253,6 +256,7 @@ void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);
 void quality_per_mesh(const Store& st, double* out, hipStream_t s);
 void element_metrics(const Store& st, Met* out, hipStream_t s);
+void vertex_records(const Store& st, VRec* out, hipStream_t s);
 void fp64_probe(const double* a, const double* b, int n, double* q, double* r, hipStream_t s);
 
 }  // namespace pm

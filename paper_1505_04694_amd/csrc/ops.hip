@@ -1253,6 +1253,27 @@ void element_metrics(const Store& st, Met* out, hipStream_t s) {
   k_elem_metric<<<grid_for(st.T), kBlock, 0, s>>>(st, out);
 }
 
+__global__ void k_vertex_records(Store st, VRec* __restrict__ out) {
+  for (int v = gtid(); v < st.V; v += gstride()) {
+    double2 p = st.xy[v];
+    Met m = st.met[v];
+    VRec r;
+    r.x = p.x;
+    r.y = p.y;
+    r.a = m.a;
+    r.b = m.b;
+    r.c = m.c;
+    r.tag = st.tag[v];
+    r.pad0 = 0;
+    r.pad1 = 0.0;
+    r.pad2 = 0.0;
+    out[v] = r;
+  }
+}
+void vertex_records(const Store& st, VRec* out, hipStream_t s) {
+  if (st.V > 0) k_vertex_records<<<grid_for(st.V), kBlock, 0, s>>>(st, out);
+}
+
 // element t's geometry with vertex v at p; the mean tensor comes from the
 // per-element array when present (the same value, computed once)
 __device__ __forceinline__ Geo patch_elem_geo(const Store& st, int t, const Elem& e, int v, double2 p) {
@@ -1662,16 +1683,18 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
   // its rows' entries; then each neighbour's round word and data and each
   // element; the deferral test comes after them
   uint64_t rv = a.rw[v];
-  double2 pv = st.xy[v];
-  Met mv = st.met[v];
-  uint8_t tv = st.tag[v];
+  VRec rcv = st.vr[v];
+  double2 pv = make_double2(rcv.x, rcv.y);
+  Met mv{rcv.a, rcv.b, rcv.c};
+  int tv = rcv.tag;
   int w = ownn ? st.nn[h.x + g.j] : -1;
   int t = owne ? st.ne[h.z + g.j] : -1;
   int ws = max(w, 0);
   uint64_t xw = a.rw[ws];
-  double2 pw = st.xy[ws];
-  Met mw = st.met[ws];
-  uint8_t tw = st.tag[ws];
+  VRec rcw = st.vr[ws];
+  double2 pw = make_double2(rcw.x, rcw.y);
+  Met mw{rcw.a, rcw.b, rcw.c};
+  int tw = rcw.tag;
   Elem e = st.tri[max(t, 0)];
   bool beat = ownn && (xw & kRwAct) && (int)(xw & 0xFF) == a.cls && rw_beats(xw, w, rv, v);
   if (gany_of<G>(beat, g)) {
@@ -1698,10 +1721,11 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
     k = slot_of(e, v);
     o0 = at(e, k == 2 ? 0 : k + 1);  // next after v
     o1 = at(e, k == 0 ? 2 : k - 1);  // before v
-    q0 = st.xy[o0];
-    q1 = st.xy[o1];
-    n0 = st.met[o0];
-    n1 = st.met[o1];
+    VRec r0 = st.vr[o0], r1 = st.vr[o1];
+    q0 = make_double2(r0.x, r0.y);
+    q1 = make_double2(r1.x, r1.y);
+    n0 = Met{r0.a, r0.b, r0.c};
+    n1 = Met{r1.a, r1.b, r1.c};
   }
   double lastL = -INFINITY;
   int lastU = -1, u = -1;
@@ -1807,8 +1831,9 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
   // data and its rows' entries, then the neighbours' round words and the
   // elements; the deferral test comes after them
   uint64_t rv = a.rw[v];
-  double2 pv = st.xy[v];
-  Met mv = st.met[v];
+  VRec rcv = st.vr[v];
+  double2 pv = make_double2(rcv.x, rcv.y);
+  Met mv{rcv.a, rcv.b, rcv.c};
   int y = ownn ? st.nn[h.x + g.j] : -1;
   int T1 = owne ? st.ne[h.z + g.j] : -1;
   uint64_t ry = a.rw[max(y, 0)];
@@ -1825,10 +1850,11 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
     k1 = slot_of(e1, v);
     w = at(e1, k1 == 2 ? 0 : k1 + 1);
     av = at(e1, k1 == 0 ? 2 : k1 - 1);
-    pw = st.xy[w];
-    mw = st.met[w];
-    pa = st.xy[av];
-    ma = st.met[av];
+    VRec rcw = st.vr[w], rca = st.vr[av];
+    pw = make_double2(rcw.x, rcw.y);
+    mw = Met{rcw.a, rcw.b, rcw.c};
+    pa = make_double2(rca.x, rca.y);
+    ma = Met{rca.a, rca.b, rca.c};
   }
   // quality of T1 in its stored order (slot k1 holds v, then w, then a)
   double q1 = 0.0;
