@@ -30,7 +30,7 @@ BYTES_PER_UNIT = {
     "collapse": 436,  # per class member: 1-ring gather, evaluation, element rewrites, queueing
     "flip": 436,      # per class member
     "smooth": 148,    # per class member: own xy+metric, rows, elements, write-back, list entry
-    "commit": 216,    # per row rebuilt: headers, caps, old and new NE/NN rows, stamps, elements
+    "commit": 212,    # per row rebuilt: headers, caps, old and new NE/NN rows, target record, elements
     "adjoint": 144,   # per vertex: xy+metric, header, NE row, elements, dQ/dx and dQ/dM writes
     "quality": 36,    # per element: element ids and a third of its vertices' data
     "select": 100,    # per vertex scanned
