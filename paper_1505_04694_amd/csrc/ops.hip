@@ -104,10 +104,21 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // blocker: in, a neighbour that kept v waiting before (or -1); out, the
 // neighbour that keeps it waiting now. While that neighbour has no colour, v
 // cannot be ready, and one load settles the visit.
+// Cached: the round words are read through the caches. That is exact for a
+// launch's first visit: at the launch's start every colour set before it is
+// visible, and a colour set during it may read as unset, which only makes v
+// wait (priorities and active bits do not change during the colouring).
+// Later visits in the same launch read past the caches, to see the colours
+// that earlier passes set.
+template <bool Cached>
+__device__ __forceinline__ uint64_t rw_read(const uint64_t* rw, int v) {
+  return Cached ? rw[v] : rw_get(rw, v);
+}
+template <bool Cached>
 __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& blocker) {
   constexpr int B = 8;  // neighbours fetched side by side
-  if (blocker >= 0 && (rw_get(rd.rw, blocker) & 0xFF) == 0xFF) return false;
-  uint64_t rv = rw_get(rd.rw, v);
+  if (blocker >= 0 && (rw_read<Cached>(rd.rw, blocker) & 0xFF) == 0xFF) return false;
+  uint64_t rv = rw_read<Cached>(rd.rw, v);
   Hdr h = st.hdr[v];
   uint64_t used = 0;
   bool big = false;
@@ -116,7 +127,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& b
     uint64_t x[B];
     row8(st.nn, h.x + j0, h.y - j0, w);
 #pragma unroll
-    for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_get(rd.rw, w[q]) : 0ull;
+    for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_read<Cached>(rd.rw, w[q]) : 0ull;
     int wait = -1;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -189,7 +200,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
   bool moved = false;
 #pragma unroll
   for (int r = 0; r < kJpItems; ++r) {
-    keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr, bl[r]);
+    keep[r] = vv[r] >= 0 && !jp_try<true>(st, vv[r], rd, ctr, bl[r]);
     moved |= vv[r] >= 0 && !keep[r];
     tries += vv[r] >= 0 ? 1 : 0;
   }
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     for (int r = 0; r < kJpItems; ++r)
       if (keep[r]) {
         ++tries;
-        keep[r] = !jp_try(st, vv[r], rd, ctr, bl[r]);
+        keep[r] = !jp_try<false>(st, vv[r], rd, ctr, bl[r]);
         moved |= !keep[r];
       }
   }
@@ -385,7 +396,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     for (int i = tid; i < nw; i += kSmallThreads) {
       int v = in[i];
       int bl = it > 0 ? bin[i] : -1;
-      if (!jp_try(st, v, rd, ctr, bl)) {
+      if (!jp_try<false>(st, v, rd, ctr, bl)) {
         int k = atomicAdd(&nwait, 1);
         wout[k] = v;
         bout[k] = bl;
