@@ -104,12 +104,13 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // blocker: in, a neighbour that kept v waiting before (or -1); out, the
 // neighbour that keeps it waiting now. While that neighbour has no colour, v
 // cannot be ready, and one load settles the visit.
-// Cached: the round words are read through the caches. That is exact for a
-// launch's first visit: at the launch's start every colour set before it is
-// visible, and a colour set during it may read as unset, which only makes v
-// wait (priorities and active bits do not change during the colouring).
-// Later visits in the same launch read past the caches, to see the colours
-// that earlier passes set.
+// Cached: the round words are read through the caches (the chunked
+// colouring). At a launch's start every colour set before it is visible; a
+// colour set during the launch may read as unset, which only makes v wait
+// (priorities and active bits do not change during the colouring), and the
+// vertex of largest key still waiting is ready at every launch, so each
+// launch makes progress. The one-block colouring, which runs to completion
+// in one launch, reads past the caches.
 template <bool Cached>
 __device__ __forceinline__ uint64_t rw_read(const uint64_t* rw, int v) {
   return Cached ? rw[v] : rw_get(rw, v);
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     for (int r = 0; r < kJpItems; ++r)
       if (keep[r]) {
         ++tries;
-        keep[r] = !jp_try<false>(st, vv[r], rd, ctr, bl[r]);
+        keep[r] = !jp_try<true>(st, vv[r], rd, ctr, bl[r]);
         moved |= !keep[r];
       }
   }
