@@ -104,13 +104,15 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // blocker: in, a neighbour that kept v waiting before (or -1); out, the
 // neighbour that keeps it waiting now. While that neighbour has no colour, v
 // cannot be ready, and one load settles the visit.
-// Cached: the round words are read through the caches (the chunked
-// colouring). At a launch's start every colour set before it is visible; a
-// colour set during the launch may read as unset, which only makes v wait
-// (priorities and active bits do not change during the colouring), and the
-// vertex of largest key still waiting is ready at every launch, so each
-// launch makes progress. The one-block colouring, which runs to completion
-// in one launch, reads past the caches.
+// Cached: the round words are read through the caches. At a launch's start
+// every colour set before it is visible; a colour set during the launch may
+// read as unset, which only makes v wait (priorities and active bits do not
+// change during the colouring), and the vertex of largest key still waiting
+// is ready at every launch, so each chunked launch makes progress. The
+// one-block colouring runs to completion in one launch: its iterations are
+// separated by block barriers, and a work-group's waves share one CU's
+// vector L1, which the CU's own stores write through, so every iteration
+// sees the colours of the ones before it (its loop is bounded regardless).
 template <bool Cached>
 __device__ __forceinline__ uint64_t rw_read(const uint64_t* rw, int v) {
   return Cached ? rw[v] : rw_get(rw, v);
@@ -397,7 +399,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     for (int i = tid; i < nw; i += kSmallThreads) {
       int v = in[i];
       int bl = it > 0 ? bin[i] : -1;
-      if (!jp_try<false>(st, v, rd, ctr, bl)) {
+      if (!jp_try<true>(st, v, rd, ctr, bl)) {
         int k = atomicAdd(&nwait, 1);
         wout[k] = v;
         bout[k] = bl;
