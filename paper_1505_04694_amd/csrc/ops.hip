@@ -19,7 +19,6 @@ constexpr int kGC = 16;  // lanes per vertex in the lane-group collapse
 __device__ __forceinline__ uint64_t key_of(const Store& st, const Round& rd, int v) {
   return vkey(rd.sseed, (uint32_t)local_id(st, v));
 }
-__device__ __forceinline__ uint64_t rw_get(const uint64_t* rw, int v) { return ((volatile const uint64_t*)rw)[v]; }
 __device__ __forceinline__ void rw_put(uint64_t* rw, int v, uint64_t x) { ((volatile uint64_t*)rw)[v] = x; }
 
 __global__ void k_clear_round(const int* __restrict__ list, int n, uint64_t* __restrict__ rw) {
@@ -104,7 +103,7 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // blocker: in, a neighbour that kept v waiting before (or -1); out, the
 // neighbour that keeps it waiting now. While that neighbour has no colour, v
 // cannot be ready, and one load settles the visit.
-// Cached: the round words are read through the caches. At a launch's start
+// The round words are read through the caches. At a launch's start
 // every colour set before it is visible; a colour set during the launch may
 // read as unset, which only makes v wait (priorities and active bits do not
 // change during the colouring), and the vertex of largest key still waiting
@@ -113,15 +112,11 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
 // separated by block barriers, and a work-group's waves share one CU's
 // vector L1, which the CU's own stores write through, so every iteration
 // sees the colours of the ones before it (its loop is bounded regardless).
-template <bool Cached>
-__device__ __forceinline__ uint64_t rw_read(const uint64_t* rw, int v) {
-  return Cached ? rw[v] : rw_get(rw, v);
-}
-template <bool Cached>
 __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& blocker) {
   constexpr int B = 8;  // neighbours fetched side by side
-  if (blocker >= 0 && (rw_read<Cached>(rd.rw, blocker) & 0xFF) == 0xFF) return false;
-  uint64_t rv = rw_read<Cached>(rd.rw, v);
+  const uint64_t* rw = rd.rw;
+  if (blocker >= 0 && (rw[blocker] & 0xFF) == 0xFF) return false;
+  uint64_t rv = rw[v];
   Hdr h = st.hdr[v];
   uint64_t used = 0;
   bool big = false;
@@ -130,7 +125,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& b
     uint64_t x[B];
     row8(st.nn, h.x + j0, h.y - j0, w);
 #pragma unroll
-    for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw_read<Cached>(rd.rw, w[q]) : 0ull;
+    for (int q = 0; q < B; ++q) x[q] = w[q] >= 0 ? rw[w[q]] : 0ull;
     int wait = -1;
 #pragma unroll
     for (int q = 0; q < B; ++q) {
@@ -155,7 +150,7 @@ __device__ bool jp_try(const Store& st, int v, const Round& rd, int* ctr, int& b
       bool taken = false;
       for (int j = 0; j < h.y && !taken; ++j) {
         int w = st.nn[h.x + j];
-        uint64_t x = rw_get(rd.rw, w);
+        uint64_t x = rw[w];
         if (!(x & kRwAct) || !rw_beats(x, w, rv, v)) continue;
         taken = (int)(x & 0xFF) == c;
       }
@@ -203,7 +198,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
   bool moved = false;
 #pragma unroll
   for (int r = 0; r < kJpItems; ++r) {
-    keep[r] = vv[r] >= 0 && !jp_try<true>(st, vv[r], rd, ctr, bl[r]);
+    keep[r] = vv[r] >= 0 && !jp_try(st, vv[r], rd, ctr, bl[r]);
     moved |= vv[r] >= 0 && !keep[r];
     tries += vv[r] >= 0 ? 1 : 0;
   }
@@ -219,7 +214,7 @@ __global__ void __launch_bounds__(256) k_jp_chunk(Store st, const int* __restric
     for (int r = 0; r < kJpItems; ++r)
       if (keep[r]) {
         ++tries;
-        keep[r] = !jp_try<true>(st, vv[r], rd, ctr, bl[r]);
+        keep[r] = !jp_try(st, vv[r], rd, ctr, bl[r]);
         moved |= !keep[r];
       }
   }
@@ -399,7 +394,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     for (int i = tid; i < nw; i += kSmallThreads) {
       int v = in[i];
       int bl = it > 0 ? bin[i] : -1;
-      if (!jp_try<true>(st, v, rd, ctr, bl)) {
+      if (!jp_try(st, v, rd, ctr, bl)) {
         int k = atomicAdd(&nwait, 1);
         wout[k] = v;
         bout[k] = bl;
