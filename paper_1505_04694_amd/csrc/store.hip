@@ -315,10 +315,29 @@ __global__ void __launch_bounds__(256) k_ne_fill(const Elem* __restrict__ tri, i
     }
   }
   __syncthreads();
-  // reserve the chunk's slots: loc[i] becomes the first slot of the chunk in row vmin + i
-  for (int i = (int)threadIdx.x; i < span; i += kBlock) {
-    int c = loc[i];
-    if (c) loc[i] = hdr[vmin + i].z + atomicAdd(reinterpret_cast<int*>(&hdr[vmin + i]) + 3, c);
+  // reserve the chunk's slots: loc[i] becomes the first slot of the chunk in
+  // row vmin + i; a thread's reservations are all in flight before it uses one
+  constexpr int R = kIncSpan / kBlock;
+  int cnt[R], at[R], z[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    int i = q * kBlock + (int)threadIdx.x;
+    cnt[q] = i < span ? loc[i] : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    int i = q * kBlock + (int)threadIdx.x;
+    z[q] = cnt[q] ? hdr[vmin + i].z : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    int i = q * kBlock + (int)threadIdx.x;
+    at[q] = cnt[q] ? atomicAdd(reinterpret_cast<int*>(&hdr[vmin + i]) + 3, cnt[q]) : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    int i = q * kBlock + (int)threadIdx.x;
+    if (cnt[q]) loc[i] = z[q] + at[q];
   }
   __syncthreads();
 #pragma unroll
@@ -367,18 +386,16 @@ __device__ __forceinline__ void row_finish_reg(const Elem* __restrict__ tri, Hdr
 #pragma unroll
   for (int k = 0; k < N; ++k) r[k] = k < c ? ne[h.z + k] : INT_MAX;
   bitonic<N>(r);
+  // the elements' loads go out together (an empty slot loads the first
+  // element again rather than branch around its load)
   int nx[N], pv[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    nx[k] = INT_MAX;
-    pv[k] = INT_MAX;
-    if (k < c) {
-      ne[h.z + k] = r[k];
-      Elem e = tri[r[k]];
-      int s = slot_of(e, v);
-      nx[k] = at(e, s == 2 ? 0 : s + 1);
-      pv[k] = at(e, s == 0 ? 2 : s - 1);
-    }
+    if (k < c) ne[h.z + k] = r[k];
+    Elem e = tri[k < c ? r[k] : r[0]];
+    int s = slot_of(e, v);
+    nx[k] = k < c ? at(e, s == 2 ? 0 : s + 1) : INT_MAX;
+    pv[k] = k < c ? at(e, s == 0 ? 2 : s - 1) : INT_MAX;
   }
   bitonic<N>(nx);
   bool bad = false;
