@@ -383,15 +383,27 @@ __device__ __forceinline__ void row_finish_reg(const Elem* __restrict__ tri, Hdr
                                                int* ctr) {
   int c = h.w;
   int r[N];
+  if constexpr (N == 8) {
+    row8(ne, h.z, c, r);
 #pragma unroll
-  for (int k = 0; k < N; ++k) r[k] = k < c ? ne[h.z + k] : INT_MAX;
+    for (int k = 0; k < N; ++k)
+      if (k >= c) r[k] = INT_MAX;
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) r[k] = k < c ? ne[h.z + k] : INT_MAX;
+  }
   bitonic<N>(r);
   // the elements' loads go out together (an empty slot loads the first
   // element again rather than branch around its load)
   int nx[N], pv[N];
+  if constexpr (N == 8) {
+    // the sorted row, four entries per store (the slot holds a multiple of four)
+    *(int4*)(ne + h.z) = make_int4(r[0], r[1], r[2], r[3]);
+    if (c > 4) *(int4*)(ne + h.z + 4) = make_int4(r[4], r[5], r[6], r[7]);
+  }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    if (k < c) ne[h.z + k] = r[k];
+    if (N != 8 && k < c) ne[h.z + k] = r[k];
     Elem e = tri[k < c ? r[k] : r[0]];
     int s = slot_of(e, v);
     nx[k] = k < c ? at(e, s == 2 ? 0 : s + 1) : INT_MAX;
