@@ -441,10 +441,14 @@ pm_status build_rows(pm_mesh* m) {
 
 // free pool space check between rounds: rebuild (repack) when a round could
 // plausibly exhaust it
+// from the host copy of the pool tops
+bool needs_repack(const pm_mesh* m) {
+  int64_t nn_top = m->hctr[C_NN_TOP], ne_top = m->hctr[C_NE_TOP];
+  return nn_top * 3 > m->st.nn_pool * 2 || ne_top * 3 > m->st.ne_pool * 2;
+}
 pm_status maybe_repack(pm_mesh* m, bool fresh = false) {
   if (!fresh) TRY(read_ctr(m, C_NN_TOP, 2));
-  int64_t nn_top = m->hctr[C_NN_TOP], ne_top = m->hctr[C_NE_TOP];
-  if (nn_top * 3 > m->st.nn_pool * 2 || ne_top * 3 > m->st.ne_pool * 2) return build_rows(m);
+  if (needs_repack(m)) return build_rows(m);
   return PM_OK;
 }
 
@@ -502,18 +506,23 @@ struct Classes {
 // a launch past the end of the work finds only empty chunks.
 constexpr int kJpBatch = 4;
 
+// the classes of a one-block colouring, from the host copy of the counters
+void small_classes(pm_mesh* m, Classes& out) {
+  out.jp_iters = m->hctr[C_TOTAL];
+  out.ncol = m->hctr[C_NCOL];
+  out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
+  out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
+}
+
 pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
   if (n <= kSmallColour && !(m->variant & 4)) {
     timed(m, PM_K_JP, 0,
-          [&] { colour_small(m->st, A, n, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, m->s); });
+          [&] { colour_small(m->st, A, n, nullptr, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, m->s); });
     TRY(read_ctr(m, 0, C_NCOL + 1));
     TRY(check_err(m, true));
-    out.jp_iters = m->hctr[C_TOTAL];
-    out.ncol = m->hctr[C_NCOL];
-    out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
-    out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
+    small_classes(m, out);
     return PM_OK;
   }
   jp_init(m->st, A, n, rd, m->s);
@@ -720,11 +729,23 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
   int nA = m->hctr[C_LIST_B];
   int r = 0;
   Commit cm = commit_of(m);
+  // a small round colours the next round's list as soon as it is selected,
+  // before the read-back that returns its length: one read-back for both
+  bool ahead = false;
+  Classes next;
   while (nA > 0 && r < max_rounds) {
+    // after a repack (all rows rebuilt) the list is coloured again rather
+    // than keep classes found before it
+    bool repacked = needs_repack(m);
     TRY(maybe_repack(m, true));
     Round rd{stream_seed(m->seed, make_ctx(o->sweep, phase, r)), m->rw.p};
     Classes cl;
-    TRY(colour_list(m, m->listA.p, nA, rd, cl));
+    if (ahead && !repacked) {
+      cl = next;
+    } else {
+      TRY(colour_list(m, m->listA.p, nA, rd, cl));
+    }
+    ahead = false;
     // a small round (coloured by one block) records the rows it rebuilds, so
     // the next round's list comes from its own lists, not from every slot
     bool small = nA <= kSmallColour && !(m->variant & 4);
@@ -763,8 +784,20 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
         select_small(m->st, mode, o->L_low2, m->listA.p, nA, m->touch.p, cm.touched_cap, m->nxt.p, m->seen.p,
                      ++m->sel_mark, m->listB.p, m->ctr, m->s);
       });
-      TRY(read_ctr(m, 0, C_EVAL));
+      bool launch = r + 1 < max_rounds;
+      if (launch) {
+        Round rn{stream_seed(m->seed, make_ctx(o->sweep, phase, r + 1)), m->rw.p};
+        timed(m, PM_K_JP, 0, [&] {
+          colour_small(m->st, m->listB.p, 0, m->ctr + C_LIST_B, rn, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p,
+                       m->ctr, m->s);
+        });
+      }
+      TRY(read_ctr(m, 0, launch ? C_NCOL + 1 : C_EVAL));
       listed = m->hctr[C_LIST_B] >= 0;
+      if (launch && listed && m->hctr[C_NCOL] >= 0) {
+        ahead = true;
+        small_classes(m, next);
+      }
     }
     if (!listed) {
       set_int(m->ctr + C_LIST_B, 0, m->s);

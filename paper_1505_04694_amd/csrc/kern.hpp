@@ -234,8 +234,10 @@ void select_small(const Store& st, int mode, double L_low2, const int* A, int nA
 // writes class sizes, offsets and count like class_lists, iterations to C_TOTAL
 constexpr int kSmallColour = 8192;
 // WB: 2 * kSmallColour ints for the blockers of the waiting lists
-void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* WB, int* out, int* ctr,
-                  hipStream_t s);
+// n_dev: when given, the list length is read there instead (n ignored), and a
+// length outside [0, kSmallColour] leaves the list uncoloured with C_NCOL = -1
+void colour_small(const Store& st, const int* A, int n, const int* n_dev, Round rd, int* W0, int* W1, int* WB,
+                  int* out, int* ctr, hipStream_t s);
 
 // variant 0: one thread per member; 1: a group of 8 lanes per member
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,

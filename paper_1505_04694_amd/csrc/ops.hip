@@ -371,11 +371,20 @@ void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, in
 // launch. Classes come out in no particular order; the members of a class
 // are an independent set, so their order does not change any result.
 constexpr int kSmallThreads = 1024;
-__global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const int* __restrict__ A, int n, Round rd,
-                                                              int* W0, int* W1, int* WB, int* __restrict__ out,
-                                                              int* ctr) {
+__global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const int* __restrict__ A, int n,
+                                                              const int* n_dev, Round rd, int* W0, int* W1, int* WB,
+                                                              int* __restrict__ out, int* ctr) {
   __shared__ int nwait, hist[256], cur[256];
   int tid = (int)threadIdx.x;
+  if (n_dev) {
+    // the list length from the device (a colouring launched ahead of the
+    // read-back); a list this kernel does not take is reported as -1 colours
+    n = *n_dev;
+    if (n < 0 || n > kSmallColour) {
+      if (tid == 0) ctr[C_NCOL] = -1;
+      return;
+    }
+  }
   for (int i = tid; i < n; i += kSmallThreads) {
     int v = A[i];
     uint64_t prio = key_of(st, rd, v) >> 32;
@@ -434,9 +443,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     out[atomicAdd(&cur[(int)(rd.rw[v] & 0xFF)], 1)] = v;
   }
 }
-void colour_small(const Store& st, const int* A, int n, Round rd, int* W0, int* W1, int* WB, int* out, int* ctr,
-                  hipStream_t s) {
-  k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, rd, W0, W1, WB, out, ctr);
+void colour_small(const Store& st, const int* A, int n, const int* n_dev, Round rd, int* W0, int* W1, int* WB,
+                  int* out, int* ctr, hipStream_t s) {
+  k_colour_small<<<1, kSmallThreads, 0, s>>>(st, A, n, n_dev, rd, W0, W1, WB, out, ctr);
 }
 
 __global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mode, double L_low2,
