@@ -525,31 +525,32 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
     small_classes(m, out);
     return PM_OK;
   }
+  int nb = (n + kBlock - 1) / kBlock;
+  TRY(ensure(m, m->ctab, 256 * (size_t)nb + 256));
+  TRY(ensure(m, m->ctabs, 256 * (size_t)nb + 256));
+  TRY(ensure(m, m->spart, scan_partials_needed(256 * nb) + 2));
   jp_init(m->st, A, n, rd, m->s);
   stripe_zero(m->ctr, S_JPL, 8, m->s);
   int it = 0;
   for (;;) {
     // first batch: as many iterations as the last colouring needed, so that
-    // most colourings need one read-back
+    // most colourings need one read-back; the class lists are cut before
+    // that read-back, which then also returns them (cut again if the
+    // colouring was not finished)
     int batch = it == 0 ? std::min(std::max(m->jp_last, kJpBatch), 64) : kJpBatch;
     for (int b = 0; b < batch; ++b, ++it)
       timed(m, PM_K_JP, 0,
             [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpB.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
     stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
-    TRY(read_ctr(m, C_JP, 1));
+    zero_ints(m->ctr + C_HIST, 256, m->s);
+    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
+    TRY(read_ctr(m, 0, C_NCOL + 1));
     int left = m->hctr[C_JP];
     if (left == 0) break;
     if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
   }
   out.jp_iters = it;
   m->jp_last = it;
-  zero_ints(m->ctr + C_HIST, 256, m->s);
-  int nb = (n + kBlock - 1) / kBlock;
-  TRY(ensure(m, m->ctab, 256 * (size_t)nb + 256));
-  TRY(ensure(m, m->ctabs, 256 * (size_t)nb + 256));
-  TRY(ensure(m, m->spart, scan_partials_needed(256 * nb) + 2));
-  class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
-  TRY(read_ctr(m, 0, C_NCOL + 1));
   TRY(check_err(m, true));
   out.ncol = m->hctr[C_NCOL];
   out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
