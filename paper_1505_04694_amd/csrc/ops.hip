@@ -1475,11 +1475,15 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr);
+template <int K>
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int* ctr);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
   if (n <= 0) return;
-  if (variant == 1)
-    k_smooth_g<<<(int)(((int64_t)n * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, kind, ctr);
+  int nb = (int)(((int64_t)n * kG + kBlock - 1) / kBlock);
+  if (variant == 1 && kind == 0)
+    k_smooth_g<0><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
+  else if (variant == 1)
+    k_smooth_g<1><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else
     k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
 }
@@ -1601,7 +1605,7 @@ __device__ __forceinline__ double gpatch_q(const PatchElem& pe, bool own, double
   return gsum(q, nw, g);
 }
 
-__device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
+__device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   double2 pv = st.xy[v];
   Met mv = st.met[v];
   bool ownn = g.j < h.y, owne = g.j < h.w;
@@ -1624,9 +1628,24 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
     double eb = (mv.b + mw.b) * 0.5;
     double ec = (mv.c + mw.c) * 0.5;
     double dx = pw.x - pv.x, dy = pw.y - pv.y;
-    double Ga = gsum(ea, h.y, g), Gb = gsum(eb, h.y, g), Gc = gsum(ec, h.y, g);
-    double rx = gsum(ea * dx + eb * dy, h.y, g);
-    double ry = gsum(eb * dx + ec * dy, h.y, g);
+    // the five sums side by side, one lane's terms at a time (each sum keeps
+    // the serial rounding sequence; holding all forty shuffled terms at once
+    // would spill)
+    double fx = ea * dx + eb * dy, fy = eb * dx + ec * dy;
+    double Ga = 0.0, Gb = 0.0, Gc = 0.0, rx = 0.0, ry = 0.0;
+#pragma unroll
+    for (int k = 0; k < kG; ++k) {
+      double ta = gget(ea, k, g), tb = gget(eb, k, g), tc = gget(ec, k, g), tx = gget(fx, k, g),
+             ty = gget(fy, k, g);
+      if (k < h.y) {
+        Ga = Ga + ta;
+        Gb = Gb + tb;
+        Gc = Gc + tc;
+        rx = rx + tx;
+        ry = ry + ty;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     double det = Ga * Gc - Gb * Gb;
     p = make_double2(pv.x + (Gc * rx - Gb * ry) / det, pv.y + (Ga * ry - Gb * rx) / det);
     bool vo, vn;
@@ -1636,7 +1655,16 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   } else {
     double ex = 0.0, ey = 0.0;
     if (owne) qual_grad_x(patch_geo(pe, pv), pe.k, ex, ey);
-    double gx = gsum(ex, h.w, g), gy = gsum(ey, h.w, g);
+    double gx = 0.0, gy = 0.0;
+#pragma unroll
+    for (int k = 0; k < kG; ++k) {
+      double tx = gget(ex, k, g), ty = gget(ey, k, g);
+      if (k < h.w) {
+        gx = gx + tx;
+        gy = gy + ty;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     if (gx == 0.0 && gy == 0.0) return false;
     double ax = fabs(gx), ay = fabs(gy);
     double nrm = ax < ay ? ay : ax;
@@ -1663,7 +1691,10 @@ __device__ bool smooth_group(Store& st, int v, Hdr h, int kind, const Grp& g) {
   return true;
 }
 
-__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+// one kernel per smoothing kind (K = 0 plain, 1 gradient), each with its own
+// register allocation
+template <int K>
+__global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int* ctr) {
   Grp g = grp();
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
@@ -1671,14 +1702,16 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
     int v = list[gid];
     Hdr h = st.hdr[v];
     if (h.y > kG || h.w > kG) {
-      if (g.j == 0) status = (kind == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v)) ? 2 : 1;
+      if (g.j == 0) status = (K == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v)) ? 2 : 1;
     } else {
-      bool moved = smooth_group(st, v, h, kind, g);
+      bool moved = smooth_group(st, v, h, K, g);
       if (g.j == 0) status = moved ? 2 : 1;
     }
   }
   count_status(status, ctr);
 }
+template __global__ void k_smooth_g<0>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<1>(Store, const int*, int, int*);
 
 // ---- collapse with lane groups -----------------------------------------------------------------
 // G lanes per member (G = kGC): small classes are made of the vertices that
