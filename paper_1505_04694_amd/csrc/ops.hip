@@ -36,33 +36,15 @@ void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s
   if (n > 0) k_set_flags<<<grid_for(n), kBlock, 0, s>>>(list, n, flag, val);
 }
 
-// whether v has a neighbour u on every boundary side v lies on with
-// L^2(v, u) < L_low2; neighbours are fetched four at a time, their loads
-// side by side
 __device__ bool has_candidate(const Store& st, int v, double L_low2) {
-  constexpr int B = 4;
   Hdr h = st.hdr[v];
   double2 pv = st.xy[v];
   Met mv = st.met[v];
   uint8_t tv = st.tag[v];
-  for (int j0 = 0; j0 < h.y; j0 += B) {
-    int u[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) u[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
-    uint8_t tu[B];
-    double2 pu[B];
-    Met mu[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-      int us = max(u[q], 0);
-      tu[q] = st.tag[us];
-      pu[q] = st.xy[us];
-      mu[q] = st.met[us];
-    }
-    bool any = false;
-#pragma unroll
-    for (int q = 0; q < B; ++q) any |= u[q] >= 0 && !(tv & ~tu[q]) && len2(pv, mv, pu[q], mu[q]) < L_low2;
-    if (any) return true;
+  for (int j = 0; j < h.y; ++j) {
+    int u = st.nn[h.x + j];
+    if (tv & ~st.tag[u]) continue;
+    if (len2(pv, mv, st.xy[u], st.met[u]) < L_low2) return true;
   }
   return false;
 }
