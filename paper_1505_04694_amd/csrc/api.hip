@@ -77,6 +77,9 @@ struct pm_mesh {
   int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing, bit 2: no automatic shapes
   int64_t peak_bytes = 0, cur_bytes = 0;
   int jp_last = 8;    // JP iterations the last colouring took
+  // elements change only in coarsening, refinement and swapping: each call
+  // starts a new topology version; the per-element tensors are kept for one
+  uint64_t topo = 1, emet_topo = 0;
 };
 
 namespace {
@@ -1059,6 +1062,7 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
 pm_status pm_coarsen(pm_mesh* m, const pm_options* o, pm_stats* st) {
   if (!m || !o) return PM_E_ARG;
   if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  ++m->topo;
   pm_stats local;
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
@@ -1070,6 +1074,7 @@ pm_status pm_coarsen(pm_mesh* m, const pm_options* o, pm_stats* st) {
 pm_status pm_swap(pm_mesh* m, const pm_options* o, pm_stats* st) {
   if (!m || !o) return PM_E_ARG;
   if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  ++m->topo;
   pm_stats local;
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
@@ -1096,9 +1101,13 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   st->v[1] = n;
   st->v[5] = cl.ncol;
   st->v[12] = cl.jp_iters;
-  // topology and metrics stay fixed while smoothing: element tensors once
-  TRY(ensure(m, m->emet, (size_t)std::max(m->st.T, 1)));
-  element_metrics(m->st, m->emet.p, m->s);
+  // topology and metrics stay fixed while smoothing: element tensors once,
+  // and kept while the topology does not change
+  if (m->emet_topo != m->topo || m->emet.n < (size_t)std::max(m->st.T, 1)) {
+    TRY(ensure(m, m->emet, (size_t)std::max(m->st.T, 1)));
+    element_metrics(m->st, m->emet.p, m->s);
+    m->emet_topo = m->topo;
+  }
   m->st.emet = m->emet.p;
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
@@ -1116,6 +1125,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
 pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
   if (!m || !o) return PM_E_ARG;
   if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  ++m->topo;
   pm_stats local;
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
