@@ -757,7 +757,18 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
-    for (int c = 0; c < cl.ncol; ++c) {
+    // a small round whose classes are all small: every class in one block,
+    // one launch
+    bool all_small = small && cl.ncol > 1;
+    for (int c = 0; c < cl.ncol && all_small; ++c) all_small = cl.size[c] <= kSmallClass;
+    if (all_small) {
+      cm.epoch = m->epoch + 1;
+      m->epoch += cl.ncol;
+      OpArgs a{m->rw.p, 0, rd, o->L_low2, qmin2};
+      timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, nA,
+            [&] { round_small(m->st, m->cls.p, cl.ncol, a, cm, kind, m->ctr, m->s); });
+    }
+    for (int c = 0; c < cl.ncol && !all_small; ++c) {
       if (cl.size[c] == 0) continue;
       cm.epoch = ++m->epoch;
       OpArgs a{m->rw.p, c, rd, o->L_low2, qmin2};

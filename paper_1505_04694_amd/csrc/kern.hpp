@@ -253,6 +253,10 @@ void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips,
 // (kind 0 collapse, 1 flip)
 constexpr int kSmallClass = 32;
 void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s);
+// all ncol classes of a round (every one of at most kSmallClass members) in one
+// block: class c with epoch cm.epoch + c, size and offset from ctr[C_HIST + c],
+// ctr[C_OFF + c] (a.cls is ignored)
+void round_small(const Store& st, const int* cls, int ncol, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s);

@@ -2015,11 +2015,10 @@ void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, 
 
 // A small class in one block: the operation (collapse or flips on groups of
 // kGC lanes per member), a block barrier, then the commit of the same
-// members; one launch instead of two. Every thread reaches every barrier.
+// members. Every thread reaches every barrier.
 template <bool F>
-__global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
-                                                     Commit cm, int* ctr) {
-  __shared__ CommitLds L;
+__device__ __forceinline__ void class_body(const Store& st, const int* __restrict__ list, int n, const OpArgs& a,
+                                           const Commit& cm, int* ctr, CommitLds& L) {
   int tid = (int)threadIdx.x;
   if (tid == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   Grp g = grp_of<kGC>();
@@ -2041,12 +2040,47 @@ __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __rest
   __syncthreads();
   for (int base = 0; base < n; base += kBlock) commit_chunk<F>(st, list, base, min(kBlock, n - base), cm, ctr, L);
 }
+
+// one small class, one launch instead of two
+template <bool F>
+__global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
+                                                     Commit cm, int* ctr) {
+  __shared__ CommitLds L;
+  class_body<F>(st, list, n, a, cm, ctr, L);
+}
 void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
   if (n <= 0) return;
   if (kind)
     k_class_small<true><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
   else
     k_class_small<false><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+}
+
+// Every class of a round in one block, one after the other (a round whose
+// classes are all small): class c takes epoch cm.epoch + c and its size and
+// offset from the colouring's counters. One launch per round instead of one
+// per class, and the block's caches stay warm from class to class.
+template <bool F>
+__global__ void __launch_bounds__(256) k_round_small(Store st, const int* __restrict__ cls, int ncol, OpArgs a,
+                                                     Commit cm, int* ctr) {
+  __shared__ CommitLds L;
+  int epoch0 = cm.epoch;
+  for (int c = 0; c < ncol; ++c) {
+    int n = ctr[C_HIST + c], off = ctr[C_OFF + c];
+    if (n == 0) continue;
+    Commit cc = cm;
+    cc.epoch = epoch0 + c;
+    OpArgs ac = a;
+    ac.cls = c;
+    class_body<F>(st, cls + off, n, ac, cc, ctr, L);
+  }
+}
+void round_small(const Store& st, const int* cls, int ncol, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
+  if (ncol <= 0) return;
+  if (kind)
+    k_round_small<true><<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
+  else
+    k_round_small<false><<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
 }
 
 // ---- adjoint with lane groups ---------------------------------------------------------------------
