@@ -51,7 +51,8 @@ struct pm_mesh {
   int* ctr = nullptr;   // device counters
   int* hctr = nullptr;  // pinned mirror
   double* hq = nullptr; // pinned doubles
-  int* haux = nullptr;   // pinned ints for small read-backs
+  int* haux = nullptr;   // pinned ints for small read-backs (upper half: staged uploads)
+  hipEvent_t up_ev = nullptr;  // the last staged upload's copy
   // scratch
   DBuf<int> listA, listB, jpU0, jpU1, cls, vt0, vt1, vt2, vt3, vt4, tt0, tt1, tt2, partial, mid;
   DBuf<uint8_t> nxt, u8tmp;
@@ -387,7 +388,20 @@ pm_status upload_ranges(pm_mesh* m) {
   all.insert(all.end(), m->tbase.begin(), m->tbase.end());
   all.insert(all.end(), m->tused.begin(), m->tused.end());
   if (!m->ranges) TRY(dalloc(m, &m->ranges, all.size()));
-  HIPCHK(hipMemcpy(m->ranges, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+  if (all.size() <= (size_t)kAuxInts / 2) {
+    // staged in the upper half of the pinned ints and copied in stream
+    // order; the previous upload's copy has finished before the stage is
+    // rewritten
+    int* stage = m->haux + kAuxInts / 2;
+    if (!m->up_ev) HIPCHK(hipEventCreateWithFlags(&m->up_ev, hipEventDisableTiming));
+    else HIPCHK(hipEventSynchronize(m->up_ev));
+    std::copy(all.begin(), all.end(), stage);
+    HIPCHK(hipMemcpyAsync(m->ranges, stage, sizeof(int) * all.size(), hipMemcpyHostToDevice, m->s));
+    HIPCHK(hipEventRecord(m->up_ev, m->s));
+  } else {
+    HIPCHK(hipStreamSynchronize(m->s));
+    HIPCHK(hipMemcpy(m->ranges, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice));
+  }
   st.vbase = m->ranges;
   st.vused = st.vbase + B + 1;
   st.tbase = st.vused + B;
@@ -405,7 +419,9 @@ pm_status single_ranges(pm_mesh* m) {
 }
 
 // (Re)build every adjacency row from the element list into fresh pools.
-pm_status build_rows(pm_mesh* m) {
+// check: read the error bits back at the end (else they stay set for the
+// caller's next read-back)
+pm_status build_rows(pm_mesh* m, bool check = true) {
   Store& st = m->st;
   int V = st.V;
   TRY(ensure(m, m->vt0, V));
@@ -417,11 +433,23 @@ pm_status build_rows(pm_mesh* m) {
   zero_ints(m->vt0.p, V, m->s);
   build_count(st, m->vt0.p, m->s);
   build_caps(st, m->vt0.p, m->slack, m->vt1.p, m->vt2.p, m->s);
-  scan_excl(m->vt1.p, m->vt3.p, V, m->ctr + C_TOTAL, m->partial.p, m->s);
-  scan_excl(m->vt2.p, m->vt4.p, V, m->ctr + C_TOTAL2, m->partial.p, m->s);
-  TRY(read_ctr(m, C_TOTAL, 2));
-  int64_t nn_used = m->hctr[C_TOTAL], ne_used = m->hctr[C_TOTAL2];
-  // room for rows that outgrow their slot before the next rebuild
+  // the slot totals are the pools' new bump pointers
+  scan_excl(m->vt1.p, m->vt3.p, V, m->ctr + C_NN_TOP, m->partial.p, m->s);
+  scan_excl(m->vt2.p, m->vt4.p, V, m->ctr + C_NE_TOP, m->partial.p, m->s);
+  // room for rows that outgrow their slot before the next rebuild: 3x the
+  // used entries. Slot capacities are at most c(1+slack) + slack + 7 for a
+  // vertex in c elements, and the c sum to 3T, which bounds both totals; when
+  // the pools hold 3x that bound they are large enough without a read-back.
+  double bound = 3.0 * st.T * (1.0 + m->slack) + (double)V * (m->slack + 7.0);
+  double room = 3.0 * bound + 4096.0;
+  if (room <= (double)INT32_MAX && (double)st.nn_pool >= room && (double)st.ne_pool >= room) {
+    set_headers(st, m->vt3.p, m->vt4.p, m->vt1.p, m->vt2.p, m->s);
+    build_fill(st, nullptr, m->s);
+    build_finish(st, m->ctr, m->s);
+    return check ? check_err(m) : PM_OK;
+  }
+  TRY(read_ctr(m, C_NN_TOP, 2));
+  int64_t nn_used = m->hctr[C_NN_TOP], ne_used = m->hctr[C_NE_TOP];
   int64_t nn_need = 3 * nn_used + 4096, ne_need = 3 * ne_used + 4096;
   if (nn_need > INT32_MAX || ne_need > INT32_MAX) return fail(m, PM_E_NOMEM, "adjacency pool beyond 2^31 entries");
   if (st.nn_pool < nn_need || st.ne_pool < ne_need) {
@@ -434,12 +462,10 @@ pm_status build_rows(pm_mesh* m) {
     st.nn_pool = nn_need;
     st.ne_pool = ne_need;
   }
-  set_int(m->ctr + C_NN_TOP, (int)nn_used, m->s);
-  set_int(m->ctr + C_NE_TOP, (int)ne_used, m->s);
   set_headers(st, m->vt3.p, m->vt4.p, m->vt1.p, m->vt2.p, m->s);
   build_fill(st, nullptr, m->s);
   build_finish(st, m->ctr, m->s);
-  return check_err(m);
+  return check ? check_err(m) : PM_OK;
 }
 
 // free pool space check between rounds: rebuild (repack) when a round could
@@ -900,6 +926,10 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->ops.p, m->ops.n);
   prof_flush(m);
   for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
+  if (m->up_ev) {
+    (void)hipEventSynchronize(m->up_ev);
+    (void)hipEventDestroy(m->up_ev);
+  }
   dfree(m, m->ctr, C_COUNT);
   pinned_put(m);
   delete m;
@@ -1174,6 +1204,7 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     HIPCHK(hipMemcpyAsync(aux ? m->haux : need.data(), m->rtmp.p, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, m->s));
     stripe_sum(m->ctr, S_EDGES, 1, C_EDGES, m->s);
     TRY(read_ctr(m, 0, C_JP));
+    TRY(check_err(m, true));  // also the last row build's
     if (aux) std::copy(m->haux, m->haux + 2 * B, need.begin());
     int nv = m->hctr[C_TOTAL], nt = m->hctr[C_TOTAL2];
     int edges = m->hctr[C_EDGES];
@@ -1225,13 +1256,13 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
       m->vbase[1] = s.V;
       m->tbase[1] = s.T;
     }
-    TRY(sync(m));
     TRY(upload_ranges(m));
     st->v[4] += nv;
     st->v[8] += nv;
     st->v[9] += nt;
     ++p;
-    TRY(build_rows(m));
+    // the next pass's read-back checks this build's error bits
+    TRY(build_rows(m, p >= o->refine_passes));
   }
   s.mdone = nullptr;
   stats_zero(m);
