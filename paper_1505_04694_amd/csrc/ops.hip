@@ -491,10 +491,13 @@ __device__ __forceinline__ void claim_row(const Commit& cm, int x, int v) {
 __device__ __forceinline__ void stamp(const Commit& cm, int v, int a, int b, int c) {
   cm.ops[v] = make_int4(cm.epoch, a, b, c);
 }
-// member v collapses onto u, handing over its NE row (ne_off, ne_cnt): the
-// count's epoch is raised first (a count of an older epoch restarts at zero)
-__device__ __forceinline__ void mark_target(const Commit& cm, int u, int v, int ne_off, int ne_cnt) {
-  cm.tgt[u] = make_int4(v, ne_off, ne_cnt, cm.epoch);
+// a record (a, b, c) for row u in this epoch: the count's epoch is raised
+// first (a count of an older epoch restarts at zero). A member v collapsing
+// onto u hands over its NE row: (v, ne_off, ne_cnt). A flip of the edge
+// (v, w) with far vertices a and b gives rows a and b its two elements
+// (lo, hi, -1); rows v and w only lose elements.
+__device__ __forceinline__ void mark_target(const Commit& cm, int u, int a, int b, int c) {
+  cm.tgt[u] = make_int4(a, b, c, cm.epoch);
   unsigned long long e = (unsigned long long)(uint32_t)cm.epoch << 32;
   atomicMax((unsigned long long*)&cm.tk[u], e);
   atomicAdd((unsigned long long*)&cm.tk[u], 1ull);
@@ -696,6 +699,8 @@ __device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a,
   st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
   st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
   stamp(cm, v, lo, hi, 0);
+  mark_target(cm, ba, lo, hi, -1);
+  mark_target(cm, bb, lo, hi, -1);
   claim_row(cm, v, v);
   claim_row(cm, bw, v);
   claim_row(cm, ba, v);
@@ -790,8 +795,30 @@ __device__ __forceinline__ int row_candidates(const Store& st, const Commit& cm,
     }
     return n;
   }
-  // flips: NE(x), and the two elements of every committed flip around x
-  // (x's own and its neighbours'), four neighbour records at a time
+  // flips: NE(x), and the two elements of a flip whose far vertex x is,
+  // from x's record; x the far vertex of several flips: the two elements of
+  // every committed flip around x (x's own and its neighbours'), four
+  // neighbour records at a time
+  uint64_t tkf = cm.tk[x];
+  int4 tgf = cm.tgt[x];
+  int ntf = (uint32_t)(tkf >> 32) == (uint32_t)cm.epoch ? (int)(uint32_t)tkf : 0;
+  if (ntf <= 1) {
+    int t[B], u[B];
+    row8(st.ne, h.z, h.w, t);
+#pragma unroll
+    for (int q = 0; q < B; ++q) u[q] = -1;
+    if (ntf == 1) {
+      u[0] = tgf.x;
+      u[1] = tgf.y;
+    }
+    put_live(t);
+    if (ntf == 1) put_live(u);
+    for (int k0 = B; k0 < h.w; k0 += B) {
+      row8(st.ne, h.z + k0, h.w - k0, t);
+      put_live(t);
+    }
+    return n;
+  }
   int4 rx = cm.ops[x];
   auto scan_flips = [&](const int (&w)[B]) {
 #pragma unroll
@@ -1982,6 +2009,8 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
     st.tri[lo] = make_int4(tv.x, tv.y, tv.z, 1);
     st.tri[hi] = make_int4(tw.x, tw.y, tw.z, 1);
     stamp(cm, v, lo, hi, 0);
+    mark_target(cm, av, lo, hi, -1);
+    mark_target(cm, bv, lo, hi, -1);
     claim_row(cm, v, v);
     claim_row(cm, w, v);
     claim_row(cm, av, v);
