@@ -66,3 +66,18 @@ def test_batch_equals_plain_gpu_runs_on_uneven_sizes():
             gm.sweep(s)
         for i, gm in enumerate(gms):
             compare_one(gm.export(), gb.export_mesh(i), f"sweep {s} mesh {i}")
+
+
+def test_batch_of_many_small_meshes():
+    # more meshes than fit the pinned staging of the batch ranges (the
+    # uploads then take the synchronous path); sampled meshes against plain runs
+    mis = [inputs.make_mesh(5 + 2 * (i % 3), amp=0.15, width=0.04, ht=0.08) for i in range(2100)]
+    gb = pmesh.Batch.from_inputs(mis, seed=2)
+    sample = list(range(0, 2100, 150)) + [2099]
+    gms = {i: pmesh.Mesh.from_input(mis[i], seed=2) for i in sample}
+    for s in range(2):
+        gb.sweep(s)
+        for gm in gms.values():
+            gm.sweep(s)
+        for i, gm in gms.items():
+            compare_one(gm.export(), gb.export_mesh(i), f"sweep {s} mesh {i}")
