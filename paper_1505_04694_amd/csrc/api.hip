@@ -1265,8 +1265,9 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     TRY(build_rows(m, p >= o->refine_passes));
   }
   s.mdone = nullptr;
-  stats_zero(m);
-  TRY(stats_read(m, st));
+  // the counts above come from the passes' read-backs; the last of those
+  // also left the stream drained
+  prof_flush(m);
   st->v[0] = p;
   st->v[7] = done ? 1 : 0;
   return done ? PM_OK : PM_W_NOT_CONVERGED;
