@@ -76,8 +76,10 @@ typedef struct {
   int32_t variant;        /* kernel shapes, results identical for all: 0 =
                              defaults (collapse on 16 lanes per vertex,
                              smoothing on 8, one-block kernels for small lists
-                             and classes); bit 2 = one thread per vertex and
-                             the multi-block kernels throughout; bit 3 =
+                             and classes); bit 2 = one thread per vertex,
+                             the multi-block kernels throughout, and class
+                             lists first cut from a 4-colour table (cut
+                             again from the full one past 4 colours); bit 3 =
                              collapse on 8 lanes; bits 0, 1 = the lane-group
                              defaults, kept for older callers                   */
 } pm_options;

@@ -78,6 +78,7 @@ struct pm_mesh {
   int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing, bit 2: no automatic shapes
   int64_t peak_bytes = 0, cur_bytes = 0;
   int jp_last = 8;    // JP iterations the last colouring took
+  int class_seq = 0;  // class-list calls so far (the wide-colour flag's value)
   // elements change only in coarsening, refinement and swapping: each call
   // starts a new topology version; the per-element tensors are kept for one
   uint64_t topo = 1, emet_topo = 0;
@@ -571,12 +572,18 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
       timed(m, PM_K_JP, 0,
             [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpB.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
     stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
-    zero_ints(m->ctr + C_HIST, 256, m->s);
-    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, m->s);
+    m->class_seq = m->class_seq >= 0x3FFFFFFF ? 1 : m->class_seq + 1;
+    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, (m->variant & 4) ? 4 : kClassNarrow,
+                m->class_seq, m->s);
     TRY(read_ctr(m, 0, C_NCOL + 1));
     int left = m->hctr[C_JP];
     if (left == 0) break;
     if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
+  }
+  if (m->hctr[C_NCOL] == -2) {
+    // a colour past the narrow table: the full table
+    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, 256, 0, m->s);
+    TRY(read_ctr(m, 0, C_NCOL + 1));
   }
   out.jp_iters = it;
   m->jp_last = it;

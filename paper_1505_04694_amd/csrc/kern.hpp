@@ -27,6 +27,7 @@ enum Ctr {
   C_TOTAL = 14,     // scan totals
   C_TOTAL2 = 15,
   C_JP = 16,        // JP: vertices still waiting after the last iteration (summed)
+  C_CWIDE = 17,     // class lists: the call number of the last list with a colour past the narrow table
   C_HIST = 64,      // 64..319: colour histogram (class sizes)
   C_OFF = 320,      // 320..575: class offsets
   C_CUR = 576,      // 576..831: class cursors
@@ -220,9 +221,13 @@ constexpr int kJpChunk = 512;
 // WB holds, beside each waiting vertex, the neighbour that blocked it
 void jp_chunk(const Store& st, const int* A, int n, int* W, int* WB, int* cnt, bool first, Round rd, int* ctr,
               int it, hipStream_t s);
-// stable class lists; tab/tabscan: 256 * ceil(n/256) ints each
+// stable class lists; tab/tabscan: 256 * ceil(n/256) ints each. cm (4,
+// kClassNarrow or 256): the colours the table holds; a list with a colour of
+// cm or more reports C_NCOL = -2 and is to be cut again with cm = 256. seq: a
+// nonzero number no earlier call on this counter block used
+constexpr int kClassNarrow = 32;
 void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
-                 hipStream_t s);
+                 int cm, int seq, hipStream_t s);
 void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s);
 // next-round list of a small round from its own lists: the members A (the
 // deferred ones carry the next-round flag) and the rows rebuilt, each vertex

@@ -292,15 +292,27 @@ void stripe_sum(int* ctr, int slot, int nslots, int dst, hipStream_t s) {
 // entries) the number of each colour, an exclusive scan over (colour, block),
 // then every entry goes to its colour's range at the position of its rank
 // among equal colours in the block. Class lists keep the order of A.
+// Class lists for colours below CM: per block a colour histogram in LDS,
+// the (colour, block) table scanned in colour-major order, then each vertex
+// placed at its colour's block offset plus its rank in the block. A block
+// that meets a colour of CM or more stores seq to ctr[C_CWIDE] (only while it
+// does not hold seq yet); the lists then report -2 colours, and the caller
+// cuts them again with CM = 256. With CM = 32 the scanned table is an eighth
+// of the full one.
+template <int CM>
 __global__ void k_class_count(const int* __restrict__ A, int n, const uint64_t* __restrict__ rw, int nb,
-                              int* __restrict__ tab) {
+                              int* __restrict__ tab, int* ctr, int seq) {
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) atomicAdd(&h[(int)(rw[A[i]] & 0xFF)], 1);
   __syncthreads();
-  tab[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  if ((int)threadIdx.x < CM) tab[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+  if (CM < 256) {
+    bool wide = (int)threadIdx.x >= CM && h[threadIdx.x] > 0;
+    if (__ballot(wide) && __lane_id() == 0 && ((volatile int*)ctr)[C_CWIDE] != seq) ctr[C_CWIDE] = seq;
+  }
 }
 
 // rank of each lane among the lanes of its block holding the same colour, in lane order
@@ -327,6 +339,7 @@ __device__ int block_rank(int c, bool valid, int* wcnt /* 4 waves x 256 */) {
   return rank;
 }
 
+template <int CM>
 __global__ void k_class_place(const int* __restrict__ A, int n, const uint64_t* __restrict__ rw, int nb,
                               const int* __restrict__ tabscan, int* __restrict__ out) {
   __shared__ int wcnt[4 * 256];
@@ -337,33 +350,46 @@ __global__ void k_class_place(const int* __restrict__ A, int n, const uint64_t* 
   int v = valid ? A[i] : -1;
   int c = valid ? (int)(rw[v] & 0xFF) : 0;
   int r = block_rank(c, valid, wcnt);
-  if (valid) out[tabscan[(int64_t)c * nb + blockIdx.x] + r] = v;
+  if (valid && c < CM) out[tabscan[(int64_t)c * nb + blockIdx.x] + r] = v;
 }
 
-__global__ void k_class_sizes(const int* __restrict__ tabscan, int nb, int n, int* ctr) {
+template <int CM>
+__global__ void k_class_sizes(const int* __restrict__ tabscan, int nb, int n, int* ctr, int seq) {
   int c = threadIdx.x;
   int lo = tabscan[(int64_t)c * nb];
-  int hi = c < 255 ? tabscan[(int64_t)(c + 1) * nb] : n;
+  int hi = c < CM - 1 ? tabscan[(int64_t)(c + 1) * nb] : n;
   ctr[C_HIST + c] = hi - lo;
   ctr[C_OFF + c] = lo;
   __syncthreads();
   if (c == 0) {
     int ncol = 0;
-    for (int k = 0; k < 256; ++k)
+    for (int k = 0; k < CM; ++k)
       if (ctr[C_HIST + k]) ncol = k + 1;
+    if (CM < 256 && ctr[C_CWIDE] == seq) ncol = -2;
     ctr[C_NCOL] = ncol;
   }
 }
 
+template <int CM>
+static void class_lists_cm(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan,
+                           int* partial, int nb, int seq, hipStream_t s) {
+  k_class_count<CM><<<nb, kBlock, 0, s>>>(A, n, rw, nb, tab, ctr, seq);
+  scan_excl(tab, tabscan, CM * nb, ctr + C_TOTAL, partial, s);
+  k_class_place<CM><<<nb, kBlock, 0, s>>>(A, n, rw, nb, tabscan, out);
+  k_class_sizes<CM><<<1, CM, 0, s>>>(tabscan, nb, n, ctr, seq);
+}
+
 void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, int* tab, int* tabscan, int* partial,
-                 hipStream_t s) {
+                 int cm, int seq, hipStream_t s) {
   static_assert(kBlock == 256, "class kernels use one LDS slot per colour and thread");
   int nb = (n + kBlock - 1) / kBlock;
   if (nb < 1) nb = 1;
-  k_class_count<<<nb, kBlock, 0, s>>>(A, n, rw, nb, tab);
-  scan_excl(tab, tabscan, 256 * nb, ctr + C_TOTAL, partial, s);
-  k_class_place<<<nb, kBlock, 0, s>>>(A, n, rw, nb, tabscan, out);
-  k_class_sizes<<<1, 256, 0, s>>>(tabscan, nb, n, ctr);
+  if (cm == 4)
+    class_lists_cm<4>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
+  else if (cm == kClassNarrow)
+    class_lists_cm<kClassNarrow>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
+  else
+    class_lists_cm<256>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
 }
 
 // Small lists: one block runs the whole colouring (JP iterations separated
