@@ -262,7 +262,7 @@ def main():
     for k in range(a.steps):
         m, tr = gpu_step(mask=dmask)
         traces.append(tr)
-        pr = m.profile_read()[dominant]
+        pr = m.profile_read([dominant])[dominant]
         for key in dom:
             dom[key] += pr[key]
         if k == a.steps - 1:

@@ -235,11 +235,14 @@ void dfree(pm_mesh* m, T*& p, size_t n) {
   p = nullptr;
 }
 
-// grow-only scratch; contents are not preserved; zero = clear new memory
+// grow-only scratch; contents are not preserved; zero = clear new memory.
+// Freed blocks go back to the cache of this stream, where only later work of
+// the same stream can take them, so a first allocation needs no wait; a
+// replaced block is still waited for.
 template <class T>
 pm_status ensure(pm_mesh* m, DBuf<T>& b, size_t n, bool zero = false) {
   if (b.n >= n && b.p) return PM_OK;
-  HIPCHK(hipStreamSynchronize(m->s));
+  if (b.p) HIPCHK(hipStreamSynchronize(m->s));
   dfree(m, b.p, b.n);
   b.n = 0;
   size_t want = std::max<size_t>(n + n / 4, 64);
@@ -989,7 +992,8 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   if (!d->tags) tags_from_xy(st.xy, V, st.tag, m->s);
   tri_in(tri3, T, st.tri, m->s);
   fill_u8(st.valive, V, 1, m->s);
-  (void)hipStreamSynchronize(m->s);
+  // the staging blocks return to this stream's cache: later work on the
+  // stream is ordered after the conversions that read them
   dfree(m, tri3, 3 * (size_t)T);
   dfree(m, xyraw, 2 * (size_t)V);
   if (single_ranges(m) != PM_OK) return bail(PM_E_DEVICE);

@@ -381,8 +381,10 @@ class Mesh:
     def profile(self, mask: int):
         pm_profile(self.h, mask)
 
-    def profile_read(self):
-        return {k: pm_profile_read(self.h, i) for i, k in enumerate(KERNELS)}
+    def profile_read(self, names=None):
+        """Timing per kernel group; names: the groups to read (default all)."""
+        names = KERNELS if names is None else names
+        return {k: pm_profile_read(self.h, KERNELS.index(k)) for k in names}
 
     def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1):
         return dict(coarsen=self.coarsen(sweep), refine=self.refine(), swap=self.swap(sweep),
