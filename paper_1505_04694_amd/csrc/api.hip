@@ -1191,7 +1191,8 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
   std::vector<int> mdone(B, 0);
   if (B > 1) {
     if (!m->mdone) TRY(dalloc(m, &m->mdone, B));
-    HIPCHK(hipMemcpy(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice, m->s));
+    HIPCHK(hipStreamSynchronize(m->s));
     s.mdone = m->mdone;
   }
   while (p < o->refine_passes) {
@@ -1249,7 +1250,10 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
     bool newly_done = false;
     for (int i = 0; i < B && B > 1; ++i)
       if (!mdone[i] && need[i] == 0) mdone[i] = 1, newly_done = true;
-    if (newly_done) HIPCHK(hipMemcpy(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+    if (newly_done) {
+      HIPCHK(hipMemcpyAsync(m->mdone, mdone.data(), sizeof(int) * B, hipMemcpyHostToDevice, m->s));
+      HIPCHK(hipStreamSynchronize(m->s));
+    }
     TRY(ensure(m, m->mid, (size_t)s.nn_pool));
     if (B == 1) {
       m->vused[0] = s.V;  // unchanged until the new slots are counted below
@@ -1391,6 +1395,9 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   if (dalloc(m, &st.vmesh, nV) != PM_OK || dalloc(m, &st.tmesh, nT) != PM_OK) return bail(PM_E_NOMEM);
   double* xyraw = nullptr;
   if (dalloc(m, &xyraw, 2 * (size_t)nV) != PM_OK) return bail(PM_E_NOMEM);
+  // the copies below do not wait for the stream: let its queued clears (and
+  // any earlier user of these cached blocks) finish first
+  if (hipStreamSynchronize(m->s) != hipSuccess) return bail(PM_E_DEVICE);
   bool ok = hipMemcpy(xyraw, xy.data(), sizeof(double) * xy.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.met, met.data(), sizeof(double) * met.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.tag, tag.data(), tag.size(), hipMemcpyHostToDevice) == hipSuccess &&
