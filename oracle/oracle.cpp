@@ -18,6 +18,15 @@
 //             every independent set
 //   Sec. 3.4  worklists of touched items for the next sweep
 // Readings of points the paper leaves open are listed beside each function.
+//
+// Pins: every rule here is checked by the CPU tests against closed forms, hand
+// cases in exact arithmetic, and an independent re-derivation of each class
+// member's decision. Parity unpinned: the strictness of the gradient
+// smoother's two acceptance comparisons (patch minimum "not lower", patch sum
+// "strictly higher"). They differ from their alternatives only when a
+// continuous functional takes exactly equal values at two points of the
+// search line, which no test case reaches; the HIP path takes the same
+// comparisons.
 #include "oracle.h"
 
 #include <algorithm>
@@ -51,6 +60,7 @@ struct Mesh {
   void* hook_user = nullptr;
   uint64_t order_seed = 0;
   std::vector<int32_t> cur_members;  // the class being processed, for the hook
+  std::vector<int32_t> cur_class;    // the same class before re-validation
 };
 
 // ---- sorted-set rows ---------------------------------------------------------
@@ -279,9 +289,11 @@ void shuffle_members(Mesh& m, std::vector<int32_t>& v, uint64_t salt) {
   std::shuffle(v.begin(), v.end(), rng);
 }
 
-void run_hook(Mesh& m, int phase, int round, int cls, int stage, const std::vector<int32_t>& members) {
+void run_hook(Mesh& m, int phase, int round, int cls, int stage, const std::vector<int32_t>& members,
+              const std::vector<int32_t>& whole) {
   if (!m.hook) return;
   m.cur_members = members;
+  m.cur_class = whole;
   m.hook(m.hook_user, phase, round, cls, stage);
 }
 
@@ -646,6 +658,11 @@ int64_t orc_class_members(const orc_mesh* m, int32_t* out, int64_t cap) {
   for (int64_t i = 0; i < n && i < cap; ++i) out[i] = m->cur_members[i];
   return n;
 }
+int64_t orc_class_whole(const orc_mesh* m, int32_t* out, int64_t cap) {
+  int64_t n = (int64_t)m->cur_class.size();
+  for (int64_t i = 0; i < n && i < cap; ++i) out[i] = m->cur_class[i];
+  return n;
+}
 
 int32_t orc_colour(orc_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* colour_out) {
   std::vector<int32_t> A;
@@ -681,7 +698,7 @@ int32_t orc_coarsen(orc_mesh* mp, int32_t sweep, double L_low2, double q_min, in
       st[ORC_EVALUATED] += (int64_t)kept.size();
       for (int32_t v : deferred) next[v] = 1;
       shuffle_members(m, kept, ((uint64_t)r << 16) | (uint64_t)c);
-      run_hook(m, PH_COARSEN, r, c, 0, kept);
+      run_hook(m, PH_COARSEN, r, c, 0, kept, cls[c]);
       for (int32_t v : kept) {
         int32_t u = eval_collapse(m, v, L_low2, qmin2);
         if (u < 0) continue;
@@ -689,7 +706,7 @@ int32_t orc_coarsen(orc_mesh* mp, int32_t sweep, double L_low2, double q_min, in
         apply_collapse(m, v, u);
         st[ORC_COMMITTED] += 1;
       }
-      run_hook(m, PH_COARSEN, r, c, 1, kept);
+      run_hook(m, PH_COARSEN, r, c, 1, kept, cls[c]);
     }
     A.clear();
     for (int64_t v = 0; v < m.V; ++v) {
@@ -823,7 +840,7 @@ int32_t orc_swap(orc_mesh* mp, int32_t sweep, int32_t max_rounds, int64_t* st) {
       st[ORC_EVALUATED] += (int64_t)kept.size();
       for (int32_t v : deferred) next[v] = 1;
       shuffle_members(m, kept, ((uint64_t)r << 16) | (uint64_t)c);
-      run_hook(m, PH_SWAP, r, c, 0, kept);
+      run_hook(m, PH_SWAP, r, c, 0, kept, cls[c]);
       for (int32_t v : kept) {
         Flip f;
         if (!eval_flip(m, v, f)) continue;
@@ -831,7 +848,7 @@ int32_t orc_swap(orc_mesh* mp, int32_t sweep, int32_t max_rounds, int64_t* st) {
         next[v] = next[f.w] = next[f.a] = next[f.b] = 1;
         st[ORC_COMMITTED] += 1;
       }
-      run_hook(m, PH_SWAP, r, c, 1, kept);
+      run_hook(m, PH_SWAP, r, c, 1, kept, cls[c]);
     }
     A.clear();
     for (int64_t v = 0; v < m.V; ++v) {
@@ -861,13 +878,13 @@ int32_t orc_smooth(orc_mesh* mp, int32_t sweep, int32_t kind, int32_t sweeps, in
     for (int32_t c = 0; c < ncol; ++c) {
       std::vector<int32_t> mem = cls[c];
       shuffle_members(m, mem, ((uint64_t)s << 16) | (uint64_t)c);
-      run_hook(m, PH_SMOOTH, s, c, 0, mem);
+      run_hook(m, PH_SMOOTH, s, c, 0, mem, cls[c]);
       for (int32_t v : mem) {
         st[ORC_EVALUATED] += 1;
         bool moved = kind == 0 ? smooth_laplace(m, v) : smooth_gradient(m, v);
         st[ORC_COMMITTED] += moved ? 1 : 0;
       }
-      run_hook(m, PH_SMOOTH, s, c, 1, mem);
+      run_hook(m, PH_SMOOTH, s, c, 1, mem, cls[c]);
     }
   }
   st[ORC_ROUNDS] = sweeps;

@@ -77,6 +77,8 @@ void orc_set_hook(orc_mesh* m, orc_hook hook, void* user);
 /* members of the class the hook is called for (after re-validation);
  * returns the count, writes at most cap ids */
 int64_t orc_class_members(const orc_mesh* m, int32_t* out, int64_t cap);
+/* the same class before re-validation (ascending ids) */
+int64_t orc_class_whole(const orc_mesh* m, int32_t* out, int64_t cap);
 /* 0 = members in ascending id; otherwise a seeded shuffle of each class */
 void orc_set_order_seed(orc_mesh* m, uint64_t order_seed);
 

@@ -51,6 +51,8 @@ def lib():
         L.orc_set_order_seed.argtypes = [P, C.c_uint64]
         L.orc_class_members.restype = C.c_int64
         L.orc_class_members.argtypes = [P, P, C.c_int64]
+        L.orc_class_whole.restype = C.c_int64
+        L.orc_class_whole.argtypes = [P, P, C.c_int64]
         L.orc_coarsen.restype = C.c_int32
         L.orc_coarsen.argtypes = [P, C.c_int32, C.c_double, C.c_double, C.c_int32, P]
         L.orc_refine.restype = C.c_int32
@@ -152,6 +154,13 @@ class OracleMesh:
         n = lib().orc_class_members(self.h, None, 0)
         out = np.empty(max(n, 1), np.int32)
         lib().orc_class_members(self.h, _p(out), n)
+        return out[:n]
+
+    def class_whole(self):
+        """The class the hook is called for, before re-validation."""
+        n = lib().orc_class_whole(self.h, None, 0)
+        out = np.empty(max(n, 1), np.int32)
+        lib().orc_class_whole(self.h, _p(out), n)
         return out[:n]
 
     def set_order_seed(self, s: int):

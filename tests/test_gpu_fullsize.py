@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1505_04694_amd import inputs
-from tests import checker
+from tests import checker, fdcheck
 from tests.parity import both, compare_mesh, compare_quality, compare_stats, run_sweeps
 
 pytestmark = pytest.mark.gpu
@@ -21,8 +21,18 @@ def test_config1_three_sweeps():
 
 
 def test_config2_benchmark_step():
-    om, gm = both(inputs.config2(), 1)
+    mi = inputs.config2()
+    om, gm = both(mi, 1)
     compare_quality(om, gm, "initial")
+    # the adjoint against central differences at the 64 protocol vertices
+    _, _, gx, gmet = gm.quality(grad=True)
+    gx, gmet = gx.cpu().numpy(), gmet.cpu().numpy()
+    for v in fdcheck.protocol_vertices(mi.V):
+        v = int(v)
+        fx, fm, Qv, hx, hm = fdcheck.central_differences(om, v, mi.xy[v], mi.metric[v])
+        fdcheck.check_entries(fx, gx[v], Qv, hx, f"dQ/dx at {v}")
+        fdcheck.check_entries(fm, gmet[v], Qv, hm, f"dQ/dM at {v}")
+    del gx, gmet
     for name, fo, fg in (
             ("smooth plain", lambda: om.smooth(0, 0, 1), lambda: gm.smooth(0, 0, 1)),
             ("smooth gradient", lambda: om.smooth(0, 1, 1), lambda: gm.smooth(0, 1, 1)),

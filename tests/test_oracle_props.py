@@ -14,7 +14,7 @@ import pytest
 
 from oracle.orc import OracleMesh, PH_COARSEN, PH_SWAP, PH_SMOOTH
 from paper_1505_04694_amd import inputs
-from tests import checker
+from tests import checker, fdcheck
 
 CASES = [
     ("grid9", lambda: inputs.make_mesh(9, ht=0.3), 0),
@@ -195,39 +195,27 @@ def test_smoothing_gradient_increases_local_functional():
 
 # ---- adjoint of the quality functional ----------------------------------------------
 
-def fd_vertices(V, tags, count=24, seed=1):
-    rng = np.random.default_rng(seed)
-    inner = np.nonzero(tags == 0)[0]
-    return rng.choice(inner, size=min(count, inner.size), replace=False)
+def test_protocol_priorities_match_the_oracle():
+    from oracle.orc import prio
+    p = fdcheck.priorities(1, 0, 5000)
+    assert all(int(p[i]) == prio(1, 0, i) for i in range(0, 5000, 97))
 
 
-@pytest.mark.parametrize("n", [17, 65])
+@pytest.mark.parametrize("n", [17, 65, 2049])
 def test_adjoint_matches_central_differences(n):
+    """The config-2 protocol: at the 64 largest-key vertices, central
+    differences of the patch-local Q_v (x step 1e-7, metric step 1e-7 of the
+    tensor's size) against the oracle's dQ/dx and dQ/dM, entry by entry."""
     mi = inputs.config2(n)
     om = OracleMesh.from_input(mi, seed=1)
     Q, qmin, gx, gm = om.quality(grad=True)
-    for v in fd_vertices(mi.V, mi.tags):
+    worst = 0.0
+    for v in fdcheck.protocol_vertices(mi.V):
         v = int(v)
-        x0, y0 = mi.xy[v]
-        hx = 1e-7
-        fd = []
-        for dx, dy in ((hx, 0), (0, hx)):
-            om.set_xy(v, x0 + dx, y0 + dy); qp = om.patch_quality(v)
-            om.set_xy(v, x0 - dx, y0 - dy); qm = om.patch_quality(v)
-            fd.append((qp - qm) / (2 * hx))
-        om.set_xy(v, x0, y0)
-        g = gx[v]
-        assert np.abs(np.array(fd) - g).max() <= 1e-6 * np.abs(g).max()
-        m0 = mi.metric[v].copy()
-        fdm = []
-        for k in range(3):
-            # step relative to the tensor's size: the off-diagonal entry may be near 0
-            h = 1e-7 * max(abs(m0[0]), abs(m0[2]))
-            mp = m0.copy(); mp[k] += h; om.set_metric(v, *mp); qp = om.patch_quality(v)
-            mm = m0.copy(); mm[k] -= h; om.set_metric(v, *mm); qm = om.patch_quality(v)
-            fdm.append((qp - qm) / (2 * h))
-        om.set_metric(v, *m0)
-        assert np.abs(np.array(fdm) - gm[v]).max() <= 1e-6 * np.abs(gm[v]).max()
+        fx, fm, Qv, hx, hm = fdcheck.central_differences(om, v, mi.xy[v], mi.metric[v])
+        worst = max(worst, fdcheck.check_entries(fx, gx[v], Qv, hx, f"dQ/dx at {v}"))
+        worst = max(worst, fdcheck.check_entries(fm, gm[v], Qv, hm, f"dQ/dM at {v}"))
+    assert worst <= 1e-6
 
 
 def test_adjoint_euler_identities():
