@@ -41,11 +41,14 @@ typedef enum {
   PM_E_MESH = 2,     /* invalid mesh: orientation, manifoldness, ids, metric   */
   PM_E_NOMEM = 3,    /* device allocation failed                               */
   PM_E_DEVICE = 4,   /* HIP runtime error; the handle should be destroyed      */
-  PM_W_NOT_CONVERGED = 5 /* round/pass cap reached; the mesh is valid          */
+  PM_W_NOT_CONVERGED = 5, /* round/pass cap reached; the mesh is valid         */
+  PM_W_PAUSED = 6    /* pm_adapt stopped at a resume point (o->max_phases)     */
 } pm_status;
 
 enum { PM_MEM_HOST = 0, PM_MEM_DEVICE = 1 };
 enum { PM_SMOOTH_LAPLACE = 0, PM_SMOOTH_GRADIENT = 1 };
+/* phases of Algorithm 1 (pm_adapt's loop state, see pm_context) */
+enum { PM_PHASE_COARSEN = 1, PM_PHASE_SWAP = 2, PM_PHASE_REFINE = 3, PM_PHASE_SMOOTH = 4, PM_PHASE_DONE = 5 };
 
 typedef struct {
   const double* xy;      /* V x 2 */
@@ -56,10 +59,31 @@ typedef struct {
   int32_t mem_kind;      /* PM_MEM_HOST or PM_MEM_DEVICE for all four arrays */
 } pm_mesh_desc;
 
+/* Kernel shapes. Every choice gives bit-identical results (the tests check
+ * this); they trade occupancy, latency and launch count against each other,
+ * and pm_autotune picks them by measurement. Zero means the default. */
+typedef struct {
+  int32_t op_lanes;      /* lanes per member in collapse and flip classes: 0 = 16;
+                            1 (one thread per member), 8 or 16                   */
+  int32_t smooth_lanes;  /* lanes per vertex in smoothing classes: 0 = 8; 1 or 8  */
+  int32_t commit_chunk;  /* class members per commit work-group: 0 = by class size
+                            (16, 64 or 128); 16, 32, 64 or 128                   */
+  int32_t small_work;    /* 0: lists of up to 8192 vertices are coloured by one
+                            work-group, and classes of up to 32 members run with
+                            their commit in one launch; 1: always the grid-wide
+                            kernels                                              */
+  int32_t class_colours; /* colours counted by the first pass that cuts a
+                            colouring into class lists: 0 = 32; 4, 8, 16, 32,
+                            64, 128 or 256 (a colouring with more colours is
+                            cut again from the full table)                       */
+  int32_t reserved;      /* 0 */
+} pm_tuning;
+
 /* Thresholds are squared metric lengths. Defaults (pm_default_options):
  * L_low2 = 0.5, L_up2 = 2.0, q_min = 0.1, seed = 0, sweep = 0,
  * coarsen_rounds = 200, swap_rounds = 100, refine_passes = 32,
- * smooth_kind = PM_SMOOTH_LAPLACE, smooth_sweeps = 1, slack = 2.0. */
+ * smooth_kind = PM_SMOOTH_LAPLACE, smooth_sweeps = 1, slack = 2.0,
+ * pool_headroom = 3.0, max_iterations = 8, max_phases = 0, tune = zeros. */
 typedef struct {
   double L_low2;          /* collapse an edge when L^2 < L_low2                 */
   double L_up2;           /* split an edge when L^2 > L_up2                     */
@@ -71,17 +95,18 @@ typedef struct {
   int32_t refine_passes;  /* pass cap of pm_refine                              */
   int32_t smooth_kind;    /* PM_SMOOTH_LAPLACE or PM_SMOOTH_GRADIENT            */
   int32_t smooth_sweeps;  /* coloured sweeps of pm_smooth                       */
-  double slack;           /* adjacency row capacity factor (>= 1)               */
-  int32_t wg_size;        /* work-group size, 0 = library default               */
-  int32_t variant;        /* kernel shapes, results identical for all: 0 =
-                             defaults (collapse on 16 lanes per vertex,
-                             smoothing on 8, one-block kernels for small lists
-                             and classes); bit 2 = one thread per vertex,
-                             the multi-block kernels throughout, and class
-                             lists first cut from a 4-colour table (cut
-                             again from the full one past 4 colours); bit 3 =
-                             collapse on 8 lanes; bits 0, 1 = the lane-group
-                             defaults, kept for older callers                   */
+  double slack;           /* adjacency row capacity factor (>= 1), at creation  */
+  double pool_headroom;   /* free room kept in the adjacency pools and the
+                             commit's staging area, as a multiple of the live
+                             entries (>= 1), at creation. A round that runs out
+                             has its rows rebuilt from the element list with
+                             twice the room and goes on, so results do not
+                             depend on it; less room uses less device memory
+                             and costs rebuilds.                                */
+  int32_t max_iterations; /* pm_adapt: cap on Algorithm 1's outer iterations    */
+  int32_t max_phases;     /* pm_adapt: phases to run in this call before
+                             returning at a resume point; 0 = no limit          */
+  pm_tuning tune;         /* kernel shapes                                      */
 } pm_options;
 
 /* Per-phase counters, all integers:
@@ -96,7 +121,10 @@ typedef struct {
  * v[8] vertices created, v[9] elements created
  * v[10] deferred-update records committed
  * v[11] adjacency rows relocated by the commit
- * v[12] JP colouring iterations */
+ * v[12] JP colouring iterations
+ * v[13] rounds whose rows were rebuilt after the pools or the staging area
+ *       ran out of room
+ * pm_adapt sums its phases' counters, with v[0] = outer iterations run. */
 typedef struct {
   int64_t v[16];
 } pm_stats;
@@ -168,6 +196,46 @@ pm_status pm_swap(pm_mesh* m, const pm_options* o, pm_stats* st);
  * functional, each move kept only if the patch's minimum quality does not
  * drop and every area stays positive. */
 pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Algorithm 1 (Sec. 2.3), the mesh optimisation procedure: repeat coarsen,
+ * swap, refine until an outer iteration changes nothing (no collapse, flip or
+ * split) or o->max_iterations iterations have run, then smooth once
+ * (o->smooth_kind, o->smooth_sweeps). Iteration i runs its phases with sweep
+ * index i in the priority context; the final smoothing uses sweep index 0
+ * (o->sweep is ignored). The loop state lives in the handle (pm_context,
+ * which starts at iteration 0, phase PM_PHASE_COARSEN): with o->max_phases > 0
+ * at most that many phases run and the call returns PM_W_PAUSED at a resume
+ * point, from which the next call goes on; PM_OK once the final smoothing has
+ * run (further calls do nothing). A phase that stops at its round or pass cap
+ * does not stop the loop. Stats: the phases' counters summed, v[0] = outer
+ * iterations completed in this call, v[7] = 1 if one of them changed nothing. */
+pm_status pm_adapt(pm_mesh* m, const pm_options* o, pm_stats* st);
+
+/* Checkpoint and resume of Algorithm 1's loop state. seed: the handle's
+ * priority seed; iteration: the outer iteration in progress (its sweep
+ * index); phase: the next phase (PM_PHASE_*); changed: 1 if the iteration in
+ * progress has changed the mesh. A checkpoint is pm_get_context plus
+ * pm_mesh_export (whose arrays are in the handle's slot order); a handle
+ * created from those arrays and given the context with pm_set_context
+ * continues exactly as the saved handle would (pm_set_context also sets the
+ * handle's priority seed). */
+typedef struct {
+  uint64_t seed;
+  int32_t iteration;
+  int32_t phase;
+  int32_t changed;
+  int32_t reserved;  /* 0 */
+} pm_context;
+pm_status pm_get_context(const pm_mesh* m, pm_context* c);
+pm_status pm_set_context(pm_mesh* m, const pm_context* c);
+
+/* Replaces the coordinates (V x 2) and/or the metric (V x 3, stored entries)
+ * of every vertex slot; either pointer may be NULL; host or device memory per
+ * mem_kind; sizes as reported by pm_mesh_sizes. The new values are checked as
+ * pm_mesh_create checks its input (every live element counter-clockwise with
+ * positive area, every metric finite and SPD); on failure the old values are
+ * kept and PM_E_MESH is returned. Not for batches (PM_E_ARG). */
+pm_status pm_mesh_update(pm_mesh* m, const double* xy, const double* metric, int32_t mem_kind);
 
 /* Quality functional (Sec. 2.2): Q = sum over elements of the mean ratio
  * q = 4 sqrt(3) sqrt(det M) A / sum of squared metric edge lengths, M the mean

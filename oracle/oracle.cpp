@@ -61,6 +61,9 @@ struct Mesh {
   uint64_t order_seed = 0;
   std::vector<int32_t> cur_members;  // the class being processed, for the hook
   std::vector<int32_t> cur_class;    // the same class before re-validation
+  // Algorithm 1's loop state: outer iteration, next phase, whether the
+  // iteration has changed the mesh so far
+  int32_t ad_iter = 0, ad_phase = ORC_PHASE_COARSEN, ad_changed = 0;
 };
 
 // ---- sorted-set rows ---------------------------------------------------------
@@ -904,6 +907,9 @@ void orc_compact(orc_mesh* mp) {
   out.hook = m.hook;
   out.hook_user = m.hook_user;
   out.order_seed = m.order_seed;
+  out.ad_iter = m.ad_iter;
+  out.ad_phase = m.ad_phase;
+  out.ad_changed = m.ad_changed;
   out.V = nv;
   for (int64_t v = 0; v < m.V; ++v) {
     if (!m.valive[v]) continue;
@@ -970,5 +976,62 @@ void orc_element_quality(const orc_mesh* m, double* q) {
 }
 
 double orc_patch_quality(const orc_mesh* m, int32_t v) { return patch_q(*m, v, m->x[v], m->y[v]); }
+
+// ---- Algorithm 1 (Sec. 2.3): the mesh optimisation procedure ----------------------------
+// Reading: one outer iteration is coarsen, swap, refine, in that order. The
+// loop ends after an iteration that changes nothing (no collapse, flip or
+// split: the mesh has converged, and every later iteration would change
+// nothing either) or after max_iterations iterations; then the mesh is
+// smoothed once. Iteration i runs its phases with sweep index i; the final
+// smoothing uses sweep index 0 (its context differs from the loop's by the
+// phase). The loop state lives in the mesh, so a call that may run only
+// max_phases phases stops at a resume point and the next call goes on.
+int32_t orc_adapt(orc_mesh* mp, int32_t max_iterations, int32_t max_phases, int32_t smooth_kind,
+                  int32_t smooth_sweeps, double L_low2, double L_up2, double q_min, int32_t coarsen_rounds,
+                  int32_t swap_rounds, int32_t refine_passes, int64_t* st) {
+  Mesh& m = *mp;
+  std::fill(st, st + ORC_NSTATS, 0);
+  int64_t ph[ORC_NSTATS];
+  int32_t run = 0;
+  for (;;) {
+    if (m.ad_phase == ORC_PHASE_COARSEN && m.ad_iter >= max_iterations) m.ad_phase = ORC_PHASE_SMOOTH;
+    if (m.ad_phase == ORC_PHASE_DONE) return 0;
+    if (max_phases > 0 && run == max_phases) return 2;
+    int32_t phase = m.ad_phase, rc;
+    if (phase == ORC_PHASE_COARSEN) rc = orc_coarsen(mp, m.ad_iter, L_low2, q_min, coarsen_rounds, ph);
+    else if (phase == ORC_PHASE_SWAP) rc = orc_swap(mp, m.ad_iter, swap_rounds, ph);
+    else if (phase == ORC_PHASE_REFINE) rc = orc_refine(mp, L_up2, refine_passes, ph);
+    else rc = orc_smooth(mp, 0, smooth_kind, smooth_sweeps, ph);
+    if (rc < 0) return rc;
+    for (int k = 1; k < ORC_NSTATS; ++k)
+      if (k != ORC_CONVERGED) st[k] += ph[k];
+    if (phase != ORC_PHASE_SMOOTH && ph[ORC_COMMITTED] > 0) m.ad_changed = 1;
+    if (phase == ORC_PHASE_COARSEN) {
+      m.ad_phase = ORC_PHASE_SWAP;
+    } else if (phase == ORC_PHASE_SWAP) {
+      m.ad_phase = ORC_PHASE_REFINE;
+    } else if (phase == ORC_PHASE_REFINE) {
+      ++m.ad_iter;
+      st[ORC_ROUNDS] += 1;
+      if (!m.ad_changed) st[ORC_CONVERGED] = 1;
+      m.ad_phase = m.ad_changed ? ORC_PHASE_COARSEN : ORC_PHASE_SMOOTH;
+      m.ad_changed = 0;
+    } else {
+      m.ad_phase = ORC_PHASE_DONE;
+    }
+    ++run;
+  }
+}
+
+void orc_get_context(const orc_mesh* m, int32_t* iteration, int32_t* phase, int32_t* changed) {
+  *iteration = m->ad_iter;
+  *phase = m->ad_phase;
+  *changed = m->ad_changed;
+}
+void orc_set_context(orc_mesh* m, int32_t iteration, int32_t phase, int32_t changed) {
+  m->ad_iter = iteration;
+  m->ad_phase = phase;
+  m->ad_changed = changed;
+}
 
 }  // extern "C"

@@ -30,6 +30,9 @@ extern "C" {
 
 typedef struct orc_mesh orc_mesh;
 
+/* Algorithm 1's phases (loop state of orc_adapt) */
+enum { ORC_PHASE_COARSEN = 1, ORC_PHASE_SWAP = 2, ORC_PHASE_REFINE = 3, ORC_PHASE_SMOOTH = 4, ORC_PHASE_DONE = 5 };
+
 /* stats slots written by the phase calls (int64[ORC_NSTATS]) */
 enum {
   ORC_ROUNDS = 0,      /* rounds (coarsen/swap), passes (refine), sweeps (smooth) */
@@ -91,6 +94,19 @@ int32_t orc_swap(orc_mesh* m, int32_t sweep, int32_t max_rounds, int64_t* stats)
 int32_t orc_smooth(orc_mesh* m, int32_t sweep, int32_t kind, int32_t sweeps, int64_t* stats);
 /* stable renumbering of live vertices and elements */
 void orc_compact(orc_mesh* m);
+
+/* Algorithm 1 (Sec. 2.3): repeat coarsen, swap, refine until an iteration
+ * changes nothing or max_iterations have run, then smooth once. Iteration i
+ * uses sweep index i, the final smoothing sweep index 0. The loop state is
+ * kept in the mesh: with max_phases > 0 at most that many phases run and the
+ * call returns 2 at a resume point; 0 when the procedure has finished. Stats:
+ * the phases' counters summed, ORC_ROUNDS = iterations completed,
+ * ORC_CONVERGED = 1 if an iteration changed nothing. */
+int32_t orc_adapt(orc_mesh* m, int32_t max_iterations, int32_t max_phases, int32_t smooth_kind,
+                  int32_t smooth_sweeps, double L_low2, double L_up2, double q_min, int32_t coarsen_rounds,
+                  int32_t swap_rounds, int32_t refine_passes, int64_t* stats);
+void orc_get_context(const orc_mesh* m, int32_t* iteration, int32_t* phase, int32_t* changed);
+void orc_set_context(orc_mesh* m, int32_t iteration, int32_t phase, int32_t changed);
 
 /* Quality functional Q = sum of mean-ratio qualities; optional adjoint.
  * dQdx: V x 2, dQdM: V x 3 (stored entries m00, m01, m11). */

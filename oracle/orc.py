@@ -18,6 +18,7 @@ NSTATS = 16
 STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colours",
               "edges", "converged", "new_vertices", "new_elements"]
 PH_COARSEN, PH_SWAP, PH_SMOOTH = 1, 2, 3
+PHASE_COARSEN, PHASE_SWAP, PHASE_REFINE, PHASE_SMOOTH, PHASE_DONE = 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -62,6 +63,11 @@ def lib():
         L.orc_smooth.restype = C.c_int32
         L.orc_smooth.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
         L.orc_compact.argtypes = [P]
+        L.orc_adapt.restype = C.c_int32
+        L.orc_adapt.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_int32, C.c_int32, C.c_int32, P]
+        L.orc_get_context.argtypes = [P, P, P, P]
+        L.orc_set_context.argtypes = [P, C.c_int32, C.c_int32, C.c_int32]
         L.orc_quality.argtypes = [P, P, P, P, P]
         L.orc_element_quality.argtypes = [P, P]
         L.orc_patch_quality.restype = C.c_double
@@ -226,6 +232,24 @@ class OracleMesh:
 
     def patch_quality(self, v: int) -> float:
         return float(lib().orc_patch_quality(self.h, v))
+
+    def adapt(self, max_iterations=8, max_phases=0, smooth_kind=0, smooth_sweeps=1, L_low2=0.5, L_up2=2.0,
+              q_min=0.1, coarsen_rounds=200, swap_rounds=100, refine_passes=32):
+        """Algorithm 1 from the mesh's loop state; returns (stats, finished)."""
+        st = np.zeros(NSTATS, np.int64)
+        rc = lib().orc_adapt(self.h, max_iterations, max_phases, smooth_kind, smooth_sweeps, L_low2, L_up2, q_min,
+                             coarsen_rounds, swap_rounds, refine_passes, _p(st))
+        if rc < 0:
+            raise RuntimeError(f"oracle adapt failed: {rc}")
+        return self._stats(st), rc == 0
+
+    def get_context(self):
+        it, ph, ch = C.c_int32(), C.c_int32(), C.c_int32()
+        lib().orc_get_context(self.h, C.byref(it), C.byref(ph), C.byref(ch))
+        return dict(iteration=it.value, phase=ph.value, changed=ch.value)
+
+    def set_context(self, iteration, phase, changed):
+        lib().orc_set_context(self.h, iteration, phase, changed)
 
     def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1,
               L_low2=0.5, L_up2=2.0, q_min=0.1, coarsen_rounds=200, refine_passes=32, swap_rounds=100):

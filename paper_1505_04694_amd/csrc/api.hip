@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <initializer_list>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -69,13 +71,20 @@ struct pm_mesh {
   DBuf<int4> tgt;        // commit: collapse-target records
   int epoch = 0;         // commit epoch, one per class
   DBuf<double> qpart;
+  DBuf<double> upd;  // pm_mesh_update: the previous coordinates and metric
   DBuf<uint64_t> rw;  // round words (priority, active, colour) per vertex
   // mesh ranges (host mirror of Store::vbase/vused/tbase/tused)
   std::vector<int> vbase, vused, tbase, tused;
   int* ranges = nullptr;  // device: vbase[B+1], vused[B], tbase[B+1], tused[B]
   int* mdone = nullptr;   // device: per-mesh "refinement finished" flags
   DBuf<int> rtmp;         // per-mesh scratch (sums, new bases)
-  int variant = 0;  // bit 0: lane-group collapse, bit 1: lane-group smoothing, bit 2: no automatic shapes
+  pm_tuning tune{};      // kernel shapes of the current call (zeros: defaults)
+  double headroom = 3.0;  // pool and staging room, a multiple of the live entries
+  double stage_scale = 1.0;  // grows when the staging area ran out
+  int recoveries = 0;     // row rebuilds after running out of room, in the current phase
+  // Algorithm 1's loop state (pm_adapt): outer iteration, next phase, whether
+  // the iteration has changed the mesh
+  int ad_iter = 0, ad_phase = 1, ad_changed = 0;
   int64_t peak_bytes = 0, cur_bytes = 0;
   int jp_last = 8;    // JP iterations the last colouring took
   int class_seq = 0;  // class-list calls so far (the wide-colour flag's value)
@@ -297,6 +306,10 @@ void prof_flush(pm_mesh* m) {
   m->prof.open.clear();
 }
 
+// the counters a round reads back: pool tops, error bits, list length and the
+// epoch of a commit that ran out of room
+constexpr int kRoundCtrs = C_FAILEP + 1;
+
 // copy device counters [lo, lo+n) to the pinned mirror and wait
 pm_status read_ctr(pm_mesh* m, int lo, int n) {
   HIPCHK(hipMemcpyAsync(m->hctr + lo, m->ctr + lo, n * sizeof(int), hipMemcpyDeviceToHost, m->s));
@@ -440,12 +453,14 @@ pm_status build_rows(pm_mesh* m, bool check = true) {
   // the slot totals are the pools' new bump pointers
   scan_excl(m->vt1.p, m->vt3.p, V, m->ctr + C_NN_TOP, m->partial.p, m->s);
   scan_excl(m->vt2.p, m->vt4.p, V, m->ctr + C_NE_TOP, m->partial.p, m->s);
-  // room for rows that outgrow their slot before the next rebuild: 3x the
-  // used entries. Slot capacities are at most c(1+slack) + slack + 7 for a
-  // vertex in c elements, and the c sum to 3T, which bounds both totals; when
-  // the pools hold 3x that bound they are large enough without a read-back.
+  // room for rows that outgrow their slot before the next rebuild: the
+  // headroom (3 by default) times the used entries. Slot capacities are at
+  // most c(1+slack) + slack + 7 for a vertex in c elements, and the c sum to
+  // 3T, which bounds both totals; when the pools hold the headroom times that
+  // bound they are large enough without a read-back.
   double bound = 3.0 * st.T * (1.0 + m->slack) + (double)V * (m->slack + 7.0);
-  double room = 3.0 * bound + 4096.0;
+  double extra = m->headroom >= 3.0 ? 4096.0 : 64.0;
+  double room = m->headroom * bound + extra;
   if (room <= (double)INT32_MAX && (double)st.nn_pool >= room && (double)st.ne_pool >= room) {
     set_headers(st, m->vt3.p, m->vt4.p, m->vt1.p, m->vt2.p, m->s);
     build_fill(st, nullptr, m->s);
@@ -454,7 +469,8 @@ pm_status build_rows(pm_mesh* m, bool check = true) {
   }
   TRY(read_ctr(m, C_NN_TOP, 2));
   int64_t nn_used = m->hctr[C_NN_TOP], ne_used = m->hctr[C_NE_TOP];
-  int64_t nn_need = 3 * nn_used + 4096, ne_need = 3 * ne_used + 4096;
+  int64_t nn_need = (int64_t)(m->headroom * (double)nn_used + extra);
+  int64_t ne_need = (int64_t)(m->headroom * (double)ne_used + extra);
   if (nn_need > INT32_MAX || ne_need > INT32_MAX) return fail(m, PM_E_NOMEM, "adjacency pool beyond 2^31 entries");
   if (st.nn_pool < nn_need || st.ne_pool < ne_need) {
     TRY(sync(m));
@@ -506,8 +522,10 @@ pm_status ensure_phase_scratch(pm_mesh* m) {
   TRY(ensure(m, m->spos, V));
   TRY(ensure(m, m->spart, scan_partials_needed(V) + 2));
   // staging for the rows past the register path (more than 32 candidates):
-  // 4 ids per candidate; running out fails the phase with E_STAGE
-  size_t stage = 4 * (size_t)T + 4 * (size_t)V + 65536;
+  // 4 ids per candidate; a round that runs out is redone from a row rebuild
+  // with twice the staging
+  size_t stage = (size_t)(m->stage_scale * m->headroom / 3.0 * (4.0 * T + 4.0 * V)) +
+                 (m->headroom >= 3.0 ? 65536 : 64);
   TRY(ensure(m, m->stage, stage));
   return PM_OK;
 }
@@ -550,7 +568,7 @@ void small_classes(pm_mesh* m, Classes& out) {
 pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out = Classes();
   if (n == 0) return PM_OK;
-  if (n <= kSmallColour && !(m->variant & 4)) {
+  if (n <= kSmallColour && !m->tune.small_work) {
     timed(m, PM_K_JP, 0,
           [&] { colour_small(m->st, A, n, nullptr, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, m->s); });
     TRY(read_ctr(m, 0, C_NCOL + 1));
@@ -576,14 +594,14 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
             [&] { jp_chunk(m->st, A, n, m->jpU0.p, m->jpB.p, m->jpU1.p, it == 0, rd, m->ctr, it, m->s); });
     stripe_sum(m->ctr, S_JPL + ((it - 1) & 7), 1, C_JP, m->s);
     m->class_seq = m->class_seq >= 0x3FFFFFFF ? 1 : m->class_seq + 1;
-    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, (m->variant & 4) ? 4 : kClassNarrow,
-                m->class_seq, m->s);
+    class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p,
+                m->tune.class_colours ? m->tune.class_colours : kClassNarrow, m->class_seq, m->s);
     TRY(read_ctr(m, 0, C_NCOL + 1));
     int left = m->hctr[C_JP];
     if (left == 0) break;
     if (it > 4096) return fail(m, PM_E_DEVICE, "colouring did not finish");
   }
-  if (m->hctr[C_NCOL] == -2) {
+  if (m->hctr[C_NCOL] == -2 && m->tune.class_colours != 256) {
     // a colour past the narrow table: the full table
     class_lists(A, n, rd.rw, m->ctr, m->cls.p, m->ctab.p, m->ctabs.p, m->spart.p, 256, 0, m->s);
     TRY(read_ctr(m, 0, C_NCOL + 1));
@@ -719,11 +737,23 @@ pm_status compact(pm_mesh* m, const std::vector<int>* extra_v = nullptr, const s
   return build_rows(m);
 }
 
+bool bad_tuning(const pm_tuning& t) {
+  auto in = [](int v, std::initializer_list<int> ok) {
+    for (int x : ok)
+      if (v == x) return true;
+    return false;
+  };
+  return !in(t.op_lanes, {0, 1, 8, 16}) || !in(t.smooth_lanes, {0, 1, 8}) ||
+         !in(t.commit_chunk, {0, 16, 32, 64, 128}) || !in(t.small_work, {0, 1}) ||
+         !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || t.reserved != 0;
+}
+
 bool bad_opts(const pm_options* o) {
   return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
          o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
          (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0) ||
-         o->variant < 0 || o->variant > 15;
+         !(o->pool_headroom == 0.0 || (o->pool_headroom >= 1.0 && o->pool_headroom <= 64.0)) ||
+         o->max_iterations < 0 || o->max_iterations > 4095 || o->max_phases < 0 || bad_tuning(o->tune);
 }
 
 // Collapse runs on groups of lanes per member by default: each lane loads
@@ -731,13 +761,9 @@ bool bad_opts(const pm_options* o) {
 // keeps it in registers, so a member costs a few dependent loads and no
 // re-reads (one thread per member walks the ring serially and, with tens of
 // thousands of members in flight per XCD, re-fetches it from HBM). 16 lanes
-// by default, 8 on request; one thread per member on request.
-int collapse_shape(const pm_mesh* m, int n) {
-  (void)n;
-  if (m->variant & 4) return 0;
-  if (m->variant & 8) return 2;
-  return 1;
-}
+// by default; 8, or one thread per member, by tuning.
+int op_lanes(const pm_mesh* m) { return m->tune.op_lanes ? m->tune.op_lanes : 16; }
+int smooth_lanes(const pm_mesh* m) { return m->tune.smooth_lanes ? m->tune.smooth_lanes : 8; }
 
 pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind);
 
@@ -752,23 +778,90 @@ pm_status run_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   return r;
 }
 
+// One class of a round: the operation over its members, then the commit of
+// the rows they changed (one launch for a small class)
+void run_class(pm_mesh* m, int kind, const Classes& cl, int c, const OpArgs& a, const Commit& cm) {
+  const int* list = m->cls.p + cl.off[c];
+  int n = cl.size[c];
+  if (n <= kSmallClass && !m->tune.small_work) {
+    timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, n, [&] { class_small(m->st, list, n, a, cm, kind, m->ctr, m->s); });
+    return;
+  }
+  if (kind == 0)
+    timed(m, PM_K_COLLAPSE, n, [&] { collapse_class(m->st, list, n, a, cm, m->ctr, op_lanes(m), m->s); });
+  else
+    timed(m, PM_K_FLIP, n, [&] {
+      if (op_lanes(m) == 1) flip_class(m->st, list, n, a, cm, m->ctr, m->s);
+      else flip_class_g(m->st, list, n, a, cm, m->ctr, m->s);
+    });
+  timed(m, PM_K_COMMIT, 0,
+        [&] { commit_rows(m->st, list, n, cm, kind != 0, m->tune.commit_chunk, m->ctr, m->s); });
+}
+
+// A commit ran out of pool or staging room in this round (the host copy of
+// the counters says so): rebuild every row from the element list with twice
+// the room, then run the classes after the one that ran out. Their kernels
+// exited at once; the failing class's operations are all in the element list.
+// class_epoch[c]: the epoch class c ran with (-1: not run).
+pm_status recover_round(pm_mesh* m, int kind, const Classes& cl, std::vector<int>& class_epoch, Round rd,
+                        const pm_options* o, int listA_n) {
+  double qmin2 = o->q_min * o->q_min;
+  for (;;) {
+    int err = m->hctr[C_ERR], fe = m->hctr[C_FAILEP];
+    if (!(err & kRoomErr)) return PM_OK;
+    int cf = -1;
+    for (int c = 0; c < cl.ncol; ++c)
+      if (class_epoch[c] == fe) cf = c;
+    if (cf < 0) return fail(m, PM_E_DEVICE, "room error of an unknown class");
+    ++m->recoveries;
+    if (err & (E_NN_POOL | E_NE_POOL)) m->headroom *= 2.0;
+    if (err & E_STAGE) m->stage_scale *= 2.0;
+    set_int(m->ctr + C_ERR, err & ~kRoomErr, m->s);
+    set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
+    // every row again from the element list, packed, with the larger room
+    TRY(build_rows(m, false));
+    TRY(ensure_phase_scratch(m));
+    // the round words were cleared with the round: set them again from the
+    // class lists, run the remaining classes, clear them again
+    std::vector<int> offs(cl.off.begin(), cl.off.end());
+    TRY(ensure(m, m->rtmp, (size_t)std::max(cl.ncol, 1)));
+    HIPCHK(hipMemcpyAsync(m->rtmp.p, offs.data(), sizeof(int) * cl.ncol, hipMemcpyHostToDevice, m->s));
+    restore_round(m->st, m->cls.p, listA_n, m->rtmp.p, cl.ncol, rd, m->s);
+    Commit cm = commit_of(m);
+    cm.touched = nullptr;
+    std::vector<int> ep = class_epoch;
+    for (int c = cf + 1; c < cl.ncol; ++c) {
+      if (cl.size[c] == 0) continue;
+      cm.epoch = ++m->epoch;
+      ep[c] = cm.epoch;
+      OpArgs a{m->rw.p, c, rd, o->L_low2, qmin2};
+      run_class(m, kind, cl, c, a, cm);
+    }
+    HIPCHK(hipStreamSynchronize(m->s));  // the offsets' host copy is a local vector
+    clear_round(m->cls.p, listA_n, m->rw.p, m->s);
+    TRY(read_ctr(m, 0, kRoundCtrs));
+    class_epoch = ep;
+  }
+}
+
 pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   TRY(ensure_phase_scratch(m));
-  m->variant = o->variant;
+  m->tune = o->tune;
+  m->recoveries = 0;
   int mode = kind == 0 ? 1 : 2;
   int max_rounds = kind == 0 ? o->coarsen_rounds : o->swap_rounds;
   int phase = kind == 0 ? PH_COARSEN : PH_SWAP;
   double qmin2 = o->q_min * o->q_min;
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
+  set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
   timed(m, PM_K_SELECT, m->st.V,
-        [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p,
+        [&] { select_vertices(m->st, mode, o->L_low2, nullptr, nullptr, m->listA.p, m->ctr, m->sflag.p,
                           m->spos.p, m->spart.p, m->s); });
-  TRY(read_ctr(m, 0, C_EVAL));  // pool tops, error bits and the list length at once
+  TRY(read_ctr(m, 0, kRoundCtrs));  // pool tops, error bits and the list length at once
   TRY(check_err(m, true));
   int nA = m->hctr[C_LIST_B];
   int r = 0;
-  Commit cm = commit_of(m);
   // a small round colours the next round's list as soon as it is selected,
   // before the read-back that returns its length: one read-back for both
   bool ahead = false;
@@ -786,19 +879,22 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
       TRY(colour_list(m, m->listA.p, nA, rd, cl));
     }
     ahead = false;
+    Commit cm = commit_of(m);
     // a small round (coloured by one block) records the rows it rebuilds, so
     // the next round's list comes from its own lists, not from every slot
-    bool small = nA <= kSmallColour && !(m->variant & 4);
+    bool small = nA <= kSmallColour && !m->tune.small_work;
     cm.touched = small ? m->touch.p : nullptr;
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
+    std::vector<int> class_epoch(cl.ncol, -1);
     // a small round whose classes are all small: every class in one block,
     // one launch
     bool all_small = small && cl.ncol > 1;
     for (int c = 0; c < cl.ncol && all_small; ++c) all_small = cl.size[c] <= kSmallClass;
     if (all_small) {
       cm.epoch = m->epoch + 1;
+      for (int c = 0; c < cl.ncol; ++c) class_epoch[c] = cm.epoch + c;
       m->epoch += cl.ncol;
       OpArgs a{m->rw.p, 0, rd, o->L_low2, qmin2};
       timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, nA,
@@ -807,26 +903,9 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     for (int c = 0; c < cl.ncol && !all_small; ++c) {
       if (cl.size[c] == 0) continue;
       cm.epoch = ++m->epoch;
+      class_epoch[c] = cm.epoch;
       OpArgs a{m->rw.p, c, rd, o->L_low2, qmin2};
-      if (cl.size[c] <= kSmallClass && !(m->variant & 4)) {
-        // a small class: operation and commit in one block, one launch
-        timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, cl.size[c],
-              [&] { class_small(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, kind, m->ctr, m->s); });
-        continue;
-      }
-      if (kind == 0)
-        timed(m, PM_K_COLLAPSE, cl.size[c], [&] {
-          collapse_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, collapse_shape(m, cl.size[c]), m->s);
-        });
-      else
-        timed(m, PM_K_FLIP, cl.size[c],
-              [&] {
-                if (m->variant & 4) flip_class(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
-                else flip_class_g(m->st, m->cls.p + cl.off[c], cl.size[c], a, cm, m->ctr, m->s);
-              });
-      timed(m, PM_K_COMMIT, 0, [&] {
-        commit_rows(m->st, m->cls.p + cl.off[c], cl.size[c], cm, kind != 0, m->ctr, m->s);
-      });
+      run_class(m, kind, cl, c, a, cm);
     }
     clear_round(m->listA.p, nA, m->rw.p, m->s);
     bool listed = false;
@@ -843,20 +922,28 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
                        m->ctr, m->s);
         });
       }
-      TRY(read_ctr(m, 0, launch ? C_NCOL + 1 : C_EVAL));
+      TRY(read_ctr(m, 0, launch ? C_NCOL + 1 : kRoundCtrs));
       listed = m->hctr[C_LIST_B] >= 0;
       if (launch && listed && m->hctr[C_NCOL] >= 0) {
         ahead = true;
         small_classes(m, next);
       }
     }
-    if (!listed) {
+    auto select_all = [&]() -> pm_status {
       set_int(m->ctr + C_LIST_B, 0, m->s);
       timed(m, PM_K_SELECT, m->st.V, [&] {
-        select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr + C_LIST_B, m->sflag.p,
-                        m->spos.p, m->spart.p, m->s);
+        select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr, m->sflag.p, m->spos.p,
+                        m->spart.p, m->s);
       });
-      TRY(read_ctr(m, 0, C_EVAL));
+      return read_ctr(m, 0, kRoundCtrs);
+    };
+    if (!listed) TRY(select_all());
+    if (m->hctr[C_ERR] & kRoomErr) {
+      // the selections and the next colouring declined (they saw the error):
+      // rebuild, finish the round, then select over every slot
+      TRY(recover_round(m, kind, cl, class_epoch, rd, o, nA));
+      ahead = false;
+      TRY(select_all());
     }
     TRY(check_err(m, true));
     nA = m->hctr[C_LIST_B];
@@ -866,6 +953,7 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
   TRY(stats_read(m, st));
   st->v[0] = r;
   st->v[7] = nA == 0 ? 1 : 0;
+  st->v[13] = m->recoveries;
   return PM_OK;
 }
 
@@ -881,8 +969,10 @@ void fill_defaults(pm_options* o) {
   o->smooth_kind = PM_SMOOTH_LAPLACE;
   o->smooth_sweeps = 1;
   o->slack = 2.0;
-  o->wg_size = 0;
-  o->variant = 0;
+  o->pool_headroom = 3.0;
+  o->max_iterations = 8;
+  o->max_phases = 0;
+  o->tune = pm_tuning{};
 }
 
 }  // namespace
@@ -929,6 +1019,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->vr.p, m->vr.n);
   for (auto* b : ub) dfree(m, b->p, b->n);
   dfree(m, m->qpart.p, m->qpart.n);
+  dfree(m, m->upd.p, m->upd.n);
   dfree(m, m->rw.p, m->rw.n);
   dfree(m, m->own.p, m->own.n);
   dfree(m, m->tk.p, m->tk.n);
@@ -961,6 +1052,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
+  m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
   g_create_err.clear();
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
@@ -969,6 +1061,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   };
   if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
   zero_ints(m->ctr, C_COUNT, m->s);
+  set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
   int V = (int)d->V, T = (int)d->T;
   if (grow_vertices(m, V) != PM_OK || grow_elements(m, T) != PM_OK) return bail(PM_E_NOMEM);
   Store& st = m->st;
@@ -1094,7 +1187,7 @@ pm_status pm_colour(pm_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* co
     act_in = m->u8tmp.p;
   }
   set_int(m->ctr + C_LIST_B, 0, m->s);
-  select_vertices(st, 0, 0.0, act_in, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p, m->spos.p, m->spart.p,
+  select_vertices(st, 0, 0.0, act_in, nullptr, m->listA.p, m->ctr, m->sflag.p, m->spos.p, m->spart.p,
                   m->s);
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
@@ -1141,10 +1234,10 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   if (!st) st = &local;
   memset(st, 0, sizeof(*st));
   TRY(ensure_phase_scratch(m));
-  m->variant = o->variant;
+  m->tune = o->tune;
   stats_zero(m);
   set_int(m->ctr + C_LIST_B, 0, m->s);
-  select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr + C_LIST_B, m->sflag.p, m->spos.p,
+  select_vertices(m->st, 3, 0.0, nullptr, nullptr, m->listA.p, m->ctr, m->sflag.p, m->spos.p,
                   m->spart.p, m->s);
   TRY(read_ctr(m, C_LIST_B, 1));
   int n = m->hctr[C_LIST_B];
@@ -1164,7 +1257,7 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < cl.ncol; ++c)
       timed(m, PM_K_SMOOTH, cl.size[c], [&] {
-        smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, (m->variant & 4) ? 0 : 1, m->s);
+        smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, smooth_lanes(m), m->s);
       });
   m->st.emet = nullptr;
   clear_round(m->listA.p, n, m->rw.p, m->s);
@@ -1305,6 +1398,101 @@ pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* 
   return PM_OK;
 }
 
+pm_status pm_adapt(pm_mesh* m, const pm_options* o, pm_stats* st) {
+  if (!m || !o) return PM_E_ARG;
+  if (bad_opts(o)) return fail(m, PM_E_ARG, "bad options");
+  pm_stats local;
+  if (!st) st = &local;
+  memset(st, 0, sizeof(*st));
+  int run = 0;
+  for (;;) {
+    if (m->ad_phase == PM_PHASE_COARSEN && m->ad_iter >= o->max_iterations) m->ad_phase = PM_PHASE_SMOOTH;
+    if (m->ad_phase == PM_PHASE_DONE) return PM_OK;
+    if (o->max_phases > 0 && run == o->max_phases) return PM_W_PAUSED;
+    pm_options po = *o;
+    po.sweep = m->ad_phase == PM_PHASE_SMOOTH ? 0 : m->ad_iter;
+    pm_stats ph;
+    pm_status r;
+    int phase = m->ad_phase;
+    if (phase == PM_PHASE_COARSEN) r = pm_coarsen(m, &po, &ph);
+    else if (phase == PM_PHASE_SWAP) r = pm_swap(m, &po, &ph);
+    else if (phase == PM_PHASE_REFINE) r = pm_refine(m, &po, &ph);
+    else r = pm_smooth(m, &po, &ph);
+    if (r != PM_OK && r != PM_W_NOT_CONVERGED) return r;
+    for (int k = 1; k < 16; ++k)
+      if (k != 7) st->v[k] += ph.v[k];
+    if (phase != PM_PHASE_SMOOTH && ph.v[4] > 0) m->ad_changed = 1;
+    if (phase == PM_PHASE_COARSEN) {
+      m->ad_phase = PM_PHASE_SWAP;
+    } else if (phase == PM_PHASE_SWAP) {
+      m->ad_phase = PM_PHASE_REFINE;
+    } else if (phase == PM_PHASE_REFINE) {
+      ++m->ad_iter;
+      st->v[0] += 1;
+      if (!m->ad_changed) st->v[7] = 1;
+      m->ad_phase = m->ad_changed ? PM_PHASE_COARSEN : PM_PHASE_SMOOTH;
+      m->ad_changed = 0;
+    } else {
+      m->ad_phase = PM_PHASE_DONE;
+    }
+    ++run;
+  }
+}
+
+pm_status pm_get_context(const pm_mesh* m, pm_context* c) {
+  if (!m || !c) return PM_E_ARG;
+  c->seed = m->seed;
+  c->iteration = m->ad_iter;
+  c->phase = m->ad_phase;
+  c->changed = m->ad_changed;
+  c->reserved = 0;
+  return PM_OK;
+}
+
+pm_status pm_set_context(pm_mesh* m, const pm_context* c) {
+  if (!m || !c) return PM_E_ARG;
+  if (c->iteration < 0 || c->iteration > 4095 || c->phase < PM_PHASE_COARSEN || c->phase > PM_PHASE_DONE ||
+      (c->changed != 0 && c->changed != 1) || c->reserved != 0)
+    return fail(m, PM_E_ARG, "bad context");
+  m->seed = c->seed;
+  m->ad_iter = c->iteration;
+  m->ad_phase = c->phase;
+  m->ad_changed = c->changed;
+  return PM_OK;
+}
+
+pm_status pm_mesh_update(pm_mesh* m, const double* xy, const double* metric, int32_t mem_kind) {
+  if (!m) return PM_E_ARG;
+  if (mem_kind != PM_MEM_HOST && mem_kind != PM_MEM_DEVICE) return fail(m, PM_E_ARG, "bad mem_kind");
+  if (m->st.B != 1) return fail(m, PM_E_ARG, "pm_mesh_update takes a single mesh");
+  if (!xy && !metric) return PM_OK;
+  Store& st = m->st;
+  size_t V = (size_t)st.V;
+  hipMemcpyKind k = mem_kind == PM_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  // the old values, kept until the new ones pass the checks
+  TRY(ensure(m, m->upd, 5 * V));
+  double2* old_xy = (double2*)m->upd.p;
+  Met* old_met = (Met*)(m->upd.p + 2 * V);
+  if (xy) {
+    HIPCHK(hipMemcpyAsync(old_xy, st.xy, sizeof(double2) * V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(st.xy, xy, sizeof(double2) * V, k, m->s));
+  }
+  if (metric) {
+    HIPCHK(hipMemcpyAsync(old_met, st.met, sizeof(Met) * V, hipMemcpyDeviceToDevice, m->s));
+    HIPCHK(hipMemcpyAsync(st.met, metric, sizeof(Met) * V, k, m->s));
+  }
+  k_validate(st, m->ctr, m->s);
+  pm_status r = check_err(m);
+  if (r != PM_OK) {
+    if (xy) HIPCHK(hipMemcpyAsync(st.xy, old_xy, sizeof(double2) * V, hipMemcpyDeviceToDevice, m->s));
+    if (metric) HIPCHK(hipMemcpyAsync(st.met, old_met, sizeof(Met) * V, hipMemcpyDeviceToDevice, m->s));
+    TRY(sync(m));
+    return r;
+  }
+  ++m->topo;  // the per-element tensors smoothing keeps follow the metric
+  return PM_OK;
+}
+
 pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_options* o, void* stream,
                           pm_mesh** out) {
   if (!out) return PM_E_ARG;
@@ -1380,6 +1568,7 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
   m->slack = o->slack;
+  m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
     pm_mesh_destroy(m);
@@ -1387,6 +1576,7 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   };
   if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
   zero_ints(m->ctr, C_COUNT, m->s);
+  set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
   Store& st = m->st;
   st.B = count;
   if (grow_vertices(m, nV) != PM_OK || grow_elements(m, nT) != PM_OK) return bail(PM_E_NOMEM);

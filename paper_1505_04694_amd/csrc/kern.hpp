@@ -28,6 +28,7 @@ enum Ctr {
   C_TOTAL2 = 15,
   C_JP = 16,        // JP: vertices still waiting after the last iteration (summed)
   C_CWIDE = 17,     // class lists: the call number of the last list with a colour past the narrow table
+  C_FAILEP = 18,    // smallest commit epoch whose rows ran out of pool or staging room (INT_MAX: none)
   C_HIST = 64,      // 64..319: colour histogram (class sizes)
   C_OFF = 320,      // 320..575: class offsets
   C_CUR = 576,      // 576..831: class cursors
@@ -65,6 +66,29 @@ enum Err {
   E_COLOURS = 256,
   E_ROWCAP = 512
 };
+// A commit that runs out of adjacency-pool or staging room leaves some rows
+// unwritten (the element list and the next-round flags stay right). Every
+// later class and commit kernel then exits at once, and the host rebuilds
+// the rows from the element list with more room and redoes the rest of the
+// round.
+constexpr int kRoomErr = E_NN_POOL | E_NE_POOL | E_STAGE;
+__device__ __forceinline__ bool room_failed(const int* ctr) {
+  return (__hip_atomic_load(ctr + C_ERR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kRoomErr) != 0;
+}
+// the same answer for every thread of the block (call it where every thread
+// of the block reaches it)
+__device__ __forceinline__ bool room_failed_block(const int* ctr) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = room_failed(ctr) ? 1 : 0;
+  __syncthreads();
+  bool f = flag != 0;
+  __syncthreads();
+  return f;
+}
+__device__ __forceinline__ void room_fail(int* ctr, int err, int epoch) {
+  atomicOr(&ctr[C_ERR], err);
+  atomicMin(&ctr[C_FAILEP], epoch);
+}
 
 struct Store {
   int V = 0, T = 0;        // slot counts
@@ -210,10 +234,14 @@ struct OpArgs {
 void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s);
 void clear_round(const int* list, int n, uint64_t* rw, hipStream_t s);
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
-// selected vertices in ascending order; flag/pos: V ints, partial: scan scratch
+// selected vertices in ascending order, their count to ctr[C_LIST_B];
+// flag/pos: V ints, partial: scan scratch
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
-                     int* n, int* flag, int* pos, int* partial, hipStream_t s);
+                     int* ctr, int* flag, int* pos, int* partial, hipStream_t s);
 void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s);
+// round words of the n vertices of the class lists cls (class c starts at
+// off[c], the device copy of the class offsets) as their colouring set them
+void restore_round(const Store& st, const int* cls, int n, const int* off, int ncol, Round rd, hipStream_t s);
 // One JP iteration over a chunked list: chunk k of kJpChunk slots holds cnt[k]
 // vertices at W[k * kJpChunk ...]; the first iteration reads the n entries of
 // A instead. Waiting vertices are compacted in place, in order, per chunk.
@@ -244,16 +272,18 @@ constexpr int kSmallColour = 8192;
 void colour_small(const Store& st, const int* A, int n, const int* n_dev, Round rd, int* W0, int* W1, int* WB,
                   int* out, int* ctr, hipStream_t s);
 
-// variant 0: one thread per member; 1: a group of 8 lanes per member
-void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
+// lanes per member: 1 (one thread), 8 or 16
+void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int lanes,
                     hipStream_t s);
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
 // flips on groups of 16 lanes per member
 void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s);
-void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s);
+// lanes per vertex: 1 (one thread) or 8
+void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int lanes, hipStream_t s);
 // rebuild the rows claimed by the committed members of list[0..n) (the class
 // just processed, launched in the same shape); flips: members' own rows too
-void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s);
+// chunk: class members per work-group (0: by class size)
+void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int chunk, int* ctr, hipStream_t s);
 // a class of at most kSmallClass members: operation and commit in one block
 // (kind 0 collapse, 1 flip)
 constexpr int kSmallClass = 32;

@@ -61,9 +61,15 @@ __device__ __forceinline__ bool want(const Store& st, int v, int mode, double L_
   }
 }
 
-// flag[v] = 1 for every vertex v with (nxt == null or nxt[v]) and want(v); clears nxt
+// flag[v] = 1 for every vertex v with (nxt == null or nxt[v]) and want(v); clears nxt.
+// After a commit that ran out of room (the rows are being rebuilt) it selects
+// nothing and leaves the flags for the selection that follows the rebuild.
 __global__ void k_select_flags(Store st, int mode, double L_low2, const uint8_t* __restrict__ active,
-                               uint8_t* __restrict__ nxt, int* __restrict__ flag) {
+                               uint8_t* __restrict__ nxt, int* __restrict__ flag, const int* ctr) {
+  if (nxt && room_failed(ctr)) {
+    for (int v = xtid(); v < st.V; v += gstride()) flag[v] = 0;
+    return;
+  }
   for (int v = xtid(); v < st.V; v += gstride()) {
     bool on = nxt ? nxt[v] != 0 : true;
     if (nxt && on) nxt[v] = 0;
@@ -78,8 +84,9 @@ __global__ void k_select_scatter(int V, const int* __restrict__ flag, const int*
 // the selected vertices in ascending id order (an ordered compaction), so
 // that lists and the colour classes cut from them follow the mesh's layout
 void select_vertices(const Store& st, int mode, double L_low2, const uint8_t* active, uint8_t* nxt, int* out,
-                     int* n, int* flag, int* pos, int* partial, hipStream_t s) {
-  k_select_flags<<<grid_for(st.V), kBlock, 0, s>>>(st, mode, L_low2, active, nxt, flag);
+                     int* ctr, int* flag, int* pos, int* partial, hipStream_t s) {
+  int* n = ctr + C_LIST_B;
+  k_select_flags<<<grid_for(st.V), kBlock, 0, s>>>(st, mode, L_low2, active, nxt, flag, ctr);
   scan_excl(flag, pos, st.V, n, partial, s);
   k_select_scatter<<<grid_for(st.V), kBlock, 0, s>>>(st.V, flag, pos, out);
 }
@@ -94,6 +101,22 @@ __global__ void k_jp_init(Store st, const int* __restrict__ A, int n, Round rd) 
 }
 void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
   if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(st, A, n, rd);
+}
+
+// round words of a coloured list again, from its class lists (the list is
+// the classes' union, class c holds the vertices of colour c)
+__global__ void k_restore_round(Store st, const int* __restrict__ cls, int n, const int* __restrict__ off, int ncol,
+                                Round rd) {
+  for (int i = gtid(); i < n; i += gstride()) {
+    int c = 0;
+    while (c + 1 < ncol && off[c + 1] <= i) ++c;
+    int v = cls[i];
+    uint64_t prio = key_of(st, rd, v) >> 32;
+    rd.rw[v] = (prio << 32) | kRwAct | (uint64_t)c;
+  }
+}
+void restore_round(const Store& st, const int* cls, int n, const int* off, int ncol, Round rd, hipStream_t s) {
+  if (n > 0) k_restore_round<<<grid_for(n), kBlock, 0, s>>>(st, cls, n, off, ncol, rd);
 }
 
 // A vertex is ready once every active neighbour of larger key has a colour;
@@ -384,12 +407,15 @@ void class_lists(const int* A, int n, const uint64_t* rw, int* ctr, int* out, in
   static_assert(kBlock == 256, "class kernels use one LDS slot per colour and thread");
   int nb = (n + kBlock - 1) / kBlock;
   if (nb < 1) nb = 1;
-  if (cm == 4)
-    class_lists_cm<4>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
-  else if (cm == kClassNarrow)
-    class_lists_cm<kClassNarrow>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
-  else
-    class_lists_cm<256>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s);
+  switch (cm) {
+    case 4: class_lists_cm<4>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    case 8: class_lists_cm<8>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    case 16: class_lists_cm<16>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    case 32: class_lists_cm<32>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    case 64: class_lists_cm<64>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    case 128: class_lists_cm<128>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+    default: class_lists_cm<256>(A, n, rw, ctr, out, tab, tabscan, partial, nb, seq, s); break;
+  }
 }
 
 // Small lists: one block runs the whole colouring (JP iterations separated
@@ -481,7 +507,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mo
                                                                int mark, int* __restrict__ out, int* ctr) {
   __shared__ int cnt;
   int nt = ctr[C_TOUCH];
-  if (nt > cap) {
+  if (nt > cap || room_failed(ctr)) {
     if (threadIdx.x == 0) ctr[C_LIST_B] = -1;
     return;
   }
@@ -649,6 +675,7 @@ __device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs
 }
 
 __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  if (room_failed(ctr)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
   int status = -1;
@@ -658,12 +685,12 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
 template <int G>
 __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr);
-void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int variant,
+void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int lanes,
                     hipStream_t s) {
   if (n <= 0) return;
-  if (variant == 1)
+  if (lanes == 16)
     k_collapse_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
-  else if (variant == 2)
+  else if (lanes == 8)
     k_collapse_g<8><<<(int)(((int64_t)n * 8 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
   else
     k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
@@ -735,6 +762,7 @@ __device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a,
 }
 
 __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  if (room_failed(ctr)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
   int status = -1;
@@ -912,15 +940,16 @@ __device__ void sort_unique(int* a, int& n) {
 __device__ __forceinline__ int grown_cap(int n) { return max(8, (2 * n + 3) & ~3); }
 
 // write a sorted row, in place when it fits, else in fresh pool space; on
-// pool exhaustion the row keeps its slot and is cut to its capacity (the
-// error bit fails the phase), so no later read leaves the pool
+// pool exhaustion the row keeps its slot and is cut to its capacity, so no
+// later read leaves the pool, and the error bit has the host rebuild every
+// row before the round goes on
 __device__ int put_row(int* pool, int64_t pool_cap, int* top, int& off, int& cap, const int* src, int n, int err,
-                       int* ctr) {
+                       int epoch, int* ctr) {
   if (n > cap) {
     int nc = grown_cap(n);
     int o = atomicAdd(top, nc);
     if ((int64_t)o + nc > pool_cap) {
-      atomicOr(&ctr[C_ERR], err);
+      room_fail(ctr, err, epoch);
       n = cap;
     } else {
       off = o;
@@ -941,7 +970,7 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
   int64_t need = 4 * (int64_t)tot + 4;
   int base = atomicAdd(&ctr[C_STAGE], (int)need);
   if ((int64_t)base + need > cm.stage_cap) {
-    atomicOr(&ctr[C_ERR], E_STAGE);
+    room_fail(ctr, E_STAGE, cm.epoch);
     return;
   }
   int* s = cm.stage + base;
@@ -958,8 +987,8 @@ __device__ __forceinline__ void rebuild_staged(const Store& st, const Commit& cm
   }
   sort_unique(q, nq);
   int ne_off = h.z, ne_cap = cp.y, nn_off = h.x, nn_cap = cp.x;
-  m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, ctr);
-  nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, ctr);
+  m = put_row(st.ne, st.ne_pool, &ctr[C_NE_TOP], ne_off, ne_cap, s, m, E_NE_POOL, cm.epoch, ctr);
+  nq = put_row(st.nn, st.nn_pool, &ctr[C_NN_TOP], nn_off, nn_cap, q, nq, E_NN_POOL, cm.epoch, ctr);
   st.hdr[x] = make_int4(nn_off, nq, ne_off, m);
   st.cap[x] = make_int2(nn_cap, ne_cap);
 }
@@ -1078,7 +1107,7 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   int lim_ne = m, lim_nn = nq;
   if (ne_need) {
     if ((int64_t)at2.x + ne_need > st.ne_pool) {
-      atomicOr(&ctr[C_ERR], E_NE_POOL);
+      room_fail(ctr, E_NE_POOL, cm.epoch);
       lim_ne = min(m, ne_cap);
     } else {
       ne_off = at2.x;
@@ -1087,7 +1116,7 @@ __device__ __forceinline__ bool rebuild_reg(const Store& st, const Commit& cm, i
   }
   if (nn_need) {
     if ((int64_t)at2.y + nn_need > st.nn_pool) {
-      atomicOr(&ctr[C_ERR], E_NN_POOL);
+      room_fail(ctr, E_NN_POOL, cm.epoch);
       lim_nn = min(nq, nn_cap);
     } else {
       nn_off = at2.y;
@@ -1292,13 +1321,14 @@ template <bool F>
 __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
                                                 int* ctr) {
   __shared__ CommitLds L;
+  if (room_failed_block(ctr)) return;  // other blocks may set it meanwhile: one answer per block
   int base = xcd_block() * mpb;
   commit_chunk<F>(st, list, base, min(mpb, n - base), cm, ctr, L);
 }
 
-void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int* ctr, hipStream_t s) {
+void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int chunk, int* ctr, hipStream_t s) {
   if (n <= 0) return;
-  int mpb = n >= 256 * 1024 ? 128 : (n >= 64 * 1024 ? 64 : 16);
+  int mpb = chunk > 0 ? chunk : (n >= 256 * 1024 ? 128 : (n >= 64 * 1024 ? 64 : 16));
   int nb = (n + mpb - 1) / mpb;
   if (flips)
     k_commit<true><<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, ctr);
@@ -1530,12 +1560,12 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
 }
 template <int K>
 __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int* ctr);
-void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int variant, hipStream_t s) {
+void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int lanes, hipStream_t s) {
   if (n <= 0) return;
   int nb = (int)(((int64_t)n * kG + kBlock - 1) / kBlock);
-  if (variant == 1 && kind == 0)
+  if (lanes == kG && kind == 0)
     k_smooth_g<0><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
-  else if (variant == 1)
+  else if (lanes == kG)
     k_smooth_g<1><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else
     k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
@@ -1901,6 +1931,7 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
 template <int G>
 __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
+  if (room_failed(ctr)) return;
   Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G);
@@ -2048,6 +2079,7 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
 template <int G>
 __global__ void __launch_bounds__(256) k_flip_g(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm,
                                                 int* ctr) {
+  if (room_failed(ctr)) return;
   Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / G);
@@ -2101,6 +2133,7 @@ template <bool F>
 __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                      Commit cm, int* ctr) {
   __shared__ CommitLds L;
+  if (room_failed_block(ctr)) return;
   class_body<F>(st, list, n, a, cm, ctr, L);
 }
 void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
@@ -2121,6 +2154,9 @@ __global__ void __launch_bounds__(256) k_round_small(Store st, const int* __rest
   __shared__ CommitLds L;
   int epoch0 = cm.epoch;
   for (int c = 0; c < ncol; ++c) {
+    // a commit of this block may have run out of room: stop, the host
+    // rebuilds the rows and runs the remaining classes
+    if (room_failed_block(ctr)) return;
     int n = ctr[C_HIST + c], off = ctr[C_OFF + c];
     if (n == 0) continue;
     Commit cc = cm;

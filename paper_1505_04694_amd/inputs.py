@@ -141,7 +141,57 @@ def make_mesh(n: int, *, layers: int = 1, jitter_seed: int | None = None,
                                amp=amp, width=width, ht=ht))
 
 
+def fan(k: int = 48, radius: float = 0.25, n_outer: int = 17, layers: int = 2, scale: float = 1.0,
+        hubs: int = 1) -> MeshInput:
+    """A high-degree start: one hub at (0.5, 0.5), or two at (0.45, 0.5) and
+    (0.55, 0.5), joined to a ring of k vertices at the given radius around
+    the centre, the rest of the unit square triangulated from an
+    n_outer x n_outer grid (Delaunay of the point set, every triangle turned
+    counter-clockwise). Each hub's adjacency rows hold about k / hubs entries.
+    Metric: the layer field (layers 1 or 2) times scale; layers 0: scale times
+    the identity; layers -1: a graded isotropic field c(r) I, r the distance
+    to the centre, c = scale * min(4 + 4000 (r / radius)^4, 4004): coarse at
+    the hubs (their joining edge is the only short one), fine at the ring."""
+    from scipy.spatial import Delaunay
+    g, _ = grid(n_outer)
+    far = np.hypot(g[:, 0] - 0.5, g[:, 1] - 0.5) > radius * 1.3
+    ang = 2 * math.pi * (np.arange(k) + 0.5) / k
+    ring = np.stack([0.5 + radius * np.cos(ang), 0.5 + radius * np.sin(ang)], 1)
+    centre = [[0.5, 0.5]] if hubs == 1 else [[0.45, 0.5], [0.55, 0.5]]
+    xy = np.vstack([centre, ring, g[far]])
+    tri = Delaunay(xy).simplices.astype(np.int32)
+    p0, p1, p2 = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    D = (p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p2[:, 0] - p0[:, 0]) * (p1[:, 1] - p0[:, 1])
+    tri = tri[D > 1e-14]
+    D = D[D > 1e-14]
+    tri[D < 0] = tri[D < 0][:, [0, 2, 1]]
+    tags = unit_square_tags(xy)
+    if layers == 0:
+        met = np.tile([1.0, 0.0, 1.0], (xy.shape[0], 1))
+    elif layers == -1:
+        r = np.hypot(xy[:, 0] - 0.5, xy[:, 1] - 0.5)
+        c = np.minimum(4.0 + 4000.0 * (r / radius) ** 4, 4004.0)
+        met = np.stack([c, np.zeros_like(c), c], 1)
+    else:
+        met = layer_y(xy)
+        if layers == 2:
+            met = met + layer_x(xy)
+    return MeshInput(xy=xy, tri=np.ascontiguousarray(tri, np.int32), metric=np.ascontiguousarray(met * scale),
+                     tags=tags, n=n_outer,
+                     info=dict(k=k, radius=radius, n_outer=n_outer, layers=layers, scale=scale, hubs=hubs))
+
+
 # ---- named workloads -------------------------------------------------------
+
+def refine_start(n: int = 17, scale: float = 200.0, jitter_seed: int = 7) -> MeshInput:
+    """A coarse jittered grid under the two-layer field times scale: almost
+    every edge is long, and refinement grows 512 triangles (n = 17) to about
+    1.1e5 over seven passes."""
+    mi = make_mesh(n, layers=2, jitter_seed=jitter_seed)
+    mi.metric = np.ascontiguousarray(mi.metric * scale)
+    mi.info["scale"] = scale
+    return mi
+
 
 def config0() -> MeshInput:
     """33 x 33 grid, one-layer field; priority seed 0."""

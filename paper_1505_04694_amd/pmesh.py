@@ -16,15 +16,18 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmesh.so")
 
-PM_OK, PM_E_ARG, PM_E_MESH, PM_E_NOMEM, PM_E_DEVICE, PM_W_NOT_CONVERGED = range(6)
+PM_OK, PM_E_ARG, PM_E_MESH, PM_E_NOMEM, PM_E_DEVICE, PM_W_NOT_CONVERGED, PM_W_PAUSED = range(7)
 PM_MEM_HOST, PM_MEM_DEVICE = 0, 1
 PM_SMOOTH_LAPLACE, PM_SMOOTH_GRADIENT = 0, 1
-STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_DEVICE", 5: "PM_W_NOT_CONVERGED"}
+PM_PHASE_COARSEN, PM_PHASE_SWAP, PM_PHASE_REFINE, PM_PHASE_SMOOTH, PM_PHASE_DONE = 1, 2, 3, 4, 5
+STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_DEVICE", 5: "PM_W_NOT_CONVERGED",
+          6: "PM_W_PAUSED"}
 STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colours", "edges", "converged",
-              "new_vertices", "new_elements", "records", "relocated", "jp_iterations"]
+              "new_vertices", "new_elements", "records", "relocated", "jp_iterations", "room_rebuilds"]
 
 EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_memory", "pm_mesh_export",
            "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
+           "pm_adapt", "pm_get_context", "pm_set_context", "pm_mesh_update",
            "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read",
            "pm_batch_create", "pm_batch_count", "pm_batch_sizes", "pm_batch_export", "pm_batch_quality"]
 KERNELS = ["jp", "collapse", "flip", "smooth", "commit", "adjoint", "quality", "select"]
@@ -36,11 +39,37 @@ class PMError(RuntimeError):
         self.status = status
 
 
+class Tuning(C.Structure):
+    _fields_ = [("op_lanes", C.c_int32), ("smooth_lanes", C.c_int32), ("commit_chunk", C.c_int32),
+                ("small_work", C.c_int32), ("class_colours", C.c_int32), ("reserved", C.c_int32)]
+    KEYS = ["op_lanes", "smooth_lanes", "commit_chunk", "small_work", "class_colours"]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k in self.KEYS}
+
+    @classmethod
+    def of(cls, d=None):
+        t = cls()
+        for k, v in (d or {}).items():
+            setattr(t, k, v)
+        return t
+
+
 class Options(C.Structure):
     _fields_ = [("L_low2", C.c_double), ("L_up2", C.c_double), ("q_min", C.c_double), ("seed", C.c_uint64),
                 ("sweep", C.c_int32), ("coarsen_rounds", C.c_int32), ("swap_rounds", C.c_int32),
                 ("refine_passes", C.c_int32), ("smooth_kind", C.c_int32), ("smooth_sweeps", C.c_int32),
-                ("slack", C.c_double), ("wg_size", C.c_int32), ("variant", C.c_int32)]
+                ("slack", C.c_double), ("pool_headroom", C.c_double), ("max_iterations", C.c_int32),
+                ("max_phases", C.c_int32), ("tune", Tuning)]
+
+
+class Context(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("iteration", C.c_int32), ("phase", C.c_int32), ("changed", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return dict(seed=int(self.seed), iteration=int(self.iteration), phase=int(self.phase),
+                    changed=int(self.changed))
 
 
 class Stats(C.Structure):
@@ -85,11 +114,17 @@ def lib():
         L.pm_mesh_rows.argtypes = [P, P, P, P, P, P, P]
         L.pm_colour.restype = S
         L.pm_colour.argtypes = [P, P, C.c_uint32, P, P, C.c_int32]
-        for f in ("pm_coarsen", "pm_refine", "pm_swap", "pm_smooth"):
+        for f in ("pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_adapt"):
             getattr(L, f).restype = S
             getattr(L, f).argtypes = [P, C.POINTER(Options), C.POINTER(Stats)]
         L.pm_quality.restype = S
         L.pm_quality.argtypes = [P, P, P, P, P]
+        L.pm_get_context.restype = S
+        L.pm_get_context.argtypes = [P, C.POINTER(Context)]
+        L.pm_set_context.restype = S
+        L.pm_set_context.argtypes = [P, C.POINTER(Context)]
+        L.pm_mesh_update.restype = S
+        L.pm_mesh_update.argtypes = [P, P, P, C.c_int32]
         L.pm_last_error.restype = C.c_char_p
         L.pm_last_error.argtypes = [P]
         L.pm_version.restype = C.c_char_p
@@ -123,7 +158,7 @@ def _p(a):
 
 
 def _check(h, status, allow_warn=True):
-    if status == PM_OK or (allow_warn and status == PM_W_NOT_CONVERGED):
+    if status == PM_OK or (allow_warn and status in (PM_W_NOT_CONVERGED, PM_W_PAUSED)):
         return status
     msg = lib().pm_last_error(h).decode() if h else ""
     raise PMError(status, msg)
@@ -135,9 +170,12 @@ def _stream():
 
 
 def pm_default_options(**kw) -> Options:
+    """Defaults, with any field set by keyword; tune takes a dict of Tuning fields."""
     o = Options()
     _check(None, lib().pm_default_options(C.byref(o)))
     for k, v in kw.items():
+        if k == "tune":
+            v = Tuning.of(v) if not isinstance(v, Tuning) else v
         setattr(o, k, v)
     return o
 
@@ -263,6 +301,37 @@ def pm_smooth(h, options: Options | None = None):
     return _phase("pm_smooth", h, options)
 
 
+def pm_adapt(h, options: Options | None = None):
+    return _phase("pm_adapt", h, options)
+
+
+def pm_get_context(h) -> dict:
+    c = Context()
+    _check(h, lib().pm_get_context(h, C.byref(c)))
+    return c.as_dict()
+
+
+def pm_set_context(h, ctx: dict):
+    c = Context()
+    c.seed, c.iteration, c.phase, c.changed = ctx["seed"], ctx["iteration"], ctx["phase"], ctx["changed"]
+    _check(h, lib().pm_set_context(h, C.byref(c)))
+
+
+def pm_mesh_update(h, xy=None, metric=None):
+    """New coordinates and/or metric: host numpy arrays or device torch tensors (float64)."""
+    on_dev = any(a is not None and hasattr(a, "is_cuda") and a.is_cuda for a in (xy, metric))
+    conv = []
+    for a, w in ((xy, 2), (metric, 3)):
+        if a is None:
+            conv.append(None)
+        elif on_dev:
+            import torch
+            conv.append(a.detach().to(torch.float64).contiguous())
+        else:
+            conv.append(np.ascontiguousarray(a, dtype=np.float64))
+    _check(h, lib().pm_mesh_update(h, _p(conv[0]), _p(conv[1]), PM_MEM_DEVICE if on_dev else PM_MEM_HOST))
+
+
 def pm_quality(h, grad: bool = False):
     """Q and qmin; with grad, also dQ/dx (V x 2) and dQ/dM (V x 3) as torch tensors on the GPU."""
     Q, qmin = C.c_double(), C.c_double()
@@ -331,9 +400,11 @@ def pm_batch_quality(h):
 class Mesh:
     """Owning wrapper around a pm_mesh handle."""
 
-    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None, variant: int = 0):
-        self.variant = variant
-        self.h = pm_mesh_create(xy, tri, metric, tags, pm_default_options(seed=seed, slack=slack), stream)
+    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
+                 pool_headroom: float = 3.0):
+        self.tune = dict(tune or {})
+        self.h = pm_mesh_create(xy, tri, metric, tags,
+                                pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom), stream)
 
     @classmethod
     def from_input(cls, mi, seed: int = 0, **kw):
@@ -363,17 +434,33 @@ class Mesh:
 
     def coarsen(self, sweep=0, L_low2=0.5, q_min=0.1, max_rounds=200):
         return pm_coarsen(self.h, pm_default_options(sweep=sweep, L_low2=L_low2, q_min=q_min,
-                                                     coarsen_rounds=max_rounds, variant=self.variant))
+                                                     coarsen_rounds=max_rounds, tune=self.tune))
 
     def refine(self, L_up2=2.0, max_passes=32):
-        return pm_refine(self.h, pm_default_options(L_up2=L_up2, refine_passes=max_passes))
+        return pm_refine(self.h, pm_default_options(L_up2=L_up2, refine_passes=max_passes, tune=self.tune))
 
     def swap(self, sweep=0, max_rounds=100):
-        return pm_swap(self.h, pm_default_options(sweep=sweep, swap_rounds=max_rounds, variant=self.variant))
+        return pm_swap(self.h, pm_default_options(sweep=sweep, swap_rounds=max_rounds, tune=self.tune))
 
     def smooth(self, sweep=0, kind=0, sweeps=1):
         return pm_smooth(self.h, pm_default_options(sweep=sweep, smooth_kind=kind, smooth_sweeps=sweeps,
-                                                    variant=self.variant))
+                                                    tune=self.tune))
+
+    def adapt(self, max_iterations=8, max_phases=0, smooth_kind=0, smooth_sweeps=1):
+        """Algorithm 1 from the handle's loop state; returns (stats, finished)."""
+        st = pm_adapt(self.h, pm_default_options(max_iterations=max_iterations, max_phases=max_phases,
+                                                 smooth_kind=smooth_kind, smooth_sweeps=smooth_sweeps,
+                                                 tune=self.tune))
+        return st, st["status"] == "PM_OK"
+
+    def get_context(self):
+        return pm_get_context(self.h)
+
+    def set_context(self, ctx):
+        pm_set_context(self.h, ctx)
+
+    def update(self, xy=None, metric=None):
+        pm_mesh_update(self.h, xy, metric)
 
     def quality(self, grad: bool = False):
         return pm_quality(self.h, grad)
@@ -394,9 +481,11 @@ class Mesh:
 class Batch(Mesh):
     """A batch of independent meshes adapted by the same kernel launches."""
 
-    def __init__(self, meshes, seed: int = 0, slack: float = 2.0, stream=None, variant: int = 0):
-        self.variant = variant
-        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack), stream)
+    def __init__(self, meshes, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
+                 pool_headroom: float = 3.0):
+        self.tune = dict(tune or {})
+        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom),
+                                 stream)
 
     @classmethod
     def from_inputs(cls, mis, seed: int = 0, **kw):
@@ -410,3 +499,38 @@ class Batch(Mesh):
 
     def quality_per_mesh(self):
         return pm_batch_quality(self.h)
+
+
+def _autograd_function():
+    import torch
+
+    class QualityFn(torch.autograd.Function):
+        """Q(xy, metric) = the sum of the mean-ratio qualities of a mesh's
+        elements (Sec. 2.2), as a differentiable function of its vertex
+        coordinates (V x 2) and metric (V x 3 stored entries m00, m01, m11).
+        forward writes xy and metric into the handle (pm_mesh_update) and runs
+        pm_quality with the adjoint; backward scales the library's dQ/dx and
+        dQ/dM by the incoming gradient. Usage: Q = QualityFn.apply(xy, metric, mesh)."""
+
+        @staticmethod
+        def forward(ctx, xy, metric, mesh):
+            pm_mesh_update(mesh.h, xy, metric)
+            Q, _, gx, gm = pm_quality(mesh.h, grad=True)
+            ctx.save_for_backward(gx, gm)
+            return torch.tensor(Q, dtype=torch.float64, device=xy.device)
+
+        @staticmethod
+        def backward(ctx, gQ):
+            gx, gm = ctx.saved_tensors
+            return gQ * gx, gQ * gm, None
+
+    return QualityFn
+
+
+def __getattr__(name):
+    # QualityFn needs torch; built on first use so that the module imports without it
+    if name == "QualityFn":
+        fn = _autograd_function()
+        globals()["QualityFn"] = fn
+        return fn
+    raise AttributeError(name)

@@ -76,26 +76,35 @@ def test_full_sweeps(name, make, seed):
     compare_quality(om, gm, "end")
 
 
-@pytest.mark.parametrize("variant", [4, 8])
+# kernel shapes: every choice must give the oracle's result
+TUNINGS = [
+    # one thread per member, grid-wide kernels throughout, class lists first
+    # cut from a 4-colour table (so every round with more colours takes the
+    # full-table recount)
+    dict(op_lanes=1, smooth_lanes=1, small_work=1, class_colours=4),
+    dict(op_lanes=8),
+    dict(commit_chunk=16, class_colours=256),
+    dict(commit_chunk=32, small_work=1),
+    dict(commit_chunk=128, class_colours=64),
+]
+
+
+@pytest.mark.parametrize("tune", TUNINGS, ids=lambda t: "-".join(f"{k}{v}" for k, v in t.items()))
 @pytest.mark.parametrize("name,make,seed", SMALL[2:4])
-def test_kernel_shapes_match(name, make, seed, variant):
-    # one thread per vertex and multi-block kernels throughout (4), or collapse
-    # on groups of 8 lanes (8), give the same results as the oracle; variant 4
-    # also cuts the class lists from a 4-colour table first, so every round
-    # with more colours than that takes the full-table recount
+def test_kernel_shapes_match(name, make, seed, tune):
     mi = make()
     om, gm = both(mi, seed)
-    gm.variant = variant
+    gm.tune = tune
     run_sweeps(om, gm, 2, smooth_kinds=(0, 1))
     compare_quality(om, gm, "end")
 
 
 @pytest.mark.parametrize("kind", [0, 1])
-@pytest.mark.parametrize("variant", [0, 4])
-def test_smoothing_sweeps_on_jittered_mesh(kind, variant):
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_smoothing_sweeps_on_jittered_mesh(kind, lanes):
     mi = inputs.config2(129)
     om, gm = both(mi, 1)
-    gm.variant = variant
+    gm.tune = dict(smooth_lanes=lanes)
     compare_stats(om.smooth(0, kind, 3), gm.smooth(0, kind, 3), "smooth")
     compare_mesh(om, gm, "smooth", rows=False)
     compare_quality(om, gm, "after smoothing")

@@ -230,3 +230,78 @@ def test_adjoint_euler_identities():
     assert abs((xy * gx).sum()) <= 1e-10 * np.abs(xy * gx).sum()
     hom = met * gm
     assert abs(hom.sum()) <= 1e-10 * np.abs(hom).sum()
+
+
+def test_fan_start_reaches_rows_past_the_register_paths():
+    """The high-degree start used by the GPU parity tests: a member with more
+    than 16 neighbours (past the lane groups) and a commit row with more than
+    32 candidate elements (past the register paths: the target's old row plus
+    the rows of the members collapsed onto it) both occur in its first
+    coarsening."""
+    mi = inputs.fan(48, hubs=2, layers=-1)
+    om = OracleMesh.from_input(mi, seed=1)
+    seen = dict(deg=0, cand=0)
+    snap = {}
+
+    def hook(phase, rnd, cls, stage):
+        if phase != PH_COARSEN:
+            return
+        d = om.export()
+        if stage == 0:
+            nn_off, _, ne_off, ne = om.rows()
+            snap["d"], snap["ne_off"], snap["ne"] = d, ne_off, ne
+            for v in om.class_members():
+                seen["deg"] = max(seen["deg"], int(nn_off[v + 1] - nn_off[v]))
+            return
+        b, ne_off, ne = snap["d"], snap["ne_off"], snap["ne"]
+        cand = {}
+        for w in np.nonzero(b["valive"] & ~d["valive"])[0]:
+            rows = ne[ne_off[w]:ne_off[w + 1]]
+            for t in rows:
+                if d["talive"][t]:
+                    u = int((set(d["tri"][t].tolist()) - set(b["tri"][t].tolist())).pop())
+                    cand[u] = cand.get(u, int(ne_off[u + 1] - ne_off[u])) + len(rows)
+                    break
+        if cand:
+            seen["cand"] = max(seen["cand"], max(cand.values()))
+
+    om.set_hook(hook)
+    om.coarsen()
+    assert seen["deg"] > 16 and seen["cand"] > 32, seen
+
+
+@pytest.mark.parametrize("pause", [1, 3, 5])
+def test_oracle_algorithm1_resume_from_an_export(pause):
+    """Algorithm 1 stopped at a resume point, exported, and continued on a new
+    mesh built from the export with the saved loop state gives the same mesh
+    as an uninterrupted run (the export is the whole state besides the loop
+    state: slots are live and in id order at every resume point)."""
+    mi = inputs.config2(33)
+    whole = OracleMesh.from_input(mi, seed=1)
+    st_whole, done = whole.adapt(max_iterations=3)
+    assert done
+    first = OracleMesh.from_input(mi, seed=1)
+    _, done = first.adapt(max_iterations=3, max_phases=pause)
+    assert not done
+    ctx = first.get_context()
+    e = first.export()
+    assert e["valive"].all() and e["talive"].all()
+    resumed = OracleMesh(e["xy"], e["tri"], e["metric"], e["tags"], seed=1)
+    resumed.set_context(**ctx)
+    _, done = resumed.adapt(max_iterations=3)
+    assert done
+    a, b = whole.export(), resumed.export()
+    for k in ("xy", "tri", "metric", "tags"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_oracle_algorithm1_runs_coarsen_swap_refine_then_smooths_once():
+    mi = inputs.config0()
+    om = OracleMesh.from_input(mi, seed=0)
+    phases = []
+    om.set_hook(lambda ph, r, c, stage: phases.append(ph) if stage == 0 and (not phases or phases[-1] != ph) else None)
+    st, done = om.adapt(max_iterations=2)
+    assert done and st["rounds"] == 2
+    # two iterations of coarsen, swap (refinement has no classes), then one smoothing
+    assert phases == [PH_COARSEN, PH_SWAP, PH_COARSEN, PH_SWAP, PH_SMOOTH]
+    checker.check_mesh(om.export(), exact=False, rows=om.rows())
