@@ -244,6 +244,20 @@ pm_status pm_mesh_update(pm_mesh* m, const double* xy, const double* metric, int
  * device pointers or NULL; when given, the adjoint is written there. */
 pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM);
 
+/* pm_quality for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same results as pm_quality (the same reduction, bit for bit), with no
+ * allocation of any kind during the call. The reduction's partial sums go to a
+ * fixed array of 2 x 2048 + 2 doubles (32 KB) inside the library, one copy
+ * per device, held until the process ends; a reduction of more than 2048
+ * partial sums is rejected with PM_E_ARG (pm_quality never takes more, so
+ * no handle this library creates reaches it). Call it with the handle's
+ * device current (else PM_E_ARG). Calls that overlap on one device, from any
+ * handles or streams, race on that array; serialise them. Outputs as
+ * pm_quality: Q and qmin host pointers, dQdx and dQdM device pointers, any
+ * may be NULL. */
+pm_status pm_quality_noalloc(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM);
+
 /* Diagnostic: computes quot[i] = a[i] / b[i] and root[i] = sqrt(a[i]) in FP64
  * on the current device (host arrays of n doubles), so a caller can check
  * that the device rounds division and square root exactly as IEEE-754 binary64

@@ -45,6 +45,8 @@ struct Prof {
 
 struct pm_mesh {
   hipStream_t s = nullptr;
+  int dev = 0;                // device current at creation
+  double* scratch = nullptr;  // that device's copy of the no-allocation scratch array
   Prof prof;
   Store st;
   uint64_t seed = 0;
@@ -957,6 +959,43 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
   return PM_OK;
 }
 
+// partial sums of the quality reduction: one per 256 element slots, at most
+// kQualityParts (the same shape for pm_quality and pm_quality_noalloc)
+constexpr int kQualityParts = 2048;
+int quality_parts(const pm_mesh* m) { return std::min(std::max((m->st.T + 255) / 256, 1), kQualityParts); }
+
+// Device memory that pm_quality_noalloc works in instead of allocating: the
+// quality reduction's partial sums and minima and its two results. Each
+// device that runs the library holds its own copy until the process ends.
+// Host code never uses this name as an address: the device address of each
+// device's copy comes from hipGetSymbolAddress, taken once per device with
+// that device current (at the first handle created on it).
+constexpr int kScratchDoubles = 2 * kQualityParts + 2;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_at[kMaxDevices] = {};
+
+// the current device's copy of the scratch array, for handle m
+pm_status scratch_setup(pm_mesh* m) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(m, PM_E_DEVICE, "device index past the scratch table");
+  m->dev = dev;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(m, PM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch_at[dev] = (double*)p;
+  }
+  m->scratch = g_scratch_at[dev];
+  return PM_OK;
+}
+
 void fill_defaults(pm_options* o) {
   o->L_low2 = 0.5;
   o->L_up2 = 2.0;
@@ -1060,6 +1099,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
     return st;
   };
   if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
+  if (scratch_setup(m) != PM_OK) return bail(PM_E_DEVICE);
   zero_ints(m->ctr, C_COUNT, m->s);
   set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
   int V = (int)d->V, T = (int)d->T;
@@ -1383,7 +1423,7 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st) {
 
 pm_status pm_quality(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM) {
   if (!m) return PM_E_ARG;
-  int nparts = std::min(std::max((m->st.T + 255) / 256, 1), 2048);
+  int nparts = quality_parts(m);
   TRY(ensure(m, m->qpart, 2 * (size_t)nparts + 2));
   if (Q || qmin) {
     timed(m, PM_K_QUALITY, m->st.T,
@@ -1493,6 +1533,27 @@ pm_status pm_mesh_update(pm_mesh* m, const double* xy, const double* metric, int
   return PM_OK;
 }
 
+pm_status pm_quality_noalloc(pm_mesh* m, double* Q, double* qmin, double* dQdx, double* dQdM) {
+  if (!m) return PM_E_ARG;
+  int nparts = quality_parts(m);
+  if (nparts > kQualityParts)  // cannot happen for a handle this library made (T < 2^30)
+    return fail(m, PM_E_ARG, "pm_quality_noalloc: more than " + std::to_string(kQualityParts) + " partial sums");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (!m->scratch || dev != m->dev)
+    return fail(m, PM_E_ARG, "pm_quality_noalloc: call it with the handle's device current");
+  double* ps = m->scratch;
+  if (Q || qmin) {
+    quality_sum(m->st, ps, ps + nparts, nparts, ps + 2 * nparts, m->s);
+    HIPCHK(hipMemcpyAsync(m->hq, ps + 2 * nparts, 2 * sizeof(double), hipMemcpyDeviceToHost, m->s));
+  }
+  if (dQdx || dQdM) quality_adjoint(m->st, dQdx, dQdM, m->s);
+  HIPCHK(hipStreamSynchronize(m->s));
+  if (Q) *Q = m->hq[0];
+  if (qmin) *qmin = m->hq[1];
+  return PM_OK;
+}
+
 pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_options* o, void* stream,
                           pm_mesh** out) {
   if (!out) return PM_E_ARG;
@@ -1575,6 +1636,7 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
     return st;
   };
   if (dalloc(m, &m->ctr, C_COUNT) != PM_OK || !pinned_get(m)) return bail(PM_E_NOMEM);
+  if (scratch_setup(m) != PM_OK) return bail(PM_E_DEVICE);
   zero_ints(m->ctr, C_COUNT, m->s);
   set_int(m->ctr + C_FAILEP, INT_MAX, m->s);
   Store& st = m->st;

@@ -27,7 +27,7 @@ STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colou
 
 EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_sizes", "pm_mesh_memory", "pm_mesh_export",
            "pm_mesh_rows", "pm_colour", "pm_coarsen", "pm_refine", "pm_swap", "pm_smooth", "pm_quality",
-           "pm_adapt", "pm_get_context", "pm_set_context", "pm_mesh_update",
+           "pm_adapt", "pm_get_context", "pm_set_context", "pm_mesh_update", "pm_quality_noalloc",
            "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read",
            "pm_batch_create", "pm_batch_count", "pm_batch_sizes", "pm_batch_export", "pm_batch_quality"]
 KERNELS = ["jp", "collapse", "flip", "smooth", "commit", "adjoint", "quality", "select"]
@@ -119,6 +119,8 @@ def lib():
             getattr(L, f).argtypes = [P, C.POINTER(Options), C.POINTER(Stats)]
         L.pm_quality.restype = S
         L.pm_quality.argtypes = [P, P, P, P, P]
+        L.pm_quality_noalloc.restype = S
+        L.pm_quality_noalloc.argtypes = [P, P, P, P, P]
         L.pm_get_context.restype = S
         L.pm_get_context.argtypes = [P, C.POINTER(Context)]
         L.pm_set_context.restype = S
@@ -344,6 +346,14 @@ def pm_quality(h, grad: bool = False):
     gm = torch.empty((V, 3), dtype=torch.float64, device="cuda")
     _check(h, lib().pm_quality(h, C.byref(Q), C.byref(qmin), _p(gx), _p(gm)))
     return Q.value, qmin.value, gx, gm
+
+
+def pm_quality_noalloc(h, dQdx=None, dQdM=None):
+    """Q and qmin with no device allocation in the library; gradients are
+    written into caller-provided float64 device tensors (V x 2, V x 3) when given."""
+    Q, qmin = C.c_double(), C.c_double()
+    _check(h, lib().pm_quality_noalloc(h, C.byref(Q), C.byref(qmin), _p(dQdx), _p(dQdM)))
+    return Q.value, qmin.value
 
 
 def pm_batch_create(meshes, options: Options | None = None, stream=None):
