@@ -9,12 +9,22 @@ Metric: adaptation vertex+edge operations per second, where vertex ops are
 vertices coloured plus members evaluated (coarsen, swap, smooth) and edge ops
 are edges tested by refinement (identical counts on the oracle).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--n 2049]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--n 2049]
+       python bench.py --config4                      (the 4097^2 workload, peak device memory)
+       python bench.py --summarise-trace DIR --out PREFIX --command CMD
+       python bench.py --summarise-counters FETCH_DIR WRITE_DIR --out PREFIX --command CMD
+The last two turn rocprofv3 CSV output (--stats / --pmc runs of this script)
+into the summaries kept under profiles/.
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
+import platform
+import re
+import statistics
 import sys
 import time
 
@@ -23,25 +33,39 @@ sys.path.insert(0, ROOT)
 
 PRIO_SEED = 1
 HBM_PEAK_GBS = 8000.0
-# algorithmic (compulsory) HBM bytes per unit of work of each timed kernel;
-# the derivations are listed with the kernels' descriptions in the design notes
+# Algorithmic (compulsory) HBM bytes per unit of work of each timed kernel
+# group, with the unit. The derivations are listed with the kernels'
+# descriptions in the design notes.
 BYTES_PER_UNIT = {
-    "jp": 53,         # per active vertex visited by one Jones-Plassmann iteration
-    "collapse": 436,  # per class member: 1-ring gather, evaluation, element rewrites, queueing
-    "flip": 436,      # per class member
-    "smooth": 148,    # per class member: own xy+metric, rows, elements, write-back, list entry
-    "commit": 212,    # per row rebuilt: headers, caps, old and new NE/NN rows, target record, elements
-    "adjoint": 144,   # per vertex: xy+metric, header, NE row, elements, dQ/dx and dQ/dM writes
-    "quality": 36,    # per element: element ids and a third of its vertices' data
-    "select": 100,    # per vertex scanned
+    "jp": (53, "active vertex visited by one Jones-Plassmann iteration"),
+    "collapse": (436, "class member (1-ring gather, evaluation, element rewrites)"),
+    "flip": (436, "class member"),
+    "smooth": (148, "class member (own xy+metric, rows, elements, write-back, list entry)"),
+    "commit_ops": (1250, "committed collapse or flip (records, touched rows read and written; 0.9-1.6 KB)"),
+    "commit": (212, "row rebuilt (headers, caps, old and new rows, target record, elements)"),
+    "adjoint": (144, "vertex (xy+metric, header, NE row, elements, dQ/dx and dQ/dM writes)"),
+    "quality": (36, "element (ids and a third of its vertices' data)"),
+    "select": (100, "vertex scanned"),
 }
+COMMIT_OPS_RANGE = (900, 1600)
+# rocprofv3 kernel names -> the groups above
+GROUPS = [
+    ("jp", r"k_jp_chunk|k_colour_small|k_jp_init"),
+    ("collapse", r"k_collapse|k_class_small<false>|k_round_small<false>"),
+    ("flip", r"k_flip|k_class_small<true>|k_round_small<true>"),
+    ("smooth", r"k_smooth"),
+    ("commit", r"k_commit"),
+    ("adjoint", r"k_adjoint"),
+    ("quality", r"k_quality"),
+    ("select", r"k_select"),
+]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_step(mesh, counts=None):
+def run_step(mesh):
     """The step's phase sequence; works on pmesh.Mesh and on the oracle's mesh."""
     out = []
     out.append(("quality", mesh.quality(grad=True)[:2]))
@@ -56,50 +80,62 @@ def run_step(mesh, counts=None):
 
 
 def op_count(trace):
-    ops = 0
-    for name, st in trace:
-        if isinstance(st, dict):
-            ops += st["coloured"] + st["evaluated"] + st["edges"]
-    return ops
+    return sum(st["coloured"] + st["evaluated"] + st["edges"] for _, st in trace if isinstance(st, dict))
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1505_04694_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(name):
-    """HBM bytes per launch of kernel `name` from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    import glob
+    """Counter-measured bytes per launch of kernel group `name` from the
+    committed summary, or None when the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", "traffic_2049.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1505_04694_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
-    if h.hexdigest() != d.get("sources_sha256") or name not in d.get("kernels", {}):
+    if d.get("sources_sha256") != sources_sha():
         return None
-    return d["kernels"][name]["traffic_bytes_per_launch"]
+    k = d.get("kernels", {}).get("commit" if name == "commit_ops" else name)
+    return None if k is None else k["traffic_bytes_per_launch"]
 
 
-def roofline(name, dom):
-    """Achieved algorithmic bandwidth of the dominant kernel over the timed steps."""
+def roofline(name, dom, copy_gbs, per_row=None):
+    """Achieved algorithmic bandwidth of the dominant kernel group over the timed steps."""
     launches = max(dom["launches"], 1)
-    bytes_per_launch = BYTES_PER_UNIT[name] * dom["units"] / launches
+    bpu, unit = BYTES_PER_UNIT[name]
+    units = dom["units"] / launches
     avg_s = dom["ms"] * 1e-3 / launches
-    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(name),
-            "bytes_per_unit": BYTES_PER_UNIT[name], "units_per_launch": round(dom["units"] / launches, 1),
-            "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"]}
+    achieved = bpu * units / avg_s / 1e9 if avg_s > 0 else 0.0
+    out = {"kernel": "commit" if name == "commit_ops" else name, "bound": "hbm", "achieved": round(achieved, 2),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+           "traffic": measured_traffic(name), "bytes_per_unit": bpu, "unit_of_work": unit,
+           "units_per_launch": round(units, 1), "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"],
+           "copy_bandwidth_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 5)}
+    if name == "commit_ops":
+        lo, hi = (b * units / avg_s / 1e9 / HBM_PEAK_GBS for b in COMMIT_OPS_RANGE)
+        out["frac_range"] = [round(lo, 5), round(hi, 5)]
+    if per_row is not None:
+        rb, ru = BYTES_PER_UNIT["commit"]
+        rows = per_row["units"] / max(per_row["launches"], 1)
+        a2 = rb * rows / avg_s / 1e9 if avg_s > 0 else 0.0
+        out["per_row_basis"] = {"bytes_per_unit": rb, "unit_of_work": ru, "units_per_launch": round(rows, 1),
+                                "achieved": round(a2, 2), "frac": round(a2 / HBM_PEAK_GBS, 5)}
+    return out
 
 
 def kernel_roofline(prof):
-    """Achieved algorithmic bandwidth of every timed kernel over one profiled step."""
+    """Achieved algorithmic bandwidth of every timed kernel group over one profiled step."""
     out = {}
     for name, p in prof.items():
-        if p["ms"] <= 0 or p["units"] <= 0:
+        if p["ms"] <= 0 or p["units"] <= 0 or name not in BYTES_PER_UNIT:
             continue
-        gbs = BYTES_PER_UNIT[name] * p["units"] / (p["ms"] * 1e-3) / 1e9
+        gbs = BYTES_PER_UNIT[name][0] * p["units"] / (p["ms"] * 1e-3) / 1e9
         out[name] = {"ms": round(p["ms"], 3), "launches": p["launches"], "units": p["units"],
-                     "bytes_per_unit": BYTES_PER_UNIT[name], "achieved": round(gbs, 2),
+                     "bytes_per_unit": BYTES_PER_UNIT[name][0], "achieved": round(gbs, 2),
                      "frac": round(gbs / HBM_PEAK_GBS, 5)}
     return out
 
@@ -109,6 +145,63 @@ def topo_hash(export):
     h.update(export["tri"][export["talive"]].tobytes())
     h.update(export["tags"][export["valive"]].tobytes())
     return h.hexdigest()[:16]
+
+
+def copy_bandwidth(torch, dev, gib=1):
+    """Device-to-device copy of `gib` GiB (read + write counted), best of 5."""
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    best = float("inf")
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2 * (gib << 30) / best / 1e9
+
+
+def host_cpu():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(mi, runs=3):
+    """The oracle on one host core over a bounded sample of the step: mesh
+    creation and the coarsening phase (the graph-mutating rounds, most of the
+    GPU step's time) on the same input; median of `runs` runs pinned to one
+    core."""
+    from oracle.orc import OracleMesh
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    times, ops = [], None
+    try:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            om = OracleMesh.from_input(mi, seed=PRIO_SEED)
+            st = om.coarsen(0)
+            times.append(time.perf_counter() - t0)
+            ops = st["coloured"] + st["evaluated"] + st["edges"]
+            del om
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    med = statistics.median(times)
+    model, ncpu, navail = host_cpu()
+    return {"value": ops / med, "unit": "ops/s", "cores": 1, "kind": "oracle",
+            "sample": f"mesh creation + the coarsening phase of the same 2049x2049 input ({ops} ops), "
+                      f"median of {runs} runs pinned to one core",
+            "runs_s": [round(t, 2) for t in times], "host_cpu": model, "host_threads": ncpu,
+            "host_threads_available": navail}, ops
 
 
 def batch_bench(count, torch, inputs, pmesh, sweeps=2, seed=2):
@@ -172,6 +265,7 @@ def config4_run(n=4097, sweeps=2, seed=3):
     met = torch.from_numpy(mi.metric).to(dev)
     tags = torch.from_numpy(mi.tags).to(dev)
     torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     log(f"inputs ready: {mi.V} vertices, {mi.T} triangles")
     t0 = time.perf_counter()
     m = pmesh.Mesh(xy, tri, met, tags, seed=seed)
@@ -186,6 +280,7 @@ def config4_run(n=4097, sweeps=2, seed=3):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     cur, peak = m.memory()
+    free1 = torch.cuda.mem_get_info()[0]
     V, T = m.sizes()
     q = m.quality()
     m.close()
@@ -194,7 +289,108 @@ def config4_run(n=4097, sweeps=2, seed=3):
                       "vertices": mi.V, "triangles": mi.T, "create_ms": (t1 - t0) * 1e3,
                       "sweeps_ms": (t2 - t1) * 1e3, "ops": ops, "ops_per_s": ops / (t2 - t1),
                       "peak_device_bytes": peak, "peak_fraction_of_288GB": peak / 288e9,
+                      "device_free_drop_bytes": free0 - free1,
                       "final": {"vertices": V, "triangles": T, "quality": q}, "phases": phases}), flush=True)
+
+
+# ---- rocprofv3 summaries ---------------------------------------------------------------
+
+def _csvs(d, suffix):
+    return sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+
+
+def group_of(kernel_name):
+    for g, pat in GROUPS:
+        if re.search(pat, kernel_name):
+            return g
+    return None
+
+
+def summarise_trace(d, out, command):
+    """--stats output (kernel_stats.csv) -> a markdown table of every kernel."""
+    f = _csvs(d, "kernel_stats.csv")
+    if not f:
+        raise SystemExit(f"no kernel_stats.csv under {d}")
+    rows = list(csv.DictReader(open(f[0])))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = ["# rocprofv3 kernel-trace summary: 2049x2049 benchmark workload", "",
+             "Command (from /tmp with TMPDIR=/tmp, repository root in $R):", "", "```", command, "```", "",
+             f"Total kernel time: {tot / 1e6:.3f} ms", "",
+             "| kernel | group | calls | total ms | % | avg us | min us | max us |", "|---|---|---:|---:|---:|---:|---:|---:|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        nm = r["Name"]
+        short = re.sub(r"\(.*$", "", nm)
+        lines.append(f"| `{short}` | {group_of(nm) or ''} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    open(out + ".md", "w").write("\n".join(lines) + "\n")
+    print(f"wrote {out}.md")
+
+
+def _counter_rows(d, counter):
+    f = _csvs(d, "counter_collection.csv")
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    per = {}
+    for r in csv.DictReader(open(f[0])):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Kernel_Name"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    return per
+
+
+def summarise_counters(fetch_dir, write_dir, out, command):
+    """FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch) -> bytes per launch
+    per kernel group, scaled by what the counters read for a device copy of
+    known size in the same run (the bandwidth probe: 1 GiB read and 1 GiB
+    written, the largest copy dispatch)."""
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = _counter_rows(d, counter)
+        copies = [v for (_, nm), v in per.items() if re.search(r"copy", nm, re.I)]
+        if not copies:
+            raise SystemExit(f"no copy dispatch in the {counter} run")
+        scale = (1 << 20) / max(copies)
+        groups = {}
+        for (_, nm), v in per.items():
+            g = group_of(nm)
+            if g:
+                s = groups.setdefault(g, [0, 0.0])
+                s[0] += 1
+                s[1] += v
+        res[counter] = dict(scale=scale, read_kib=max(copies), groups=groups)
+    kernels = {}
+    for g in sorted(res["FETCH_SIZE"]["groups"]):
+        nf, fk = res["FETCH_SIZE"]["groups"][g]
+        nw, wk = res["WRITE_SIZE"]["groups"].get(g, (nf, 0.0))
+        f_l, w_l = fk / nf, wk / max(nw, 1)
+        kernels[g] = dict(launches=nf, fetch_kib_per_launch=f_l, write_kib_per_launch=w_l,
+                          traffic_bytes_per_launch=1024 * (f_l * res["FETCH_SIZE"]["scale"] +
+                                                           w_l * res["WRITE_SIZE"]["scale"]))
+    doc = dict(workload="2049x2049 benchmark step", command=command,
+               calibration=dict(copy_bytes=1 << 30, fetch_kib_read=res["FETCH_SIZE"]["read_kib"],
+                                write_kib_read=res["WRITE_SIZE"]["read_kib"],
+                                fetch_scale=res["FETCH_SIZE"]["scale"], write_scale=res["WRITE_SIZE"]["scale"]),
+               sources_sha256=sources_sha(), kernels=kernels)
+    json.dump(doc, open(out + ".json", "w"), indent=1)
+    lines = ["# Memory traffic per launch, 2049x2049 benchmark step", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 --pmc runs, each scaled by what it",
+             "reads for a 1 GiB device copy in the same run. FETCH_SIZE counts L2 fills from the memory fabric,",
+             "which include hits in the Infinity Cache (MALL): an upper bound on HBM reads.", "",
+             f"Copy calibration: FETCH_SIZE read {res['FETCH_SIZE']['read_kib']:.1f} KiB for 1048576 KiB "
+             f"(scale {res['FETCH_SIZE']['scale']:.4f}); WRITE_SIZE read {res['WRITE_SIZE']['read_kib']:.1f} KiB "
+             f"(scale {res['WRITE_SIZE']['scale']:.4f}).", "",
+             "Commands (from /tmp with TMPDIR=/tmp, repository root in $R; the second run swaps FETCH_SIZE for "
+             "WRITE_SIZE):", "", "```", command, "```", "",
+             "| kernel group | launches | fetch KiB/launch | write KiB/launch | traffic MB/launch |",
+             "|---|---:|---:|---:|---:|"]
+    for g, k in kernels.items():
+        lines.append(f"| {g} | {k['launches']} | {k['fetch_kib_per_launch']:.1f} | {k['write_kib_per_launch']:.1f} | "
+                     f"{k['traffic_bytes_per_launch'] / 1e6:.2f} |")
+    lines += ["", f"Kernel sources sha256: `{doc['sources_sha256']}` (bench.py reports traffic only while it matches)."]
+    open(out + ".md", "w").write("\n".join(lines) + "\n")
+    print(f"wrote {out}.json and {out}.md")
 
 
 def main():
@@ -205,20 +401,28 @@ def main():
     ap.add_argument("--n", type=int, default=2049)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a device copy of 1 GiB (a kernel of known traffic for counter scaling)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--config4", action="store_true",
                     help="instead: the 4097x4097 workload, two sweeps with gradient smoothing, peak device memory")
+    ap.add_argument("--summarise-trace", metavar="DIR")
+    ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "summary"))
+    ap.add_argument("--command", default="")
     a = ap.parse_args()
+    if a.summarise_trace:
+        summarise_trace(a.summarise_trace, a.out, a.command)
+        return
+    if a.summarise_counters:
+        summarise_counters(*a.summarise_counters, a.out, a.command)
+        return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the path is single-device", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}): the path is single-device; "
+              "sharding across GPUs is not built", file=sys.stderr)
         sys.exit(2)
     if a.config4:
         config4_run()
         return
 
-    import numpy as np
     import torch
     from paper_1505_04694_amd import inputs, pmesh
 
@@ -239,18 +443,17 @@ def main():
         return m, tr
 
     log(f"inputs ready: {mi.V} vertices, {mi.T} triangles")
-    if a.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    # one profiled step finds the kernel with the most device time
+    # a plain device copy of known size: the measured bandwidth beside the
+    # vendor peak, and the calibration kernel of the counter runs
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
+    # one profiled step finds the kernel group with the most device time
     m, _ = gpu_step(mask=0xFF)
     prof_all = m.profile_read()
     m.close()
-    dominant = max(prof_all, key=lambda k: prof_all[k]["ms"])
+    dominant = max(pmesh.KERNELS, key=lambda k: prof_all[k]["ms"])
     dmask = 1 << pmesh.KERNELS.index(dominant)
+    reads = ["commit", "commit_ops"] if dominant == "commit" else [dominant]
     for _ in range(a.warmup):
         m, tr = gpu_step()
         m.close()
@@ -258,13 +461,14 @@ def main():
     t0 = time.perf_counter()
     traces = []
     last = None
-    dom = dict(ms=0.0, launches=0, units=0)
+    dom = {r: dict(ms=0.0, launches=0, units=0) for r in reads}
     for k in range(a.steps):
         m, tr = gpu_step(mask=dmask)
         traces.append(tr)
-        pr = m.profile_read([dominant])[dominant]
-        for key in dom:
-            dom[key] += pr[key]
+        pr = m.profile_read(reads)
+        for r in reads:
+            for key in dom[r]:
+                dom[r][key] += pr[r][key]
         if k == a.steps - 1:
             last = m
         else:
@@ -277,6 +481,10 @@ def main():
     gpu_final = last.export()
     gpu_hash = topo_hash(gpu_final)
     last.close()
+    if dominant == "commit":
+        rl = roofline("commit_ops", dom["commit_ops"], copy_gbs, per_row=dom["commit"])
+    else:
+        rl = roofline(dominant, dom[dominant], copy_gbs)
 
     result = {
         "metric": "adaptation vertex+edge ops/s",
@@ -295,8 +503,8 @@ def main():
                                "priority seed 1; quality+adjoint, plain+gradient smoothing sweeps, "
                                "coarsen->refine->swap->smooth", "vertices": mi.V, "triangles": mi.T,
                    "ops_per_step": ops},
-        "roofline": roofline(dominant, dom),
-        "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in prof_all.items()},
+        "roofline": rl,
+        "kernels_ms_per_step": {k: round(v["ms"], 3) for k, v in prof_all.items() if k in pmesh.KERNELS},
         "kernel_roofline": kernel_roofline(prof_all),
         "phases": {name: st for name, st in traces[-1] if isinstance(st, dict)},
         "topology_hash": gpu_hash,
@@ -306,19 +514,16 @@ def main():
         result["batch"] = batch_bench(a.batch_count, torch, inputs, pmesh)
 
     log(f"timed steps: {ms:.2f} ms/step")
+    # the oracle's result for this step (tests/golden/make_bench_step.py)
+    gold_path = os.path.join(ROOT, "tests", "golden", f"bench_step_{a.n}.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        result["parity"] = {"topology_equal_oracle": gold["topology_hash"] == gpu_hash,
+                            "ops_equal_oracle": gold["ops"] == ops,
+                            "final_quality": traces[-1][-1][1], "final_quality_oracle": gold["final_quality"]}
     if not a.no_cpu:
-        log("oracle step (CPU baseline)")
-        from oracle.orc import OracleMesh
-        t2 = time.perf_counter()
-        om = OracleMesh.from_input(mi, seed=PRIO_SEED)
-        otr = run_step(om)
-        t3 = time.perf_counter()
-        o_ops = op_count(otr)
-        ohash = topo_hash(om.export())
-        result["cpu_baseline"] = {"value": o_ops / (t3 - t2), "unit": "ops/s", "cores": 1, "kind": "oracle",
-                                  "sample": f"one full step of the same workload ({t3 - t2:.1f} s, serial)"}
-        result["parity"] = {"ops_equal": o_ops == ops, "topology_equal": ohash == gpu_hash,
-                            "final_quality_gpu": traces[-1][-1][1], "final_quality_oracle": otr[-1][1]}
+        log("oracle sample (CPU baseline, 3 runs on one core)")
+        result["cpu_baseline"], _ = cpu_baseline(mi)
     print(json.dumps(result), flush=True)
 
 

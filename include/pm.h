@@ -294,7 +294,10 @@ enum {
   PM_K_ADJOINT = 5,  /* quality adjoint; units: vertices                            */
   PM_K_QUALITY = 6,  /* quality functional; units: elements                         */
   PM_K_SELECT = 7,   /* worklist selection over all vertices; units: vertices       */
-  PM_K_COUNT = 8
+  PM_K_COUNT = 8,
+  /* pm_profile_read only: the commit kernels' time and launches, with units =
+   * the committed operations (collapses, flips) whose rows they rebuilt */
+  PM_K_COMMIT_OPS = 8
 };
 
 /* Enables HIP-event timing (on the handle's stream) around every launch of

@@ -1739,21 +1739,25 @@ pm_status pm_profile(pm_mesh* m, uint32_t mask) {
     m->prof.launches[k] = m->prof.units[k] = 0;
   }
   stripe_zero(m->ctr, S_PJP, 2, m->s);
+  stripe_zero(m->ctr, S_POPS, 1, m->s);
   return sync(m);
 }
 
 pm_status pm_profile_read(pm_mesh* m, int32_t id, double* ms, int64_t* launches, int64_t* units) {
-  if (!m || id < 0 || id >= PM_K_COUNT) return PM_E_ARG;
+  if (!m || id < 0 || id > PM_K_COMMIT_OPS) return PM_E_ARG;
   TRY(sync(m));
   prof_flush(m);
   stripe_sum(m->ctr, S_PJP, 2, C_PROF_JP, m->s);
-  TRY(read_ctr(m, C_PROF_JP, 2));
-  if (ms) *ms = m->prof.ms[id];
-  if (launches) *launches = m->prof.launches[id];
+  stripe_sum(m->ctr, S_POPS, 1, C_PROF_OPS, m->s);
+  TRY(read_ctr(m, C_PROF_JP, 3));
+  int k = id == PM_K_COMMIT_OPS ? PM_K_COMMIT : id;
+  if (ms) *ms = m->prof.ms[k];
+  if (launches) *launches = m->prof.launches[k];
   if (units) {
-    *units = m->prof.units[id];
+    *units = m->prof.units[k];
     if (id == PM_K_JP) *units = m->hctr[C_PROF_JP];
     if (id == PM_K_COMMIT) *units = m->hctr[C_PROF_ROWS];
+    if (id == PM_K_COMMIT_OPS) *units = m->hctr[C_PROF_OPS];
   }
   return PM_OK;
 }

@@ -35,6 +35,7 @@ enum Ctr {
   C_NCOL = 832,     // number of colours
   C_PROF_JP = 833,  // profiling: active vertices visited by JP iterations (summed)
   C_PROF_ROWS = 834,  // profiling: rows rebuilt by the commit (summed)
+  C_PROF_OPS = 835,   // profiling: committed operations whose rows the commit kernels rebuilt (summed)
   C_STRIPE = 1024,  // kStripes stripes of kStripeW ints, one 128-byte line each
   C_COUNT = 1024 + 64 * 32
 };
@@ -45,7 +46,8 @@ constexpr int kStripes = 64, kStripeW = 32;
 enum Slot {
   S_EVAL = 0, S_DEFER = 1, S_COMMIT = 2, S_RELOC = 3, S_ROWS = 4, S_EDGES = 5,  // stats
   S_PJP = 6, S_PROWS = 7,  // profiling units
-  S_JPL = 8                // 8..15: JP vertices left, by iteration modulo 8
+  S_JPL = 8,               // 8..15: JP vertices left, by iteration modulo 8
+  S_POPS = 16              // profiling units: committed operations handled by the commit kernels
 };
 __device__ __forceinline__ int* stripe_ptr(int* ctr, int slot) {
   int w = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kStripes - 1));

@@ -1270,6 +1270,8 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
     }
   }
   uint64_t key = own_key(cm.epoch, v);
+  uint64_t coms = __ballot(com);
+  if (__lane_id() == 0 && coms) atomicAdd(stripe_ptr(ctr, S_POPS), __popcll(coms));
   int* mycol = L.col + tid;
   if (tid == 0) L.bqn = 0;
   bool own_round = F;

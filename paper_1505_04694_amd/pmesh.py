@@ -31,6 +31,8 @@ EXPORTS = ["pm_default_options", "pm_mesh_create", "pm_mesh_destroy", "pm_mesh_s
            "pm_last_error", "pm_version", "pm_fp64_selfcheck", "pm_profile", "pm_profile_read",
            "pm_batch_create", "pm_batch_count", "pm_batch_sizes", "pm_batch_export", "pm_batch_quality"]
 KERNELS = ["jp", "collapse", "flip", "smooth", "commit", "adjoint", "quality", "select"]
+# ids pm_profile_read takes: the kernels, and the commit counted in committed operations
+PROFILE_READS = KERNELS + ["commit_ops"]
 
 
 class PMError(RuntimeError):
@@ -480,8 +482,8 @@ class Mesh:
 
     def profile_read(self, names=None):
         """Timing per kernel group; names: the groups to read (default all)."""
-        names = KERNELS if names is None else names
-        return {k: pm_profile_read(self.h, KERNELS.index(k)) for k in names}
+        names = PROFILE_READS if names is None else names
+        return {k: pm_profile_read(self.h, PROFILE_READS.index(k)) for k in names}
 
     def sweep(self, sweep: int, smooth_kind: int = 0, smooth_sweeps: int = 1):
         return dict(coarsen=self.coarsen(sweep), refine=self.refine(), swap=self.swap(sweep),

@@ -44,3 +44,32 @@ def test_config2_benchmark_step():
         compare_mesh(om, gm, name, rows=name not in ("smooth plain", "smooth gradient"))
     compare_quality(om, gm, "end")
     checker.check_mesh(gm.export(), exact=False, rows=gm.rows())
+
+
+def test_config4_two_sweeps_match_the_oracle_result():
+    """The 4097 x 4097 workload (two sweeps, gradient smoothing) against the
+    oracle's stored result (tests/golden/make_config4.py): every phase's op
+    counts, and the final topology, tags, metric and coordinates."""
+    import json
+    import os
+    import torch
+    from paper_1505_04694_amd import pmesh
+    from tests.golden.make_config4 import N, SEED, SWEEPS, summary
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config4_4097.json")))
+    mi = inputs.config4(N)
+    assert mi.digest() == gold["input"]
+    dev = torch.device("cuda")
+    gm = pmesh.Mesh(*(torch.from_numpy(a).to(dev) for a in (mi.xy, mi.tri, mi.metric, mi.tags)), seed=SEED)
+    for s in range(SWEEPS):
+        g = gold["phases"][s]
+        for name, fg in (("coarsen", lambda: gm.coarsen(s)), ("refine", lambda: gm.refine()),
+                         ("swap", lambda: gm.swap(s)), ("smooth", lambda: gm.smooth(s, 1, 1))):
+            compare_stats(g[name], fg(), f"sweep {s} {name}")
+    got = summary(gm.export())
+    want = gold["final"]
+    for k in ("V", "T", "tri", "tags", "metric"):
+        assert got[k] == want[k], k
+    if got["xy"] != want["xy"]:
+        assert abs(got["xy_sum"] - want["xy_sum"]) <= 1e-12 * abs(want["xy_sum"])
+    Q, qmin = gm.quality()
+    assert abs(Q - gold["quality"][0]) <= 1e-12 * abs(Q) and qmin == gold["quality"][1]
