@@ -76,7 +76,11 @@ typedef struct {
                             colouring into class lists: 0 = 32; 4, 8, 16, 32,
                             64, 128 or 256 (a colouring with more colours is
                             cut again from the full table)                       */
-  int32_t reserved;      /* 0 */
+  int32_t host_rounds;   /* 0: rounds whose list is coloured by one work-group
+                            run device-driven (each kernel takes its sizes from
+                            device counters; two rounds are captured once as a
+                            graph and replayed, the host reads back every four
+                            rounds); 1: the host drives every round             */
 } pm_tuning;
 
 /* Thresholds are squared metric lengths. Defaults (pm_default_options):

@@ -45,6 +45,7 @@ struct Prof {
 
 struct pm_mesh {
   hipStream_t s = nullptr;
+  hipStream_t cap_s = nullptr;  // private stream that graph captures are recorded on
   int dev = 0;                // device current at creation
   double* scratch = nullptr;  // that device's copy of the no-allocation scratch array
   Prof prof;
@@ -75,6 +76,7 @@ struct pm_mesh {
   DBuf<double> qpart;
   DBuf<double> upd;  // pm_mesh_update: the previous coordinates and metric
   DBuf<uint64_t> rw;  // round words (priority, active, colour) per vertex
+  DBuf<uint64_t> seeds;  // device-driven rounds: the stream seed of every round of the phase
   // mesh ranges (host mirror of Store::vbase/vused/tbase/tused)
   std::vector<int> vbase, vused, tbase, tused;
   int* ranges = nullptr;  // device: vbase[B+1], vused[B], tbase[B+1], tused[B]
@@ -336,6 +338,24 @@ pm_status check_err(pm_mesh* m, bool fresh = false) {
   pm_status st = (e & (E_MESH_ID | E_MESH_ORIENT | E_MESH_MANIFOLD | E_MESH_METRIC)) ? PM_E_MESH : PM_E_NOMEM;
   if (e & E_COLOURS) st = PM_E_MESH;
   return fail(m, st, msg);
+}
+
+// Records the launches f(stream) issues into an executable graph: captured on
+// the handle's private stream (a graph cannot be captured from the null
+// stream, which a caller's stream may be) and later launched on the handle's
+// stream, in its order. Only kernel launches are recorded (no memsets).
+template <class F>
+pm_status capture(pm_mesh* m, F&& f, hipGraphExec_t* out) {
+  *out = nullptr;
+  if (!m->cap_s) HIPCHK(hipStreamCreateWithFlags(&m->cap_s, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(m->cap_s, hipStreamCaptureModeThreadLocal));
+  f(m->cap_s);
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamEndCapture(m->cap_s, &g));
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(m, PM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return PM_OK;
 }
 
 // ---- store allocation -----------------------------------------------------------------------
@@ -747,7 +767,7 @@ bool bad_tuning(const pm_tuning& t) {
   };
   return !in(t.op_lanes, {0, 1, 8, 16}) || !in(t.smooth_lanes, {0, 1, 8}) ||
          !in(t.commit_chunk, {0, 16, 32, 64, 128}) || !in(t.small_work, {0, 1}) ||
-         !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || t.reserved != 0;
+         !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || !in(t.host_rounds, {0, 1});
 }
 
 bool bad_opts(const pm_options* o) {
@@ -846,6 +866,73 @@ pm_status recover_round(pm_mesh* m, int kind, const Classes& cl, std::vector<int
   }
 }
 
+// Rounds r, r + 1, ... of a phase whose lists fit one work-group, driven by
+// the device: each kernel takes its sizes from the counters, so the host
+// issues rounds without reading anything back. Two rounds (list A -> B -> A)
+// are captured once as a graph, replayed twice per read-back. Round r's
+// classes must be coloured (counters and class lists set). Returns with the
+// round counter, list and length of where the chain stopped: the list empty,
+// the round cap, a list too long for one work-group (r_out's list, not
+// coloured), or a selection that declined (declined: round r_out ran, its
+// next list is not selected; the host selects over every slot, after
+// rebuilding the rows if a commit ran out of room).
+pm_status device_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind, int phase, int max_rounds, int r,
+                        int* r_out, int* n_out, bool* declined) {
+  int mode = kind == 0 ? 1 : 2;
+  double qmin2 = o->q_min * o->q_min;
+  std::vector<uint64_t> seeds(max_rounds + 1);
+  for (int k = 0; k <= max_rounds; ++k) seeds[k] = stream_seed(m->seed, make_ctx(o->sweep, phase, k));
+  TRY(ensure(m, m->seeds, seeds.size()));
+  HIPCHK(hipMemcpyAsync(m->seeds.p, seeds.data(), sizeof(uint64_t) * seeds.size(), hipMemcpyHostToDevice, m->s));
+  dev_rounds_start(m->ctr, r, m->epoch + 1, m->sel_mark, r >= max_rounds ? 1 : 0, m->s);
+  int* L[2] = {m->listA.p, m->listB.p};
+  Round rd{0, m->rw.p, m->seeds.p};
+  OpArgs a{m->rw.p, 0, rd, o->L_low2, qmin2};
+  Commit cm = commit_of(m);
+  cm.touched = m->touch.p;
+  auto rounds = [&](hipStream_t q) {
+    for (int k = 0; k < 2; ++k) {
+      const int* A = L[k];
+      int* B = L[k ^ 1];
+      round_small(m->st, m->cls.p, -1, a, cm, kind, m->ctr, q);
+      clear_round_dev(A, m->ctr + C_LIST_B, m->rw.p, q);
+      select_small(m->st, mode, o->L_low2, A, -1, m->touch.p, cm.touched_cap, m->nxt.p, m->seen.p, 0, max_rounds, B,
+                   m->ctr, q);
+      colour_small(m->st, B, 0, m->ctr + C_LIST_B, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, q);
+    }
+  };
+  hipGraphExec_t ge = nullptr;
+  TRY(capture(m, rounds, &ge));
+  pm_status res = PM_OK;
+  for (;;) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k)
+      timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, 0, [&] { e = hipGraphLaunch(ge, m->s); });
+    if (e != hipSuccess) {
+      res = fail(m, PM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+      break;
+    }
+    res = read_ctr(m, 0, C_NCOL + 1);
+    if (res != PM_OK || m->hctr[C_DSTOP]) break;
+  }
+  (void)hipGraphExecDestroy(ge);
+  TRY(res);
+  int rr = m->hctr[C_DROUND];
+  st->v[1] += m->hctr[C_ACC_COL];
+  st->v[5] += m->hctr[C_ACC_NCOL];
+  st->v[12] += m->hctr[C_ACC_IT];
+  m->epoch = m->hctr[C_DEPOCH] - 1;
+  m->sel_mark = m->hctr[C_DMARK];
+  // the list of round rr is L[(rr - r) & 1]
+  int cur = (rr - r) & 1;
+  m->listA.p = L[cur];
+  m->listB.p = L[cur ^ 1];
+  *r_out = rr;
+  *n_out = m->hctr[C_LIST_B];
+  *declined = m->hctr[C_LIST_B] < 0;
+  return PM_OK;
+}
+
 pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind) {
   TRY(ensure_phase_scratch(m));
   m->tune = o->tune;
@@ -889,6 +976,45 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
+    if (small && !m->tune.host_rounds && cl.ncol > 0) {
+      int rr = r, nl = 0;
+      bool declined = false;
+      TRY(device_rounds(m, o, st, kind, phase, max_rounds, r, &rr, &nl, &declined));
+      if (!declined) {
+        // the next round's list is coloured when it fits one work-group (the
+        // counters hold its classes), else the host colours it
+        nA = nl;
+        r = rr;
+        ahead = m->hctr[C_NCOL] >= 0 && nl > 0;
+        if (ahead) small_classes(m, next);
+        continue;
+      }
+      // round rr ran, its selection declined: the classes from the counters
+      if (m->hctr[C_NCOL] < 0 || m->hctr[C_NCOL] > kMaxColours)
+        return fail(m, PM_E_DEVICE, "device-driven round left no class counters");
+      Classes dc;
+      small_classes(m, dc);
+      std::vector<int> dep(dc.ncol);
+      for (int c = 0; c < dc.ncol; ++c) dep[c] = m->hctr[C_DEPOCH0] + c;
+      int n_rr = 0;
+      for (int c = 0; c < dc.ncol; ++c) n_rr += dc.size[c];
+      if (m->hctr[C_ERR] & kRoomErr) {
+        Round rdd{stream_seed(m->seed, make_ctx(o->sweep, phase, rr)), m->rw.p};
+        TRY(recover_round(m, kind, dc, dep, rdd, o, n_rr));
+      }
+      set_int(m->ctr + C_LIST_B, 0, m->s);
+      timed(m, PM_K_SELECT, m->st.V, [&] {
+        select_vertices(m->st, mode, o->L_low2, nullptr, m->nxt.p, m->listB.p, m->ctr, m->sflag.p, m->spos.p,
+                        m->spart.p, m->s);
+      });
+      TRY(read_ctr(m, 0, kRoundCtrs));
+      TRY(check_err(m, true));
+      nA = m->hctr[C_LIST_B];
+      std::swap(m->listA, m->listB);
+      r = rr + 1;
+      ahead = false;
+      continue;
+    }
     std::vector<int> class_epoch(cl.ncol, -1);
     // a small round whose classes are all small: every class in one block,
     // one launch
@@ -914,7 +1040,7 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     if (small) {
       timed(m, PM_K_SELECT, nA, [&] {
         select_small(m->st, mode, o->L_low2, m->listA.p, nA, m->touch.p, cm.touched_cap, m->nxt.p, m->seen.p,
-                     ++m->sel_mark, m->listB.p, m->ctr, m->s);
+                     ++m->sel_mark, max_rounds, m->listB.p, m->ctr, m->s);
       });
       bool launch = r + 1 < max_rounds;
       if (launch) {
@@ -1060,6 +1186,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   dfree(m, m->qpart.p, m->qpart.n);
   dfree(m, m->upd.p, m->upd.n);
   dfree(m, m->rw.p, m->rw.n);
+  dfree(m, m->seeds.p, m->seeds.n);
   dfree(m, m->own.p, m->own.n);
   dfree(m, m->tk.p, m->tk.n);
   dfree(m, m->tgt.p, m->tgt.n);
@@ -1072,6 +1199,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   }
   dfree(m, m->ctr, C_COUNT);
   pinned_put(m);
+  if (m->cap_s) (void)hipStreamDestroy(m->cap_s);
   delete m;
   return PM_OK;
 }
@@ -1294,11 +1422,31 @@ pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st) {
     m->emet_topo = m->topo;
   }
   m->st.emet = m->emet.p;
-  for (int s = 0; s < o->smooth_sweeps; ++s)
+  auto sweep_on = [&](hipStream_t q) {
+    for (int c = 0; c < cl.ncol; ++c)
+      smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, smooth_lanes(m), q);
+  };
+  int64_t members = 0;
+  for (int c = 0; c < cl.ncol; ++c) members += cl.size[c];
+  if (o->smooth_sweeps > 1) {
+    // the classes' launches of one sweep, captured once as a graph and
+    // replayed for every sweep (they read only the class lists and the store)
+    hipGraphExec_t ge = nullptr;
+    TRY(capture(m, sweep_on, &ge));
+    pm_status r = PM_OK;
+    for (int s = 0; s < o->smooth_sweeps && r == PM_OK; ++s) {
+      hipError_t e = hipSuccess;
+      timed(m, PM_K_SMOOTH, members, [&] { e = hipGraphLaunch(ge, m->s); });
+      if (e != hipSuccess) r = fail(m, PM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    }
+    (void)hipGraphExecDestroy(ge);
+    TRY(r);
+  } else {
     for (int c = 0; c < cl.ncol; ++c)
       timed(m, PM_K_SMOOTH, cl.size[c], [&] {
         smooth_class(m->st, m->cls.p + cl.off[c], cl.size[c], o->smooth_kind, m->ctr, smooth_lanes(m), m->s);
       });
+  }
   m->st.emet = nullptr;
   clear_round(m->listA.p, n, m->rw.p, m->s);
   TRY(stats_read(m, st));

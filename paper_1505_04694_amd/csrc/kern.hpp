@@ -29,6 +29,15 @@ enum Ctr {
   C_JP = 16,        // JP: vertices still waiting after the last iteration (summed)
   C_CWIDE = 17,     // class lists: the call number of the last list with a colour past the narrow table
   C_FAILEP = 18,    // smallest commit epoch whose rows ran out of pool or staging room (INT_MAX: none)
+  // device-driven small rounds (the kernels decide, the host reads back every few rounds)
+  C_DROUND = 19,    // the round in progress
+  C_DEPOCH = 20,    // the next commit epoch
+  C_DEPOCH0 = 21,   // the first epoch of the last round run
+  C_DMARK = 22,     // the selection stamp last used
+  C_DSTOP = 23,     // 1: no further round (list empty, round cap, or a selection that declined)
+  C_ACC_COL = 24,   // vertices coloured, colours and colouring iterations of the rounds run
+  C_ACC_NCOL = 25,
+  C_ACC_IT = 26,
   C_HIST = 64,      // 64..319: colour histogram (class sizes)
   C_OFF = 320,      // 320..575: class offsets
   C_CUR = 576,      // 576..831: class cursors
@@ -198,6 +207,9 @@ __host__ __device__ __forceinline__ bool rw_beats(uint64_t rw_w, int w, uint64_t
 struct Round {
   uint64_t sseed;      // stream seed of this round's priorities
   uint64_t* rw;        // round words
+  // device-driven rounds: the stream seed of round r is seeds[r], r =
+  // ctr[C_DROUND] (null: sseed above)
+  const uint64_t* seeds = nullptr;
 };
 
 // Deferred update by pull: a committing member stamps its operation and
@@ -235,6 +247,8 @@ struct OpArgs {
 
 void set_flags(const int* list, int n, uint8_t* flag, uint8_t val, hipStream_t s);
 void clear_round(const int* list, int n, uint64_t* rw, hipStream_t s);
+// the same with the list length read from the device (*n_dev; nothing when <= 0)
+void clear_round_dev(const int* list, const int* n_dev, uint64_t* rw, hipStream_t s);
 // mode: 0 colour (active flags or all live), 1 coarsen, 2 swap, 3 smooth
 // selected vertices in ascending order, their count to ctr[C_LIST_B];
 // flag/pos: V ints, partial: scan scratch
@@ -244,6 +258,7 @@ void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s);
 // round words of the n vertices of the class lists cls (class c starts at
 // off[c], the device copy of the class offsets) as their colouring set them
 void restore_round(const Store& st, const int* cls, int n, const int* off, int ncol, Round rd, hipStream_t s);
+void dev_rounds_start(int* ctr, int r, int epoch, int mark, int stop, hipStream_t s);
 // One JP iteration over a chunked list: chunk k of kJpChunk slots holds cnt[k]
 // vertices at W[k * kJpChunk ...]; the first iteration reads the n entries of
 // A instead. Waiting vertices are compacted in place, in order, per chunk.
@@ -263,8 +278,11 @@ void colour_out(const Store& st, const uint64_t* rw, int* out, hipStream_t s);
 // deferred ones carry the next-round flag) and the rows rebuilt, each vertex
 // once (stamp array `seen`, marker `mark`); writes the count to C_LIST_B, or
 // -1 when the rebuilt rows overflowed their list (then select over all slots)
+// nA < 0: device-driven round (length ctr[C_LIST_B], stamp ctr[C_DMARK] + 1;
+// at the end the round counter advances and C_DSTOP is raised when the list
+// is empty or max_rounds is reached; nothing runs while C_DSTOP is set)
 void select_small(const Store& st, int mode, double L_low2, const int* A, int nA, const int* touched, int cap,
-                  uint8_t* nxt, int* seen, int mark, int* out, int* ctr, hipStream_t s);
+                  uint8_t* nxt, int* seen, int mark, int max_rounds, int* out, int* ctr, hipStream_t s);
 // lists up to kSmallColour entries: colouring and class lists in one block;
 // writes class sizes, offsets and count like class_lists, iterations to C_TOTAL
 constexpr int kSmallColour = 8192;
@@ -293,6 +311,8 @@ void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, i
 // all ncol classes of a round (every one of at most kSmallClass members) in one
 // block: class c with epoch cm.epoch + c, size and offset from ctr[C_HIST + c],
 // ctr[C_OFF + c] (a.cls is ignored)
+// ncol < 0: device-driven round (ncol = ctr[C_NCOL], epochs from C_DEPOCH,
+// nothing while C_DSTOP is set)
 void round_small(const Store& st, const int* cls, int ncol, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s);
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s);

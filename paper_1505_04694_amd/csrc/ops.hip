@@ -27,6 +27,13 @@ __global__ void k_clear_round(const int* __restrict__ list, int n, uint64_t* __r
 void clear_round(const int* list, int n, uint64_t* rw, hipStream_t s) {
   if (n > 0) k_clear_round<<<grid_for(n), kBlock, 0, s>>>(list, n, rw);
 }
+__global__ void k_clear_round_dev(const int* __restrict__ list, const int* n_dev, uint64_t* __restrict__ rw) {
+  int n = *n_dev;
+  for (int i = gtid(); i < n; i += gstride()) rw[list[i]] = 0;
+}
+void clear_round_dev(const int* list, const int* n_dev, uint64_t* rw, hipStream_t s) {
+  k_clear_round_dev<<<grid_for(kSmallColour), kBlock, 0, s>>>(list, n_dev, rw);
+}
 
 // ---- flags and lists -----------------------------------------------------------------
 __global__ void k_set_flags(const int* __restrict__ list, int n, uint8_t* __restrict__ flag, uint8_t val) {
@@ -101,6 +108,24 @@ __global__ void k_jp_init(Store st, const int* __restrict__ A, int n, Round rd) 
 }
 void jp_init(const Store& st, const int* A, int n, Round rd, hipStream_t s) {
   if (n > 0) k_jp_init<<<grid_for(n), kBlock, 0, s>>>(st, A, n, rd);
+}
+
+// start of device-driven rounds: round r, next epoch, last stamp; the
+// accumulated statistics cleared
+__global__ void k_dev_rounds_start(int* ctr, int r, int epoch, int mark, int stop) {
+  if (threadIdx.x == 0) {
+    ctr[C_DROUND] = r;
+    ctr[C_DEPOCH] = epoch;
+    ctr[C_DEPOCH0] = epoch;
+    ctr[C_DMARK] = mark;
+    ctr[C_DSTOP] = stop;
+    ctr[C_ACC_COL] = 0;
+    ctr[C_ACC_NCOL] = 0;
+    ctr[C_ACC_IT] = 0;
+  }
+}
+void dev_rounds_start(int* ctr, int r, int epoch, int mark, int stop, hipStream_t s) {
+  k_dev_rounds_start<<<1, 64, 0, s>>>(ctr, r, epoch, mark, stop);
 }
 
 // round words of a coloured list again, from its class lists (the list is
@@ -431,12 +456,20 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
   if (n_dev) {
     // the list length from the device (a colouring launched ahead of the
     // read-back); a list this kernel does not take is reported as -1 colours
+    // a device-driven chain that has stopped leaves the counters as they
+    // are (they describe the round that ran last)
+    if (rd.seeds && ctr[C_DSTOP]) return;
     n = *n_dev;
     if (n < 0 || n > kSmallColour) {
-      if (tid == 0) ctr[C_NCOL] = -1;
+      __syncthreads();
+      if (tid == 0) {
+        ctr[C_NCOL] = -1;
+        if (rd.seeds) ctr[C_DSTOP] = 1;  // a device-driven chain ends here
+      }
       return;
     }
   }
+  if (rd.seeds) rd.sseed = rd.seeds[ctr[C_DROUND]];
   for (int i = tid; i < n; i += kSmallThreads) {
     int v = A[i];
     uint64_t prio = key_of(st, rd, v) >> 32;
@@ -488,6 +521,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     ctr[C_TOUCH] = 0;
     ctr[C_TOTAL] = it;
     atomicAdd(ctr + C_STRIPE + S_PJP, visited);
+    if (rd.seeds) {
+      ctr[C_ACC_COL] += n;
+      ctr[C_ACC_NCOL] += ncol;
+      ctr[C_ACC_IT] += it;
+    }
   }
   __syncthreads();
   for (int i = tid; i < n; i += kSmallThreads) {
@@ -504,11 +542,24 @@ __global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mo
                                                                const int* __restrict__ A, int nA,
                                                                const int* __restrict__ touched, int cap,
                                                                uint8_t* __restrict__ nxt, int* __restrict__ seen,
-                                                               int mark, int* __restrict__ out, int* ctr) {
+                                                               int mark, int max_rounds, int* __restrict__ out,
+                                                               int* ctr) {
   __shared__ int cnt;
+  bool dev = nA < 0;
+  if (dev) {
+    if (ctr[C_DSTOP]) return;
+    nA = ctr[C_LIST_B];
+    mark = ctr[C_DMARK] + 1;
+  }
   int nt = ctr[C_TOUCH];
   if (nt > cap || room_failed(ctr)) {
-    if (threadIdx.x == 0) ctr[C_LIST_B] = -1;
+    // the host selects over every slot (and rebuilds the rows first after a
+    // commit that ran out of room)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      ctr[C_LIST_B] = -1;
+      if (dev) ctr[C_DSTOP] = 1;
+    }
     return;
   }
   if (threadIdx.x == 0) cnt = 0;
@@ -520,11 +571,20 @@ __global__ void __launch_bounds__(kSmallThreads) k_select_small(Store st, int mo
     if (want(st, x, mode, L_low2, nullptr)) out[atomicAdd(&cnt, 1)] = x;
   }
   __syncthreads();
-  if (threadIdx.x == 0) ctr[C_LIST_B] = cnt;
+  if (threadIdx.x == 0) {
+    ctr[C_LIST_B] = cnt;
+    if (dev) {
+      int r = ctr[C_DROUND] + 1;
+      ctr[C_DROUND] = r;
+      ctr[C_DMARK] = mark;
+      if (cnt == 0 || r >= max_rounds) ctr[C_DSTOP] = 1;
+    }
+  }
 }
 void select_small(const Store& st, int mode, double L_low2, const int* A, int nA, const int* touched, int cap,
-                  uint8_t* nxt, int* seen, int mark, int* out, int* ctr, hipStream_t s) {
-  k_select_small<<<1, kSmallThreads, 0, s>>>(st, mode, L_low2, A, nA, touched, cap, nxt, seen, mark, out, ctr);
+                  uint8_t* nxt, int* seen, int mark, int max_rounds, int* out, int* ctr, hipStream_t s) {
+  k_select_small<<<1, kSmallThreads, 0, s>>>(st, mode, L_low2, A, nA, touched, cap, nxt, seen, mark, max_rounds,
+                                             out, ctr);
 }
 
 __global__ void k_colour_out(int V, const uint64_t* __restrict__ rw, int* __restrict__ out) {
@@ -2155,6 +2215,17 @@ __global__ void __launch_bounds__(256) k_round_small(Store st, const int* __rest
                                                      Commit cm, int* ctr) {
   __shared__ CommitLds L;
   int epoch0 = cm.epoch;
+  bool dev = ncol < 0;
+  if (dev) {
+    if (ctr[C_DSTOP]) return;
+    ncol = ctr[C_NCOL];
+    epoch0 = ctr[C_DEPOCH];
+    __syncthreads();  // every thread has read the counters before they change
+    if (threadIdx.x == 0) {
+      ctr[C_DEPOCH0] = epoch0;
+      ctr[C_DEPOCH] = epoch0 + max(ncol, 0);
+    }
+  }
   for (int c = 0; c < ncol; ++c) {
     // a commit of this block may have run out of room: stop, the host
     // rebuilds the rows and runs the remaining classes
@@ -2169,7 +2240,7 @@ __global__ void __launch_bounds__(256) k_round_small(Store st, const int* __rest
   }
 }
 void round_small(const Store& st, const int* cls, int ncol, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
-  if (ncol <= 0) return;
+  if (ncol == 0) return;
   if (kind)
     k_round_small<true><<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
   else

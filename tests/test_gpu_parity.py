@@ -86,6 +86,7 @@ TUNINGS = [
     dict(commit_chunk=16, class_colours=256),
     dict(commit_chunk=32, small_work=1),
     dict(commit_chunk=128, class_colours=64),
+    dict(host_rounds=1),
 ]
 
 
