@@ -76,11 +76,17 @@ typedef struct {
                             colouring into class lists: 0 = 32; 4, 8, 16, 32,
                             64, 128 or 256 (a colouring with more colours is
                             cut again from the full table)                       */
+  int32_t commit_order;  /* 0: the commit of a class of at least V/64 members
+                            walks the rows in vertex order, smaller classes from
+                            their members; 1: always from the members; 2:
+                            always in vertex order                              */
   int32_t host_rounds;   /* 0: rounds whose list is coloured by one work-group
-                            run device-driven (each kernel takes its sizes from
+                            and whose classes have at most 32 members run
+                            device-driven (each kernel takes its sizes from
                             device counters; two rounds are captured once as a
                             graph and replayed, the host reads back every four
                             rounds); 1: the host drives every round             */
+  int32_t reserved;      /* 0 */
 } pm_tuning;
 
 /* Thresholds are squared metric lengths. Defaults (pm_default_options):

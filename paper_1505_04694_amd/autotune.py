@@ -27,6 +27,7 @@ SPACE = {
     "smooth_lanes": [8, 1],
     "small_work": [0, 1],
     "class_colours": [32, 256],
+    "commit_order": [0, 1, 2],
     "host_rounds": [0, 1],
 }
 CACHE_ENV = "PMESH_TUNE_CACHE"

@@ -582,7 +582,7 @@ constexpr int kJpBatch = 4;
 // the classes of a one-block colouring, from the host copy of the counters
 void small_classes(pm_mesh* m, Classes& out) {
   out.jp_iters = m->hctr[C_TOTAL];
-  out.ncol = m->hctr[C_NCOL];
+  out.ncol = std::max(m->hctr[C_NCOL], 0);
   out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
   out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
 }
@@ -631,7 +631,7 @@ pm_status colour_list(pm_mesh* m, const int* A, int n, Round rd, Classes& out) {
   out.jp_iters = it;
   m->jp_last = it;
   TRY(check_err(m, true));
-  out.ncol = m->hctr[C_NCOL];
+  out.ncol = std::max(m->hctr[C_NCOL], 0);
   out.size.assign(m->hctr + C_HIST, m->hctr + C_HIST + out.ncol);
   out.off.assign(m->hctr + C_OFF, m->hctr + C_OFF + out.ncol);
   return PM_OK;
@@ -767,7 +767,8 @@ bool bad_tuning(const pm_tuning& t) {
   };
   return !in(t.op_lanes, {0, 1, 8, 16}) || !in(t.smooth_lanes, {0, 1, 8}) ||
          !in(t.commit_chunk, {0, 16, 32, 64, 128}) || !in(t.small_work, {0, 1}) ||
-         !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || !in(t.host_rounds, {0, 1});
+         !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || !in(t.commit_order, {0, 1, 2}) ||
+         !in(t.host_rounds, {0, 1}) || t.reserved != 0;
 }
 
 bool bad_opts(const pm_options* o) {
@@ -816,8 +817,13 @@ void run_class(pm_mesh* m, int kind, const Classes& cl, int c, const OpArgs& a, 
       if (op_lanes(m) == 1) flip_class(m->st, list, n, a, cm, m->ctr, m->s);
       else flip_class_g(m->st, list, n, a, cm, m->ctr, m->s);
     });
-  timed(m, PM_K_COMMIT, 0,
-        [&] { commit_rows(m->st, list, n, cm, kind != 0, m->tune.commit_chunk, m->ctr, m->s); });
+  bool sweep = m->tune.commit_order == 2 || (m->tune.commit_order == 0 && (int64_t)n * 64 >= m->st.V);
+  if (sweep) {
+    timed(m, PM_K_COMMIT, 0, [&] { commit_sweep(m->st, cm, kind != 0, m->ctr, m->s); });
+  } else {
+    timed(m, PM_K_COMMIT, 0,
+          [&] { commit_rows(m->st, list, n, cm, kind != 0, m->tune.commit_chunk, m->ctr, m->s); });
+  }
 }
 
 // A commit ran out of pool or staging room in this round (the host copy of
@@ -976,13 +982,16 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     st->v[1] += nA;
     st->v[5] += cl.ncol;
     st->v[12] += cl.jp_iters;
-    if (small && !m->tune.host_rounds && cl.ncol > 0) {
+    bool fits = cl.ncol > 0;
+    for (int c = 0; c < cl.ncol && fits; ++c) fits = cl.size[c] <= kSmallClass;
+    if (small && !m->tune.host_rounds && fits) {
       int rr = r, nl = 0;
       bool declined = false;
       TRY(device_rounds(m, o, st, kind, phase, max_rounds, r, &rr, &nl, &declined));
       if (!declined) {
         // the next round's list is coloured when it fits one work-group (the
-        // counters hold its classes), else the host colours it
+        // counters hold its classes; a class too large for the chain stopped
+        // it), else the host colours it
         nA = nl;
         r = rr;
         ahead = m->hctr[C_NCOL] >= 0 && nl > 0;

@@ -56,7 +56,8 @@ enum Slot {
   S_EVAL = 0, S_DEFER = 1, S_COMMIT = 2, S_RELOC = 3, S_ROWS = 4, S_EDGES = 5,  // stats
   S_PJP = 6, S_PROWS = 7,  // profiling units
   S_JPL = 8,               // 8..15: JP vertices left, by iteration modulo 8
-  S_POPS = 16              // profiling units: committed operations handled by the commit kernels
+  S_POPS = 16              // profiling units: operations committed by the grid-wide class kernels,
+                           // whose rows the separate commit kernels rebuild
 };
 __device__ __forceinline__ int* stripe_ptr(int* ctr, int slot) {
   int w = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kStripes - 1));
@@ -304,6 +305,8 @@ void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, i
 // just processed, launched in the same shape); flips: members' own rows too
 // chunk: class members per work-group (0: by class size)
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int chunk, int* ctr, hipStream_t s);
+// the same in vertex order: every row claimed in this epoch, one thread per vertex slot
+void commit_sweep(const Store& st, Commit cm, bool flips, int* ctr, hipStream_t s);
 // a class of at most kSmallClass members: operation and commit in one block
 // (kind 0 collapse, 1 flip)
 constexpr int kSmallClass = 32;

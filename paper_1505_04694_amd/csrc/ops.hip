@@ -522,9 +522,18 @@ __global__ void __launch_bounds__(kSmallThreads) k_colour_small(Store st, const 
     ctr[C_TOTAL] = it;
     atomicAdd(ctr + C_STRIPE + S_PJP, visited);
     if (rd.seeds) {
-      ctr[C_ACC_COL] += n;
-      ctr[C_ACC_NCOL] += ncol;
-      ctr[C_ACC_IT] += it;
+      // a device-driven chain takes rounds whose classes all fit one block's
+      // pass; a larger class ends it here, coloured, for the host to run
+      // (and count)
+      bool big = false;
+      for (int c = 0; c < ncol; ++c) big |= hist[c] > kSmallClass;
+      if (big) {
+        ctr[C_DSTOP] = 1;
+      } else {
+        ctr[C_ACC_COL] += n;
+        ctr[C_ACC_NCOL] += ncol;
+        ctr[C_ACC_IT] += it;
+      }
     }
   }
   __syncthreads();
@@ -635,8 +644,10 @@ __device__ __forceinline__ Geo geo_of(const Store& st, const Elem& e) {
   return make_geo(st.xy[e.x], st.xy[e.y], st.xy[e.z], st.met[e.x], st.met[e.y], st.met[e.z]);
 }
 
-// per-wave stats: evaluated / deferred / committed
-__device__ __forceinline__ void count_status(int status, int* ctr) {
+// per-wave stats: evaluated / deferred / committed; pops: also count the
+// committed operations as the unit of the separate commit kernel that follows
+// (grid-wide class kernels)
+__device__ __forceinline__ void count_status(int status, int* ctr, bool pops = false) {
   // status: -1 idle lane, 0 deferred, 1 evaluated, 2 evaluated + committed
   uint64_t d = __ballot(status == 0);
   uint64_t e = __ballot(status >= 1);
@@ -646,6 +657,7 @@ __device__ __forceinline__ void count_status(int status, int* ctr) {
     if (d) atomicAdd(sp + S_DEFER, __popcll(d));
     if (e) atomicAdd(sp + S_EVAL, __popcll(e));
     if (c) atomicAdd(sp + S_COMMIT, __popcll(c));
+    if (c && pops) atomicAdd(sp + S_POPS, __popcll(c));
   }
 }
 
@@ -740,7 +752,7 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
   int i = xtid();
   int status = -1;
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
-  count_status(status, ctr);
+  count_status(status, ctr, true);
 }
 template <int G>
 __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
@@ -827,7 +839,7 @@ __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, 
   int i = xtid();
   int status = -1;
   if (i < n) status = flip_one(st, list[i], a, cm, ctr);
-  count_status(status, ctr);
+  count_status(status, ctr, true);
 }
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
   if (n > 0) k_flip<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
@@ -1330,8 +1342,6 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
     }
   }
   uint64_t key = own_key(cm.epoch, v);
-  uint64_t coms = __ballot(com);
-  if (__lane_id() == 0 && coms) atomicAdd(stripe_ptr(ctr, S_POPS), __popcll(coms));
   int* mycol = L.col + tid;
   if (tid == 0) L.bqn = 0;
   bool own_round = F;
@@ -1386,6 +1396,54 @@ __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restri
   if (room_failed_block(ctr)) return;  // other blocks may set it meanwhile: one answer per block
   int base = xcd_block() * mpb;
   commit_chunk<F>(st, list, base, min(mpb, n - base), cm, ctr, L);
+}
+
+// The same rebuild in vertex order, for classes whose claimed rows cover a
+// good part of the mesh: a work-group scans kSweepChunk consecutive vertex
+// slots, queues the rows claimed in this epoch in LDS in slot order (a
+// block-wide ordered compaction, so every lane of a rebuild pass has a row),
+// and rebuilds them kBlock at a time. Consecutive rows then read nearby
+// headers, capacities, owner keys and target records, and walk rows and
+// elements in the order they are laid out, where the member-driven form above
+// touches them in its members' neighbour order. Every row is still rebuilt
+// once, from the same candidates, so the rows are the same.
+constexpr int kSweepChunk = kPairB * kBlock;
+template <bool F>
+__global__ void __launch_bounds__(256, 5) k_commit_sweep(Store st, Commit cm, int* ctr) {
+  __shared__ CommitLds L;
+  if (room_failed_block(ctr)) return;
+  int tid = (int)threadIdx.x;
+  int base = xcd_block() * kSweepChunk;
+  int qn = 0;
+  for (int b = 0; b < kSweepChunk; b += kBlock) {
+    int x = base + b + tid;
+    bool dirty = x < st.V && (uint32_t)(cm.own[x] >> 32) == (uint32_t)cm.epoch;
+    int at;
+    int tot = block_scan(dirty ? 1 : 0, at, L.wsum);
+    if (dirty) L.q[qn + at] = x;
+    qn += tot;
+    __syncthreads();  // wsum is reused by the next scan
+  }
+  if (tid == 0) L.bqn = 0;
+  __syncthreads();
+  for (int r0 = 0; r0 < qn; r0 += kBlock)
+    rebuild_row<F, kRegSmall, kBlock>(st, cm, r0 + tid < qn ? L.q[r0 + tid] : -1, L.col + tid, ctr, L.bq, &L.bqn);
+  __syncthreads();
+  int nbig = min(L.bqn, kBlock);
+  constexpr int H = kBlock / 2;
+  for (int b0 = 0; b0 < nbig; b0 += H) {
+    int y = (tid < H && b0 + tid < nbig) ? L.bq[b0 + tid] : -1;
+    rebuild_row<F, kRegRow, H>(st, cm, y, L.col + (tid & (H - 1)), ctr, nullptr, nullptr);
+  }
+}
+
+void commit_sweep(const Store& st, Commit cm, bool flips, int* ctr, hipStream_t s) {
+  int nb = (st.V + kSweepChunk - 1) / kSweepChunk;
+  if (nb <= 0) return;
+  if (flips)
+    k_commit_sweep<true><<<nb, kBlock, 0, s>>>(st, cm, ctr);
+  else
+    k_commit_sweep<false><<<nb, kBlock, 0, s>>>(st, cm, ctr);
 }
 
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int chunk, int* ctr, hipStream_t s) {
@@ -2008,7 +2066,7 @@ __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __re
       if (g.j == 0) status = r;
     }
   }
-  count_status(status, ctr);
+  count_status(status, ctr, true);
 }
 template __global__ void k_collapse_g<8>(Store, const int*, int, OpArgs, Commit, int*);
 template __global__ void k_collapse_g<16>(Store, const int*, int, OpArgs, Commit, int*);
@@ -2156,7 +2214,7 @@ __global__ void __launch_bounds__(256) k_flip_g(Store st, const int* __restrict_
       if (g.j == 0) status = r;
     }
   }
-  count_status(status, ctr);
+  count_status(status, ctr, true);
 }
 void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
   if (n > 0) k_flip_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);

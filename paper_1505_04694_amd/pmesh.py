@@ -43,8 +43,9 @@ class PMError(RuntimeError):
 
 class Tuning(C.Structure):
     _fields_ = [("op_lanes", C.c_int32), ("smooth_lanes", C.c_int32), ("commit_chunk", C.c_int32),
-                ("small_work", C.c_int32), ("class_colours", C.c_int32), ("host_rounds", C.c_int32)]
-    KEYS = ["op_lanes", "smooth_lanes", "commit_chunk", "small_work", "class_colours", "host_rounds"]
+                ("small_work", C.c_int32), ("class_colours", C.c_int32), ("commit_order", C.c_int32),
+                ("host_rounds", C.c_int32), ("reserved", C.c_int32)]
+    KEYS = ["op_lanes", "smooth_lanes", "commit_chunk", "small_work", "class_colours", "commit_order", "host_rounds"]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k in self.KEYS}

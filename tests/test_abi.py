@@ -34,8 +34,8 @@ def test_options_layout_and_defaults():
     o = pmesh.pm_default_options()
     assert (o.L_low2, o.L_up2, o.q_min, o.slack) == (0.5, 2.0, 0.1, 2.0)
     assert (o.coarsen_rounds, o.swap_rounds, o.refine_passes, o.smooth_sweeps) == (200, 100, 32, 1)
-    assert ctypes.sizeof(pmesh.Options) == 104
-    assert ctypes.sizeof(pmesh.Tuning) == 24
+    assert ctypes.sizeof(pmesh.Options) == 112
+    assert ctypes.sizeof(pmesh.Tuning) == 32
     assert ctypes.sizeof(pmesh.Context) == 24
     assert ctypes.sizeof(pmesh.Stats) == 128
 
