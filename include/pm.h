@@ -83,9 +83,11 @@ typedef struct {
   int32_t host_rounds;   /* 0: rounds whose list is coloured by one work-group
                             and whose classes have at most 32 members run
                             device-driven (each kernel takes its sizes from
-                            device counters; two rounds are captured once as a
-                            graph and replayed, the host reads back every four
-                            rounds); 1: the host drives every round             */
+                            device counters, the host reads back every four
+                            rounds); 2: the same, two rounds captured as a
+                            graph that the handle keeps and replays while its
+                            launch arguments are unchanged; 1: the host drives
+                            every round                                         */
   int32_t reserved;      /* 0 */
 } pm_tuning;
 

@@ -28,7 +28,7 @@ SPACE = {
     "small_work": [0, 1],
     "class_colours": [32, 256],
     "commit_order": [0, 1, 2],
-    "host_rounds": [0, 1],
+    "host_rounds": [0, 1, 2],
 }
 CACHE_ENV = "PMESH_TUNE_CACHE"
 

@@ -46,6 +46,8 @@ struct Prof {
 struct pm_mesh {
   hipStream_t s = nullptr;
   hipStream_t cap_s = nullptr;  // private stream that graph captures are recorded on
+  // device-driven rounds: instantiated graphs, by the bytes of their launch arguments
+  std::vector<std::pair<std::string, hipGraphExec_t>> dr_graphs;
   int dev = 0;                // device current at creation
   double* scratch = nullptr;  // that device's copy of the no-allocation scratch array
   Prof prof;
@@ -768,7 +770,7 @@ bool bad_tuning(const pm_tuning& t) {
   return !in(t.op_lanes, {0, 1, 8, 16}) || !in(t.smooth_lanes, {0, 1, 8}) ||
          !in(t.commit_chunk, {0, 16, 32, 64, 128}) || !in(t.small_work, {0, 1}) ||
          !in(t.class_colours, {0, 4, 8, 16, 32, 64, 128, 256}) || !in(t.commit_order, {0, 1, 2}) ||
-         !in(t.host_rounds, {0, 1}) || t.reserved != 0;
+         !in(t.host_rounds, {0, 1, 2}) || t.reserved != 0;
 }
 
 bool bad_opts(const pm_options* o) {
@@ -907,13 +909,40 @@ pm_status device_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind,
       colour_small(m->st, B, 0, m->ctr + C_LIST_B, rd, m->jpU0.p, m->jpU1.p, m->jpB.p, m->cls.p, m->ctr, q);
     }
   };
+  // the graph of two rounds is kept while its launch arguments stay the same
+  // (the same store layout, buffers and parameters; the seed table is read
+  // when it runs)
   hipGraphExec_t ge = nullptr;
-  TRY(capture(m, rounds, &ge));
+  if (m->tune.host_rounds == 2) {
+    std::string key;
+    auto add = [&](const void* p, size_t n) { key.append((const char*)p, n); };
+    add(&m->st, sizeof(Store));
+    add(L, sizeof(L));
+    add(&a, sizeof(a));
+    add(&cm, sizeof(cm));
+    int ints[4] = {kind, mode, max_rounds, 0};
+    add(ints, sizeof(ints));
+    void* ptrs[8] = {m->cls.p, m->ctr, m->nxt.p, m->seen.p, m->jpU0.p, m->jpU1.p, m->jpB.p, m->touch.p};
+    add(ptrs, sizeof(ptrs));
+    for (auto& g : m->dr_graphs)
+      if (g.first == key) ge = g.second;
+    if (!ge) {
+      TRY(capture(m, rounds, &ge));
+      if (m->dr_graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(m->dr_graphs.front().second);
+        m->dr_graphs.erase(m->dr_graphs.begin());
+      }
+      m->dr_graphs.push_back({key, ge});
+    }
+  }
   pm_status res = PM_OK;
   for (;;) {
     hipError_t e = hipSuccess;
     for (int k = 0; k < 2 && e == hipSuccess; ++k)
-      timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, 0, [&] { e = hipGraphLaunch(ge, m->s); });
+      timed(m, kind == 0 ? PM_K_COLLAPSE : PM_K_FLIP, 0, [&] {
+        if (ge) e = hipGraphLaunch(ge, m->s);
+        else rounds(m->s);
+      });
     if (e != hipSuccess) {
       res = fail(m, PM_E_DEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
       break;
@@ -921,7 +950,6 @@ pm_status device_rounds(pm_mesh* m, const pm_options* o, pm_stats* st, int kind,
     res = read_ctr(m, 0, C_NCOL + 1);
     if (res != PM_OK || m->hctr[C_DSTOP]) break;
   }
-  (void)hipGraphExecDestroy(ge);
   TRY(res);
   int rr = m->hctr[C_DROUND];
   st->v[1] += m->hctr[C_ACC_COL];
@@ -984,7 +1012,7 @@ pm_status run_rounds_in(pm_mesh* m, const pm_options* o, pm_stats* st, int kind)
     st->v[12] += cl.jp_iters;
     bool fits = cl.ncol > 0;
     for (int c = 0; c < cl.ncol && fits; ++c) fits = cl.size[c] <= kSmallClass;
-    if (small && !m->tune.host_rounds && fits) {
+    if (small && m->tune.host_rounds != 1 && fits) {
       int rr = r, nl = 0;
       bool declined = false;
       TRY(device_rounds(m, o, st, kind, phase, max_rounds, r, &rr, &nl, &declined));
@@ -1208,6 +1236,7 @@ pm_status pm_mesh_destroy(pm_mesh* m) {
   }
   dfree(m, m->ctr, C_COUNT);
   pinned_put(m);
+  for (auto& g : m->dr_graphs) (void)hipGraphExecDestroy(g.second);
   if (m->cap_s) (void)hipStreamDestroy(m->cap_s);
   delete m;
   return PM_OK;

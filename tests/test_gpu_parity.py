@@ -87,6 +87,7 @@ TUNINGS = [
     dict(commit_chunk=32, small_work=1),
     dict(commit_chunk=128, class_colours=64),
     dict(host_rounds=1),
+    dict(host_rounds=2),
     dict(commit_order=1),
     dict(commit_order=2, commit_chunk=64),
 ]
