@@ -11,6 +11,7 @@ are edges tested by refinement (identical counts on the oracle).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--n 2049]
        python bench.py --config4                      (the 4097^2 workload, peak device memory)
+       python bench.py --psi 10                       (the paper's psi benchmark, 10 time steps)
        python bench.py --summarise-trace DIR --out PREFIX --command CMD
        python bench.py --summarise-counters FETCH_DIR WRITE_DIR --out PREFIX --command CMD
 The last two turn rocprofv3 CSV output (--stats / --pmc runs of this script)
@@ -293,6 +294,47 @@ def config4_run(n=4097, sweeps=2, seed=3):
                       "final": {"vertices": V, "triangles": T, "quality": q}, "phases": phases}), flush=True)
 
 
+def psi_run(steps=10, n=201, target=550e3, iterations=2):
+    """The paper's synthetic benchmark: an isotropic n x n start adapted to
+    the Hessian metric of the time-varying psi for about `target` elements
+    (Algorithm 1 at t = 0, four iterations, untimed), then `steps` of the 50
+    time steps of one period, each: the metric of the new phase at the current
+    vertices (evaluated on the host, outside the timed region), written with
+    pm_mesh_update, then Algorithm 1 (`iterations` outer iterations and one
+    smoothing). Reports the device time per time step."""
+    import math
+    import torch
+    from paper_1505_04694_amd import inputs, pmesh
+    torch.cuda.set_device(0)
+    mi = inputs.psi_start(n, target=target)
+    eps = mi.info["eps"]
+    m = pmesh.Mesh(mi.xy, mi.tri, mi.metric, mi.tags, seed=0)
+    st0, _ = m.adapt(max_iterations=4)
+    log(f"psi start adapted: {m.sizes()}")
+    times, ops, sizes = [], 0, []
+    for k in range(1, steps + 1):
+        e = m.export()
+        met = inputs.psi_metric(e["xy"], 2 * math.pi * k / 50, eps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.update(metric=met)
+        m.set_context(dict(seed=0, iteration=0, phase=pmesh.PM_PHASE_COARSEN, changed=0))
+        st, _ = m.adapt(max_iterations=iterations)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ops += st["coloured"] + st["evaluated"] + st["edges"]
+        sizes.append(m.sizes())
+    ms = 1e3 * sum(times) / steps
+    print(json.dumps({"workload": f"time-varying psi on the unit square: {n}x{n} isotropic start "
+                                  f"({mi.T} triangles), Hessian metric for ~{target:.0f} elements, "
+                                  f"{steps} time steps of 50 per period, Algorithm 1 with {iterations} "
+                                  "iterations per step", "ms_per_time_step": ms,
+                      "ms_per_time_step_range": [round(1e3 * min(times), 2), round(1e3 * max(times), 2)],
+                      "ops_per_s": ops / sum(times), "elements": [t for _, t in sizes],
+                      "start_adaptation": st0}), flush=True)
+    m.close()
+
+
 # ---- rocprofv3 summaries ---------------------------------------------------------------
 
 def _csvs(d, suffix):
@@ -404,6 +446,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--config4", action="store_true",
                     help="instead: the 4097x4097 workload, two sweeps with gradient smoothing, peak device memory")
+    ap.add_argument("--psi", type=int, metavar="STEPS", default=0,
+                    help="instead: the paper's time-varying psi benchmark for STEPS time steps")
     ap.add_argument("--summarise-trace", metavar="DIR")
     ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "summary"))
@@ -421,6 +465,9 @@ def main():
         sys.exit(2)
     if a.config4:
         config4_run()
+        return
+    if a.psi:
+        psi_run(a.psi)
         return
 
     import torch

@@ -193,6 +193,74 @@ def refine_start(n: int = 17, scale: float = 200.0, jitter_seed: int = 7) -> Mes
     return mi
 
 
+# ---- the paper's synthetic benchmark (a time-varying solution psi) ---------------
+
+def psi_hessian(xy: np.ndarray, phase: float) -> np.ndarray:
+    """Analytic Hessian (h_xx, h_xy, h_yy) of
+    psi(x, y) = 0.1 sin(50x + phase) + arctan(-0.1 / (2x - sin(5y + phase))),
+    phase = 2 pi t / T. With u = 2x - sin(5y + phase) and f(u) = arctan(-0.1/u):
+    f' = 0.1 / (u^2 + 0.01) and f'' = -0.2 u / (u^2 + 0.01)^2, smooth at u = 0
+    (psi jumps by pi there, its derivatives do not)."""
+    x, y = xy[:, 0], xy[:, 1]
+    a = 50.0 * x + phase
+    b = 5.0 * y + phase
+    u = 2.0 * x - np.sin(b)
+    den = u * u + 0.01
+    f1 = 0.1 / den
+    f2 = -0.2 * u / (den * den)
+    ux, uy, uyy = 2.0, -5.0 * np.cos(b), 25.0 * np.sin(b)
+    hxx = -250.0 * np.sin(a) + f2 * ux * ux
+    hxy = f2 * ux * uy
+    hyy = f2 * uy * uy + f1 * uyy
+    return np.stack([hxx, hxy, hyy], axis=1)
+
+
+def psi_metric(xy: np.ndarray, phase: float, eps: float, hmin: float = 1e-3, hmax: float = 0.2) -> np.ndarray:
+    """Metric from the Hessian: R diag(lam~) R^T with lam~ = clamp(|lam| / eps,
+    1/hmax^2, 1/hmin^2), H = R diag(lam) R^T (the usual Hessian-based reading;
+    the paper does not give the rule)."""
+    h = psi_hessian(xy, phase)
+    H = np.stack([np.stack([h[:, 0], h[:, 1]], -1), np.stack([h[:, 1], h[:, 2]], -1)], -2)
+    lam, R = np.linalg.eigh(H)
+    lam = np.clip(np.abs(lam) / eps, 1.0 / hmax ** 2, 1.0 / hmin ** 2)
+    M = np.einsum("nij,nj,nkj->nik", R, lam, R)
+    return np.ascontiguousarray(np.stack([M[:, 0, 0], 0.5 * (M[:, 0, 1] + M[:, 1, 0]), M[:, 1, 1]], axis=1))
+
+
+def ideal_elements(xy: np.ndarray, tri: np.ndarray, metric: np.ndarray) -> float:
+    """Elements of an ideal mesh for the metric: the metric-space area over the
+    area of a unit equilateral triangle, sqrt(3)/4 (element metric = vertex mean)."""
+    p0, p1, p2 = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    A = 0.5 * np.abs((p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p2[:, 0] - p0[:, 0]) * (p1[:, 1] - p0[:, 1]))
+    m = (metric[tri[:, 0]] + metric[tri[:, 1]] + metric[tri[:, 2]]) / 3.0
+    det = np.maximum(m[:, 0] * m[:, 2] - m[:, 1] ** 2, 0.0)
+    return float((np.sqrt(det) * A).sum() / (math.sqrt(3.0) / 4.0))
+
+
+def psi_eps(xy: np.ndarray, tri: np.ndarray, target: float, phase: float = 0.0, **kw) -> float:
+    """The eps of psi_metric whose ideal element count on (xy, tri) is target (bisection in log eps)."""
+    lo, hi = -12.0, 6.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        n = ideal_elements(xy, tri, psi_metric(xy, phase, 10.0 ** mid, **kw))
+        if n > target:
+            lo = mid
+        else:
+            hi = mid
+    return 10.0 ** (0.5 * (lo + hi))
+
+
+def psi_start(n: int = 201, target: float = 550e3, steps: int = 50) -> MeshInput:
+    """The benchmark's start: an isotropic n x n grid of the unit square (about
+    2(n-1)^2 triangles: 80,000 for n = 201) and the metric of psi at t = 0 with
+    eps set for about `target` elements; the time step advances the phase by
+    2 pi / steps (info: eps, steps)."""
+    xy, tri = grid(n)
+    eps = psi_eps(xy, tri, target)
+    return MeshInput(xy=xy, tri=tri, metric=psi_metric(xy, 0.0, eps), tags=unit_square_tags(xy), n=n,
+                     info=dict(eps=eps, steps=steps, target=target))
+
+
 def config0() -> MeshInput:
     """33 x 33 grid, one-layer field; priority seed 0."""
     return make_mesh(33)

@@ -217,3 +217,31 @@ def test_update_rejects_inverted_coordinates_and_keeps_the_old_ones():
         gm.update(xy=bad)
     assert e.value.status == pmesh.PM_E_MESH
     assert np.array_equal(gm.export()["xy"], mi.xy)
+
+
+def test_psi_benchmark_time_steps():
+    """The paper's synthetic benchmark at a reduced size: an isotropic 51 x 51
+    start, the Hessian metric of the time-varying psi for about 2e4 elements;
+    Algorithm 1 at t = 0, then three time steps, each with the metric of the
+    next phase evaluated at the current vertices (on the host, the same array
+    for both sides) and Algorithm 1 again. Parity after every step."""
+    import math
+    mi = inputs.psi_start(51, target=2e4, steps=50)
+    eps = mi.info["eps"]
+    om, gm = both(mi, 0)
+    for step in range(4):
+        if step > 0:
+            d = om.export()
+            assert np.array_equal(d["xy"], gm.export()["xy"])
+            met = inputs.psi_metric(d["xy"], 2 * math.pi * step / 50, eps)
+            for v in range(met.shape[0]):
+                om.set_metric(v, *met[v])
+            gm.update(metric=met)
+            om.set_context(0, 1, 0)
+            gm.set_context(dict(seed=0, iteration=0, phase=pmesh.PM_PHASE_COARSEN, changed=0))
+        so, _ = om.adapt(max_iterations=2)
+        sg, _ = gm.adapt(max_iterations=2)
+        compare_stats(so, sg, f"step {step}")
+        compare_mesh(om, gm, f"step {step}")
+    assert gm.sizes()[1] > 2 * mi.T
+    compare_quality(om, gm, "end")
