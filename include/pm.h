@@ -46,7 +46,9 @@ typedef enum {
 } pm_status;
 
 enum { PM_MEM_HOST = 0, PM_MEM_DEVICE = 1 };
-enum { PM_SMOOTH_LAPLACE = 0, PM_SMOOTH_GRADIENT = 1 };
+/* smoothing kinds: the Laplacian in the metric; a gradient step on the patch's
+ * quality sum; min-max, an ascent step on the patch's worst quality */
+enum { PM_SMOOTH_LAPLACE = 0, PM_SMOOTH_GRADIENT = 1, PM_SMOOTH_MINMAX = 2 };
 /* phases of Algorithm 1 (pm_adapt's loop state, see pm_context) */
 enum { PM_PHASE_COARSEN = 1, PM_PHASE_SWAP = 2, PM_PHASE_REFINE = 3, PM_PHASE_SMOOTH = 4, PM_PHASE_DONE = 5 };
 
@@ -204,9 +206,13 @@ pm_status pm_refine(pm_mesh* m, const pm_options* o, pm_stats* st);
 pm_status pm_swap(pm_mesh* m, const pm_options* o, pm_stats* st);
 
 /* Smoothing (Sec. 2.4.4): o->smooth_sweeps coloured sweeps over interior
- * vertices, Laplacian in the metric or a gradient step on the local quality
- * functional, each move kept only if the patch's minimum quality does not
- * drop and every area stays positive. */
+ * vertices. PM_SMOOTH_LAPLACE: the Laplacian in the metric, kept if every area
+ * stays positive and the patch's minimum quality does not drop;
+ * PM_SMOOTH_GRADIENT: a step along the gradient of the patch's quality sum,
+ * kept on the same conditions when the sum rises; PM_SMOOTH_MINMAX: a step
+ * along the ascent direction of the patch's worst quality (the worst
+ * element's gradient, or the nearest-to-origin point between the two worst
+ * within 1%), kept when every area stays positive and the minimum rises. */
 pm_status pm_smooth(pm_mesh* m, const pm_options* o, pm_stats* st);
 
 /* Algorithm 1 (Sec. 2.3), the mesh optimisation procedure: repeat coarsen,

@@ -529,6 +529,76 @@ bool smooth_gradient(Mesh& m, int32_t v) {
   return false;
 }
 
+// Min-max optimisation smoothing (Sec. 2.4.4 cites optimisation-based
+// smoothing, which aims at the worst element). Reading: ascent on the
+// patch's minimum quality. The worst element is the one of smallest q
+// (ties: the first in NE(v), ascending ids), the second worst likewise among
+// the rest. Direction: the gradient of the worst element's q in x_v; when the
+// second worst is within 1% (q2 <= 1.01 q1), the point nearest the origin on
+// the segment between the two gradients (the ascent direction of the smaller
+// of the two). Normalised in the max-norm; steps h/2 .. h/16 with h as in the
+// gradient step; the first step that keeps every area positive and raises
+// the patch minimum of q^2 strictly is taken.
+bool smooth_minmax(Mesh& m, int32_t v) {
+  double xv = m.x[v], yv = m.y[v];
+  int32_t t1 = -1, t2 = -1;
+  double q1 = 0.0, q2 = 0.0;
+  for (int32_t t : m.NE[v]) {
+    double q = qual(geo(m, m.tri[t]));
+    if (t1 < 0 || q < q1) {
+      t2 = t1;
+      q2 = q1;
+      t1 = t;
+      q1 = q;
+    } else if (t2 < 0 || q < q2) {
+      t2 = t;
+      q2 = q;
+    }
+  }
+  if (t1 < 0) return false;
+  double ax, ay;
+  qual_grad_x(geo(m, m.tri[t1]), pos_in(m.tri[t1], v), &ax, &ay);
+  double gx = ax, gy = ay;
+  if (t2 >= 0 && q2 <= q1 * 1.01) {
+    double bx, by;
+    qual_grad_x(geo(m, m.tri[t2]), pos_in(m.tri[t2], v), &bx, &by);
+    double ex = bx - ax, ey = by - ay;
+    double den = ex * ex + ey * ey;
+    if (den > 0.0) {
+      double lam = -(ax * ex + ay * ey) / den;
+      lam = lam < 0.0 ? 0.0 : (lam > 1.0 ? 1.0 : lam);
+      gx = ax + lam * ex;
+      gy = ay + lam * ey;
+    }
+  }
+  if (gx == 0.0 && gy == 0.0) return false;
+  double nx = std::fabs(gx), ny = std::fabs(gy);
+  double nrm = nx < ny ? ny : nx;
+  double dx = gx / nrm, dy = gy / nrm;
+  double h = 0.0;
+  bool first = true;
+  for (int32_t j : m.NN[v]) {
+    double hx = std::fabs(m.x[j] - xv), hy = std::fabs(m.y[j] - yv);
+    double hj = hx < hy ? hy : hx;
+    if (first || hj < h) h = hj;
+    first = false;
+  }
+  bool vo;
+  double oldmin = patch_min_q2(m, v, xv, yv, vo);
+  double step = h;
+  for (int k = 1; k <= 4; ++k) {
+    step = step * 0.5;
+    double px = xv + step * dx, py = yv + step * dy;
+    bool vn;
+    double newmin = patch_min_q2(m, v, px, py, vn);
+    if (!vn || !(newmin > oldmin)) continue;
+    m.x[v] = px;
+    m.y[v] = py;
+    return true;
+  }
+  return false;
+}
+
 }  // namespace
 
 struct orc_mesh : Mesh {};
@@ -884,7 +954,7 @@ int32_t orc_smooth(orc_mesh* mp, int32_t sweep, int32_t kind, int32_t sweeps, in
       run_hook(m, PH_SMOOTH, s, c, 0, mem, cls[c]);
       for (int32_t v : mem) {
         st[ORC_EVALUATED] += 1;
-        bool moved = kind == 0 ? smooth_laplace(m, v) : smooth_gradient(m, v);
+        bool moved = kind == 0 ? smooth_laplace(m, v) : (kind == 1 ? smooth_gradient(m, v) : smooth_minmax(m, v));
         st[ORC_COMMITTED] += moved ? 1 : 0;
       }
       run_hook(m, PH_SMOOTH, s, c, 1, mem, cls[c]);

@@ -90,7 +90,8 @@ int32_t orc_coarsen(orc_mesh* m, int32_t sweep, double L_low2, double q_min,
                     int32_t max_rounds, int64_t* stats);
 int32_t orc_refine(orc_mesh* m, double L_up2, int32_t max_passes, int64_t* stats);
 int32_t orc_swap(orc_mesh* m, int32_t sweep, int32_t max_rounds, int64_t* stats);
-/* kind 0 = Laplacian in metric, 1 = gradient of the quality functional */
+/* kind 0 = Laplacian in metric, 1 = gradient of the quality functional,
+ * 2 = min-max: ascent on the patch's worst quality */
 int32_t orc_smooth(orc_mesh* m, int32_t sweep, int32_t kind, int32_t sweeps, int64_t* stats);
 /* stable renumbering of live vertices and elements */
 void orc_compact(orc_mesh* m);

@@ -776,7 +776,8 @@ bool bad_tuning(const pm_tuning& t) {
 bool bad_opts(const pm_options* o) {
   return !(o->L_low2 > 0.0) || !(o->L_up2 > 0.0) || !(o->q_min >= 0.0) || o->coarsen_rounds < 0 ||
          o->swap_rounds < 0 || o->refine_passes < 0 || o->smooth_sweeps < 0 || o->sweep < 0 || o->sweep > 4095 ||
-         (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT) || !(o->slack >= 1.0) ||
+         (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT &&
+          o->smooth_kind != PM_SMOOTH_MINMAX) || !(o->slack >= 1.0) ||
          !(o->pool_headroom == 0.0 || (o->pool_headroom >= 1.0 && o->pool_headroom <= 64.0)) ||
          o->max_iterations < 0 || o->max_iterations > 4095 || o->max_phases < 0 || bad_tuning(o->tune);
 }

@@ -1668,12 +1668,83 @@ __device__ bool smooth_gradient(Store st, int v) {
   return true;
 }
 
+// Min-max: ascent on the patch's smallest quality. The worst element (the
+// smallest q, ties to the first in NE(v)) gives the direction, its gradient
+// in x_v; when the second worst is within 1% (q2 <= 1.01 q1), the point
+// nearest the origin on the segment between the two gradients. Normalised in
+// the max-norm; steps h/2 .. h/16 as in the gradient step; the first step
+// that keeps every area positive and raises the patch minimum of q^2
+// strictly is taken.
+__device__ bool smooth_minmax(Store st, int v) {
+  Hdr h = st.hdr[v];
+  double2 pv = st.xy[v];
+  int i1 = -1, i2 = -1;
+  double q1 = 0.0, q2 = 0.0;
+  for (int i = 0; i < h.w; ++i) {
+    int t = st.ne[h.z + i];
+    double q = qual(patch_elem_geo(st, t, st.tri[t], v, pv));
+    if (i1 < 0 || q < q1) {
+      i2 = i1;
+      q2 = q1;
+      i1 = i;
+      q1 = q;
+    } else if (i2 < 0 || q < q2) {
+      i2 = i;
+      q2 = q;
+    }
+  }
+  if (i1 < 0) return false;
+  int t1 = st.ne[h.z + i1];
+  Elem e1 = st.tri[t1];
+  double ax, ay;
+  qual_grad_x(patch_elem_geo(st, t1, e1, v, pv), slot_of(e1, v), ax, ay);
+  double gx = ax, gy = ay;
+  if (i2 >= 0 && q2 <= q1 * 1.01) {
+    int t2 = st.ne[h.z + i2];
+    Elem e2 = st.tri[t2];
+    double bx, by;
+    qual_grad_x(patch_elem_geo(st, t2, e2, v, pv), slot_of(e2, v), bx, by);
+    double ex = bx - ax, ey = by - ay;
+    double den = ex * ex + ey * ey;
+    if (den > 0.0) {
+      double lam = -(ax * ex + ay * ey) / den;
+      lam = lam < 0.0 ? 0.0 : (lam > 1.0 ? 1.0 : lam);
+      gx = ax + lam * ex;
+      gy = ay + lam * ey;
+    }
+  }
+  if (gx == 0.0 && gy == 0.0) return false;
+  double nx = fabs(gx), ny = fabs(gy);
+  double nrm = nx < ny ? ny : nx;
+  double dx = gx / nrm, dy = gy / nrm;
+  double hh = 0.0;
+  for (int j = 0; j < h.y; ++j) {
+    double2 pw = st.xy[st.nn[h.x + j]];
+    double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
+    double hj = hx < hy ? hy : hx;
+    if (j == 0 || hj < hh) hh = hj;
+  }
+  bool vo;
+  double oldmin = patch_min_q2(st, v, h, pv, vo);
+  double step = hh;
+  for (int k = 0; k < 4; ++k) {
+    step = step * 0.5;
+    double2 p = make_double2(pv.x + step * dx, pv.y + step * dy);
+    bool vn;
+    double newmin = patch_min_q2(st, v, h, p, vn);
+    if (!vn || !(newmin > oldmin)) continue;
+    st.xy[v] = p;
+    return true;
+  }
+  return false;
+}
+
 __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
   int i = xtid();
   int status = -1;
   if (i < n) {
     int v = list[i];
-    bool moved = kind == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v);
+    bool moved = kind == 0 ? smooth_laplace(st, v) : (kind == 1 ? smooth_gradient(st, v) : smooth_minmax(st, v));
     status = moved ? 2 : 1;
   }
   count_status(status, ctr);
@@ -1683,7 +1754,9 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int lanes, hipStream_t s) {
   if (n <= 0) return;
   int nb = (int)(((int64_t)n * kG + kBlock - 1) / kBlock);
-  if (lanes == kG && kind == 0)
+  if (kind == 2)  // min-max: one thread per vertex
+    k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+  else if (lanes == kG && kind == 0)
     k_smooth_g<0><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else if (lanes == kG)
     k_smooth_g<1><<<nb, kBlock, 0, s>>>(st, list, n, ctr);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpmesh.so")
 
 PM_OK, PM_E_ARG, PM_E_MESH, PM_E_NOMEM, PM_E_DEVICE, PM_W_NOT_CONVERGED, PM_W_PAUSED = range(7)
 PM_MEM_HOST, PM_MEM_DEVICE = 0, 1
-PM_SMOOTH_LAPLACE, PM_SMOOTH_GRADIENT = 0, 1
+PM_SMOOTH_LAPLACE, PM_SMOOTH_GRADIENT, PM_SMOOTH_MINMAX = 0, 1, 2
 PM_PHASE_COARSEN, PM_PHASE_SWAP, PM_PHASE_REFINE, PM_PHASE_SMOOTH, PM_PHASE_DONE = 1, 2, 3, 4, 5
 STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_DEVICE", 5: "PM_W_NOT_CONVERGED",
           6: "PM_W_PAUSED"}

@@ -144,6 +144,68 @@ def gradient_decision(P: Patches, v, steps=4):
     return False, xy[v].copy(), margin, 0
 
 
+def _torch_elem_grad(xy, met, row, v):
+    """q of one element and its gradient in x_v (torch float64, matrix form)."""
+    X = torch.tensor(xy, dtype=torch.float64)
+    xv = X[v].clone().requires_grad_(True)
+    Mt = torch.tensor(met, dtype=torch.float64)
+    pts = [xv if w == v else X[w] for w in row]
+    Mm = (Mt[row[0]] + Mt[row[1]] + Mt[row[2]]) / 3.0
+    M = torch.stack([torch.stack([Mm[0], Mm[1]]), torch.stack([Mm[1], Mm[2]])])
+    e = [pts[1] - pts[0], pts[2] - pts[1], pts[0] - pts[2]]
+    S = sum(ei @ M @ ei for ei in e)
+    A = 0.5 * ((pts[1][0] - pts[0][0]) * (pts[2][1] - pts[0][1]) - (pts[2][0] - pts[0][0]) * (pts[1][1] - pts[0][1]))
+    q = 4.0 * np.sqrt(3.0) * torch.sqrt(torch.det(M)) * A / S
+    q.backward()
+    return float(q.detach()), xv.grad.numpy().copy()
+
+
+def minmax_decision(P: Patches, v, steps=4):
+    """Ascent on the patch minimum: the gradient of the worst element's q
+    (ties to the first in ascending element order), or, when the second worst
+    is within 1%, the point nearest the origin on the segment between the two
+    gradients; max-norm normalised; steps h/2 .. h/2^steps; the first step
+    keeping the areas positive and raising the patch minimum strictly wins.
+    Returns (moves, new position, margin)."""
+    xy, met = P.d["xy"], P.d["metric"]
+    rows = P.rows_of(v)
+    qs = checker.mean_ratio(xy, met, rows)
+    order = sorted(range(len(rows)), key=lambda i: (qs[i], P.tid[P.elems[v][i]]))
+    i1 = order[0]
+    margin = 1.0
+    if len(order) > 1:
+        margin = min(margin, _rel(qs[order[1]], qs[i1]))
+    _, g1 = _torch_elem_grad(xy, met, rows[i1].tolist(), v)
+    g = g1
+    if len(order) > 1:
+        i2 = order[1]
+        margin = min(margin, abs(qs[i2] - 1.01 * qs[i1]) / qs[i1])
+        if qs[i2] <= 1.01 * qs[i1]:
+            _, g2 = _torch_elem_grad(xy, met, rows[i2].tolist(), v)
+            e = g2 - g1
+            den = float(e @ e)
+            if den > 0:
+                lam = min(max(-float(g1 @ e) / den, 0.0), 1.0)
+                g = g1 + lam * e
+    if g[0] == 0.0 and g[1] == 0.0:
+        return False, xy[v].copy(), margin
+    dvec = g / np.abs(g).max()
+    h = min(float(np.abs(xy[j] - xy[v]).max()) for j in P.nbrs[v])
+    _, old = _min_q(xy, met, rows)
+    t = h
+    for k in range(1, steps + 1):
+        t = t * 0.5
+        p = xy[v] + t * dvec
+        xy2 = xy.copy()
+        xy2[v] = p
+        D = checker.doubled_areas(xy2, rows)
+        new = float(checker.mean_ratio(xy2, met, rows).min())
+        margin = min(margin, _rel(new, old), float(np.abs(D).min() / max(np.abs(D).max(), 1e-300)))
+        if (D > 0).all() and new > old:
+            return True, p, margin
+    return False, xy[v].copy(), margin
+
+
 # ---- swapping ---------------------------------------------------------------------
 
 def flip_decision(P: Patches, v):

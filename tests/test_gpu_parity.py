@@ -71,7 +71,7 @@ def test_config0_round_then_smooth():
 def test_full_sweeps(name, make, seed):
     mi = make()
     om, gm = both(mi, seed)
-    run_sweeps(om, gm, 2, smooth_kinds=(0, 1))
+    run_sweeps(om, gm, 3, smooth_kinds=(0, 1, 2))
     checker.check_mesh(gm.export(), exact=True, rows=gm.rows())
     compare_quality(om, gm, "end")
 
@@ -103,7 +103,7 @@ def test_kernel_shapes_match(name, make, seed, tune):
     compare_quality(om, gm, "end")
 
 
-@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("lanes", [0, 1])
 def test_smoothing_sweeps_on_jittered_mesh(kind, lanes):
     mi = inputs.config2(129)

@@ -198,11 +198,11 @@ def test_quality_gradient_ascent_with_torch():
     for _ in range(5):
         opt.zero_grad()
         Q = pmesh.QualityFn.apply(xy, met, gm)
-        Q0 = float(Q) if Q0 is None else Q0
+        Q0 = float(Q.detach()) if Q0 is None else Q0
         Q.backward()
         xy.grad.mul_(inner)
         opt.step()
-    Q1 = float(pmesh.QualityFn.apply(xy, met, gm))
+    Q1 = float(pmesh.QualityFn.apply(xy, met, gm).detach())
     assert Q1 > Q0
     checker.check_mesh(gm.export(), exact=False, rows=gm.rows())
 

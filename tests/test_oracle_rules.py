@@ -385,3 +385,34 @@ def test_quality_constant_is_the_double_nearest_4_sqrt_3():
     om = OracleMesh(np.array([[0, 0], [1, 0], [0, 1]], float), np.array([[0, 1, 2]], np.int32),
                     np.tile([1.0, 0.0, 1.0], (3, 1)), np.zeros(3, np.uint8))
     assert om.element_quality()[0] * 8.0 == k
+
+
+@pytest.mark.parametrize("name,make,seed", JITTERED)
+def test_minmax_moves_follow_the_ascent_on_the_worst_element(name, make, seed):
+    """Min-max smoothing: every accepted move is the independent rule's (worst
+    element's gradient, or the segment point for two near-equal worst
+    elements; halving steps; strict rise of the patch minimum), every rejected
+    vertex stays, and the patch minimum rises on every move."""
+    om = OracleMesh.from_input(make(), seed=seed)
+    tally = dict(moved=0, kept=0, skipped=0)
+
+    def check(before, after, mem, whole, rnd):
+        P = ind.Patches(before)
+        for v in mem.tolist():
+            ok, p, margin = ind.minmax_decision(P, v)
+            if margin < 1e-6:
+                tally["skipped"] += 1
+                continue
+            if ok:
+                np.testing.assert_allclose(after["xy"][v], p, rtol=0, atol=POS_ATOL, err_msg=f"vertex {v}")
+                tally["moved"] += 1
+            else:
+                assert np.array_equal(after["xy"][v], before["xy"][v]), f"vertex {v} moved but should not"
+                tally["kept"] += 1
+
+    on_classes(om, PH_SMOOTH, check)
+    q0 = om.quality()[1]
+    st = om.smooth(kind=2, sweeps=2)
+    assert tally["moved"] > 50 and tally["kept"] > 0, tally
+    assert tally["moved"] + tally["kept"] + tally["skipped"] == st["evaluated"]
+    assert om.quality()[1] > q0
