@@ -43,6 +43,8 @@ namespace {
 
 // the double nearest 4*sqrt(3) (4 * RN(sqrt 3) is exact scaling)
 const double K4R3 = 6.928203230275509;
+// the double nearest 12*sqrt(3)
+const double K12R3 = 20.784609690826528;
 const uint8_t TX0 = 1, TX1 = 2, TY0 = 4, TY1 = 8;
 enum { PH_COARSEN = 1, PH_SWAP = 2, PH_SMOOTH = 3 };
 
@@ -64,6 +66,8 @@ struct Mesh {
   // Algorithm 1's loop state: outer iteration, next phase, whether the
   // iteration has changed the mesh so far
   int32_t ad_iter = 0, ad_phase = ORC_PHASE_COARSEN, ad_changed = 0;
+  // element quality functional: ORC_QUALITY_MEAN_RATIO or ORC_QUALITY_VASILEVSKII
+  int32_t qk = ORC_QUALITY_MEAN_RATIO;
 };
 
 // ---- sorted-set rows ---------------------------------------------------------
@@ -216,6 +220,108 @@ void qual_grad_m(const Geo& g, double* da, double* db, double* dc) {
   *dc = (KA * ((g.a * p.S) / (2.0 * s) - s * Syy)) / SS;
 }
 
+// ---- Vasilevskii's functional with its size factor (Sec. 2.2) ---------------
+// Q_V = 12 sqrt(3) |K|_M / P^2 * F(P / 3), P the perimeter in the metric (sum
+// of the three edge lengths in the element metric), |K|_M = sqrt(det M) A, and
+// F(x) = (m (2 - m))^3 with m = min(x, 1/x). Q_V = 1 exactly for the
+// equilateral triangle with unit metric edges; F penalises any other size.
+// Decisions compare Q_V^2 (the product rounded once) with q_min^2, as the mean
+// ratio's decisions compare q^2.
+struct VParts {
+  double A, s, P;
+  double L[3], ex[3], ey[3];
+};
+
+VParts vparts(const Geo& g) {
+  VParts v;
+  v.A = 0.5 * area2(g);
+  for (int k = 0; k < 3; ++k) {
+    int k1 = (k + 1) % 3;
+    v.ex[k] = g.x[k1] - g.x[k];
+    v.ey[k] = g.y[k1] - g.y[k];
+  }
+  for (int k = 0; k < 3; ++k)
+    v.L[k] = std::sqrt(((g.a * v.ex[k]) * v.ex[k] + ((2.0 * g.b) * v.ex[k]) * v.ey[k]) + (g.c * v.ey[k]) * v.ey[k]);
+  v.P = (v.L[0] + v.L[1]) + v.L[2];
+  v.s = std::sqrt(g.a * g.c - g.b * g.b);
+  return v;
+}
+
+// size factor F at x = P / 3 and the derivative of G(P) = F(P/3) / P^2
+void vas_size(double P, double* G, double* dG) {
+  double x = P / 3.0;
+  bool below = x < 1.0;
+  double mm = below ? x : 1.0 / x;
+  double f = mm * (2.0 - mm);
+  double F = (f * f) * f;
+  double dm = below ? 1.0 : -1.0 / (x * x);
+  double dF = ((3.0 * (f * f)) * (2.0 - 2.0 * mm)) * dm;
+  double P2 = P * P;
+  *G = F / P2;
+  *dG = dF / (3.0 * P2) - (2.0 * F) / (P2 * P);
+}
+
+double qual_vas(const Geo& g) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, &G, &dG);
+  return ((K12R3 * v.s) * v.A) * G;
+}
+
+void vas_grad_x(const Geo& g, int k, double* gx, double* gy) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, &G, &dG);
+  int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+  double dAx = 0.5 * (g.y[k1] - g.y[k2]);
+  double dAy = 0.5 * (g.x[k2] - g.x[k1]);
+  // x_k ends edge k-1 and starts edge k: dP/dx_k = M e_{k-1} / L_{k-1} - M e_k / L_k
+  double dPx = (g.a * v.ex[k2] + g.b * v.ey[k2]) / v.L[k2] - (g.a * v.ex[k] + g.b * v.ey[k]) / v.L[k];
+  double dPy = (g.b * v.ex[k2] + g.c * v.ey[k2]) / v.L[k2] - (g.b * v.ex[k] + g.c * v.ey[k]) / v.L[k];
+  double Ks = K12R3 * v.s;
+  *gx = Ks * (dAx * G + (v.A * dG) * dPx);
+  *gy = Ks * (dAy * G + (v.A * dG) * dPy);
+}
+
+void vas_grad_m(const Geo& g, double* da, double* db, double* dc) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, &G, &dG);
+  double Pa = 0.0, Pb = 0.0, Pc = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    Pa = Pa + (v.ex[j] * v.ex[j]) / (2.0 * v.L[j]);
+    Pb = Pb + (v.ex[j] * v.ey[j]) / v.L[j];
+    Pc = Pc + (v.ey[j] * v.ey[j]) / (2.0 * v.L[j]);
+  }
+  double KA = K12R3 * v.A;
+  *da = KA * ((g.c / (2.0 * v.s)) * G + (v.s * dG) * Pa);
+  *db = KA * (-(g.b / v.s) * G + (v.s * dG) * Pb);
+  *dc = KA * ((g.a / (2.0 * v.s)) * G + (v.s * dG) * Pc);
+}
+
+// the handle's functional: value used by decisions (squared), reported value,
+// and its derivatives
+double dq2(const Mesh& m, const Geo& g) {
+  if (m.qk == ORC_QUALITY_VASILEVSKII) {
+    double q = qual_vas(g);
+    return q * q;
+  }
+  return qual2(g);
+}
+double qval(const Mesh& m, const Geo& g) { return m.qk == ORC_QUALITY_VASILEVSKII ? qual_vas(g) : qual(g); }
+void qgrad_x(const Mesh& m, const Geo& g, int k, double* gx, double* gy) {
+  if (m.qk == ORC_QUALITY_VASILEVSKII)
+    vas_grad_x(g, k, gx, gy);
+  else
+    qual_grad_x(g, k, gx, gy);
+}
+void qgrad_m(const Mesh& m, const Geo& g, double* da, double* db, double* dc) {
+  if (m.qk == ORC_QUALITY_VASILEVSKII)
+    vas_grad_m(g, da, db, dc);
+  else
+    qual_grad_m(g, da, db, dc);
+}
+
 int pos_in(const Tri& t, int32_t v) { return t[0] == v ? 0 : (t[1] == v ? 1 : 2); }
 
 // ---- priorities (Sec. 3.2: colouring from random priorities) ----------------
@@ -339,7 +445,7 @@ int32_t eval_collapse(const Mesh& m, int32_t v, double L_low2, double qmin2) {
       r[pos_in(e, v)] = u;
       Tri rc = canon(r[0], r[1], r[2]);
       Geo g = geo(m, rc);
-      if (!(area2(g) > 0.0) || !(qual2(g) >= qmin2)) {
+      if (!(area2(g) > 0.0) || !(dq2(m, g) >= qmin2)) {
         ok = false;
         break;
       }
@@ -404,8 +510,8 @@ bool eval_flip(const Mesh& m, int32_t v, Flip& best) {
     Tri tv = canon(v, b, a), tw = canon(w, a, b);
     Geo gv = geo(m, tv), gw = geo(m, tw);
     if (!(area2(gv) > 0.0) || !(area2(gw) > 0.0)) continue;
-    double qv = qual2(gv), qw = qual2(gw);
-    double q1 = qual2(geo(m, e1)), q2 = qual2(geo(m, e2));
+    double qv = dq2(m, gv), qw = dq2(m, gw);
+    double q1 = dq2(m, geo(m, e1)), q2 = dq2(m, geo(m, e2));
     double nmin = qw < qv ? qw : qv;
     double omin = q2 < q1 ? q2 : q1;
     if (!(nmin > omin)) continue;
@@ -444,7 +550,7 @@ double patch_min_q2(const Mesh& m, int32_t v, double px, double py, bool& valid)
   for (int32_t t : m.NE[v]) {
     Geo g = geo(m, m.tri[t], v, px, py);
     if (!(area2(g) > 0.0)) valid = false;
-    double q2 = qual2(g);
+    double q2 = dq2(m, g);
     if (first || q2 < mn) mn = q2;
     first = false;
   }
@@ -453,7 +559,7 @@ double patch_min_q2(const Mesh& m, int32_t v, double px, double py, bool& valid)
 
 double patch_q(const Mesh& m, int32_t v, double px, double py) {
   double s = 0.0;
-  for (int32_t t : m.NE[v]) s = s + qual(geo(m, m.tri[t], v, px, py));
+  for (int32_t t : m.NE[v]) s = s + qval(m, geo(m, m.tri[t], v, px, py));
   return s;
 }
 
@@ -495,7 +601,7 @@ bool smooth_gradient(Mesh& m, int32_t v) {
   for (int32_t t : m.NE[v]) {
     const Tri& e = m.tri[t];
     double ex, ey;
-    qual_grad_x(geo(m, e), pos_in(e, v), &ex, &ey);
+    qgrad_x(m, geo(m, e), pos_in(e, v), &ex, &ey);
     gx = gx + ex;
     gy = gy + ey;
   }
@@ -544,7 +650,7 @@ bool smooth_minmax(Mesh& m, int32_t v) {
   int32_t t1 = -1, t2 = -1;
   double q1 = 0.0, q2 = 0.0;
   for (int32_t t : m.NE[v]) {
-    double q = qual(geo(m, m.tri[t]));
+    double q = qval(m, geo(m, m.tri[t]));
     if (t1 < 0 || q < q1) {
       t2 = t1;
       q2 = q1;
@@ -557,11 +663,11 @@ bool smooth_minmax(Mesh& m, int32_t v) {
   }
   if (t1 < 0) return false;
   double ax, ay;
-  qual_grad_x(geo(m, m.tri[t1]), pos_in(m.tri[t1], v), &ax, &ay);
+  qgrad_x(m, geo(m, m.tri[t1]), pos_in(m.tri[t1], v), &ax, &ay);
   double gx = ax, gy = ay;
   if (t2 >= 0 && q2 <= q1 * 1.01) {
     double bx, by;
-    qual_grad_x(geo(m, m.tri[t2]), pos_in(m.tri[t2], v), &bx, &by);
+    qgrad_x(m, geo(m, m.tri[t2]), pos_in(m.tri[t2], v), &bx, &by);
     double ex = bx - ax, ey = by - ay;
     double den = ex * ex + ey * ey;
     if (den > 0.0) {
@@ -726,6 +832,11 @@ void orc_set_hook(orc_mesh* m, orc_hook hook, void* user) {
   m->hook_user = user;
 }
 void orc_set_order_seed(orc_mesh* m, uint64_t s) { m->order_seed = s; }
+int32_t orc_set_quality(orc_mesh* m, int32_t kind) {
+  if (kind != ORC_QUALITY_MEAN_RATIO && kind != ORC_QUALITY_VASILEVSKII) return -1;
+  m->qk = kind;
+  return 0;
+}
 int64_t orc_class_members(const orc_mesh* m, int32_t* out, int64_t cap) {
   int64_t n = (int64_t)m->cur_members.size();
   for (int64_t i = 0; i < n && i < cap; ++i) out[i] = m->cur_members[i];
@@ -980,6 +1091,7 @@ void orc_compact(orc_mesh* mp) {
   out.ad_iter = m.ad_iter;
   out.ad_phase = m.ad_phase;
   out.ad_changed = m.ad_changed;
+  out.qk = m.qk;
   out.V = nv;
   for (int64_t v = 0; v < m.V; ++v) {
     if (!m.valive[v]) continue;
@@ -1007,7 +1119,7 @@ void orc_quality(const orc_mesh* m, double* Q, double* qmin, double* dQdx, doubl
   bool first = true;
   for (int64_t t = 0; t < m->T; ++t) {
     if (!m->talive[t]) continue;
-    double q = qual(geo(*m, m->tri[t]));
+    double q = qval(*m, geo(*m, m->tri[t]));
     s = s + q;
     if (first || q < mn) mn = q;
     first = false;
@@ -1021,8 +1133,8 @@ void orc_quality(const orc_mesh* m, double* Q, double* qmin, double* dQdx, doubl
       const Tri& e = m->tri[t];
       Geo g = geo(*m, e);
       double ex, ey, da, db, dc;
-      qual_grad_x(g, pos_in(e, (int32_t)v), &ex, &ey);
-      qual_grad_m(g, &da, &db, &dc);
+      qgrad_x(*m, g, pos_in(e, (int32_t)v), &ex, &ey);
+      qgrad_m(*m, g, &da, &db, &dc);
       gx = gx + ex;
       gy = gy + ey;
       ga = ga + da / 3.0;
@@ -1042,7 +1154,7 @@ void orc_quality(const orc_mesh* m, double* Q, double* qmin, double* dQdx, doubl
 }
 
 void orc_element_quality(const orc_mesh* m, double* q) {
-  for (int64_t t = 0; t < m->T; ++t) q[t] = m->talive[t] ? qual(geo(*m, m->tri[t])) : 0.0;
+  for (int64_t t = 0; t < m->T; ++t) q[t] = m->talive[t] ? qval(*m, geo(*m, m->tri[t])) : 0.0;
 }
 
 double orc_patch_quality(const orc_mesh* m, int32_t v) { return patch_q(*m, v, m->x[v], m->y[v]); }

@@ -30,6 +30,11 @@ extern "C" {
 
 typedef struct orc_mesh orc_mesh;
 
+/* element quality functionals (Sec. 2.2): the mean ratio
+ * q = 4 sqrt(3) sqrt(det M) A / sum of squared metric edge lengths, and
+ * Vasilevskii's functional with its size factor */
+enum { ORC_QUALITY_MEAN_RATIO = 0, ORC_QUALITY_VASILEVSKII = 1 };
+
 /* Algorithm 1's phases (loop state of orc_adapt) */
 enum { ORC_PHASE_COARSEN = 1, ORC_PHASE_SWAP = 2, ORC_PHASE_REFINE = 3, ORC_PHASE_SMOOTH = 4, ORC_PHASE_DONE = 5 };
 
@@ -53,6 +58,9 @@ enum {
 orc_mesh* orc_create(int64_t V, int64_t T, const double* xy, const int32_t* tri,
                      const double* metric, const uint8_t* tags, uint64_t seed);
 void orc_destroy(orc_mesh* m);
+/* the functional every decision, smoothing step and orc_quality uses (the
+ * mean ratio by default); returns -1 for an unknown kind */
+int32_t orc_set_quality(orc_mesh* m, int32_t kind);
 /* slot counts (dead slots included until compaction) */
 void orc_sizes(const orc_mesh* m, int64_t* V, int64_t* T);
 /* raw export of all slots; any pointer may be NULL */

@@ -19,6 +19,7 @@ STAT_NAMES = ["rounds", "coloured", "evaluated", "deferred", "committed", "colou
               "edges", "converged", "new_vertices", "new_elements"]
 PH_COARSEN, PH_SWAP, PH_SMOOTH = 1, 2, 3
 PHASE_COARSEN, PHASE_SWAP, PHASE_REFINE, PHASE_SMOOTH, PHASE_DONE = 1, 2, 3, 4, 5
+QUALITY_MEAN_RATIO, QUALITY_VASILEVSKII = 0, 1
 
 _lib = None
 
@@ -50,6 +51,8 @@ def lib():
         L.orc_colour.argtypes = [P, P, C.c_uint32, P]
         L.orc_set_hook.argtypes = [P, HOOK, P]
         L.orc_set_order_seed.argtypes = [P, C.c_uint64]
+        L.orc_set_quality.restype = C.c_int32
+        L.orc_set_quality.argtypes = [P, C.c_int32]
         L.orc_class_members.restype = C.c_int64
         L.orc_class_members.argtypes = [P, P, C.c_int64]
         L.orc_class_whole.restype = C.c_int64
@@ -95,7 +98,7 @@ def ctx_of(sweep: int, phase: int, rnd: int) -> int:
 class OracleMesh:
     """One mesh held by the oracle."""
 
-    def __init__(self, xy, tri, metric, tags=None, seed: int = 0):
+    def __init__(self, xy, tri, metric, tags=None, seed: int = 0, quality: int = QUALITY_MEAN_RATIO):
         xy = np.ascontiguousarray(xy, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         metric = np.ascontiguousarray(metric, dtype=np.float64)
@@ -104,10 +107,13 @@ class OracleMesh:
         if not self.h:
             raise ValueError("oracle rejected the mesh")
         self._hook_ref = None
+        self._hook_exc = None
+        if lib().orc_set_quality(self.h, quality) != 0:
+            raise ValueError(f"unknown quality functional {quality}")
 
     @classmethod
-    def from_input(cls, mi, seed: int = 0):
-        return cls(mi.xy, mi.tri, mi.metric, mi.tags, seed)
+    def from_input(cls, mi, seed: int = 0, quality: int = QUALITY_MEAN_RATIO):
+        return cls(mi.xy, mi.tri, mi.metric, mi.tags, seed, quality)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -152,9 +158,27 @@ class OracleMesh:
             self._hook_ref = None
             lib().orc_set_hook(self.h, HOOK(0), None)
             return
-        cb = HOOK(lambda user, ph, r, c, st: fn(ph, r, c, st))
+        # an exception cannot cross the C frames: the first one is kept, later
+        # calls are skipped, and the phase call raises it when it returns
+        self._hook_exc = None
+
+        def call(user, ph, r, c, st):
+            if self._hook_exc is not None:
+                return
+            try:
+                fn(ph, r, c, st)
+            except BaseException as e:  # noqa: BLE001 - re-raised by _raise_hook
+                self._hook_exc = e
+
+        cb = HOOK(call)
         self._hook_ref = cb
         lib().orc_set_hook(self.h, cb, None)
+
+    def _raise_hook(self):
+        e = getattr(self, "_hook_exc", None)
+        if e is not None:
+            self._hook_exc = None
+            raise e
 
     def class_members(self):
         n = lib().orc_class_members(self.h, None, 0)
@@ -186,6 +210,7 @@ class OracleMesh:
     def coarsen(self, sweep=0, L_low2=0.5, q_min=0.1, max_rounds=200):
         st = np.zeros(NSTATS, np.int64)
         rc = lib().orc_coarsen(self.h, sweep, L_low2, q_min, max_rounds, _p(st))
+        self._raise_hook()
         if rc < 0:
             raise RuntimeError(f"oracle coarsen failed: {rc}")
         return self._stats(st)
@@ -193,6 +218,7 @@ class OracleMesh:
     def refine(self, L_up2=2.0, max_passes=32):
         st = np.zeros(NSTATS, np.int64)
         rc = lib().orc_refine(self.h, L_up2, max_passes, _p(st))
+        self._raise_hook()
         if rc < 0:
             raise RuntimeError(f"oracle refine failed: {rc}")
         return self._stats(st)
@@ -200,6 +226,7 @@ class OracleMesh:
     def swap(self, sweep=0, max_rounds=100):
         st = np.zeros(NSTATS, np.int64)
         rc = lib().orc_swap(self.h, sweep, max_rounds, _p(st))
+        self._raise_hook()
         if rc < 0:
             raise RuntimeError(f"oracle swap failed: {rc}")
         return self._stats(st)
@@ -207,6 +234,7 @@ class OracleMesh:
     def smooth(self, sweep=0, kind=0, sweeps=1):
         st = np.zeros(NSTATS, np.int64)
         rc = lib().orc_smooth(self.h, sweep, kind, sweeps, _p(st))
+        self._raise_hook()
         if rc < 0:
             raise RuntimeError(f"oracle smooth failed: {rc}")
         return self._stats(st)
@@ -239,6 +267,7 @@ class OracleMesh:
         st = np.zeros(NSTATS, np.int64)
         rc = lib().orc_adapt(self.h, max_iterations, max_phases, smooth_kind, smooth_sweeps, L_low2, L_up2, q_min,
                              coarsen_rounds, swap_rounds, refine_passes, _p(st))
+        self._raise_hook()
         if rc < 0:
             raise RuntimeError(f"oracle adapt failed: {rc}")
         return self._stats(st), rc == 0

@@ -151,6 +151,34 @@ def metric_len2(xy, met, a, b):
     return M[:, 0] * e[:, 0] ** 2 + 2 * M[:, 1] * e[:, 0] * e[:, 1] + M[:, 2] * e[:, 1] ** 2
 
 
+def size_factor(x):
+    """(m (2 - m))^3 with m = min(x, 1/x): 1 at x = 1, below 1 elsewhere."""
+    m = np.minimum(x, 1.0 / x)
+    return (m * (2.0 - m)) ** 3
+
+
+def vasilevskii(xy, met, tri):
+    """Vasilevskii's functional 12 sqrt(3) |K|_M / P^2 * F(P / 3), computed
+    from the three metric edge lengths alone: |K|_M by Heron's formula, P
+    their sum (M the element's mean tensor, constant over the element)."""
+    M = (met[tri[:, 0]] + met[tri[:, 1]] + met[tri[:, 2]]) / 3.0
+    Mm = np.stack([np.stack([M[:, 0], M[:, 1]], -1), np.stack([M[:, 1], M[:, 2]], -1)], -2)
+    P = xy[tri]
+    L = []
+    for i, j in ((0, 1), (1, 2), (2, 0)):
+        e = P[:, j] - P[:, i]
+        L.append(np.sqrt(np.einsum("ni,nij,nj->n", e, Mm, e)))
+    a, b, c = L
+    per = a + b + c
+    area = 0.25 * np.sqrt(np.maximum(per * (b + c - a) * (a - b + c) * (a + b - c), 0.0))
+    return 12.0 * np.sqrt(3.0) * area / per ** 2 * size_factor(per / 3.0)
+
+
+def quality(xy, met, tri, kind=0):
+    """The element functional: 0 the mean ratio, 1 Vasilevskii's."""
+    return vasilevskii(xy, met, tri) if kind == 1 else mean_ratio(xy, met, tri)
+
+
 def mean_ratio(xy, met, tri):
     """4 sqrt(3) sqrt(det M) A / sum_e e^T M e with M the element's mean tensor."""
     M = (met[tri[:, 0]] + met[tri[:, 1]] + met[tri[:, 2]]) / 3.0

@@ -35,8 +35,9 @@ class Patches:
     """Elements and neighbours around each vertex of a snapshot (rebuilt with
     numpy from the live element list)."""
 
-    def __init__(self, d):
+    def __init__(self, d, kind=0):
         self.d = d
+        self.kind = kind  # element functional: 0 mean ratio, 1 Vasilevskii
         tri, tid = live_tri(d)
         self.tri = tri
         self.tid = tid
@@ -51,9 +52,27 @@ class Patches:
         return self.tri[self.elems[v]]
 
 
-def _min_q(xy, met, rows):
+def _min_q(xy, met, rows, kind=0):
     D = checker.doubled_areas(xy, rows)
-    return bool((D > 0).all()), float(checker.mean_ratio(xy, met, rows).min())
+    return bool((D > 0).all()), float(checker.quality(xy, met, rows, kind).min())
+
+
+def _torch_q(pts, Mm, kind):
+    """The element functional in torch float64 from its corner points and
+    mean tensor: the mean ratio in matrix form, or Vasilevskii's from the
+    metric edge lengths with Heron's formula."""
+    M = torch.stack([torch.stack([Mm[0], Mm[1]]), torch.stack([Mm[1], Mm[2]])])
+    e = [pts[1] - pts[0], pts[2] - pts[1], pts[0] - pts[2]]
+    if kind == 1:
+        a, b, c = (torch.sqrt(ei @ M @ ei) for ei in e)
+        per = a + b + c
+        area = 0.25 * torch.sqrt(per * (b + c - a) * (a - b + c) * (a + b - c))
+        x = per / 3.0
+        m = torch.minimum(x, 1.0 / x)
+        return 12.0 * np.sqrt(3.0) * area / per ** 2 * (m * (2.0 - m)) ** 3
+    S = sum(ei @ M @ ei for ei in e)
+    A = 0.5 * ((pts[1][0] - pts[0][0]) * (pts[2][1] - pts[0][1]) - (pts[2][0] - pts[0][0]) * (pts[1][1] - pts[0][1]))
+    return 4.0 * np.sqrt(3.0) * torch.sqrt(torch.det(M)) * A / S
 
 
 def _rel(a, b):
@@ -81,18 +100,18 @@ def laplace_decision(P: Patches, v):
     xy, met = P.d["xy"], P.d["metric"]
     rows = P.rows_of(v)
     p = laplace_target(P, v)
-    _, old = _min_q(xy, met, rows)
+    _, old = _min_q(xy, met, rows, P.kind)
     xy2 = xy.copy()
     xy2[v] = p
     D = checker.doubled_areas(xy2, rows)
-    new = float(checker.mean_ratio(xy2, met, rows).min())
+    new = float(checker.quality(xy2, met, rows, P.kind).min())
     margin = min(_rel(new, old), float(np.abs(D).min() / max(np.abs(D).max(), 1e-300)))
     ok = bool((D > 0).all()) and new >= old
     return ok, p, margin
 
 
-def _torch_patch_q(xy, met, rows, v):
-    """Q_v as a function of x_v (torch float64), matrix form."""
+def _torch_patch_q(xy, met, rows, v, kind=0):
+    """Q_v as a function of x_v (torch float64)."""
     X = torch.tensor(xy, dtype=torch.float64)
     xv = X[v].clone().requires_grad_(True)
     Mt = torch.tensor(met, dtype=torch.float64)
@@ -100,16 +119,12 @@ def _torch_patch_q(xy, met, rows, v):
     for row in rows.tolist():
         pts = [xv if w == v else X[w] for w in row]
         Mm = (Mt[row[0]] + Mt[row[1]] + Mt[row[2]]) / 3.0
-        M = torch.stack([torch.stack([Mm[0], Mm[1]]), torch.stack([Mm[1], Mm[2]])])
-        e = [pts[1] - pts[0], pts[2] - pts[1], pts[0] - pts[2]]
-        S = sum(ei @ M @ ei for ei in e)
-        A = 0.5 * ((pts[1][0] - pts[0][0]) * (pts[2][1] - pts[0][1]) - (pts[2][0] - pts[0][0]) * (pts[1][1] - pts[0][1]))
-        total = total + 4.0 * np.sqrt(3.0) * torch.sqrt(torch.det(M)) * A / S
+        total = total + _torch_q(pts, Mm, kind)
     return total, xv
 
 
 def patch_gradient(P: Patches, v):
-    total, xv = _torch_patch_q(P.d["xy"], P.d["metric"], P.rows_of(v), v)
+    total, xv = _torch_patch_q(P.d["xy"], P.d["metric"], P.rows_of(v), v, P.kind)
     total.backward()
     return xv.grad.numpy().copy(), float(total.detach())
 
@@ -126,7 +141,7 @@ def gradient_decision(P: Patches, v, steps=4):
         return False, xy[v].copy(), 1.0, 0
     dvec = g / np.abs(g).max()
     h = min(float(np.abs(xy[j] - xy[v]).max()) for j in P.nbrs[v])
-    _, old = _min_q(xy, met, rows)
+    _, old = _min_q(xy, met, rows, P.kind)
     margin = 1.0
     t = h
     for k in range(1, steps + 1):
@@ -135,8 +150,8 @@ def gradient_decision(P: Patches, v, steps=4):
         xy2 = xy.copy()
         xy2[v] = p
         D = checker.doubled_areas(xy2, rows)
-        new = float(checker.mean_ratio(xy2, met, rows).min())
-        Qp = float(checker.mean_ratio(xy2, met, rows).sum())
+        new = float(checker.quality(xy2, met, rows, P.kind).min())
+        Qp = float(checker.quality(xy2, met, rows, P.kind).sum())
         margin = min(margin, _rel(new, old), _rel(Qp, Q0),
                      float(np.abs(D).min() / max(np.abs(D).max(), 1e-300)))
         if (D > 0).all() and new >= old and Qp > Q0:
@@ -144,18 +159,14 @@ def gradient_decision(P: Patches, v, steps=4):
     return False, xy[v].copy(), margin, 0
 
 
-def _torch_elem_grad(xy, met, row, v):
-    """q of one element and its gradient in x_v (torch float64, matrix form)."""
+def _torch_elem_grad(xy, met, row, v, kind=0):
+    """q of one element and its gradient in x_v (torch float64)."""
     X = torch.tensor(xy, dtype=torch.float64)
     xv = X[v].clone().requires_grad_(True)
     Mt = torch.tensor(met, dtype=torch.float64)
     pts = [xv if w == v else X[w] for w in row]
     Mm = (Mt[row[0]] + Mt[row[1]] + Mt[row[2]]) / 3.0
-    M = torch.stack([torch.stack([Mm[0], Mm[1]]), torch.stack([Mm[1], Mm[2]])])
-    e = [pts[1] - pts[0], pts[2] - pts[1], pts[0] - pts[2]]
-    S = sum(ei @ M @ ei for ei in e)
-    A = 0.5 * ((pts[1][0] - pts[0][0]) * (pts[2][1] - pts[0][1]) - (pts[2][0] - pts[0][0]) * (pts[1][1] - pts[0][1]))
-    q = 4.0 * np.sqrt(3.0) * torch.sqrt(torch.det(M)) * A / S
+    q = _torch_q(pts, Mm, kind)
     q.backward()
     return float(q.detach()), xv.grad.numpy().copy()
 
@@ -169,19 +180,19 @@ def minmax_decision(P: Patches, v, steps=4):
     Returns (moves, new position, margin)."""
     xy, met = P.d["xy"], P.d["metric"]
     rows = P.rows_of(v)
-    qs = checker.mean_ratio(xy, met, rows)
+    qs = checker.quality(xy, met, rows, P.kind)
     order = sorted(range(len(rows)), key=lambda i: (qs[i], P.tid[P.elems[v][i]]))
     i1 = order[0]
     margin = 1.0
     if len(order) > 1:
         margin = min(margin, _rel(qs[order[1]], qs[i1]))
-    _, g1 = _torch_elem_grad(xy, met, rows[i1].tolist(), v)
+    _, g1 = _torch_elem_grad(xy, met, rows[i1].tolist(), v, P.kind)
     g = g1
     if len(order) > 1:
         i2 = order[1]
         margin = min(margin, abs(qs[i2] - 1.01 * qs[i1]) / qs[i1])
         if qs[i2] <= 1.01 * qs[i1]:
-            _, g2 = _torch_elem_grad(xy, met, rows[i2].tolist(), v)
+            _, g2 = _torch_elem_grad(xy, met, rows[i2].tolist(), v, P.kind)
             e = g2 - g1
             den = float(e @ e)
             if den > 0:
@@ -191,7 +202,7 @@ def minmax_decision(P: Patches, v, steps=4):
         return False, xy[v].copy(), margin
     dvec = g / np.abs(g).max()
     h = min(float(np.abs(xy[j] - xy[v]).max()) for j in P.nbrs[v])
-    _, old = _min_q(xy, met, rows)
+    _, old = _min_q(xy, met, rows, P.kind)
     t = h
     for k in range(1, steps + 1):
         t = t * 0.5
@@ -199,7 +210,7 @@ def minmax_decision(P: Patches, v, steps=4):
         xy2 = xy.copy()
         xy2[v] = p
         D = checker.doubled_areas(xy2, rows)
-        new = float(checker.mean_ratio(xy2, met, rows).min())
+        new = float(checker.quality(xy2, met, rows, P.kind).min())
         margin = min(margin, _rel(new, old), float(np.abs(D).min() / max(np.abs(D).max(), 1e-300)))
         if (D > 0).all() and new > old:
             return True, p, margin
@@ -214,7 +225,7 @@ def flip_decision(P: Patches, v):
     element list)."""
     xy, met = P.d["xy"], P.d["metric"]
     tri = P.tri
-    q = checker.mean_ratio(xy, met, tri[P.elems[v]]) if P.elems[v] else []
+    q = checker.quality(xy, met, tri[P.elems[v]], P.kind) if P.elems[v] else []
     qd = dict(zip(P.elems[v], q))
     cands = []
     margin = 1.0
@@ -237,7 +248,7 @@ def flip_decision(P: Patches, v):
         margin = min(margin, float(np.abs(D).min() / max(np.abs(D).max(), 1e-300)))
         if not (D > 0).all():
             continue
-        nmin = float(checker.mean_ratio(xy, met, new).min())
+        nmin = float(checker.quality(xy, met, new, P.kind).min())
         omin = min(qd[t1], qd[t2])
         margin = min(margin, _rel(nmin, omin))
         if nmin > omin:
