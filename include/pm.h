@@ -46,6 +46,18 @@ typedef enum {
 } pm_status;
 
 enum { PM_MEM_HOST = 0, PM_MEM_DEVICE = 1 };
+/* Element quality functionals (Sec. 2.2), both 1 exactly for the equilateral
+ * triangle with unit edges in the metric, computed with the element's tensor
+ * M = the mean of its three vertex tensors and A its Euclidean area:
+ *  PM_QUALITY_MEAN_RATIO: q = 4 sqrt(3) sqrt(det M) A / (sum of the squared
+ *    metric edge lengths); invariant under M -> cM, so it measures shape only;
+ *  PM_QUALITY_VASILEVSKII: Vasilevskii's functional with its size factor,
+ *    Q = 12 sqrt(3) sqrt(det M) A / P^2 * F(P / 3), P the metric perimeter,
+ *    F(x) = (m (2 - m))^3 with m = min(x, 1/x).
+ * Decisions compare the square of the value (q^2, or Q * Q rounded once) with
+ * q_min^2. */
+enum { PM_QUALITY_MEAN_RATIO = 0, PM_QUALITY_VASILEVSKII = 1 };
+
 /* smoothing kinds: the Laplacian in the metric; a gradient step on the patch's
  * quality sum; min-max, an ascent step on the patch's worst quality */
 enum { PM_SMOOTH_LAPLACE = 0, PM_SMOOTH_GRADIENT = 1, PM_SMOOTH_MINMAX = 2 };
@@ -97,7 +109,8 @@ typedef struct {
  * L_low2 = 0.5, L_up2 = 2.0, q_min = 0.1, seed = 0, sweep = 0,
  * coarsen_rounds = 200, swap_rounds = 100, refine_passes = 32,
  * smooth_kind = PM_SMOOTH_LAPLACE, smooth_sweeps = 1, slack = 2.0,
- * pool_headroom = 3.0, max_iterations = 8, max_phases = 0, tune = zeros. */
+ * pool_headroom = 3.0, max_iterations = 8, max_phases = 0, tune = zeros,
+ * quality = PM_QUALITY_MEAN_RATIO. */
 typedef struct {
   double L_low2;          /* collapse an edge when L^2 < L_low2                 */
   double L_up2;           /* split an edge when L^2 > L_up2                     */
@@ -121,6 +134,10 @@ typedef struct {
   int32_t max_phases;     /* pm_adapt: phases to run in this call before
                              returning at a resume point; 0 = no limit          */
   pm_tuning tune;         /* kernel shapes                                      */
+  int32_t quality;        /* element functional of every decision and of
+                             pm_quality, fixed at creation: PM_QUALITY_MEAN_RATIO
+                             or PM_QUALITY_VASILEVSKII                          */
+  int32_t reserved;       /* 0                                                  */
 } pm_options;
 
 /* Per-phase counters, all integers:

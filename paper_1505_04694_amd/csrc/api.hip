@@ -779,7 +779,8 @@ bool bad_opts(const pm_options* o) {
          (o->smooth_kind != PM_SMOOTH_LAPLACE && o->smooth_kind != PM_SMOOTH_GRADIENT &&
           o->smooth_kind != PM_SMOOTH_MINMAX) || !(o->slack >= 1.0) ||
          !(o->pool_headroom == 0.0 || (o->pool_headroom >= 1.0 && o->pool_headroom <= 64.0)) ||
-         o->max_iterations < 0 || o->max_iterations > 4095 || o->max_phases < 0 || bad_tuning(o->tune);
+         o->max_iterations < 0 || o->max_iterations > 4095 || o->max_phases < 0 || bad_tuning(o->tune) ||
+         (o->quality != PM_QUALITY_MEAN_RATIO && o->quality != PM_QUALITY_VASILEVSKII) || o->reserved != 0;
 }
 
 // Collapse runs on groups of lanes per member by default: each lane loads
@@ -1176,6 +1177,8 @@ void fill_defaults(pm_options* o) {
   o->max_iterations = 8;
   o->max_phases = 0;
   o->tune = pm_tuning{};
+  o->quality = PM_QUALITY_MEAN_RATIO;
+  o->reserved = 0;
 }
 
 }  // namespace
@@ -1259,6 +1262,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   m->seed = o->seed;
   m->slack = o->slack;
   m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
+  m->st.qk = o->quality;
   g_create_err.clear();
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
@@ -1817,6 +1821,7 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   m->seed = o->seed;
   m->slack = o->slack;
   m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
+  m->st.qk = o->quality;
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
     pm_mesh_destroy(m);

@@ -34,6 +34,7 @@ typedef int4 Hdr;
 
 constexpr int kWave = 64;
 constexpr double kK4R3 = 6.928203230275509;  // the double nearest 4 sqrt(3)
+constexpr double kK12R3 = 20.784609690826528;  // the double nearest 12 sqrt(3)
 
 // ---- metric geometry (Sec. 2.2) ---------------------------------------------
 
@@ -140,6 +141,115 @@ __device__ __forceinline__ void qual_grad_m(const Geo& g, double& da, double& db
   da = (KA * ((g.c * p.S) / (2.0 * s) - s * Sxx)) / SS;
   db = (KA * (-(g.b * p.S) / s - (2.0 * s) * Sxy)) / SS;
   dc = (KA * ((g.a * p.S) / (2.0 * s) - s * Syy)) / SS;
+}
+
+// ---- Vasilevskii's functional with its size factor (Sec. 2.2) ---------------------
+// Q_V = 12 sqrt(3) sqrt(det M) A / P^2 * F(P / 3), P the sum of the three metric
+// edge lengths, F(x) = (m (2 - m))^3 with m = min(x, 1/x): 1 exactly for the
+// equilateral triangle with unit metric edges. Decisions compare Q_V^2 (the
+// product rounded once) with q_min^2, as the mean ratio's compare q^2.
+
+struct VParts {
+  double A, s, P;
+  double L[3], ex[3], ey[3];
+};
+
+__device__ __forceinline__ VParts vparts(const Geo& g) {
+  VParts v;
+  v.A = 0.5 * area2(g);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int k1 = k == 2 ? 0 : k + 1;
+    v.ex[k] = g.x[k1] - g.x[k];
+    v.ey[k] = g.y[k1] - g.y[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+    v.L[k] = sqrt(((g.a * v.ex[k]) * v.ex[k] + ((2.0 * g.b) * v.ex[k]) * v.ey[k]) + (g.c * v.ey[k]) * v.ey[k]);
+  v.P = (v.L[0] + v.L[1]) + v.L[2];
+  v.s = sqrt(g.a * g.c - g.b * g.b);
+  return v;
+}
+
+// G(P) = F(P / 3) / P^2 and dG/dP
+__device__ __forceinline__ void vas_size(double P, double& G, double& dG) {
+  double x = P / 3.0;
+  bool below = x < 1.0;
+  double mm = below ? x : 1.0 / x;
+  double f = mm * (2.0 - mm);
+  double F = (f * f) * f;
+  double dm = below ? 1.0 : -1.0 / (x * x);
+  double dF = ((3.0 * (f * f)) * (2.0 - 2.0 * mm)) * dm;
+  double P2 = P * P;
+  G = F / P2;
+  dG = dF / (3.0 * P2) - (2.0 * F) / (P2 * P);
+}
+
+__device__ __forceinline__ double vas_q(const Geo& g) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, G, dG);
+  return ((kK12R3 * v.s) * v.A) * G;
+}
+
+__device__ __forceinline__ void vas_grad_x(const Geo& g, int k, double& gx, double& gy) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, G, dG);
+  double x1 = sel3(g.x[1], g.x[2], g.x[0], k), x2 = sel3(g.x[2], g.x[0], g.x[1], k);
+  double y1 = sel3(g.y[1], g.y[2], g.y[0], k), y2 = sel3(g.y[2], g.y[0], g.y[1], k);
+  double exk = sel3(v.ex[0], v.ex[1], v.ex[2], k), exm = sel3(v.ex[2], v.ex[0], v.ex[1], k);
+  double eyk = sel3(v.ey[0], v.ey[1], v.ey[2], k), eym = sel3(v.ey[2], v.ey[0], v.ey[1], k);
+  double Lk = sel3(v.L[0], v.L[1], v.L[2], k), Lm = sel3(v.L[2], v.L[0], v.L[1], k);
+  double dAx = 0.5 * (y1 - y2);
+  double dAy = 0.5 * (x2 - x1);
+  // x_k ends edge k-1 and starts edge k: dP/dx_k = M e_{k-1} / L_{k-1} - M e_k / L_k
+  double dPx = (g.a * exm + g.b * eym) / Lm - (g.a * exk + g.b * eyk) / Lk;
+  double dPy = (g.b * exm + g.c * eym) / Lm - (g.b * exk + g.c * eyk) / Lk;
+  double Ks = kK12R3 * v.s;
+  gx = Ks * (dAx * G + (v.A * dG) * dPx);
+  gy = Ks * (dAy * G + (v.A * dG) * dPy);
+}
+
+__device__ __forceinline__ void vas_grad_m(const Geo& g, double& da, double& db, double& dc) {
+  VParts v = vparts(g);
+  double G, dG;
+  vas_size(v.P, G, dG);
+  double Pa = 0.0, Pb = 0.0, Pc = 0.0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    Pa = Pa + (v.ex[j] * v.ex[j]) / (2.0 * v.L[j]);
+    Pb = Pb + (v.ex[j] * v.ey[j]) / v.L[j];
+    Pc = Pc + (v.ey[j] * v.ey[j]) / (2.0 * v.L[j]);
+  }
+  double KA = kK12R3 * v.A;
+  da = KA * ((g.c / (2.0 * v.s)) * G + (v.s * dG) * Pa);
+  db = KA * (-(g.b / v.s) * G + (v.s * dG) * Pb);
+  dc = KA * ((g.a / (2.0 * v.s)) * G + (v.s * dG) * Pc);
+}
+
+// The element functional a handle was created with (qk: 0 the mean ratio,
+// 1 Vasilevskii's): the squared value every decision compares, the reported
+// value, and its derivatives.
+__device__ __forceinline__ double qd2(const Geo& g, int qk) {
+  if (qk) {
+    double q = vas_q(g);
+    return q * q;
+  }
+  return qual2(g);
+}
+__device__ __forceinline__ double qval(const Geo& g, int qk) { return qk ? vas_q(g) : qual(g); }
+__device__ __forceinline__ void qgrad_x(const Geo& g, int k, int qk, double& gx, double& gy) {
+  if (qk)
+    vas_grad_x(g, k, gx, gy);
+  else
+    qual_grad_x(g, k, gx, gy);
+}
+__device__ __forceinline__ void qgrad_m(const Geo& g, int qk, double& da, double& db, double& dc) {
+  if (qk)
+    vas_grad_m(g, da, db, dc);
+  else
+    qual_grad_m(g, da, db, dc);
 }
 
 // ---- ids ----------------------------------------------------------------------

@@ -132,6 +132,9 @@ struct Store {
   // V: coordinates, metric and tag per vertex in one line, valid while
   // vertices stay fixed (coarsening and swapping rounds); may be null
   VRec* vr = nullptr;
+  // element functional of every decision and of the quality outputs:
+  // 0 the mean ratio, 1 Vasilevskii's with its size factor
+  int qk = 0;
 };
 
 // local id of a vertex within its mesh (priorities are drawn per mesh)

@@ -716,7 +716,7 @@ __device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs
       int k = slot_of(e, v);
       int3 r = rot_min(k == 0 ? bU : e.x, k == 1 ? bU : e.y, k == 2 ? bU : e.z);
       Geo g = geo_of(st, r);
-      if (!(area2(g) > 0.0) || !(qual2(g) >= a.qmin2)) ok = false;
+      if (!(area2(g) > 0.0) || !(qd2(g, st.qk) >= a.qmin2)) ok = false;
     }
     if (ok) {
       u = bU;
@@ -746,7 +746,9 @@ __device__ __forceinline__ int collapse_one(const Store& st, int v, const OpArgs
   return 2;
 }
 
+template <int QK>
 __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   if (room_failed(ctr)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
@@ -754,18 +756,20 @@ __global__ void k_collapse(Store st, const int* __restrict__ list, int n, OpArgs
   if (i < n) status = collapse_one(st, list[i], a, cm, ctr);
   count_status(status, ctr, true);
 }
-template <int G>
+template <int G, int QK>
 __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr);
 void collapse_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, int lanes,
                     hipStream_t s) {
   if (n <= 0) return;
   if (lanes == 16)
-    k_collapse_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    (st.qk ? k_collapse_g<16, 1> : k_collapse_g<16, 0>)<<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        st, list, n, a, cm, ctr);
   else if (lanes == 8)
-    k_collapse_g<8><<<(int)(((int64_t)n * 8 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    (st.qk ? k_collapse_g<8, 1> : k_collapse_g<8, 0>)<<<(int)(((int64_t)n * 8 + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        st, list, n, a, cm, ctr);
   else
-    k_collapse<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    (st.qk ? k_collapse<1> : k_collapse<0>)<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
 
 // ---- swapping (Sec. 2.4.3) ------------------------------------------------------------------
@@ -804,8 +808,8 @@ __device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a,
     Geo gv = geo_of(st, rot_min(v, bv, av));
     Geo gw = geo_of(st, rot_min(w, av, bv));
     if (!(area2(gv) > 0.0) || !(area2(gw) > 0.0)) continue;
-    double qv = qual2(gv), qw = qual2(gw);
-    double q1 = qual2(geo_of(st, e1)), q2 = qual2(geo_of(st, e2));
+    double qv = qd2(gv, st.qk), qw = qd2(gw, st.qk);
+    double q1 = qd2(geo_of(st, e1), st.qk), q2 = qd2(geo_of(st, e2), st.qk);
     double nmin = qw < qv ? qw : qv;
     double omin = q2 < q1 ? q2 : q1;
     if (!(nmin > omin)) continue;
@@ -833,7 +837,9 @@ __device__ __forceinline__ int flip_one(const Store& st, int v, const OpArgs& a,
   return 2;
 }
 
+template <int QK>
 __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   if (room_failed(ctr)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
   int i = xtid();
@@ -842,7 +848,7 @@ __global__ void k_flip(Store st, const int* __restrict__ list, int n, OpArgs a, 
   count_status(status, ctr, true);
 }
 void flip_class(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
-  if (n > 0) k_flip<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+  if (n > 0) (st.qk ? k_flip<1> : k_flip<0>)<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
 
 // ---- deferred update: commit ------------------------------------------------------------------
@@ -1525,7 +1531,7 @@ __device__ double patch_min_q2(const Store& st, int v, Hdr h, double2 p, bool& v
     Elem e = st.tri[t];
     Geo g = patch_elem_geo(st, t, e, v, p);
     if (!(area2(g) > 0.0)) valid = false;
-    double q2 = qual2(g);
+    double q2 = qd2(g, st.qk);
     if (first || q2 < mn) mn = q2;
     first = false;
   }
@@ -1537,7 +1543,7 @@ __device__ double patch_q(const Store& st, int v, Hdr h, double2 p) {
   for (int i = 0; i < h.w; ++i) {
     int t = st.ne[h.z + i];
     Elem e = st.tri[t];
-    s = s + qual(patch_elem_geo(st, t, e, v, p));
+    s = s + qval(patch_elem_geo(st, t, e, v, p), st.qk);
   }
   return s;
 }
@@ -1583,9 +1589,9 @@ __device__ bool smooth_laplace(Store st, int v) {
     gn.y[1] = k == 1 ? p.y : go.y[1];
     gn.x[2] = k == 2 ? p.x : go.x[2];
     gn.y[2] = k == 2 ? p.y : go.y[2];
-    run_min(qual2(go), i == 0, oldmin);
+    run_min(qd2(go, st.qk), i == 0, oldmin);
     if (!(area2(gn) > 0.0)) vn = false;
-    run_min(qual2(gn), i == 0, newmin);
+    run_min(qd2(gn, st.qk), i == 0, newmin);
   }
   if (vn && newmin >= oldmin) {
     st.xy[v] = p;
@@ -1616,11 +1622,11 @@ __device__ bool smooth_gradient(Store st, int v) {
     Elem e = st.tri[t];
     Geo g = patch_elem_geo(st, t, e, v, pv);
     double ex, ey;
-    qual_grad_x(g, slot_of(e, v), ex, ey);
+    qgrad_x(g, slot_of(e, v), st.qk, ex, ey);
     gx = gx + ex;
     gy = gy + ey;
-    Qold = Qold + qual(g);
-    run_min(qual2(g), i == 0, oldmin);
+    Qold = Qold + qval(g, st.qk);
+    run_min(qd2(g, st.qk), i == 0, oldmin);
   }
   if (gx == 0.0 && gy == 0.0) return false;
   double ax = fabs(gx), ay = fabs(gy);
@@ -1652,8 +1658,8 @@ __device__ bool smooth_gradient(Store st, int v) {
     for (int k = 0; k < 4; ++k) {
       Geo gk = moved(g, sl, p[k]);
       if (!(area2(gk) > 0.0)) ok[k] = false;
-      run_min(qual2(gk), i == 0, mn[k]);
-      Q[k] = Q[k] + qual(gk);
+      run_min(qd2(gk, st.qk), i == 0, mn[k]);
+      Q[k] = Q[k] + qval(gk, st.qk);
     }
   }
   int pick = -1;
@@ -1682,7 +1688,7 @@ __device__ bool smooth_minmax(Store st, int v) {
   double q1 = 0.0, q2 = 0.0;
   for (int i = 0; i < h.w; ++i) {
     int t = st.ne[h.z + i];
-    double q = qual(patch_elem_geo(st, t, st.tri[t], v, pv));
+    double q = qval(patch_elem_geo(st, t, st.tri[t], v, pv), st.qk);
     if (i1 < 0 || q < q1) {
       i2 = i1;
       q2 = q1;
@@ -1697,13 +1703,13 @@ __device__ bool smooth_minmax(Store st, int v) {
   int t1 = st.ne[h.z + i1];
   Elem e1 = st.tri[t1];
   double ax, ay;
-  qual_grad_x(patch_elem_geo(st, t1, e1, v, pv), slot_of(e1, v), ax, ay);
+  qgrad_x(patch_elem_geo(st, t1, e1, v, pv), slot_of(e1, v), st.qk, ax, ay);
   double gx = ax, gy = ay;
   if (i2 >= 0 && q2 <= q1 * 1.01) {
     int t2 = st.ne[h.z + i2];
     Elem e2 = st.tri[t2];
     double bx, by;
-    qual_grad_x(patch_elem_geo(st, t2, e2, v, pv), slot_of(e2, v), bx, by);
+    qgrad_x(patch_elem_geo(st, t2, e2, v, pv), slot_of(e2, v), st.qk, bx, by);
     double ex = bx - ax, ey = by - ay;
     double den = ex * ex + ey * ey;
     if (den > 0.0) {
@@ -1739,7 +1745,9 @@ __device__ bool smooth_minmax(Store st, int v) {
   return false;
 }
 
+template <int QK>
 __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   int i = xtid();
   int status = -1;
   if (i < n) {
@@ -1749,19 +1757,19 @@ __global__ void k_smooth(Store st, const int* __restrict__ list, int n, int kind
   }
   count_status(status, ctr);
 }
-template <int K>
+template <int K, int QK>
 __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int* ctr);
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int lanes, hipStream_t s) {
   if (n <= 0) return;
   int nb = (int)(((int64_t)n * kG + kBlock - 1) / kBlock);
   if (kind == 2)  // min-max: one thread per vertex
-    k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+    (st.qk ? k_smooth<1> : k_smooth<0>)<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
   else if (lanes == kG && kind == 0)
-    k_smooth_g<0><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
+    (st.qk ? k_smooth_g<0, 1> : k_smooth_g<0, 0>)<<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else if (lanes == kG)
-    k_smooth_g<1><<<nb, kBlock, 0, s>>>(st, list, n, ctr);
+    (st.qk ? k_smooth_g<1, 1> : k_smooth_g<1, 0>)<<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else
-    k_smooth<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+    (st.qk ? k_smooth<1> : k_smooth<0>)<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
 }
 
 // ---- lane groups: 8 lanes per vertex ----------------------------------------------------------
@@ -1864,20 +1872,20 @@ __device__ __forceinline__ Geo patch_geo(const PatchElem& pe, double2 p) {
 
 // patch minimum of q^2 and validity with the vertex at p (lanes j < nw own elements)
 __device__ __forceinline__ double gpatch_min(const PatchElem& pe, bool own, double2 p, int nw, const Grp& g,
-                                             bool& valid) {
+                                             int qk, bool& valid) {
   double q2 = 0.0;
   bool bad = false;
   if (own) {
     Geo gg = patch_geo(pe, p);
     bad = !(area2(gg) > 0.0);
-    q2 = qual2(gg);
+    q2 = qd2(gg, qk);
   }
   valid = !gany(bad, g);
   return gmin(q2, nw, g);
 }
 
-__device__ __forceinline__ double gpatch_q(const PatchElem& pe, bool own, double2 p, int nw, const Grp& g) {
-  double q = own ? qual(patch_geo(pe, p)) : 0.0;
+__device__ __forceinline__ double gpatch_q(const PatchElem& pe, bool own, double2 p, int nw, const Grp& g, int qk) {
+  double q = own ? qval(patch_geo(pe, p), qk) : 0.0;
   return gsum(q, nw, g);
 }
 
@@ -1925,12 +1933,12 @@ __device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, 
     double det = Ga * Gc - Gb * Gb;
     p = make_double2(pv.x + (Gc * rx - Gb * ry) / det, pv.y + (Ga * ry - Gb * rx) / det);
     bool vo, vn;
-    double oldmin = gpatch_min(pe, owne, pv, h.w, g, vo);
-    double newmin = gpatch_min(pe, owne, p, h.w, g, vn);
+    double oldmin = gpatch_min(pe, owne, pv, h.w, g, st.qk, vo);
+    double newmin = gpatch_min(pe, owne, p, h.w, g, st.qk, vn);
     if (!(vn && newmin >= oldmin)) return false;
   } else {
     double ex = 0.0, ey = 0.0;
-    if (owne) qual_grad_x(patch_geo(pe, pv), pe.k, ex, ey);
+    if (owne) qgrad_x(patch_geo(pe, pv), pe.k, st.qk, ex, ey);
     double gx = 0.0, gy = 0.0;
 #pragma unroll
     for (int k = 0; k < kG; ++k) {
@@ -1948,17 +1956,17 @@ __device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, 
     double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
     double hh = gmin(hx < hy ? hy : hx, h.y, g);
     bool vo;
-    double oldmin = gpatch_min(pe, owne, pv, h.w, g, vo);
-    double Qold = gpatch_q(pe, owne, pv, h.w, g);
+    double oldmin = gpatch_min(pe, owne, pv, h.w, g, st.qk, vo);
+    double Qold = gpatch_q(pe, owne, pv, h.w, g, st.qk);
     double step = hh;
     bool ok = false;
     for (int k = 1; k <= 4 && !ok; ++k) {
       step = step * 0.5;
       p = make_double2(pv.x + step * dx, pv.y + step * dy);
       bool vn;
-      double newmin = gpatch_min(pe, owne, p, h.w, g, vn);
+      double newmin = gpatch_min(pe, owne, p, h.w, g, st.qk, vn);
       if (!vn || !(newmin >= oldmin)) continue;
-      if (!(gpatch_q(pe, owne, p, h.w, g) > Qold)) continue;
+      if (!(gpatch_q(pe, owne, p, h.w, g, st.qk) > Qold)) continue;
       ok = true;
     }
     if (!ok) return false;
@@ -1969,8 +1977,9 @@ __device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, 
 
 // one kernel per smoothing kind (K = 0 plain, 1 gradient), each with its own
 // register allocation
-template <int K>
+template <int K, int QK>
 __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __restrict__ list, int n, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   Grp g = grp();
   int gid = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   int status = -1;
@@ -1986,8 +1995,10 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
   }
   count_status(status, ctr);
 }
-template __global__ void k_smooth_g<0>(Store, const int*, int, int*);
-template __global__ void k_smooth_g<1>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<0, 0>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<0, 1>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<1, 0>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<1, 1>(Store, const int*, int, int*);
 
 // ---- collapse with lane groups -----------------------------------------------------------------
 // G lanes per member (G = kGC): small classes are made of the vertices that
@@ -2091,7 +2102,7 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
       Met d1 = r == 0 ? n0 : (r == 1 ? n1 : mu);
       Met d2 = r == 0 ? n1 : (r == 1 ? mu : n0);
       Geo gg = make_geo(c0, c1, c2, d0, d1, d2);
-      bad = !(area2(gg) > 0.0) || !(qual2(gg) >= a.qmin2);
+      bad = !(area2(gg) > 0.0) || !(qd2(gg, st.qk) >= a.qmin2);
     }
     if (!gany_of<G>(bad, g)) {
       u = bU;
@@ -2121,9 +2132,10 @@ __device__ __forceinline__ int collapse_group(const Store& st, int v, Hdr h, con
   return 2;
 }
 
-template <int G>
+template <int G, int QK>
 __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                     Commit cm, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   if (room_failed(ctr)) return;
   Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
@@ -2141,8 +2153,10 @@ __global__ void __launch_bounds__(256, 5) k_collapse_g(Store st, const int* __re
   }
   count_status(status, ctr, true);
 }
-template __global__ void k_collapse_g<8>(Store, const int*, int, OpArgs, Commit, int*);
-template __global__ void k_collapse_g<16>(Store, const int*, int, OpArgs, Commit, int*);
+template __global__ void k_collapse_g<8, 0>(Store, const int*, int, OpArgs, Commit, int*);
+template __global__ void k_collapse_g<8, 1>(Store, const int*, int, OpArgs, Commit, int*);
+template __global__ void k_collapse_g<16, 0>(Store, const int*, int, OpArgs, Commit, int*);
+template __global__ void k_collapse_g<16, 1>(Store, const int*, int, OpArgs, Commit, int*);
 
 // ---- flips with lane groups -----------------------------------------------------------------------
 // Lane j owns the member's j-th element T1 = (v, w, a) (cyclic from v): the
@@ -2193,7 +2207,7 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
     Met n0 = k1 == 0 ? mv : (k1 == 1 ? ma : mw);
     Met n1 = k1 == 1 ? mv : (k1 == 2 ? ma : mw);
     Met n2 = k1 == 2 ? mv : (k1 == 0 ? ma : mw);
-    q1 = qual2(make_geo(s0, s1, s2, n0, n1, n2));
+    q1 = qd2(make_geo(s0, s1, s2, n0, n1, n2), st.qk);
   }
   // the lane whose element has w before v holds T2
   int j2 = -1;
@@ -2231,7 +2245,7 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
     if (!(area2(gv) > 0.0) || !(area2(gw) > 0.0)) {
       cand = false;
     } else {
-      double qv = qual2(gv), qw = qual2(gw);
+      double qv = qd2(gv, st.qk), qw = qd2(gw, st.qk);
       nmin = qw < qv ? qw : qv;
       double omin = q2 < q1 ? q2 : q1;
       cand = nmin > omin;
@@ -2269,9 +2283,10 @@ __device__ __forceinline__ int flip_group(const Store& st, int v, Hdr h, const O
   return 2;
 }
 
-template <int G>
+template <int G, int QK>
 __global__ void __launch_bounds__(256) k_flip_g(Store st, const int* __restrict__ list, int n, OpArgs a, Commit cm,
                                                 int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   if (room_failed(ctr)) return;
   Grp g = grp_of<G>();
   if (blockIdx.x == 0 && threadIdx.x == 0) ctr[C_STAGE] = 0;  // the commit's fallback staging
@@ -2290,7 +2305,8 @@ __global__ void __launch_bounds__(256) k_flip_g(Store st, const int* __restrict_
   count_status(status, ctr, true);
 }
 void flip_class_g(const Store& st, const int* list, int n, OpArgs a, Commit cm, int* ctr, hipStream_t s) {
-  if (n > 0) k_flip_g<16><<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+  if (n > 0) (st.qk ? k_flip_g<16, 1> : k_flip_g<16, 0>)<<<(int)(((int64_t)n * 16 + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      st, list, n, a, cm, ctr);
 }
 
 // A small class in one block: the operation (collapse or flips on groups of
@@ -2322,9 +2338,10 @@ __device__ __forceinline__ void class_body(const Store& st, const int* __restric
 }
 
 // one small class, one launch instead of two
-template <bool F>
+template <bool F, int QK>
 __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __restrict__ list, int n, OpArgs a,
                                                      Commit cm, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   __shared__ CommitLds L;
   if (room_failed_block(ctr)) return;
   class_body<F>(st, list, n, a, cm, ctr, L);
@@ -2332,18 +2349,19 @@ __global__ void __launch_bounds__(256) k_class_small(Store st, const int* __rest
 void class_small(const Store& st, const int* list, int n, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
   if (n <= 0) return;
   if (kind)
-    k_class_small<true><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    (st.qk ? k_class_small<true, 1> : k_class_small<true, 0>)<<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
   else
-    k_class_small<false><<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
+    (st.qk ? k_class_small<false, 1> : k_class_small<false, 0>)<<<1, kBlock, 0, s>>>(st, list, n, a, cm, ctr);
 }
 
 // Every class of a round in one block, one after the other (a round whose
 // classes are all small): class c takes epoch cm.epoch + c and its size and
 // offset from the colouring's counters. One launch per round instead of one
 // per class, and the block's caches stay warm from class to class.
-template <bool F>
+template <bool F, int QK>
 __global__ void __launch_bounds__(256) k_round_small(Store st, const int* __restrict__ cls, int ncol, OpArgs a,
                                                      Commit cm, int* ctr) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   __shared__ CommitLds L;
   int epoch0 = cm.epoch;
   bool dev = ncol < 0;
@@ -2373,13 +2391,15 @@ __global__ void __launch_bounds__(256) k_round_small(Store st, const int* __rest
 void round_small(const Store& st, const int* cls, int ncol, OpArgs a, Commit cm, int kind, int* ctr, hipStream_t s) {
   if (ncol == 0) return;
   if (kind)
-    k_round_small<true><<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
+    (st.qk ? k_round_small<true, 1> : k_round_small<true, 0>)<<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
   else
-    k_round_small<false><<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
+    (st.qk ? k_round_small<false, 1> : k_round_small<false, 0>)<<<1, kBlock, 0, s>>>(st, cls, ncol, a, cm, ctr);
 }
 
 // ---- adjoint with lane groups ---------------------------------------------------------------------
+template <int QK>
 __global__ void __launch_bounds__(256) k_adjoint_g(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   Grp g = grp();
   int v = (int)(((int64_t)xcd_block() * blockDim.x + threadIdx.x) / kG);
   if (v >= st.V) return;
@@ -2391,8 +2411,8 @@ __global__ void __launch_bounds__(256) k_adjoint_g(Store st, double* __restrict_
     if (g.j < nw) {
       Elem e = st.tri[st.ne[h.z + c0 + g.j]];
       Geo gg = geo_of(st, e);
-      qual_grad_x(gg, slot_of(e, v), ex, ey);
-      qual_grad_m(gg, da, db, dc);
+      qgrad_x(gg, slot_of(e, v), st.qk, ex, ey);
+      qgrad_m(gg, st.qk, da, db, dc);
       da = da / 3.0;
       db = db / 3.0;
       dc = dc / 3.0;
@@ -2426,13 +2446,15 @@ __global__ void __launch_bounds__(256) k_adjoint_g(Store st, double* __restrict_
 // ---- quality functional and adjoint (Sec. 2.2) --------------------------------------------------
 constexpr int QB = 256;
 
+template <int QK>
 __global__ void k_quality(Store st, double* __restrict__ psum, double* __restrict__ pmin) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   __shared__ double ls[QB], lm[QB];
   double s = 0.0, mn = INFINITY;
   for (int t = gtid(); t < st.T; t += gstride()) {
     Elem e = st.tri[t];
     if (!e.w) continue;
-    double q = qual(geo_of(st, e));
+    double q = qval(geo_of(st, e), st.qk);
     s = s + q;
     mn = q < mn ? q : mn;
   }
@@ -2477,7 +2499,9 @@ __global__ void k_quality_final(const double* __restrict__ psum, const double* _
   }
 }
 // one block per mesh of a batch: Q and qmin of each mesh's element range
+template <int QK>
 __global__ void k_quality_mesh(Store st, double* __restrict__ out) {
+  st.qk = QK;  // the functional as a constant: one instantiation per kind
   __shared__ double ls[QB], lm[QB];
   int i = blockIdx.x;
   int lo = st.tbase[i], hi = st.tbase[i] + st.tused[i];
@@ -2485,7 +2509,7 @@ __global__ void k_quality_mesh(Store st, double* __restrict__ out) {
   for (int t = lo + (int)threadIdx.x; t < hi; t += QB) {
     Elem e = st.tri[t];
     if (!e.w) continue;
-    double q = qual(geo_of(st, e));
+    double q = qval(geo_of(st, e), st.qk);
     s = s + q;
     mn = q < mn ? q : mn;
   }
@@ -2506,44 +2530,17 @@ __global__ void k_quality_mesh(Store st, double* __restrict__ out) {
   }
 }
 void quality_per_mesh(const Store& st, double* out, hipStream_t s) {
-  k_quality_mesh<<<st.B, QB, 0, s>>>(st, out);
+  (st.qk ? k_quality_mesh<1> : k_quality_mesh<0>)<<<st.B, QB, 0, s>>>(st, out);
 }
 
 void quality_sum(const Store& st, double* psum, double* pmin, int nparts, double* out2, hipStream_t s) {
-  k_quality<<<nparts, QB, 0, s>>>(st, psum, pmin);
+  (st.qk ? k_quality<1> : k_quality<0>)<<<nparts, QB, 0, s>>>(st, psum, pmin);
   k_quality_final<<<1, QB, 0, s>>>(psum, pmin, nparts, out2);
 }
 
-// per vertex, summed over NE(v) in ascending element id: no floating-point atomics
-__global__ void k_adjoint(Store st, double* __restrict__ dQdx, double* __restrict__ dQdM) {
-  for (int v = xtid(); v < st.V; v += gstride()) {
-    Hdr h = st.hdr[v];
-    double gx = 0.0, gy = 0.0, ga = 0.0, gb = 0.0, gc = 0.0;
-    for (int i = 0; i < h.w; ++i) {
-      Elem e = st.tri[st.ne[h.z + i]];
-      Geo g = geo_of(st, e);
-      double ex, ey, da, db, dc;
-      qual_grad_x(g, slot_of(e, v), ex, ey);
-      qual_grad_m(g, da, db, dc);
-      gx = gx + ex;
-      gy = gy + ey;
-      ga = ga + da / 3.0;
-      gb = gb + db / 3.0;
-      gc = gc + dc / 3.0;
-    }
-    if (dQdx) {
-      dQdx[2 * v] = gx;
-      dQdx[2 * v + 1] = gy;
-    }
-    if (dQdM) {
-      dQdM[3 * v] = ga;
-      dQdM[3 * v + 1] = gb;
-      dQdM[3 * v + 2] = gc;
-    }
-  }
-}
 void quality_adjoint(const Store& st, double* dQdx, double* dQdM, hipStream_t s) {
-  k_adjoint_g<<<(int)(((int64_t)st.V * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(st, dQdx, dQdM);
+  (st.qk ? k_adjoint_g<1> : k_adjoint_g<0>)<<<(int)(((int64_t)st.V * kG + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      st, dQdx, dQdM);
 }
 
 __global__ void k_fp64_probe(const double* __restrict__ a, const double* __restrict__ b, int n,

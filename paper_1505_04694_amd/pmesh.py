@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpmesh.so")
 PM_OK, PM_E_ARG, PM_E_MESH, PM_E_NOMEM, PM_E_DEVICE, PM_W_NOT_CONVERGED, PM_W_PAUSED = range(7)
 PM_MEM_HOST, PM_MEM_DEVICE = 0, 1
 PM_SMOOTH_LAPLACE, PM_SMOOTH_GRADIENT, PM_SMOOTH_MINMAX = 0, 1, 2
+PM_QUALITY_MEAN_RATIO, PM_QUALITY_VASILEVSKII = 0, 1
 PM_PHASE_COARSEN, PM_PHASE_SWAP, PM_PHASE_REFINE, PM_PHASE_SMOOTH, PM_PHASE_DONE = 1, 2, 3, 4, 5
 STATUS = {0: "PM_OK", 1: "PM_E_ARG", 2: "PM_E_MESH", 3: "PM_E_NOMEM", 4: "PM_E_DEVICE", 5: "PM_W_NOT_CONVERGED",
           6: "PM_W_PAUSED"}
@@ -63,7 +64,7 @@ class Options(C.Structure):
                 ("sweep", C.c_int32), ("coarsen_rounds", C.c_int32), ("swap_rounds", C.c_int32),
                 ("refine_passes", C.c_int32), ("smooth_kind", C.c_int32), ("smooth_sweeps", C.c_int32),
                 ("slack", C.c_double), ("pool_headroom", C.c_double), ("max_iterations", C.c_int32),
-                ("max_phases", C.c_int32), ("tune", Tuning)]
+                ("max_phases", C.c_int32), ("tune", Tuning), ("quality", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Context(C.Structure):
@@ -414,10 +415,11 @@ class Mesh:
     """Owning wrapper around a pm_mesh handle."""
 
     def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
-                 pool_headroom: float = 3.0):
+                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO):
         self.tune = dict(tune or {})
         self.h = pm_mesh_create(xy, tri, metric, tags,
-                                pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom), stream)
+                                pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom,
+                                                   quality=quality), stream)
 
     @classmethod
     def from_input(cls, mi, seed: int = 0, **kw):
@@ -495,10 +497,10 @@ class Batch(Mesh):
     """A batch of independent meshes adapted by the same kernel launches."""
 
     def __init__(self, meshes, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
-                 pool_headroom: float = 3.0):
+                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO):
         self.tune = dict(tune or {})
-        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom),
-                                 stream)
+        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom,
+                                                            quality=quality), stream)
 
     @classmethod
     def from_inputs(cls, mis, seed: int = 0, **kw):

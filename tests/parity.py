@@ -58,8 +58,9 @@ def compare_quality(om, gm, where, grad=True):
     return Qo, qmo
 
 
-def both(mi, seed):
-    return OracleMesh.from_input(mi, seed=seed), pmesh.Mesh.from_input(mi, seed=seed)
+def both(mi, seed, quality=0, **kw):
+    return (OracleMesh.from_input(mi, seed=seed, quality=quality),
+            pmesh.Mesh.from_input(mi, seed=seed, quality=quality, **kw))
 
 
 def run_sweeps(om, gm, sweeps, smooth_kinds=(0,), rows=True, log=None):

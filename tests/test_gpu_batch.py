@@ -56,6 +56,24 @@ def test_batch_equals_solo_oracle_runs(count, nmax):
         checker.check_mesh(gb.export_mesh(i), exact=True)
 
 
+def test_vasilevskii_batch_equals_solo_oracle_runs():
+    mis = small_batch(6, nmax=33)
+    vas = pmesh.PM_QUALITY_VASILEVSKII
+    gb = pmesh.Batch.from_inputs(mis, seed=2, quality=vas)
+    oms = [OracleMesh.from_input(mi, seed=2, quality=vas) for mi in mis]
+    for s in range(2):
+        so = [om.sweep(s, smooth_kind=2 - s) for om in oms]
+        sg = gb.sweep(s, smooth_kind=2 - s)
+        for ph in ("coarsen", "refine", "swap", "smooth"):
+            assert sum(x[ph]["committed"] for x in so) == sg[ph]["committed"], f"sweep {s} {ph}"
+        for i, om in enumerate(oms):
+            compare_one(om.export(), gb.export_mesh(i), f"sweep {s} mesh {i}")
+    Qg, qg = gb.quality_per_mesh()
+    for i, om in enumerate(oms):
+        Q, q = om.quality()
+        assert abs(Q - Qg[i]) <= 1e-12 * abs(Q) and q == qg[i]
+
+
 def test_batch_equals_plain_gpu_runs_on_uneven_sizes():
     mis = [inputs.make_mesh(n, amp=0.15, width=0.04, ht=0.08) for n in (17, 90, 33, 129, 20)]
     gb = pmesh.Batch.from_inputs(mis, seed=2)

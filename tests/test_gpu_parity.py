@@ -114,6 +114,36 @@ def test_smoothing_sweeps_on_jittered_mesh(kind, lanes):
     compare_quality(om, gm, "after smoothing")
 
 
+# Vasilevskii's functional (Sec. 2.2): every decision, both smoothers, min-max
+# and the adjoint read it
+VAS = [SMALL[1], SMALL[3], SMALL[5]]
+
+
+@pytest.mark.parametrize("name,make,seed", VAS)
+def test_vasilevskii_quality_and_adjoint(name, make, seed):
+    om, gm = both(make(), seed, quality=pmesh.PM_QUALITY_VASILEVSKII)
+    compare_quality(om, gm, "initial")
+
+
+@pytest.mark.parametrize("name,make,seed", VAS)
+def test_vasilevskii_full_sweeps(name, make, seed):
+    om, gm = both(make(), seed, quality=pmesh.PM_QUALITY_VASILEVSKII)
+    run_sweeps(om, gm, 3, smooth_kinds=(0, 1, 2))
+    checker.check_mesh(gm.export(), exact=True, rows=gm.rows())
+    compare_quality(om, gm, "end")
+
+
+@pytest.mark.parametrize("lanes", [0, 1])
+def test_vasilevskii_smoothing_lanes(lanes):
+    mi = inputs.config2(129)
+    om, gm = both(mi, 1, quality=pmesh.PM_QUALITY_VASILEVSKII)
+    gm.tune = dict(smooth_lanes=lanes, op_lanes=[16, 1][lanes])
+    for kind in (0, 1, 2):
+        compare_stats(om.smooth(0, kind, 2), gm.smooth(0, kind, 2), f"smooth kind {kind}")
+        compare_mesh(om, gm, f"smooth kind {kind}", rows=False)
+    compare_quality(om, gm, "after smoothing")
+
+
 def test_invalid_meshes_are_rejected():
     xy = np.array([[0, 0], [1, 0], [0, 1]], float)
     met = np.tile([1.0, 0, 1.0], (3, 1))
