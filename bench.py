@@ -335,6 +335,36 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
     m.close()
 
 
+def smooth_compare(n=2049, sweeps=10, seed=1):
+    """The 2049^2 jittered two-layer input smoothed by `sweeps` sweeps of each
+    smoother on a fresh handle (no topology change): device time, moves, and
+    the final minimum and mean element quality of each."""
+    import torch
+    from paper_1505_04694_amd import inputs, pmesh
+    torch.cuda.set_device(0)
+    mi = inputs.config2(n)
+    out = {}
+    for kind, name in ((pmesh.PM_SMOOTH_LAPLACE, "plain"), (pmesh.PM_SMOOTH_GRADIENT, "gradient"),
+                       (pmesh.PM_SMOOTH_MINMAX, "minmax")):
+        m = pmesh.Mesh(mi.xy, mi.tri, mi.metric, mi.tags, seed=seed)
+        Q0, q0 = m.quality()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = m.smooth(0, kind, sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Q, q = m.quality()
+        T = m.sizes()[1]
+        out[name] = {"ms": dt * 1e3, "ms_per_sweep": dt * 1e3 / sweeps, "moves": st["committed"],
+                     "evaluated": st["evaluated"], "min_quality": q, "mean_quality": Q / T,
+                     "start_min_quality": q0, "start_mean_quality": Q0 / T}
+        m.close()
+        log(f"{name}: {out[name]}")
+    print(json.dumps({"workload": f"{n}x{n} grid, interior jitter 0.2h (seed 1), two-layer metric, priority "
+                                  f"seed {seed}; {sweeps} smoothing sweeps per smoother, each on a fresh handle",
+                      "vertices": mi.V, "triangles": mi.T, "smoothers": out}), flush=True)
+
+
 # ---- rocprofv3 summaries ---------------------------------------------------------------
 
 def _csvs(d, suffix):
@@ -448,6 +478,8 @@ def main():
                     help="instead: the 4097x4097 workload, two sweeps with gradient smoothing, peak device memory")
     ap.add_argument("--psi", type=int, metavar="STEPS", default=0,
                     help="instead: the paper's time-varying psi benchmark for STEPS time steps")
+    ap.add_argument("--smooth-compare", type=int, metavar="SWEEPS", default=0,
+                    help="instead: SWEEPS plain, gradient and min-max smoothing sweeps on the 2049x2049 input")
     ap.add_argument("--summarise-trace", metavar="DIR")
     ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "summary"))
@@ -468,6 +500,9 @@ def main():
         return
     if a.psi:
         psi_run(a.psi)
+        return
+    if a.smooth_compare:
+        smooth_compare(sweeps=a.smooth_compare)
         return
 
     import torch

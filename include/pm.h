@@ -75,7 +75,8 @@ typedef struct {
 
 /* Kernel shapes. Every choice gives bit-identical results (the tests check
  * this); they trade occupancy, latency and launch count against each other,
- * and pm_autotune picks them by measurement. Zero means the default. */
+ * and the package's autotuner (autotune.py) picks them by measurement.
+ * Zero means the default. */
 typedef struct {
   int32_t op_lanes;      /* lanes per member in collapse and flip classes: 0 = 16;
                             1 (one thread per member), 8 or 16                   */
