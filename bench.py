@@ -85,9 +85,11 @@ def op_count(trace):
 
 
 def sources_sha():
+    """Hash of the device code: the kernel sources and the headers they
+    include (the host-side api.hip launches kernels but defines none)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1505_04694_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for name in ("common.hpp", "kern.hpp", "ops.hip", "store.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1505_04694_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 

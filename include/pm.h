@@ -29,6 +29,7 @@
  */
 #ifndef PMESH_PM_H
 #define PMESH_PM_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -106,12 +107,29 @@ typedef struct {
   int32_t reserved;      /* 0 */
 } pm_tuning;
 
+/* Device memory provider for a handle (optional: pm_options.allocator, read
+ * at creation). Every device buffer the handle holds comes from
+ * alloc(bytes, stream, user) and goes back through release(ptr, bytes,
+ * stream, user) with the byte count it was allocated with; both are called
+ * from the calling host thread with the handle's stream. Releases are stream
+ * ordered: work already queued on the stream may still use a released block,
+ * so the provider may hand it out again only to later work on that stream
+ * (the semantics of stream-ordered caching allocators such as torch's). alloc
+ * returns NULL when it cannot serve a request, and the call then fails with
+ * PM_E_NOMEM. The provider must outlive the handle. Without one, the library
+ * keeps its own stream-ordered block cache over hipMalloc. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*release)(void* ptr, size_t bytes, void* stream, void* user);
+  void* user;
+} pm_allocator;
+
 /* Thresholds are squared metric lengths. Defaults (pm_default_options):
  * L_low2 = 0.5, L_up2 = 2.0, q_min = 0.1, seed = 0, sweep = 0,
  * coarsen_rounds = 200, swap_rounds = 100, refine_passes = 32,
  * smooth_kind = PM_SMOOTH_LAPLACE, smooth_sweeps = 1, slack = 2.0,
  * pool_headroom = 3.0, max_iterations = 8, max_phases = 0, tune = zeros,
- * quality = PM_QUALITY_MEAN_RATIO. */
+ * quality = PM_QUALITY_MEAN_RATIO, allocator = NULL. */
 typedef struct {
   double L_low2;          /* collapse an edge when L^2 < L_low2                 */
   double L_up2;           /* split an edge when L^2 > L_up2                     */
@@ -139,6 +157,8 @@ typedef struct {
                              pm_quality, fixed at creation: PM_QUALITY_MEAN_RATIO
                              or PM_QUALITY_VASILEVSKII                          */
   int32_t reserved;       /* 0                                                  */
+  const pm_allocator* allocator; /* device memory provider, at creation; NULL =
+                                    the library's own block cache             */
 } pm_options;
 
 /* Per-phase counters, all integers:

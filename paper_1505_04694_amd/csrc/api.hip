@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -92,6 +93,10 @@ struct pm_mesh {
   // the iteration has changed the mesh
   int ad_iter = 0, ad_phase = 1, ad_changed = 0;
   int64_t peak_bytes = 0, cur_bytes = 0;
+  // caller's device memory provider (pm_options.allocator at creation), and
+  // the byte count of each block it handed out
+  pm_allocator va{};
+  std::unordered_map<void*, size_t> va_live;
   int jp_last = 8;    // JP iterations the last colouring took
   int class_seq = 0;  // class-list calls so far (the wide-colour flag's value)
   // elements change only in coarsening, refinement and swapping: each call
@@ -199,10 +204,17 @@ template <class T>
 pm_status dalloc(pm_mesh* m, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  hipError_t e = cache_get(m->s, (void**)p, n * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  if (m->va.alloc) {
+    void* q = m->va.alloc(n * sizeof(T), (void*)m->s, m->va.user);
+    if (!q) return fail(m, PM_E_NOMEM, "the caller's allocator refused " + std::to_string(n * sizeof(T)) + " bytes");
+    m->va_live[q] = n * sizeof(T);
+    *p = (T*)q;
+  } else {
+    hipError_t e = cache_get(m->s, (void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
   }
   m->cur_bytes += (int64_t)(n * sizeof(T));
   m->peak_bytes = std::max(m->peak_bytes, m->cur_bytes);
@@ -243,7 +255,14 @@ void pinned_put(pm_mesh* m) {
 
 template <class T>
 void dfree(pm_mesh* m, T*& p, size_t n) {
-  if (p) {
+  if (p && m->va.release) {
+    auto it = m->va_live.find((void*)p);
+    if (it != m->va_live.end()) {
+      m->va.release((void*)p, it->second, (void*)m->s, m->va.user);
+      m->cur_bytes -= (int64_t)it->second;
+      m->va_live.erase(it);
+    }
+  } else if (p) {
     cache_put(p);
     m->cur_bytes -= (int64_t)(std::max<size_t>(n, 1) * sizeof(T));
   }
@@ -780,7 +799,8 @@ bool bad_opts(const pm_options* o) {
           o->smooth_kind != PM_SMOOTH_MINMAX) || !(o->slack >= 1.0) ||
          !(o->pool_headroom == 0.0 || (o->pool_headroom >= 1.0 && o->pool_headroom <= 64.0)) ||
          o->max_iterations < 0 || o->max_iterations > 4095 || o->max_phases < 0 || bad_tuning(o->tune) ||
-         (o->quality != PM_QUALITY_MEAN_RATIO && o->quality != PM_QUALITY_VASILEVSKII) || o->reserved != 0;
+         (o->quality != PM_QUALITY_MEAN_RATIO && o->quality != PM_QUALITY_VASILEVSKII) || o->reserved != 0 ||
+         (o->allocator && (!o->allocator->alloc || !o->allocator->release));
 }
 
 // Collapse runs on groups of lanes per member by default: each lane loads
@@ -1179,6 +1199,7 @@ void fill_defaults(pm_options* o) {
   o->tune = pm_tuning{};
   o->quality = PM_QUALITY_MEAN_RATIO;
   o->reserved = 0;
+  o->allocator = nullptr;
 }
 
 }  // namespace
@@ -1263,6 +1284,7 @@ pm_status pm_mesh_create(const pm_mesh_desc* d, const pm_options* o, void* strea
   m->slack = o->slack;
   m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
   m->st.qk = o->quality;
+  if (o->allocator) m->va = *o->allocator;
   g_create_err.clear();
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_mesh_create failed") : m->err;
@@ -1822,6 +1844,7 @@ pm_status pm_batch_create(const pm_mesh_desc* meshes, int32_t count, const pm_op
   m->slack = o->slack;
   m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
   m->st.qk = o->quality;
+  if (o->allocator) m->va = *o->allocator;
   auto bail = [&](pm_status st) {
     g_create_err = m->err.empty() ? std::string("pm_batch_create failed") : m->err;
     pm_mesh_destroy(m);

@@ -59,12 +59,48 @@ class Tuning(C.Structure):
         return t
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class Allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", C.c_void_p)]
+
+
+def torch_allocator():
+    """A pm_allocator whose blocks come from torch's caching allocator on the
+    handle's stream (so torch's memory statistics and limits cover the
+    handle). Keep the returned object alive as long as the handle."""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # noqa: BLE001 - the library turns NULL into PM_E_NOMEM
+            return None
+
+    def release(ptr, nbytes, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = Allocator(ALLOC_FN(alloc), RELEASE_FN(release), None)
+    return a
+
+
+def _allocator_of(allocator):
+    if allocator is None or isinstance(allocator, Allocator):
+        return allocator
+    if allocator == "torch":
+        return torch_allocator()
+    raise ValueError(f"unknown allocator {allocator!r}")
+
+
 class Options(C.Structure):
     _fields_ = [("L_low2", C.c_double), ("L_up2", C.c_double), ("q_min", C.c_double), ("seed", C.c_uint64),
                 ("sweep", C.c_int32), ("coarsen_rounds", C.c_int32), ("swap_rounds", C.c_int32),
                 ("refine_passes", C.c_int32), ("smooth_kind", C.c_int32), ("smooth_sweeps", C.c_int32),
                 ("slack", C.c_double), ("pool_headroom", C.c_double), ("max_iterations", C.c_int32),
-                ("max_phases", C.c_int32), ("tune", Tuning), ("quality", C.c_int32), ("reserved", C.c_int32)]
+                ("max_phases", C.c_int32), ("tune", Tuning), ("quality", C.c_int32), ("reserved", C.c_int32),
+                ("allocator", C.POINTER(Allocator))]
 
 
 class Context(C.Structure):
@@ -415,11 +451,15 @@ class Mesh:
     """Owning wrapper around a pm_mesh handle."""
 
     def __init__(self, xy, tri, metric, tags=None, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
-                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO):
+                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO, allocator=None):
+        """allocator: None (the library's block cache), "torch" (torch's
+        caching allocator) or an Allocator, kept alive with the handle."""
         self.tune = dict(tune or {})
-        self.h = pm_mesh_create(xy, tri, metric, tags,
-                                pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom,
-                                                   quality=quality), stream)
+        o = pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom, quality=quality)
+        self._allocator = _allocator_of(allocator)
+        if self._allocator is not None:
+            o.allocator = C.pointer(self._allocator)
+        self.h = pm_mesh_create(xy, tri, metric, tags, o, stream)
 
     @classmethod
     def from_input(cls, mi, seed: int = 0, **kw):
@@ -497,10 +537,13 @@ class Batch(Mesh):
     """A batch of independent meshes adapted by the same kernel launches."""
 
     def __init__(self, meshes, seed: int = 0, slack: float = 2.0, stream=None, tune=None,
-                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO):
+                 pool_headroom: float = 3.0, quality: int = PM_QUALITY_MEAN_RATIO, allocator=None):
         self.tune = dict(tune or {})
-        self.h = pm_batch_create(meshes, pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom,
-                                                            quality=quality), stream)
+        o = pm_default_options(seed=seed, slack=slack, pool_headroom=pool_headroom, quality=quality)
+        self._allocator = _allocator_of(allocator)
+        if self._allocator is not None:
+            o.allocator = C.pointer(self._allocator)
+        self.h = pm_batch_create(meshes, o, stream)
 
     @classmethod
     def from_inputs(cls, mis, seed: int = 0, **kw):

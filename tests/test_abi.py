@@ -36,7 +36,8 @@ def test_options_layout_and_defaults():
     assert (o.L_low2, o.L_up2, o.q_min, o.slack) == (0.5, 2.0, 0.1, 2.0)
     assert (o.coarsen_rounds, o.swap_rounds, o.refine_passes, o.smooth_sweeps) == (200, 100, 32, 1)
     assert o.quality == pmesh.PM_QUALITY_MEAN_RATIO and o.reserved == 0
-    assert ctypes.sizeof(pmesh.Options) == 120
+    assert ctypes.sizeof(pmesh.Options) == 128
+    assert not o.allocator
     assert ctypes.sizeof(pmesh.Tuning) == 32
     assert ctypes.sizeof(pmesh.Context) == 24
     assert ctypes.sizeof(pmesh.Stats) == 128
@@ -51,7 +52,7 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = {"pm_options": pmesh.Options, "pm_tuning": pmesh.Tuning, "pm_context": pmesh.Context,
-               "pm_stats": pmesh.Stats, "pm_mesh_desc": pmesh.MeshDesc}
+               "pm_stats": pmesh.Stats, "pm_mesh_desc": pmesh.MeshDesc, "pm_allocator": pmesh.Allocator}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pm.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')

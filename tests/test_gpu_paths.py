@@ -245,3 +245,48 @@ def test_psi_benchmark_time_steps():
         compare_mesh(om, gm, f"step {step}")
     assert gm.sizes()[1] > 2 * mi.T
     compare_quality(om, gm, "end")
+
+
+def test_torch_allocator_owns_the_handle_memory():
+    """A handle created with torch's caching allocator as its device memory
+    provider gives the same mesh as one on the library's own cache; its blocks
+    show in torch's statistics while it lives and all go back when it closes."""
+    import torch
+    mi = inputs.config2(129)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    gm = pmesh.Mesh.from_input(mi, seed=1, allocator="torch")
+    ref = pmesh.Mesh.from_input(mi, seed=1)
+    assert torch.cuda.memory_allocated() > base
+    cur, _ = gm.memory()
+    # torch rounds each block up to a multiple of 512 bytes
+    assert cur <= torch.cuda.memory_allocated() - base <= cur + 512 * 256
+    for m in (gm, ref):
+        m.sweep(0, smooth_kind=1)
+        m.sweep(1, smooth_kind=2)
+    a, b = gm.export(), ref.export()
+    for k in ("xy", "tri", "tags", "metric"):
+        assert np.array_equal(a[k], b[k]), k
+    assert gm.quality() == ref.quality()
+    gm.close()
+    ref.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+
+
+def test_torch_allocator_on_a_batch():
+    import torch
+    mis = [inputs.make_mesh(n, amp=0.15, width=0.04, ht=0.08) for n in (17, 33, 20)]
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    gb = pmesh.Batch.from_inputs(mis, seed=2, allocator="torch")
+    rb = pmesh.Batch.from_inputs(mis, seed=2)
+    for b in (gb, rb):
+        b.sweep(0, smooth_kind=0)
+    for i in range(3):
+        a, c = gb.export_mesh(i), rb.export_mesh(i)
+        assert np.array_equal(a["tri"], c["tri"]) and np.array_equal(a["xy"], c["xy"]), i
+    gb.close()
+    rb.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
