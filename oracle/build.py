@@ -9,7 +9,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 def build(verbose: bool = False) -> str:
     cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-o", LIB + ".tmp", os.path.join(HERE, "oracle.cpp")]
+           "-Wall", "-o", LIB + ".tmp", os.path.join(HERE, "oracle.cpp"), os.path.join(HERE, "oracle3.cpp")]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -125,6 +125,32 @@ void orc_element_quality(const orc_mesh* m, double* q);
 /* Q_v: sum of q over the elements around v */
 double orc_patch_quality(const orc_mesh* m, int32_t v);
 
+/* ---- tetrahedral meshes of the unit cube (Sec. 4's extrusion to 3D) ----------
+ * Coarsening, refinement and Laplacian smoothing in the metric; no swaps.
+ * xyz: V x 3; tet: T x 4 ids, positively oriented; metric: V x 6 entries
+ * (m00, m01, m02, m11, m12, m22); tags: 6 bits (x = 0, x = 1, y = 0, y = 1,
+ * z = 0, z = 1) or NULL to derive them from exact coordinates. */
+typedef struct orc3_mesh orc3_mesh;
+orc3_mesh* orc3_create(int64_t V, int64_t T, const double* xyz, const int32_t* tet, const double* metric,
+                       const uint8_t* tags, uint64_t seed);
+void orc3_destroy(orc3_mesh* m);
+void orc3_sizes(const orc3_mesh* m, int64_t* V, int64_t* T);
+void orc3_export(const orc3_mesh* m, double* xyz, int32_t* tet, double* metric, uint8_t* tags, uint8_t* valive,
+                 uint8_t* talive);
+void orc3_row_totals(const orc3_mesh* m, int64_t* nn_total, int64_t* ne_total);
+void orc3_export_rows(const orc3_mesh* m, int64_t* nn_off, int32_t* nn, int64_t* ne_off, int32_t* ne);
+void orc3_set_xyz(orc3_mesh* m, int32_t v, double x, double y, double z);
+void orc3_set_hook(orc3_mesh* m, orc_hook hook, void* user);
+int64_t orc3_class_members(const orc3_mesh* m, int32_t* out, int64_t cap);
+int64_t orc3_class_whole(const orc3_mesh* m, int32_t* out, int64_t cap);
+int32_t orc3_colour(orc3_mesh* m, const uint8_t* active, uint32_t ctx, int32_t* colour_out);
+int32_t orc3_coarsen(orc3_mesh* m, int32_t sweep, double L_low2, double q_min, int32_t max_rounds, int64_t* stats);
+int32_t orc3_refine(orc3_mesh* m, double L_up2, int32_t max_passes, int64_t* stats);
+int32_t orc3_smooth(orc3_mesh* m, int32_t sweep, int32_t sweeps, int64_t* stats);
+/* sum and minimum of the element quality (live elements) */
+void orc3_quality(const orc3_mesh* m, double* Q, double* qmin);
+void orc3_element_quality(const orc3_mesh* m, double* q);
+
 #ifdef __cplusplus
 }
 #endif

@@ -302,3 +302,148 @@ def config3(count: int = 256, seed: int = 2) -> list[MeshInput]:
 
 
 PRIORITY_SEED = {0: 0, 1: 0, 2: 1, 3: 2, 4: 3}
+
+
+# ---- tetrahedral meshes of the unit cube ------------------------------------------------
+
+@dataclass
+class MeshInput3:
+    xyz: np.ndarray         # (V, 3) float64
+    tet: np.ndarray         # (T, 4) int32, positively oriented
+    metric: np.ndarray      # (V, 6) float64: m00, m01, m02, m11, m12, m22
+    tags: np.ndarray        # (V,) uint8: x=0, x=1, y=0, y=1, z=0, z=1 bits
+    n: int = 0
+    info: dict = field(default_factory=dict)
+
+    @property
+    def V(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def T(self) -> int:
+        return int(self.tet.shape[0])
+
+
+def cube_grid(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """Kuhn (Freudenthal) triangulation of the unit cube on an n x n x n vertex
+    grid: vertex id = (k n + j) n + i, every cube split into the six
+    tetrahedra along its main diagonal (one per order of the three axes,
+    ascending order of the axis permutations), positively oriented. The same
+    split in every cube makes the mesh conforming."""
+    if n < 2:
+        raise ValueError("cube_grid needs n >= 2")
+    s = np.arange(n, dtype=np.float64) / (n - 1)
+    K, J, I = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    xyz = np.stack([s[I.ravel()], s[J.ravel()], s[K.ravel()]], axis=1)
+    c = np.arange(n - 1)
+    k, j, i = [a.ravel() for a in np.meshgrid(c, c, c, indexing="ij")]
+
+    def vid(di, dj, dk):
+        return ((k + dk) * n + (j + dj)) * n + (i + di)
+
+    tets = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        p = [0, 0, 0]
+        path = [vid(0, 0, 0)]
+        for ax in perm:
+            p[ax] = 1
+            path.append(vid(*p))
+        # the path's volume has the sign of the permutation
+        inversions = sum(1 for a in range(3) for b in range(a + 1, 3) if perm[a] > perm[b])
+        if inversions % 2:
+            path[2], path[3] = path[3], path[2]
+        tets.append(np.stack(path, axis=1))
+    tet = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
+    return xyz, tet
+
+
+def unit_cube_tags(xyz: np.ndarray) -> np.ndarray:
+    t = np.zeros(xyz.shape[0], dtype=np.uint8)
+    for ax in range(3):
+        t |= np.where(xyz[:, ax] == 0.0, 1 << (2 * ax), 0).astype(np.uint8)
+        t |= np.where(xyz[:, ax] == 1.0, 2 << (2 * ax), 0).astype(np.uint8)
+    return t
+
+
+def _met6(M: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(np.stack([M[:, 0, 0], 0.5 * (M[:, 0, 1] + M[:, 1, 0]), 0.5 * (M[:, 0, 2] + M[:, 2, 0]),
+                                          M[:, 1, 1], 0.5 * (M[:, 1, 2] + M[:, 2, 1]), M[:, 2, 2]], axis=1))
+
+
+def layer_z(xyz: np.ndarray, amp: float = 0.1, width: float = 0.05, ht: float = 0.1, scale: float = 1.0,
+            amp_y: float = 0.0) -> np.ndarray:
+    """Boundary layer along the surface z = 0.5 + amp sin(2 pi x) + amp_y
+    sin(2 pi y): h_n across it (0.01 at the surface, growing to 0.21 away from
+    it over `width`), h_t along it; times `scale`. With amp_y != 0 the normal
+    has all three components, so every tensor entry is non-zero."""
+    x, y, z = xyz[:, 0], xyz[:, 1], xyz[:, 2]
+    d = z - 0.5 - amp * np.sin(2 * math.pi * x) - amp_y * np.sin(2 * math.pi * y)
+    hn = 0.01 + 0.2 * (1.0 - np.exp(-np.abs(d) / width))
+    nrm = np.stack([-2 * math.pi * amp * np.cos(2 * math.pi * x), -2 * math.pi * amp_y * np.cos(2 * math.pi * y),
+                    np.ones_like(x)], axis=1)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    P = np.einsum("ni,nj->nij", nrm, nrm)
+    M = P / hn[:, None, None] ** 2 + (np.eye(3)[None] - P) / ht ** 2
+    return _met6(M * scale)
+
+
+def jitter3(xyz: np.ndarray, tags: np.ndarray, n: int, seed: int, frac: float = 0.1) -> np.ndarray:
+    """Interior vertices moved uniformly by up to frac * h per coordinate
+    (h = 1/(n-1); 0.1 h keeps every Kuhn tetrahedron positive, whose smallest
+    height is h / sqrt(2))."""
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-frac, frac, xyz.shape) / (n - 1)
+    out = xyz.copy()
+    inner = tags == 0
+    out[inner] += d[inner]
+    return out
+
+
+def make_mesh3(n: int, *, jitter_seed: int | None = None, scale: float = 1.0, amp: float = 0.1,
+               width: float = 0.05, ht: float = 0.1, amp_y: float = 0.0) -> MeshInput3:
+    xyz, tet = cube_grid(n)
+    tags = unit_cube_tags(xyz)
+    if jitter_seed is not None:
+        xyz = jitter3(xyz, tags, n, jitter_seed)
+    return MeshInput3(xyz=xyz, tet=tet, metric=layer_z(xyz, amp, width, ht, scale, amp_y), tags=tags, n=n,
+                      info=dict(jitter_seed=jitter_seed, scale=scale, amp_y=amp_y))
+
+
+def psi_metric3(xyz: np.ndarray, phase: float, eps: float, hmin: float = 1e-3, hmax: float = 0.2) -> np.ndarray:
+    """psi extruded along z: its Hessian has no z row, so the metric is the 2D
+    rule in (x, y) and 1/hmax^2 along z."""
+    h = psi_hessian(np.ascontiguousarray(xyz[:, :2]), phase)
+    H = np.zeros((xyz.shape[0], 3, 3))
+    H[:, 0, 0], H[:, 0, 1], H[:, 1, 0], H[:, 1, 1] = h[:, 0], h[:, 1], h[:, 1], h[:, 2]
+    lam, R = np.linalg.eigh(H)
+    lam = np.clip(np.abs(lam) / eps, 1.0 / hmax ** 2, 1.0 / hmin ** 2)
+    return _met6(np.einsum("nij,nj,nkj->nik", R, lam, R))
+
+
+def ideal_elements3(xyz: np.ndarray, tet: np.ndarray, metric: np.ndarray) -> float:
+    """Elements of an ideal mesh for the metric: the metric-space volume over
+    the volume of the regular tetrahedron with unit edges, sqrt(2)/12."""
+    p = xyz[tet]
+    a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
+    vol = np.abs(np.einsum("ni,ni->n", a, np.cross(b, c))) / 6.0
+    m = metric[tet].mean(axis=1)
+    M = np.stack([np.stack([m[:, 0], m[:, 1], m[:, 2]], -1), np.stack([m[:, 1], m[:, 3], m[:, 4]], -1),
+                  np.stack([m[:, 2], m[:, 4], m[:, 5]], -1)], -2)
+    return float((np.sqrt(np.maximum(np.linalg.det(M), 0.0)) * vol).sum() / (math.sqrt(2.0) / 12.0))
+
+
+def psi_start3(n: int = 29, target: float = 210e3, steps: int = 50) -> MeshInput3:
+    """The 3D benchmark's start: a Kuhn grid of the unit cube (n = 29: 131,712
+    tetrahedra, about 50^3) and psi's metric at t = 0 with eps set for about
+    `target` elements."""
+    xyz, tet = cube_grid(n)
+    lo, hi = -12.0, 6.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if ideal_elements3(xyz, tet, psi_metric3(xyz, 0.0, 10.0 ** mid)) > target:
+            lo = mid
+        else:
+            hi = mid
+    eps = 10.0 ** (0.5 * (lo + hi))
+    return MeshInput3(xyz=xyz, tet=tet, metric=psi_metric3(xyz, 0.0, eps), tags=unit_cube_tags(xyz), n=n,
+                      info=dict(eps=eps, steps=steps, target=target))

@@ -16,6 +16,6 @@ def pytest_configure(config):
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
     from oracle import build
-    if not os.path.exists(build.LIB) or os.path.getmtime(build.LIB) < os.path.getmtime(
-            os.path.join(build.HERE, "oracle.cpp")):
+    srcs = [os.path.join(build.HERE, f) for f in ("oracle.cpp", "oracle3.cpp", "oracle.h")]
+    if not os.path.exists(build.LIB) or os.path.getmtime(build.LIB) < max(os.path.getmtime(f) for f in srcs):
         build.build()
