@@ -180,6 +180,11 @@ typedef struct {
 typedef struct {
   int64_t v[16];
 } pm_stats;
+/* slots of pm_stats.v */
+enum {
+  PM_S_ROUNDS = 0, PM_S_COLOURED = 1, PM_S_EVALUATED = 2, PM_S_DEFERRED = 3, PM_S_COMMITTED = 4,
+  PM_S_COLOURS = 5, PM_S_EDGES = 6, PM_S_CONVERGED = 7, PM_S_NEWV = 8, PM_S_NEWT = 9
+};
 
 typedef struct pm_mesh pm_mesh;
 

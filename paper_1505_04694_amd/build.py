@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpmesh.so")
-SOURCES = ["store.hip", "ops.hip", "api.hip"]
+SOURCES = ["store.hip", "ops.hip", "api.hip", "mesh3.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-mcode-object-version=5", "-ffp-contract=off",
          "-fno-fast-math",

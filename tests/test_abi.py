@@ -13,9 +13,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared():
-    src = open(os.path.join(ROOT, "include", "pm.h")).read()
+    src = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("pm.h", "pm3.h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(pm3?_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_named_calls():
@@ -29,6 +29,9 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
     assert set(pmesh.EXPORTS) <= set(declared())
+    from paper_1505_04694_amd import pmesh3
+    assert set(pmesh3.EXPORTS3) <= set(declared())
+    pmesh3.lib()  # every 3D entry point resolves
 
 
 def test_options_layout_and_defaults():
@@ -51,9 +54,11 @@ def test_binding_structs_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
+    from paper_1505_04694_amd import pmesh3
     structs = {"pm_options": pmesh.Options, "pm_tuning": pmesh.Tuning, "pm_context": pmesh.Context,
+               "pm3_mesh_desc": pmesh3.MeshDesc3,
                "pm_stats": pmesh.Stats, "pm_mesh_desc": pmesh.MeshDesc, "pm_allocator": pmesh.Allocator}
-    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pm.h"', "int main(void) {"]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pm3.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
         for f, _ in cls._fields_:
