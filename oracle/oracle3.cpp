@@ -31,6 +31,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "oracle.h"
@@ -616,7 +617,8 @@ int32_t orc3_refine(orc3_mesh* mp, double L_up2, int32_t max_passes, int64_t* st
     }
     st[ORC_NEWV] += m.V - V0;
     st[ORC_COMMITTED] += (int64_t)splits.size();
-    std::sort(splits.begin(), splits.end(), split_before);
+    std::map<std::pair<int32_t, int32_t>, Split> by_edge;
+    for (const Split& s : splits) by_edge[{s.a, s.b}] = s;
     int64_t T0 = m.T;
     std::vector<Split> own;
     std::vector<Tet> leaves;
@@ -624,9 +626,13 @@ int32_t orc3_refine(orc3_mesh* mp, double L_up2, int32_t max_passes, int64_t* st
       if (!m.talive[t]) continue;
       const Tet e = m.tet[t];
       own.clear();
-      for (const Split& s : splits)
-        if (has(e, s.a) && has(e, s.b)) own.push_back(s);
+      for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j) {
+          auto it = by_edge.find({std::min(e[i], e[j]), std::max(e[i], e[j])});
+          if (it != by_edge.end()) own.push_back(it->second);
+        }
       if (own.empty()) continue;
+      std::sort(own.begin(), own.end(), split_before);
       leaves.clear();
       bisect(e, own, leaves);
       m.tet[t] = canon(leaves[0]);

@@ -260,6 +260,34 @@ __device__ void isort(int* a, int n) {
   }
 }
 
+// Loose rows for the rounds of a coarsening phase: NE(v) in any order, NN(v)
+// the other three vertices of each NE(v) element (repeats included). The
+// class kernels read rows only through order-free questions (is a same-class
+// neighbour of larger key present, the smallest candidate pair above the last
+// one, mark every neighbour), so loose rows give the same decisions as sorted
+// ones; sorted rows are built once the phase ends.
+__global__ void k_ne_fill_loose(Store3 st, const int* __restrict__ off, int* cur) {
+  for (int t = gtid(); t < st.T; t += gstride()) {
+    if (!st.talive[t]) continue;
+    int4 e = st.tet[t];
+    int id[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int pos = off[id[k]] + atomicAdd(&cur[id[k]], 1);
+      st.ne[pos] = t;
+      int* nb = st.nn + 3 * pos;
+      int q = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j != k) nb[q++] = id[j];
+    }
+  }
+}
+
+__global__ void k_hdr_loose(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
+  for (int v = gtid(); v < st.V; v += gstride()) st.hdr[v] = make_int4(3 * off[v], 3 * cnt[v], off[v], cnt[v]);
+}
+
 // sort NE(v); NN(v) = the sorted distinct other vertices of NE(v)'s elements,
 // built in a slot of three entries per NE entry
 __global__ void k_rows_finish(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
@@ -905,8 +933,9 @@ pm_status scan_total(pm3_mesh* m, const int* in, int* out, int n, int* total) {
   return PM_OK;
 }
 
-// every row from the live elements
-pm_status build_rows(pm3_mesh* m) {
+// every row from the live elements; sorted rows, or loose ones inside a
+// coarsening phase
+pm_status build_rows(pm3_mesh* m, bool sorted = true) {
   Store3& st = m->st;
   int V = st.V;
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cnt, V + 1, 0);
@@ -923,8 +952,13 @@ pm_status build_rows(pm3_mesh* m) {
     m->mcap = 3 * nc;
   }
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0);
-  k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
-  k_rows_finish<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
+  if (sorted) {
+    k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
+    k_rows_finish<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
+  } else {
+    k_ne_fill_loose<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
+    k_hdr_loose<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
+  }
   H3(hipGetLastError());
   return PM_OK;
 }
@@ -1260,7 +1294,7 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
       sv[PM_S_EVALUATED] += m->hctr[K_EVAL];
       sv[PM_S_DEFERRED] += m->hctr[K_DEFER];
       sv[PM_S_COMMITTED] += m->hctr[K_COMMIT];
-      if (m->hctr[K_COMMIT] > 0) T3(build_rows(m));
+      if (m->hctr[K_COMMIT] > 0) T3(build_rows(m, false));
     }
     T3(select_list(m, 1, o->L_low2, &n));
     ++r;

@@ -105,3 +105,21 @@ def test_device_arrays_and_invalid_meshes():
     bad[0, [1, 2]] = bad[0, [2, 1]]                 # negative volume
     with pytest.raises(PMError):
         Mesh3(mi.xyz, bad, mi.metric, mi.tags)
+
+
+@pytest.mark.parametrize("n,target", [(11, 8000.0), (17, 40000.0)])
+def test_psi_benchmark_adaptation_matches_the_oracle(n, target):
+    """The 3D benchmark's procedure at reduced size: psi extruded along z,
+    two iterations of coarsen then refine, then a smoothing sweep; every phase
+    compared with the oracle."""
+    mi = inputs.psi_start3(n, target=target)
+    om, gm = both(mi, 0)
+    for it in range(2):
+        compare_stats(om.coarsen(it), gm.coarsen(it), f"iteration {it} coarsen")
+        compare(om, gm, f"iteration {it} coarsen")
+        compare_stats(om.refine(), gm.refine(), f"iteration {it} refine")
+        compare(om, gm, f"iteration {it} refine")
+    compare_stats(om.smooth(0, 1), gm.smooth(0, 1), "smooth")
+    compare(om, gm, "smooth")
+    compare_quality(om, gm, "end")
+    checker3.check_mesh(gm.export(), rows=gm.rows())
