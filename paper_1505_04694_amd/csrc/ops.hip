@@ -1762,8 +1762,8 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
 void smooth_class(const Store& st, const int* list, int n, int kind, int* ctr, int lanes, hipStream_t s) {
   if (n <= 0) return;
   int nb = (int)(((int64_t)n * kG + kBlock - 1) / kBlock);
-  if (kind == 2)  // min-max: one thread per vertex
-    (st.qk ? k_smooth<1> : k_smooth<0>)<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(st, list, n, kind, ctr);
+  if (lanes == kG && kind == 2)
+    (st.qk ? k_smooth_g<2, 1> : k_smooth_g<2, 0>)<<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else if (lanes == kG && kind == 0)
     (st.qk ? k_smooth_g<0, 1> : k_smooth_g<0, 0>)<<<nb, kBlock, 0, s>>>(st, list, n, ctr);
   else if (lanes == kG)
@@ -1936,7 +1936,7 @@ __device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, 
     double oldmin = gpatch_min(pe, owne, pv, h.w, g, st.qk, vo);
     double newmin = gpatch_min(pe, owne, p, h.w, g, st.qk, vn);
     if (!(vn && newmin >= oldmin)) return false;
-  } else {
+  } else if (kind == 1) {
     double ex = 0.0, ey = 0.0;
     if (owne) qgrad_x(patch_geo(pe, pv), pe.k, st.qk, ex, ey);
     double gx = 0.0, gy = 0.0;
@@ -1970,6 +1970,62 @@ __device__ __forceinline__ bool smooth_group(Store& st, int v, Hdr h, int kind, 
       ok = true;
     }
     if (!ok) return false;
+  } else {
+    // min-max: the worst element (smallest q, ties to the first in NE(v)) and
+    // the second worst, taken in row order as a serial loop takes them
+    double q = owne ? qval(patch_geo(pe, pv), st.qk) : 0.0;
+    int i1 = -1, i2 = -1;
+    double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kG; ++k) {
+      double t = gget(q, k, g);
+      if (k < h.w) {
+        if (i1 < 0 || t < q1) {
+          i2 = i1;
+          q2 = q1;
+          i1 = k;
+          q1 = t;
+        } else if (i2 < 0 || t < q2) {
+          i2 = k;
+          q2 = t;
+        }
+      }
+    }
+    if (i1 < 0) return false;
+    double ex = 0.0, ey = 0.0;
+    if (owne) qgrad_x(patch_geo(pe, pv), pe.k, st.qk, ex, ey);
+    double ax = gget(ex, i1, g), ay = gget(ey, i1, g);
+    double bx = gget(ex, max(i2, 0), g), by = gget(ey, max(i2, 0), g);
+    double gx = ax, gy = ay;
+    if (i2 >= 0 && q2 <= q1 * 1.01) {
+      double fx = bx - ax, fy = by - ay;
+      double den = fx * fx + fy * fy;
+      if (den > 0.0) {
+        double lam = -(ax * fx + ay * fy) / den;
+        lam = lam < 0.0 ? 0.0 : (lam > 1.0 ? 1.0 : lam);
+        gx = ax + lam * fx;
+        gy = ay + lam * fy;
+      }
+    }
+    if (gx == 0.0 && gy == 0.0) return false;
+    double nx = fabs(gx), ny = fabs(gy);
+    double nrm = nx < ny ? ny : nx;
+    double dx = gx / nrm, dy = gy / nrm;
+    double hx = fabs(pw.x - pv.x), hy = fabs(pw.y - pv.y);
+    double hh = gmin(hx < hy ? hy : hx, h.y, g);
+    bool vo;
+    double oldmin = gpatch_min(pe, owne, pv, h.w, g, st.qk, vo);
+    double step = hh;
+    bool ok = false;
+    for (int k = 0; k < 4 && !ok; ++k) {
+      step = step * 0.5;
+      p = make_double2(pv.x + step * dx, pv.y + step * dy);
+      bool vn;
+      double newmin = gpatch_min(pe, owne, p, h.w, g, st.qk, vn);
+      if (!vn || !(newmin > oldmin)) continue;
+      ok = true;
+    }
+    if (!ok) return false;
   }
   if (g.j == 0) st.xy[v] = p;
   return true;
@@ -1987,7 +2043,8 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
     int v = list[gid];
     Hdr h = st.hdr[v];
     if (h.y > kG || h.w > kG) {
-      if (g.j == 0) status = (K == 0 ? smooth_laplace(st, v) : smooth_gradient(st, v)) ? 2 : 1;
+      if (g.j == 0)
+        status = (K == 0 ? smooth_laplace(st, v) : (K == 1 ? smooth_gradient(st, v) : smooth_minmax(st, v))) ? 2 : 1;
     } else {
       bool moved = smooth_group(st, v, h, K, g);
       if (g.j == 0) status = moved ? 2 : 1;
@@ -1998,6 +2055,8 @@ __global__ void __launch_bounds__(256, 4) k_smooth_g(Store st, const int* __rest
 template __global__ void k_smooth_g<0, 0>(Store, const int*, int, int*);
 template __global__ void k_smooth_g<0, 1>(Store, const int*, int, int*);
 template __global__ void k_smooth_g<1, 0>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<2, 0>(Store, const int*, int, int*);
+template __global__ void k_smooth_g<2, 1>(Store, const int*, int, int*);
 template __global__ void k_smooth_g<1, 1>(Store, const int*, int, int*);
 
 // ---- collapse with lane groups -----------------------------------------------------------------

@@ -323,6 +323,12 @@ class MeshInput3:
     def T(self) -> int:
         return int(self.tet.shape[0])
 
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.xyz, self.tet, self.metric, self.tags):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()[:16]
+
 
 def cube_grid(n: int) -> tuple[np.ndarray, np.ndarray]:
     """Kuhn (Freudenthal) triangulation of the unit cube on an n x n x n vertex
@@ -411,25 +417,38 @@ def make_mesh3(n: int, *, jitter_seed: int | None = None, scale: float = 1.0, am
 
 def psi_metric3(xyz: np.ndarray, phase: float, eps: float, hmin: float = 1e-3, hmax: float = 0.2) -> np.ndarray:
     """psi extruded along z: its Hessian has no z row, so the metric is the 2D
-    rule in (x, y) and 1/hmax^2 along z."""
+    rule in (x, y) and 1/hmax^2 along z. The 2x2 eigen-decomposition is
+    written in closed form (elementwise, so the same on every host):
+    lam = (a + c)/2 +- sqrt(((a - c)/2)^2 + b^2), the first eigenvector at
+    angle 0.5 atan2(2b, a - c)."""
     h = psi_hessian(np.ascontiguousarray(xyz[:, :2]), phase)
-    H = np.zeros((xyz.shape[0], 3, 3))
-    H[:, 0, 0], H[:, 0, 1], H[:, 1, 0], H[:, 1, 1] = h[:, 0], h[:, 1], h[:, 1], h[:, 2]
-    lam, R = np.linalg.eigh(H)
-    lam = np.clip(np.abs(lam) / eps, 1.0 / hmax ** 2, 1.0 / hmin ** 2)
-    return _met6(np.einsum("nij,nj,nkj->nik", R, lam, R))
+    a, b, c = h[:, 0], h[:, 1], h[:, 2]
+    mean = 0.5 * (a + c)
+    rad = np.sqrt((0.5 * (a - c)) ** 2 + b * b)
+    lo, hi = 1.0 / hmax ** 2, 1.0 / hmin ** 2
+    l1 = np.clip(np.abs(mean + rad) / eps, lo, hi)
+    l2 = np.clip(np.abs(mean - rad) / eps, lo, hi)
+    th = 0.5 * np.arctan2(2.0 * b, a - c)
+    cs, sn = np.cos(th), np.sin(th)
+    m00 = l1 * cs * cs + l2 * sn * sn
+    m01 = (l1 - l2) * cs * sn
+    m11 = l1 * sn * sn + l2 * cs * cs
+    z = np.zeros_like(a)
+    return np.ascontiguousarray(np.stack([m00, m01, z, m11, z, np.full_like(a, lo)], axis=1))
 
 
 def ideal_elements3(xyz: np.ndarray, tet: np.ndarray, metric: np.ndarray) -> float:
     """Elements of an ideal mesh for the metric: the metric-space volume over
-    the volume of the regular tetrahedron with unit edges, sqrt(2)/12."""
+    the volume of the regular tetrahedron with unit edges, sqrt(2)/12
+    (determinants in closed form, elementwise)."""
     p = xyz[tet]
     a, b, c = p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]
-    vol = np.abs(np.einsum("ni,ni->n", a, np.cross(b, c))) / 6.0
+    vol = np.abs(a[:, 0] * (b[:, 1] * c[:, 2] - b[:, 2] * c[:, 1]) - a[:, 1] * (b[:, 0] * c[:, 2] - b[:, 2] * c[:, 0])
+                 + a[:, 2] * (b[:, 0] * c[:, 1] - b[:, 1] * c[:, 0])) / 6.0
     m = metric[tet].mean(axis=1)
-    M = np.stack([np.stack([m[:, 0], m[:, 1], m[:, 2]], -1), np.stack([m[:, 1], m[:, 3], m[:, 4]], -1),
-                  np.stack([m[:, 2], m[:, 4], m[:, 5]], -1)], -2)
-    return float((np.sqrt(np.maximum(np.linalg.det(M), 0.0)) * vol).sum() / (math.sqrt(2.0) / 12.0))
+    det = (m[:, 0] * (m[:, 3] * m[:, 5] - m[:, 4] * m[:, 4]) - m[:, 1] * (m[:, 1] * m[:, 5] - m[:, 4] * m[:, 2])
+           + m[:, 2] * (m[:, 1] * m[:, 4] - m[:, 3] * m[:, 2]))
+    return float((np.sqrt(np.maximum(det, 0.0)) * vol).sum() / (math.sqrt(2.0) / 12.0))
 
 
 def psi_start3(n: int = 29, target: float = 210e3, steps: int = 50) -> MeshInput3:

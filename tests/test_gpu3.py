@@ -123,3 +123,31 @@ def test_psi_benchmark_adaptation_matches_the_oracle(n, target):
     compare(om, gm, "smooth")
     compare_quality(om, gm, "end")
     checker3.check_mesh(gm.export(), rows=gm.rows())
+
+
+def test_psi_benchmark_full_size_matches_the_oracle_result():
+    """The 3D benchmark procedure at its full size (29^3 Kuhn grid, about 50^3
+    tetrahedra, adapted to 1.4 M) against the oracle's stored result
+    (tests/golden/make_psi3.py): every phase's op counts and the final
+    topology, tags, metric and coordinates."""
+    import json
+    import os
+    import torch
+    from tests.golden.make_psi3 import ITERATIONS, N, SEED, TARGET, summary
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "psi3_29.json")))
+    mi = inputs.psi_start3(N, target=TARGET)
+    assert mi.digest() == gold["input"]
+    dev = torch.device("cuda")
+    gm = Mesh3(*(torch.from_numpy(a).to(dev) for a in (mi.xyz, mi.tet, mi.metric, mi.tags)), seed=SEED)
+    for it in range(ITERATIONS):
+        g = gold["phases"][it]
+        compare_stats(g["coarsen"], gm.coarsen(it), f"iteration {it} coarsen")
+        compare_stats(g["refine"], gm.refine(), f"iteration {it} refine")
+    compare_stats(gold["smooth"], gm.smooth(0, 1), "smooth")
+    got, want = summary(gm.export()), gold["final"]
+    for k in ("V", "T", "tet", "tags", "metric"):
+        assert got[k] == want[k], k
+    if got["xyz"] != want["xyz"]:
+        assert abs(got["xyz_sum"] - want["xyz_sum"]) <= 1e-12 * abs(want["xyz_sum"])
+    Q, qmin = gm.quality()
+    assert abs(Q - gold["quality"][0]) <= 1e-12 * abs(Q) and abs(qmin - gold["quality"][1]) <= 1e-14 * qmin
