@@ -157,16 +157,19 @@ void cache_drop_all() {
   g_cache_bytes = 0;
 }
 
-hipError_t cache_get(hipStream_t s, void** p, size_t bytes) {
+// *got: the size of the block handed out (a reused block may be larger)
+hipError_t cache_get(hipStream_t s, void** p, size_t bytes, size_t* got) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   CacheKey want{dev, (uintptr_t)s, bytes};
+  *got = bytes;
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache_free.lower_bound(want);
     if (it != g_cache_free.end() && it->first.dev == dev && it->first.stream == want.stream &&
         it->first.bytes <= 2 * bytes) {
       *p = it->second;
+      *got = it->first.bytes;
       g_cache_bytes -= it->first.bytes;
       g_cache_live[*p] = it->first;
       g_cache_free.erase(it);
@@ -185,19 +188,21 @@ hipError_t cache_get(hipStream_t s, void** p, size_t bytes) {
   return hipSuccess;
 }
 
-void cache_put(void* p) {
+// returns the block's size (0 if it is not a cache block)
+size_t cache_put(void* p) {
   std::unique_lock<std::mutex> lk(g_cache_mu);
   auto it = g_cache_live.find(p);
-  if (it == g_cache_live.end()) return;
+  if (it == g_cache_live.end()) return 0;
   CacheKey k = it->second;
   g_cache_live.erase(it);
   if (g_cache_bytes + k.bytes > kCacheMax) {
     lk.unlock();
     (void)hipFree(p);
-    return;
+    return k.bytes;
   }
   g_cache_free.insert({k, p});
   g_cache_bytes += k.bytes;
+  return k.bytes;
 }
 
 template <class T>
@@ -210,11 +215,15 @@ pm_status dalloc(pm_mesh* m, T** p, size_t n) {
     m->va_live[q] = n * sizeof(T);
     *p = (T*)q;
   } else {
-    hipError_t e = cache_get(m->s, (void**)p, n * sizeof(T));
+    size_t got = 0;
+    hipError_t e = cache_get(m->s, (void**)p, n * sizeof(T), &got);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(m, PM_E_NOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
     }
+    m->cur_bytes += (int64_t)got;
+    m->peak_bytes = std::max(m->peak_bytes, m->cur_bytes);
+    return PM_OK;
   }
   m->cur_bytes += (int64_t)(n * sizeof(T));
   m->peak_bytes = std::max(m->peak_bytes, m->cur_bytes);
@@ -263,8 +272,7 @@ void dfree(pm_mesh* m, T*& p, size_t n) {
       m->va_live.erase(it);
     }
   } else if (p) {
-    cache_put(p);
-    m->cur_bytes -= (int64_t)(std::max<size_t>(n, 1) * sizeof(T));
+    m->cur_bytes -= (int64_t)cache_put(p);  // the block's real size
   }
   p = nullptr;
 }

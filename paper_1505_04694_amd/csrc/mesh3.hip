@@ -46,6 +46,7 @@ enum {
   K_COMMIT = 5,     // collapses / accepted moves
   K_EDGES = 6,      // edges tested by refinement
   K_TOTAL = 7,      // scan total
+  K_CCOMMIT = 8,    // collapses of the class in progress (gates its row rebuild)
   K_COUNT = 16
 };
 enum { E_MESH = 1, E_METRIC = 2, E_COLOURS = 4, E_LEAVES = 8 };
@@ -225,7 +226,8 @@ __global__ void k_orient(Store3 st, int* ctr) {
 
 // ---- rows from the element list ----------------------------------------------------------
 
-__global__ void k_ne_count(Store3 st, int* cnt) {
+__global__ void k_ne_count(Store3 st, int* cnt, const int* __restrict__ gate = nullptr) {
+  if (gate && *gate == 0) return;
   for (int t = gtid(); t < st.T; t += gstride()) {
     if (!st.talive[t]) continue;
     int4 e = st.tet[t];
@@ -266,7 +268,8 @@ __device__ void isort(int* a, int n) {
 // neighbour of larger key present, the smallest candidate pair above the last
 // one, mark every neighbour), so loose rows give the same decisions as sorted
 // ones; sorted rows are built once the phase ends.
-__global__ void k_ne_fill_loose(Store3 st, const int* __restrict__ off, int* cur) {
+__global__ void k_ne_fill_loose(Store3 st, const int* __restrict__ off, int* cur, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   for (int t = gtid(); t < st.T; t += gstride()) {
     if (!st.talive[t]) continue;
     int4 e = st.tet[t];
@@ -284,8 +287,16 @@ __global__ void k_ne_fill_loose(Store3 st, const int* __restrict__ off, int* cur
   }
 }
 
-__global__ void k_hdr_loose(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
+__global__ void k_hdr_loose(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt,
+                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   for (int v = gtid(); v < st.V; v += gstride()) st.hdr[v] = make_int4(3 * off[v], 3 * cnt[v], off[v], cnt[v]);
+}
+
+// fills p[0, n) with x unless the gate counter is zero (the class changed nothing)
+__global__ void k_fill_gated(int* p, int n, int x, const int* __restrict__ gate) {
+  if (*gate == 0) return;
+  for (int i = gtid(); i < n; i += gstride()) p[i] = x;
 }
 
 // sort NE(v); NN(v) = the sorted distinct other vertices of NE(v)'s elements,
@@ -487,6 +498,7 @@ __global__ void k_collapse(Store3 st, const int* __restrict__ list, int n, const
   stripe_add(ctr, K_EVAL, ev);
   stripe_add(ctr, K_DEFER, df);
   stripe_add(ctr, K_COMMIT, cm);
+  stripe_add(ctr, K_CCOMMIT, cm);
 }
 
 // stable renumbering of live vertices and elements (a monotone map keeps the
@@ -938,6 +950,20 @@ pm_status scan_total(pm3_mesh* m, const int* in, int* out, int n, int* total) {
 pm_status build_rows(pm3_mesh* m, bool sorted = true) {
   Store3& st = m->st;
   int V = st.V;
+  if (!sorted) {
+    // inside a coarsening phase: the element count only falls, so the rows fit
+    // their arrays, and the rebuild runs only if the class collapsed anything
+    // (the kernels check the class's counter): nothing is read back
+    const int* gate = m->ctr + K_CCOMMIT;
+    k_fill_gated<<<grid(V + 1), kB, 0, m->s>>>(m->cnt, V + 1, 0, gate);
+    k_ne_count<<<grid(st.T), kB, 0, m->s>>>(st, m->cnt, gate);
+    pm::scan_excl(m->cnt, m->off, V, m->ctr + K_TOTAL, m->partial, m->s);
+    k_fill_gated<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0, gate);
+    k_ne_fill_loose<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur, gate);
+    k_hdr_loose<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt, gate);
+    H3(hipGetLastError());
+    return PM_OK;
+  }
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cnt, V + 1, 0);
   k_ne_count<<<grid(st.T), kB, 0, m->s>>>(st, m->cnt);
   int total = 0;
@@ -952,13 +978,8 @@ pm_status build_rows(pm3_mesh* m, bool sorted = true) {
     m->mcap = 3 * nc;
   }
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0);
-  if (sorted) {
-    k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
-    k_rows_finish<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
-  } else {
-    k_ne_fill_loose<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
-    k_hdr_loose<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
-  }
+  k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
+  k_rows_finish<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
   H3(hipGetLastError());
   return PM_OK;
 }
@@ -1284,19 +1305,21 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
     sv[PM_S_COLOURED] += n;
     sv[PM_S_COLOURS] += ncol;
     T3(class_lists(m, n, ncol, off, size));
+    // the colouring zeroed the counters: the round's stats accumulate on the
+    // device and come back with the next list's length
     for (int c = 0; c < ncol; ++c) {
       if (size[c] == 0) continue;
-      T3(zero_ctr(m));
+      k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_CCOMMIT, 1, 0);
       k_collapse<<<grid(size[c]), kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3,
                                                   m->nxt, m->ctr);
       H3(hipGetLastError());
-      T3(read_ctr(m));
-      sv[PM_S_EVALUATED] += m->hctr[K_EVAL];
-      sv[PM_S_DEFERRED] += m->hctr[K_DEFER];
-      sv[PM_S_COMMITTED] += m->hctr[K_COMMIT];
-      if (m->hctr[K_COMMIT] > 0) T3(build_rows(m, false));
+      T3(build_rows(m, false));
     }
     T3(select_list(m, 1, o->L_low2, &n));
+    T3(read_ctr(m));
+    sv[PM_S_EVALUATED] += m->hctr[K_EVAL];
+    sv[PM_S_DEFERRED] += m->hctr[K_DEFER];
+    sv[PM_S_COMMITTED] += m->hctr[K_COMMIT];
     ++r;
   }
   sv[PM_S_ROUNDS] = r;
