@@ -424,45 +424,59 @@ __global__ void k_compact_list(const int* __restrict__ flag, const int* __restri
 
 // ---- coarsening (Sec. 2.4.1) -------------------------------------------------------------------
 
-__device__ bool collapse_ok(const Store3& st, int v, int u, int4 hv, double qmin3) {
-  for (int i = 0; i < hv.w; ++i) {
-    int4 e = st.tet[st.ne[hv.z + i]];
-    if (has4(e, u)) continue;
-    Geo3 g = geo(st, canon4(replace4(e, v, u)), -1, make_double4(0, 0, 0, 0));
-    if (!(vol6(g) > 0.0) || !(qual3(g) >= qmin3)) return false;
-  }
-  return true;
-}
 
 // One class: re-validation against the current graph, then each kept
 // member's collapse, evaluated and applied (members are pairwise
-// non-adjacent, so no member reads what another writes).
-__global__ void k_collapse(Store3 st, const int* __restrict__ list, int n, const int* __restrict__ col, int c,
-                           uint64_t sseed, double L_low2, double qmin3, uint8_t* nxt, int* ctr) {
-  int ev = 0, df = 0, cm = 0;
-  for (int i = gtid(); i < n; i += gstride()) {
-    int v = list[i];
-    int4 h = st.hdr[v];
-    uint64_t kv = vkey(sseed, (uint32_t)v);
-    bool beaten = false;
-    for (int j = 0; j < h.y && !beaten; ++j) {
+// non-adjacent, so no member reads what another writes). A member runs on a
+// group of kL lanes: lane j takes the row entries j, j + kL, ..., so a
+// member's neighbours and elements are gathered side by side; the group
+// combines its lanes' answers (any beaten, the smallest candidate pair, every
+// re-pointed element valid), which are exact, so the decisions are those of a
+// serial loop over the rows.
+constexpr int kL = 16;
+
+__device__ __forceinline__ bool grp_any(bool p) {
+  uint64_t b = __ballot(p);
+  int base = __lane_id() & ~(kL - 1);
+  return ((b >> base) & ((1ull << kL) - 1)) != 0;
+}
+
+__global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restrict__ list, int n,
+                                                  const int* __restrict__ col, int c, uint64_t sseed, double L_low2,
+                                                  double qmin3, uint8_t* nxt, int* ctr) {
+  int j0 = __lane_id() & (kL - 1);
+  int gid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kL);
+  bool act = gid < n;
+  int v = act ? list[gid] : 0;
+  int4 h = act ? st.hdr[v] : make_int4(0, 0, 0, 0);
+  uint64_t kv = vkey(sseed, (uint32_t)v);
+  bool b = false;
+  for (int jb = 0; jb < h.y; jb += kL) {
+    int j = jb + j0;
+    if (j < h.y) {
       int w = st.nn[h.x + j];
-      if (col[w] == c && vkey(sseed, (uint32_t)w) > kv) beaten = true;
+      b = b || (col[w] == c && vkey(sseed, (uint32_t)w) > kv);
     }
-    if (beaten) {
-      nxt[v] = 1;
-      ++df;
-      continue;
-    }
-    ++ev;
+  }
+  bool beaten = grp_any(b);
+  int ev = 0, df = 0, cm = 0;
+  if (act && beaten) {
+    if (j0 == 0) nxt[v] = 1;
+    df = 1;
+  }
+  int target = -1;
+  if (act && !beaten) {
+    ev = 1;
     // candidates in ascending (L^2, u): each step takes the smallest pair
     // above the previous one
     double pL = -1.0;
-    int pu = -1, target = -1;
+    int pu = -1;
     for (;;) {
       double bL = 0.0;
       int bu = -1;
-      for (int j = 0; j < h.y; ++j) {
+      for (int jb = 0; jb < h.y; jb += kL) {
+        int j = jb + j0;
+        if (j >= h.y) continue;
         int u = st.nn[h.x + j];
         if (!tag_ok(st, v, u)) continue;
         double L = len2(st, v, u);
@@ -474,16 +488,37 @@ __global__ void k_collapse(Store3 st, const int* __restrict__ list, int n, const
           bu = u;
         }
       }
+#pragma unroll
+      for (int d = kL / 2; d > 0; d >>= 1) {
+        double oL = __shfl_xor(bL, d);
+        int ou = __shfl_xor(bu, d);
+        if (ou >= 0 && (bu < 0 || oL < bL || (oL == bL && ou < bu))) {
+          bL = oL;
+          bu = ou;
+        }
+      }
       if (bu < 0) break;
-      if (collapse_ok(st, v, bu, h, qmin3)) {
+      bool bad = false;
+      for (int kb = 0; kb < h.w; kb += kL) {
+        int k = kb + j0;
+        if (k >= h.w) continue;
+        int4 e = st.tet[st.ne[h.z + k]];
+        if (has4(e, bu)) continue;
+        Geo3 g = geo(st, canon4(replace4(e, v, bu)), -1, make_double4(0, 0, 0, 0));
+        if (!(vol6(g) > 0.0) || !(qual3(g) >= qmin3)) bad = true;
+      }
+      if (!grp_any(bad)) {
         target = bu;
         break;
       }
       pL = bL;
       pu = bu;
     }
-    if (target < 0) continue;
-    for (int k = 0; k < h.w; ++k) {
+  }
+  if (target >= 0) {
+    for (int kb = 0; kb < h.w; kb += kL) {
+      int k = kb + j0;
+      if (k >= h.w) continue;
       int t = st.ne[h.z + k];
       int4 e = st.tet[t];
       if (has4(e, target))
@@ -491,14 +526,22 @@ __global__ void k_collapse(Store3 st, const int* __restrict__ list, int n, const
       else
         st.tet[t] = canon4(replace4(e, v, target));
     }
-    st.valive[v] = 0;
-    for (int j = 0; j < h.y; ++j) nxt[st.nn[h.x + j]] = 1;
-    ++cm;
+    for (int jb = 0; jb < h.y; jb += kL) {
+      int j = jb + j0;
+      if (j < h.y) nxt[st.nn[h.x + j]] = 1;
+    }
+    if (j0 == 0) st.valive[v] = 0;
+    cm = 1;
   }
-  stripe_add(ctr, K_EVAL, ev);
-  stripe_add(ctr, K_DEFER, df);
-  stripe_add(ctr, K_COMMIT, cm);
-  stripe_add(ctr, K_CCOMMIT, cm);
+  if (j0 != 0) ev = df = cm = 0;
+  // one add per wavefront and counter
+  uint64_t me = __ballot(ev), md = __ballot(df), mc = __ballot(cm);
+  if (__lane_id() == 0) {
+    stripe_add(ctr, K_EVAL, __popcll(me));
+    stripe_add(ctr, K_DEFER, __popcll(md));
+    stripe_add(ctr, K_COMMIT, __popcll(mc));
+    stripe_add(ctr, K_CCOMMIT, __popcll(mc));
+  }
 }
 
 // stable renumbering of live vertices and elements (a monotone map keeps the
@@ -1310,8 +1353,9 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
     for (int c = 0; c < ncol; ++c) {
       if (size[c] == 0) continue;
       k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_CCOMMIT, 1, 0);
-      k_collapse<<<grid(size[c]), kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3,
-                                                  m->nxt, m->ctr);
+      int nb = (int)(((int64_t)size[c] * kL + kB - 1) / kB);
+      k_collapse<<<nb, kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3, m->nxt,
+                                       m->ctr);
       H3(hipGetLastError());
       T3(build_rows(m, false));
     }
