@@ -12,7 +12,7 @@ are edges tested by refinement (identical counts on the oracle).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--n 2049]
        python bench.py --config4                      (the 4097^2 workload, peak device memory)
        python bench.py --psi 10                       (the paper's psi benchmark, 10 time steps)
-       python bench.py --summarise-trace DIR --out PREFIX --command CMD
+       python bench.py --summarise-trace DIR --out PREFIX --command CMD [--title WORKLOAD]
        python bench.py --summarise-counters FETCH_DIR WRITE_DIR --out PREFIX --command CMD
 The last two turn rocprofv3 CSV output (--stats / --pmc runs of this script)
 into the summaries kept under profiles/.
@@ -430,14 +430,14 @@ def group_of(kernel_name):
     return "3d" if "pm3::" in kernel_name else None
 
 
-def summarise_trace(d, out, command):
+def summarise_trace(d, out, command, title="2049x2049 benchmark workload"):
     """--stats output (kernel_stats.csv) -> a markdown table of every kernel."""
     f = _csvs(d, "kernel_stats.csv")
     if not f:
         raise SystemExit(f"no kernel_stats.csv under {d}")
     rows = list(csv.DictReader(open(f[0])))
     tot = sum(float(r["TotalDurationNs"]) for r in rows)
-    lines = ["# rocprofv3 kernel-trace summary: 2049x2049 benchmark workload", "",
+    lines = [f"# rocprofv3 kernel-trace summary: {title}", "",
              "Command (from /tmp with TMPDIR=/tmp, repository root in $R):", "", "```", command, "```", "",
              f"Total kernel time: {tot / 1e6:.3f} ms", "",
              "| kernel | group | calls | total ms | % | avg us | min us | max us |", "|---|---|---:|---:|---:|---:|---:|---:|"]
@@ -538,9 +538,10 @@ def main():
     ap.add_argument("--summarise-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles", "summary"))
     ap.add_argument("--command", default="")
+    ap.add_argument("--title", default="2049x2049 benchmark workload", help="workload named in a trace summary")
     a = ap.parse_args()
     if a.summarise_trace:
-        summarise_trace(a.summarise_trace, a.out, a.command)
+        summarise_trace(a.summarise_trace, a.out, a.command, a.title)
         return
     if a.summarise_counters:
         summarise_counters(*a.summarise_counters, a.out, a.command)

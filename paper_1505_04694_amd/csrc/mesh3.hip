@@ -306,18 +306,28 @@ __global__ void k_rows_finish(Store3 st, const int* __restrict__ off, const int*
     int o = off[v], n = cnt[v];
     int* row = st.ne + o;
     isort(row, n);
+    // sorted distinct neighbours, inserted one at a time (each neighbour
+    // comes from several elements: a binary search finds and skips repeats)
     int* nb = st.nn + 3 * o;
-    int k = 0;
+    int u = 0;
     for (int i = 0; i < n; ++i) {
       int4 e = st.tet[row[i]];
       int id[4] = {e.x, e.y, e.z, e.w};
-      for (int j = 0; j < 4; ++j)
-        if (id[j] != v) nb[k++] = id[j];
+      for (int j = 0; j < 4; ++j) {
+        int x = id[j];
+        if (x == v) continue;
+        int lo = 0, hi = u;
+        while (lo < hi) {
+          int mid = (lo + hi) >> 1;
+          if (nb[mid] < x) lo = mid + 1;
+          else hi = mid;
+        }
+        if (lo < u && nb[lo] == x) continue;
+        for (int q = u; q > lo; --q) nb[q] = nb[q - 1];
+        nb[lo] = x;
+        ++u;
+      }
     }
-    isort(nb, k);
-    int u = 0;
-    for (int i = 0; i < k; ++i)
-      if (u == 0 || nb[i] != nb[u - 1]) nb[u++] = nb[i];
     st.hdr[v] = make_int4(3 * o, u, o, n);
   }
 }
