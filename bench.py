@@ -364,8 +364,9 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
     m = pmesh.Mesh(mi.xy, mi.tri, mi.metric, mi.tags, seed=0)
     st0, _ = m.adapt(max_iterations=4)
     log(f"psi start adapted: {m.sizes()}")
-    times, ops, sizes = [], 0, []
-    for k in range(1, steps + 1):
+    times, ops, sizes, first = [], 0, [], None
+
+    def time_step(k, prof=0):
         e = m.export()
         met = inputs.psi_metric(e["xy"], 2 * math.pi * k / 50, eps)
         torch.cuda.synchronize()
@@ -374,18 +375,67 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
         m.set_context(dict(seed=0, iteration=0, phase=pmesh.PM_PHASE_COARSEN, changed=0))
         st, _ = m.adapt(max_iterations=iterations)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+        return e, met, st, time.perf_counter() - t0
+
+    for k in range(1, steps + 1):
+        e, met, st, dt = time_step(k)
+        if first is None:
+            first = (e, met, st)
+        times.append(dt)
         ops += st["coloured"] + st["evaluated"] + st["edges"]
         sizes.append(m.sizes())
     ms = 1e3 * sum(times) / steps
+    # two more steps with every kernel timed by events (outside the timed
+    # steps above): the kernel breakdown and the dominant kernel's roofline
+    copy_gbs = copy_bandwidth(torch, torch.device("cuda:0"))
+    m.profile(0xFF)
+    for k in range(steps + 1, steps + 3):
+        time_step(k)
+    prof = m.profile_read(pmesh.PROFILE_READS)
+    dominant = max(pmesh.KERNELS, key=lambda k: prof[k]["ms"])
+    if dominant == "commit":
+        rl = roofline("commit_ops", prof["commit_ops"], copy_gbs, per_row=prof["commit"])
+    else:
+        rl = roofline(dominant, prof[dominant], copy_gbs)
+    m.close()
+    # the oracle on the first time step, from the same mesh and metric, one core
+    cpu = psi_cpu_step(first, iterations)
     print(json.dumps({"workload": f"time-varying psi on the unit square: {n}x{n} isotropic start "
                                   f"({mi.T} triangles), Hessian metric for ~{target:.0f} elements, "
                                   f"{steps} time steps of 50 per period, Algorithm 1 with {iterations} "
                                   "iterations per step", "ms_per_time_step": ms,
                       "ms_per_time_step_range": [round(1e3 * min(times), 2), round(1e3 * max(times), 2)],
                       "ops_per_s": ops / sum(times), "elements": [t for _, t in sizes],
-                      "start_adaptation": st0}), flush=True)
-    m.close()
+                      "roofline": rl, "kernels_ms_two_steps": {k: round(prof[k]["ms"], 3) for k in pmesh.KERNELS},
+                      "kernel_roofline": kernel_roofline({k: prof[k] for k in pmesh.KERNELS}),
+                      "cpu_baseline": cpu, "start_adaptation": st0}), flush=True)
+
+
+def psi_cpu_step(first, iterations):
+    """The oracle on one time step of the psi benchmark (the GPU's first one:
+    the same live mesh and the same new metric), pinned to one core; checks
+    that its op counts equal the GPU's."""
+    import numpy as np
+    from oracle.orc import OracleMesh
+    e, met, st_gpu = first
+    va, ta = e["valive"], e["talive"]
+    vmap = np.cumsum(va) - 1
+    tri = vmap[e["tri"][ta]].astype(np.int32)
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
+        om = OracleMesh(e["xy"][va], tri, met[va], e["tags"][va], seed=0)
+        t0 = time.perf_counter()
+        st, _ = om.adapt(max_iterations=iterations)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    ops = st["coloured"] + st["evaluated"] + st["edges"]
+    ops_gpu = st_gpu["coloured"] + st_gpu["evaluated"] + st_gpu["edges"]
+    model, ncpu, navail = host_cpu()
+    return {"value": ops / dt, "unit": "ops/s", "cores": 1, "kind": "oracle", "seconds": dt,
+            "sample": "the first time step (Algorithm 1 on the same mesh and metric as the GPU's), one run",
+            "ops_equal_gpu": ops == ops_gpu, "host_cpu": model, "host_threads": ncpu}
 
 
 def psi3_run(n=29, iterations=2, target=210e3, seed=0):
@@ -421,12 +471,30 @@ def psi3_run(n=29, iterations=2, target=210e3, seed=0):
         runs.append(dict(seconds=dt, ops=ops, vertices=V, tetrahedra=T, quality=q, phases=phases, smooth=sm))
         log(f"3D psi run {rep}: {dt * 1e3:.1f} ms, {T} tetrahedra")
     r = runs[-1]
+    # the oracle on the first iteration (coarsen, refine) of the same start, one core
+    from oracle.orc import OracleMesh3
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
+        om = OracleMesh3.from_input(mi, seed=seed)
+        t0 = time.perf_counter()
+        c, rf = om.coarsen(0), om.refine()
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    ops0 = c["coloured"] + c["evaluated"] + rf["edges"]
+    g0 = r["phases"][0]
+    model, ncpu, navail = host_cpu()
+    cpu = {"value": ops0 / dt, "unit": "ops/s", "cores": 1, "kind": "oracle", "seconds": dt,
+           "sample": "the first iteration (coarsen, refine) of the same start, one run",
+           "ops_equal_gpu": ops0 == g0["coarsen"]["coloured"] + g0["coarsen"]["evaluated"] + g0["refine"]["edges"],
+           "host_cpu": model, "host_threads": ncpu}
     print(json.dumps({"workload": f"psi extruded along z on the unit cube: {n}^3 Kuhn grid ({mi.T} tetrahedra), "
                                   f"metric for ~{target:.0f} elements (eps {mi.info['eps']:.4g}); {iterations} x "
                                   "(coarsen, refine), one smoothing sweep; device-resident inputs",
                       "ms": r["seconds"] * 1e3, "ops": r["ops"], "ops_per_s": r["ops"] / r["seconds"],
                       "final": {"vertices": r["vertices"], "tetrahedra": r["tetrahedra"], "quality": r["quality"]},
-                      "phases": r["phases"], "smooth": r["smooth"]}), flush=True)
+                      "cpu_baseline": cpu, "phases": r["phases"], "smooth": r["smooth"]}), flush=True)
 
 
 def smooth_compare(n=2049, sweeps=10, seed=1):
