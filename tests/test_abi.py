@@ -89,3 +89,19 @@ def test_argument_errors_without_gpu():
     assert lib.pm_mesh_create(None, None, None, None) == pmesh.PM_E_ARG
     assert lib.pm_mesh_destroy(None) == pmesh.PM_OK
     assert lib.pm_last_error(None) in (b"null handle", b"pm_mesh_create failed")
+
+
+def test_tetrahedral_argument_errors_without_gpu():
+    from paper_1505_04694_amd import pmesh3
+    lib = pmesh3.lib()
+    h = ctypes.c_void_p()
+    assert lib.pm3_mesh_create(None, None, None, ctypes.byref(h)) == pmesh.PM_E_ARG
+    xyz = np.zeros((3, 3))
+    tet = np.array([[0, 1, 2, 0]], np.int32)
+    met = np.tile([1.0, 0, 0, 1.0, 0, 1.0], (3, 1))
+    d = pmesh3.MeshDesc3(xyz.ctypes.data, tet.ctypes.data, met.ctypes.data, None, 3, 1, pmesh.PM_MEM_HOST)
+    assert lib.pm3_mesh_create(ctypes.byref(d), None, None, ctypes.byref(h)) == pmesh.PM_E_ARG   # V < 4
+    d = pmesh3.MeshDesc3(xyz.ctypes.data, tet.ctypes.data, met.ctypes.data, None, 4, 0, pmesh.PM_MEM_HOST)
+    assert lib.pm3_mesh_create(ctypes.byref(d), None, None, ctypes.byref(h)) == pmesh.PM_E_ARG   # no element
+    assert lib.pm3_mesh_destroy(None) == pmesh.PM_OK
+    assert lib.pm3_mesh_sizes(None, None, None) == pmesh.PM_E_ARG

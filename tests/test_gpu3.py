@@ -151,3 +151,26 @@ def test_psi_benchmark_full_size_matches_the_oracle_result():
         assert abs(got["xyz_sum"] - want["xyz_sum"]) <= 1e-12 * abs(want["xyz_sum"])
     Q, qmin = gm.quality()
     assert abs(Q - gold["quality"][0]) <= 1e-12 * abs(Q) and abs(qmin - gold["quality"][1]) <= 1e-14 * qmin
+
+
+def test_single_element_and_nothing_to_do():
+    # one tetrahedron: nothing to collapse (every vertex a cube corner), one
+    # refinement pass of its long edges, smoothing of no interior vertex
+    xyz = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    tet = np.array([[0, 1, 2, 3]], np.int32)
+    met = np.tile([3.0, 0, 0, 3.0, 0, 3.0], (4, 1))
+    om = OracleMesh3(xyz, tet, met, np.zeros(4, np.uint8))
+    gm = Mesh3(xyz, tet, met, np.zeros(4, np.uint8))
+    for ph, fo, fg in (("coarsen", lambda: om.coarsen(), lambda: gm.coarsen()),
+                       ("refine", lambda: om.refine(max_passes=1), lambda: gm.refine(max_passes=1)),
+                       ("smooth", lambda: om.smooth(0, 1), lambda: gm.smooth(0, 1))):
+        compare_stats(fo(), fg(), ph)
+        compare(om, gm, ph)
+    compare_quality(om, gm, "end")
+    # no short edge (every L^2 >= 1 under 4 I on the 3^3 grid): nothing to do,
+    # the phase converges at once and the mesh is unchanged
+    mi = inputs.make_mesh3(3)
+    gm2 = Mesh3(mi.xyz, mi.tet, np.tile([4.0, 0, 0, 4.0, 0, 4.0], (mi.V, 1)), mi.tags)
+    st = gm2.coarsen()
+    assert st["committed"] == 0 and st["converged"] == 1 and gm2.sizes() == (mi.V, mi.T)
+    assert np.array_equal(gm2.export()["xyz"], mi.xyz)
