@@ -218,13 +218,21 @@ def psi_hessian(xy: np.ndarray, phase: float) -> np.ndarray:
 def psi_metric(xy: np.ndarray, phase: float, eps: float, hmin: float = 1e-3, hmax: float = 0.2) -> np.ndarray:
     """Metric from the Hessian: R diag(lam~) R^T with lam~ = clamp(|lam| / eps,
     1/hmax^2, 1/hmin^2), H = R diag(lam) R^T (the usual Hessian-based reading;
-    the paper does not give the rule)."""
+    the paper does not give the rule). The 2x2 eigen-decomposition is written
+    in closed form (elementwise, so the same on every host): lam = (a + c)/2
+    +- sqrt(((a - c)/2)^2 + b^2), the first eigenvector at angle
+    0.5 atan2(2b, a - c)."""
     h = psi_hessian(xy, phase)
-    H = np.stack([np.stack([h[:, 0], h[:, 1]], -1), np.stack([h[:, 1], h[:, 2]], -1)], -2)
-    lam, R = np.linalg.eigh(H)
-    lam = np.clip(np.abs(lam) / eps, 1.0 / hmax ** 2, 1.0 / hmin ** 2)
-    M = np.einsum("nij,nj,nkj->nik", R, lam, R)
-    return np.ascontiguousarray(np.stack([M[:, 0, 0], 0.5 * (M[:, 0, 1] + M[:, 1, 0]), M[:, 1, 1]], axis=1))
+    a, b, c = h[:, 0], h[:, 1], h[:, 2]
+    mean = 0.5 * (a + c)
+    rad = np.sqrt((0.5 * (a - c)) ** 2 + b * b)
+    lo, hi = 1.0 / hmax ** 2, 1.0 / hmin ** 2
+    l1 = np.clip(np.abs(mean + rad) / eps, lo, hi)
+    l2 = np.clip(np.abs(mean - rad) / eps, lo, hi)
+    th = 0.5 * np.arctan2(2.0 * b, a - c)
+    cs, sn = np.cos(th), np.sin(th)
+    return np.ascontiguousarray(np.stack([l1 * cs * cs + l2 * sn * sn, (l1 - l2) * cs * sn,
+                                          l1 * sn * sn + l2 * cs * cs], axis=1))
 
 
 def ideal_elements(xy: np.ndarray, tri: np.ndarray, metric: np.ndarray) -> float:

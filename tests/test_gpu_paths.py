@@ -247,6 +247,32 @@ def test_psi_benchmark_time_steps():
     compare_quality(om, gm, "end")
 
 
+def test_psi_benchmark_full_size_matches_the_oracle():
+    """The psi benchmark at its full size, in the launch configuration that
+    bench.py times: the 201 x 201 isotropic start (80,000 triangles) adapted
+    to the metric for about 550,000 elements (Algorithm 1, four iterations),
+    then two time steps of Algorithm 1 with two iterations each. The metric of
+    each step is evaluated once on the host from the oracle's coordinates
+    (already checked equal to the device's) and handed to both sides."""
+    import math
+    mi = inputs.psi_start(201, target=550e3)
+    eps = mi.info["eps"]
+    om, gm = both(mi, 0)
+    compare_stats(om.adapt(max_iterations=4)[0], gm.adapt(max_iterations=4)[0], "start")
+    compare_mesh(om, gm, "start")
+    assert gm.sizes()[1] > 6 * mi.T
+    for step in (1, 2):
+        met = inputs.psi_metric(om.export()["xy"], 2 * math.pi * step / 50, eps)
+        for v in range(met.shape[0]):
+            om.set_metric(v, *met[v])
+        gm.update(metric=met)
+        om.set_context(0, 1, 0)
+        gm.set_context(dict(seed=0, iteration=0, phase=pmesh.PM_PHASE_COARSEN, changed=0))
+        compare_stats(om.adapt(max_iterations=2)[0], gm.adapt(max_iterations=2)[0], f"time step {step}")
+        compare_mesh(om, gm, f"time step {step}")
+    compare_quality(om, gm, "end")
+
+
 def test_torch_allocator_owns_the_handle_memory():
     """A handle created with torch's caching allocator as its device memory
     provider gives the same mesh as one on the library's own cache; its blocks
