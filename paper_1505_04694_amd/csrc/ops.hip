@@ -1420,16 +1420,27 @@ __global__ void __launch_bounds__(256, 5) k_commit_sweep(Store st, Commit cm, in
   if (room_failed_block(ctr)) return;
   int tid = (int)threadIdx.x;
   int base = xcd_block() * kSweepChunk;
-  int qn = 0;
-  for (int b = 0; b < kSweepChunk; b += kBlock) {
-    int x = base + b + tid;
-    bool dirty = x < st.V && (uint32_t)(cm.own[x] >> 32) == (uint32_t)cm.epoch;
-    int at;
-    int tot = block_scan(dirty ? 1 : 0, at, L.wsum);
-    if (dirty) L.q[qn + at] = x;
-    qn += tot;
-    __syncthreads();  // wsum is reused by the next scan
+  // thread tid reads the owner keys of slots base + kPairB tid + [0, kPairB),
+  // all in flight together; one block-wide scan then places the claimed rows
+  // in slot order
+  int first = base + tid * kPairB;
+  bool dirty[kPairB];
+  int mine = 0;
+  {
+    uint64_t k[kPairB];
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q) k[q] = first + q < st.V ? cm.own[first + q] : 0ull;
+#pragma unroll
+    for (int q = 0; q < kPairB; ++q) {
+      dirty[q] = first + q < st.V && (uint32_t)(k[q] >> 32) == (uint32_t)cm.epoch;
+      mine += dirty[q] ? 1 : 0;
+    }
   }
+  int at;
+  int qn = block_scan(mine, at, L.wsum);
+#pragma unroll
+  for (int q = 0; q < kPairB; ++q)
+    if (dirty[q]) L.q[at++] = first + q;
   if (tid == 0) L.bqn = 0;
   __syncthreads();
   for (int r0 = 0; r0 < qn; r0 += kBlock)
