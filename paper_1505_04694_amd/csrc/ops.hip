@@ -9,6 +9,9 @@
 // rewrites only elements the member owns, marks the adjacency rows it touches
 // dirty and queues the additions those rows need. The commit then lets the
 // owner of each dirty row rebuild it, so no two threads ever write one row.
+#include <algorithm>
+#include <atomic>
+
 #include "kern.hpp"
 
 namespace pm {
@@ -1405,46 +1408,64 @@ __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restri
 }
 
 // The same rebuild in vertex order, for classes whose claimed rows cover a
-// good part of the mesh: a work-group scans kSweepChunk consecutive vertex
-// slots, queues the rows claimed in this epoch in LDS in slot order (a
-// block-wide ordered compaction, so every lane of a rebuild pass has a row),
-// and rebuilds them kBlock at a time. Consecutive rows then read nearby
-// headers, capacities, owner keys and target records, and walk rows and
-// elements in the order they are laid out, where the member-driven form above
-// touches them in its members' neighbour order. Every row is still rebuilt
-// once, from the same candidates, so the rows are the same.
-constexpr int kSweepChunk = kPairB * kBlock;
+// good part of the mesh: a work-group scans `chunk` consecutive vertex slots
+// (at most kSweepMax), queues the rows claimed in this epoch in LDS in slot
+// order (a block-wide ordered compaction, so every lane of a rebuild pass has
+// a row), and rebuilds them kBlock at a time. Consecutive rows then read
+// nearby headers, capacities, owner keys and target records, and walk rows
+// and elements in the order they are laid out, where the member-driven form
+// above touches them in its members' neighbour order. Every row is still
+// rebuilt once, from the same candidates, so the rows are the same.
+constexpr int kSweepStep = kPairB * kBlock;  // slots scanned per block-wide pass
+constexpr int kSweepMax = 2 * kSweepStep;    // most slots per work-group (16-bit offsets in LDS)
+struct SweepLds {
+  int col[kRegSmall * kBlock];
+  uint16_t q[kSweepMax];
+  int bq[kBlock];
+  int bqn;
+  int wsum[kBlock / kWave];
+};
+static_assert(kSweepMax <= 65536, "slot offsets are 16-bit");
+
 template <bool F>
-__global__ void __launch_bounds__(256, 5) k_commit_sweep(Store st, Commit cm, int* ctr) {
-  __shared__ CommitLds L;
+__global__ void __launch_bounds__(256, 5) k_commit_sweep(Store st, Commit cm, int chunk, int* ctr) {
+  __shared__ SweepLds L;
   if (room_failed_block(ctr)) return;
   int tid = (int)threadIdx.x;
-  int base = xcd_block() * kSweepChunk;
-  // thread tid reads the owner keys of slots base + kPairB tid + [0, kPairB),
-  // all in flight together; one block-wide scan then places the claimed rows
+  int base = xcd_block() * chunk;
+  int end = min(st.V, base + chunk);
+  // each pass: thread tid reads the owner keys of kPairB consecutive slots,
+  // all in flight together, and one block-wide scan places the claimed rows
   // in slot order
-  int first = base + tid * kPairB;
-  bool dirty[kPairB];
-  int mine = 0;
-  {
-    uint64_t k[kPairB];
+  int qn = 0;
+  for (int s0 = base; s0 < end; s0 += kSweepStep) {
+    int first = s0 + tid * kPairB;
+    bool dirty[kPairB];
+    int mine = 0;
+    {
+      uint64_t k[kPairB];
 #pragma unroll
-    for (int q = 0; q < kPairB; ++q) k[q] = first + q < st.V ? cm.own[first + q] : 0ull;
+      for (int q = 0; q < kPairB; ++q) k[q] = first + q < end ? cm.own[first + q] : 0ull;
 #pragma unroll
-    for (int q = 0; q < kPairB; ++q) {
-      dirty[q] = first + q < st.V && (uint32_t)(k[q] >> 32) == (uint32_t)cm.epoch;
-      mine += dirty[q] ? 1 : 0;
+      for (int q = 0; q < kPairB; ++q) {
+        dirty[q] = first + q < end && (uint32_t)(k[q] >> 32) == (uint32_t)cm.epoch;
+        mine += dirty[q] ? 1 : 0;
+      }
     }
-  }
-  int at;
-  int qn = block_scan(mine, at, L.wsum);
+    int at;
+    int tot = block_scan(mine, at, L.wsum);
+    at += qn;
 #pragma unroll
-  for (int q = 0; q < kPairB; ++q)
-    if (dirty[q]) L.q[at++] = first + q;
+    for (int q = 0; q < kPairB; ++q)
+      if (dirty[q]) L.q[at++] = (uint16_t)(first + q - base);
+    qn += tot;
+    __syncthreads();  // wsum is reused by the next scan
+  }
   if (tid == 0) L.bqn = 0;
   __syncthreads();
   for (int r0 = 0; r0 < qn; r0 += kBlock)
-    rebuild_row<F, kRegSmall, kBlock>(st, cm, r0 + tid < qn ? L.q[r0 + tid] : -1, L.col + tid, ctr, L.bq, &L.bqn);
+    rebuild_row<F, kRegSmall, kBlock>(st, cm, r0 + tid < qn ? base + (int)L.q[r0 + tid] : -1, L.col + tid, ctr,
+                                      L.bq, &L.bqn);
   __syncthreads();
   int nbig = min(L.bqn, kBlock);
   constexpr int H = kBlock / 2;
@@ -1454,18 +1475,54 @@ __global__ void __launch_bounds__(256, 5) k_commit_sweep(Store st, Commit cm, in
   }
 }
 
+// Work-groups of `fn` (kBlock threads) resident on the current device at
+// once: work-groups per CU from the occupancy calculator times the CUs,
+// kept per device. The commits size their grids by it, so that a grid runs
+// as one generation of resident work-groups: a grid slightly larger than
+// that runs a second, short generation that leaves most of the chip idle.
+constexpr int kMaxDevices = 64;
+int resident_blocks(const void* fn, int which) {
+  static std::atomic<int> cache[4][kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = -1;
+  if (dev >= 0) {
+    int r = cache[which][dev].load(std::memory_order_relaxed);
+    if (r > 0) return r;
+  }
+  int per = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kBlock, 0) != hipSuccess || per <= 0) per = 4;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev < 0 ? 0 : dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  int r = per * cus;
+  if (dev >= 0) cache[which][dev].store(r, std::memory_order_relaxed);
+  return r;
+}
+
 void commit_sweep(const Store& st, Commit cm, bool flips, int* ctr, hipStream_t s) {
-  int nb = (st.V + kSweepChunk - 1) / kSweepChunk;
-  if (nb <= 0) return;
+  if (st.V <= 0) return;
+  int res = flips ? resident_blocks((const void*)&k_commit_sweep<true>, 0)
+                  : resident_blocks((const void*)&k_commit_sweep<false>, 1);
+  // slots per work-group: a multiple of kBlock, at most kSweepMax
+  int64_t per = ((int64_t)st.V + res - 1) / res;
+  int chunk = (int)std::min<int64_t>(kSweepMax, std::max<int64_t>(kBlock, (per + kBlock - 1) / kBlock * kBlock));
+  int nb = (st.V + chunk - 1) / chunk;
   if (flips)
-    k_commit_sweep<true><<<nb, kBlock, 0, s>>>(st, cm, ctr);
+    k_commit_sweep<true><<<nb, kBlock, 0, s>>>(st, cm, chunk, ctr);
   else
-    k_commit_sweep<false><<<nb, kBlock, 0, s>>>(st, cm, ctr);
+    k_commit_sweep<false><<<nb, kBlock, 0, s>>>(st, cm, chunk, ctr);
 }
 
 void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips, int chunk, int* ctr, hipStream_t s) {
   if (n <= 0) return;
-  int mpb = chunk > 0 ? chunk : (n >= 256 * 1024 ? 128 : (n >= 64 * 1024 ? 64 : 16));
+  int mpb = chunk;
+  if (mpb <= 0) {
+    // members per work-group: at least 16, more when that keeps the grid
+    // within one generation of resident work-groups
+    int res = flips ? resident_blocks((const void*)&k_commit<true>, 2)
+                    : resident_blocks((const void*)&k_commit<false>, 3);
+    mpb = std::min(kBlock, std::max(16, (n + res - 1) / res));
+  }
   int nb = (n + mpb - 1) / mpb;
   if (flips)
     k_commit<true><<<nb, kBlock, 0, s>>>(st, list, n, mpb, cm, ctr);
