@@ -1329,19 +1329,24 @@ struct CommitLds {
 static_assert(kRegSmall * kBlock == kRegRow * (kBlock / 2), "the large path stages in the same LDS");
 
 // Rebuild the rows claimed by the committed members list[base .. base + cnt)
-// (cnt <= kBlock), with all kBlock threads of the block. Each thread takes
-// its member's neighbours kPairB at a time (row entries, then owner keys,
-// loaded side by side); the rows the member owns are queued in LDS in block
-// order and rebuilt 256 at a time. For flips one more round queues the
-// members' own rows, after the rounds that read the members' rows.
+// (cnt <= kBlock), with all kBlock threads of the block. Each member has tpm
+// threads (a power of two: as many as fit, so a block of few members spreads
+// each member's neighbours over its threads); a thread takes kPairB of its
+// member's neighbours per pair round (row entries, then owner keys, loaded
+// side by side). The rows a member owns are queued in LDS in block order and
+// rebuilt 256 at a time. For flips one more round queues the members' own
+// rows, after the rounds that read the members' rows.
 template <bool F>
 __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restrict__ list, int base, int cnt,
                                              const Commit& cm, int* ctr, CommitLds& L) {
   int tid = (int)threadIdx.x;
+  int lg = 0;
+  while ((cnt << (lg + 1)) <= kBlock) ++lg;
+  int mi = tid >> lg, sl = tid & ((1 << lg) - 1);
   int v = -1, deg = 0, off = 0;
   bool com = false;
-  if (tid < cnt) {
-    v = list[base + tid];
+  if (mi < cnt) {
+    v = list[base + mi];
     int ep = cm.ops[v].x;
     Hdr h = st.hdr[v];
     com = ep == cm.epoch;
@@ -1354,7 +1359,7 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
   int* mycol = L.col + tid;
   if (tid == 0) L.bqn = 0;
   bool own_round = F;
-  for (int j0 = 0;; j0 += kPairB) {
+  for (int j0 = sl * kPairB;; j0 += kPairB << lg) {
     bool pairs = __syncthreads_or(j0 < deg);
     if (!pairs && !own_round) break;
     int y[kPairB];
@@ -1365,10 +1370,11 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
       for (int q = 0; q < kPairB; ++q) k[q] = y[q] >= 0 ? cm.own[y[q]] : 0ull;
     } else {
       own_round = false;
+      bool mine_row = com && sl == 0;
 #pragma unroll
       for (int q = 0; q < kPairB; ++q) y[q] = -1;
-      if (com) y[0] = v;
-      k[0] = com ? cm.own[v] : 0ull;
+      if (mine_row) y[0] = v;
+      k[0] = mine_row ? cm.own[v] : 0ull;
 #pragma unroll
       for (int q = 1; q < kPairB; ++q) k[q] = 0ull;
     }
@@ -1395,9 +1401,8 @@ __device__ __forceinline__ void commit_chunk(const Store& st, const int* __restr
   __syncthreads();  // the LDS is reused by the next chunk
 }
 
-// One block per mpb class members (128, or fewer for small classes, so that
-// more blocks share the latency-bound work), in XCD-aware block order; one
-// kernel per kind of operation.
+// One block per mpb class members (commit_rows chooses mpb), in XCD-aware
+// block order; one kernel per kind of operation.
 template <bool F>
 __global__ void __launch_bounds__(256, 5) k_commit(Store st, const int* __restrict__ list, int n, int mpb, Commit cm,
                                                 int* ctr) {
@@ -1517,11 +1522,12 @@ void commit_rows(const Store& st, const int* list, int n, Commit cm, bool flips,
   if (n <= 0) return;
   int mpb = chunk;
   if (mpb <= 0) {
-    // members per work-group: at least 16, more when that keeps the grid
-    // within one generation of resident work-groups
+    // members per work-group: at least 4 (a small class then spreads over
+    // more work-groups, each with several threads per member), more when
+    // that keeps the grid within one generation of resident work-groups
     int res = flips ? resident_blocks((const void*)&k_commit<true>, 2)
                     : resident_blocks((const void*)&k_commit<false>, 3);
-    mpb = std::min(kBlock, std::max(16, (n + res - 1) / res));
+    mpb = std::min(kBlock, std::max(4, (n + res - 1) / res));
   }
   int nb = (n + mpb - 1) / mpb;
   if (flips)
