@@ -31,6 +31,7 @@ using pm::gtid;
 using pm::make_ctx;
 using pm::stream_seed;
 using pm::vkey;
+using pm::kWave;
 
 constexpr int kB = 256;
 constexpr int kMaxColours = 256;
@@ -299,36 +300,134 @@ __global__ void k_fill_gated(int* p, int n, int x, const int* __restrict__ gate)
   for (int i = gtid(); i < n; i += gstride()) p[i] = x;
 }
 
-// sort NE(v); NN(v) = the sorted distinct other vertices of NE(v)'s elements,
-// built in a slot of three entries per NE entry
-__global__ void k_rows_finish(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
-  for (int v = gtid(); v < st.V; v += gstride()) {
-    int o = off[v], n = cnt[v];
-    int* row = st.ne + o;
-    isort(row, n);
-    // sorted distinct neighbours, inserted one at a time (each neighbour
-    // comes from several elements: a binary search finds and skips repeats)
-    int* nb = st.nn + 3 * o;
-    int u = 0;
-    for (int i = 0; i < n; ++i) {
-      int4 e = st.tet[row[i]];
-      int id[4] = {e.x, e.y, e.z, e.w};
-      for (int j = 0; j < 4; ++j) {
-        int x = id[j];
-        if (x == v) continue;
-        int lo = 0, hi = u;
-        while (lo < hi) {
-          int mid = (lo + hi) >> 1;
-          if (nb[mid] < x) lo = mid + 1;
-          else hi = mid;
+// Serial form for rows longer than a wavefront: sort NE(v) in place; NN(v) =
+// the sorted distinct other vertices of NE(v)'s elements, inserted one at a
+// time into a slot of three entries per NE entry (a binary search finds and
+// skips repeats).
+__device__ void rows_finish_serial(const Store3& st, int v, int o, int n) {
+  int* row = st.ne + o;
+  isort(row, n);
+  int* nb = st.nn + 3 * o;
+  int u = 0;
+  for (int i = 0; i < n; ++i) {
+    int4 e = st.tet[row[i]];
+    int id[4] = {e.x, e.y, e.z, e.w};
+    for (int j = 0; j < 4; ++j) {
+      int x = id[j];
+      if (x == v) continue;
+      int lo = 0, hi = u;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (nb[mid] < x) lo = mid + 1;
+        else hi = mid;
+      }
+      if (lo < u && nb[lo] == x) continue;
+      for (int q = u; q > lo; --q) nb[q] = nb[q - 1];
+      nb[lo] = x;
+      ++u;
+    }
+  }
+  st.hdr[v] = make_int4(3 * o, u, o, n);
+}
+
+// Bitonic sorting networks across a wavefront, ascending. sort_lanes: one
+// value per lane (value i on lane i). sort_lanes4: four per lane (value i on
+// lane i / 4, register i % 4); pairs four or more apart are exchanged by
+// shuffles, nearer ones inside a lane.
+__device__ __forceinline__ int sort_lanes(int a) {
+  int lane = __lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      int o = __shfl_xor(a, j);
+      bool up = (lane & k) == 0, lo = (lane & j) == 0;
+      a = lo == up ? min(a, o) : max(a, o);
+    }
+  return a;
+}
+__device__ __forceinline__ void sort_lanes4(int (&a)[4]) {
+  int lane = __lane_id();
+#pragma unroll
+  for (int k = 2; k <= 4 * kWave; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int i = 4 * lane + r;
+          int o = __shfl_xor(a[r], j >> 2);
+          bool up = (i & k) == 0, lo = (i & j) == 0;
+          a[r] = lo == up ? min(a[r], o) : max(a[r], o);
         }
-        if (lo < u && nb[lo] == x) continue;
-        for (int q = u; q > lo; --q) nb[q] = nb[q - 1];
-        nb[lo] = x;
-        ++u;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r & j) continue;
+          int r2 = r | j, i = 4 * lane + r;
+          bool up = (i & k) == 0;
+          int x = a[r], y = a[r2];
+          a[r] = up ? min(x, y) : max(x, y);
+          a[r2] = up ? max(x, y) : min(x, y);
+        }
       }
     }
-    st.hdr[v] = make_int4(3 * o, u, o, n);
+}
+
+// Sorted rows from the loose ones: NE(v) sorted; NN(v) = the sorted distinct
+// other vertices of NE(v)'s elements, in a slot of three entries per NE
+// entry. One wavefront per vertex: NE(v) one entry per lane through the lane
+// network; the three other vertices of each element in four slots per lane
+// (the fourth empty) through the four-per-lane network, repeats dropped by
+// comparing each slot with the one before it, and the rest placed by a
+// wavefront prefix sum. Rows of more than kWave elements take the serial form
+// on the wavefront's first lane.
+__global__ void __launch_bounds__(256) k_rows_finish(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
+  int lane = __lane_id();
+  int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  int nw = (int)((int64_t)gridDim.x * blockDim.x / kWave);
+  for (int v = wid; v < st.V; v += nw) {
+    int o = off[v], n = cnt[v];
+    if (n > kWave) {
+      if (lane == 0) rows_finish_serial(st, v, o, n);
+      continue;
+    }
+    bool has = lane < n;
+    int t = has ? st.ne[o + lane] : INT_MAX;
+    int4 e = st.tet[has ? t : 0];
+    int a[4] = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+    if (has) {
+      int id[4] = {e.x, e.y, e.z, e.w};
+      int q = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (id[j] != v && q < 3) a[q++] = id[j];
+    }
+    t = sort_lanes(t);
+    if (has) st.ne[o + lane] = t;
+    sort_lanes4(a);
+    int before = __shfl_up(a[3], 1);
+    bool keep[4];
+    int mine = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int prev = r > 0 ? a[r - 1] : (lane > 0 ? before : INT_MIN);
+      keep[r] = a[r] != INT_MAX && a[r] != prev;
+      mine += keep[r] ? 1 : 0;
+    }
+    int incl = mine;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      int x = __shfl_up(incl, d);
+      if (lane >= d) incl += x;
+    }
+    int u = __shfl(incl, kWave - 1);
+    int pos = incl - mine;
+    int* nb = st.nn + 3 * o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (keep[r]) nb[pos++] = a[r];
+    if (lane == 0) st.hdr[v] = make_int4(3 * o, u, o, n);
   }
 }
 
@@ -337,15 +436,21 @@ __global__ void k_rows_finish(Store3 st, const int* __restrict__ off, const int*
 // among its coloured neighbours once every active neighbour with a larger key
 // was coloured in an earlier iteration (colours read from `col`, the state
 // before this iteration; new ones written to `col2`). The result is the
-// greedy first-fit colouring in descending key order.
+// greedy first-fit colouring in descending key order. A vertex that has to
+// wait remembers the neighbour it waits for (blk) and reads its row again
+// only once that neighbour has a colour. Counts go to the counters once per
+// wavefront.
 __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t* __restrict__ act,
-                     const int* __restrict__ col, int* col2, uint64_t sseed, int* ctr) {
+                     const int* __restrict__ col, int* col2, int* blk, uint64_t sseed, int* ctr) {
+  int coloured = 0, ncol = 0;
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
     if (col[v] >= 0) continue;
+    int b = blk[v];
+    if (b >= 0 && col[b] < 0) continue;
     uint64_t kv = vkey(sseed, (uint32_t)v);
     int4 h = st.hdr[v];
-    bool wait = false;
+    int wait = -1;
     uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
     for (int j = 0; j < h.y; ++j) {
       int w = st.nn[h.x + j];
@@ -353,11 +458,14 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
       if (c >= 0) {
         used[c >> 6] |= 1ull << (c & 63);
       } else if (act[w] && vkey(sseed, (uint32_t)w) > kv) {
-        wait = true;
+        wait = w;
         break;
       }
     }
-    if (wait) continue;
+    if (wait >= 0) {
+      blk[v] = wait;
+      continue;
+    }
     int c = -1;
     for (int q = 0; q < kMaxColours / 64 && c < 0; ++q)
       if (~used[q]) c = q * 64 + __ffsll((long long)~used[q]) - 1;
@@ -366,8 +474,17 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
       c = kMaxColours - 1;
     }
     col2[v] = c;
-    atomicAdd(&ctr[K_COLOURED], 1);
-    atomicMax(&ctr[K_NCOL], c + 1);
+    ++coloured;
+    ncol = max(ncol, c + 1);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    coloured += __shfl_xor(coloured, d);
+    ncol = max(ncol, __shfl_xor(ncol, d));
+  }
+  if (__lane_id() == 0 && coloured > 0) {
+    atomicAdd(&ctr[K_COLOURED], coloured);
+    atomicMax(&ctr[K_NCOL], ncol);
   }
 }
 
@@ -386,17 +503,47 @@ __global__ void k_set_act(const int* __restrict__ A, int n, uint8_t* act, uint8_
   for (int i = gtid(); i < n; i += gstride()) act[A[i]] = x;
 }
 
-__global__ void k_class_count(const int* __restrict__ A, int n, const int* __restrict__ col, int* cnt) {
-  for (int i = gtid(); i < n; i += gstride()) atomicAdd(&cnt[col[A[i]]], 1);
+// the list's vertices active, with no neighbour to wait for yet
+__global__ void k_jp_init(const int* __restrict__ A, int n, uint8_t* act, int* blk) {
+  for (int i = gtid(); i < n; i += gstride()) {
+    act[A[i]] = 1;
+    blk[A[i]] = -1;
+  }
 }
 
-// members of one class in list order (A is ascending, so each class is too)
-__global__ void k_class_place(const int* __restrict__ A, int n, const int* __restrict__ col, const int* __restrict__ off,
-                              int* cur, int* out) {
-  for (int i = gtid(); i < n; i += gstride()) {
-    int c = col[A[i]];
-    out[off[c] + atomicAdd(&cur[c], 1)] = A[i];
+// Class sizes: a histogram of the block's list entries in LDS, then one
+// global add per colour and block.
+__global__ void k_class_count(const int* __restrict__ A, int n, const int* __restrict__ col, int ncol, int* cnt) {
+  __shared__ int h[kMaxColours];
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) h[c] = 0;
+  __syncthreads();
+  for (int i = gtid(); i < n; i += gstride()) atomicAdd(&h[col[A[i]]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x)
+    if (h[c]) atomicAdd(&cnt[c], h[c]);
+}
+
+// Class lists: each block ranks its entries per colour in LDS, reserves one
+// range per colour with a global add, and writes the entries there. The
+// order inside a class is not fixed; the members of a class are pairwise
+// non-adjacent and their decisions do not depend on it.
+__global__ void k_class_place(const int* __restrict__ A, int n, const int* __restrict__ col, int ncol,
+                              const int* __restrict__ off, int* cur, int* out) {
+  __shared__ int h[kMaxColours], base[kMaxColours];
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) h[c] = 0;
+  __syncthreads();
+  int i = (int)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  int c = -1, r = 0, v = 0;
+  if (i < n) {
+    v = A[i];
+    c = col[v];
+    r = atomicAdd(&h[c], 1);
   }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ncol; k += blockDim.x)
+    if (h[k]) base[k] = off[k] + atomicAdd(&cur[k], h[k]);
+  __syncthreads();
+  if (c >= 0) out[base[c] + r] = v;
 }
 
 // ---- selection of active vertices ------------------------------------------------------------
@@ -884,8 +1031,8 @@ struct pm3_mesh {
   int* hctr = nullptr;  // pinned mirror
   // scratch
   int *cnt = nullptr, *off = nullptr, *cur = nullptr, *flag = nullptr, *scan = nullptr, *partial = nullptr;
-  int *A = nullptr, *cls = nullptr, *col = nullptr, *col2 = nullptr, *mark = nullptr, *tcnt = nullptr,
-      *tscan = nullptr, *ccount = nullptr, *coff = nullptr;
+  int *A = nullptr, *cls = nullptr, *col = nullptr, *col2 = nullptr, *blk = nullptr, *mark = nullptr,
+      *tcnt = nullptr, *tscan = nullptr, *ccount = nullptr, *coff = nullptr;
   uint8_t *act = nullptr, *nxt = nullptr;
   double* qbuf = nullptr;
   int scap = 0, tscap = 0, pcap = 0;
@@ -968,6 +1115,7 @@ pm_status reserve(pm3_mesh* m, int V, int T) {
     T3(dgrow(m, &m->cls, m->Vcap, nc, true));
     T3(dgrow(m, &m->col, m->Vcap, nc, true));
     T3(dgrow(m, &m->col2, m->Vcap, nc, true));
+    T3(dgrow(m, &m->blk, m->Vcap, nc, true));
     T3(dgrow(m, &m->act, m->Vcap, nc, true));
     T3(dgrow(m, &m->nxt, m->Vcap, nc, true));
     m->Vcap = nc;
@@ -1032,7 +1180,7 @@ pm_status build_rows(pm3_mesh* m, bool sorted = true) {
   }
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0);
   k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
-  k_rows_finish<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt);
+  k_rows_finish<<<grid((int64_t)V * kWave), kB, 0, m->s>>>(st, m->off, m->cnt);
   H3(hipGetLastError());
   return PM_OK;
 }
@@ -1057,13 +1205,18 @@ pm_status colour_list(pm3_mesh* m, int n, uint32_t ctx, int* ncol) {
   k_fill_int<<<grid(st.V), kB, 0, m->s>>>(m->col, st.V, -1);
   k_fill_int<<<grid(st.V), kB, 0, m->s>>>(m->col2, st.V, -1);
   k_fill_u8<<<grid(st.V), kB, 0, m->s>>>(m->act, st.V, 0);
-  k_set_act<<<grid(n), kB, 0, m->s>>>(m->A, n, m->act, 1);
+  k_jp_init<<<grid(n), kB, 0, m->s>>>(m->A, n, m->act, m->blk);
   T3(zero_ctr(m));
   int done = 0;
-  for (int it = 0; done < n; ++it) {
+  // iterations in batches of kJpBatch between read-backs (an iteration after
+  // the last vertex has its colour changes nothing)
+  constexpr int kJpBatch = 4;
+  for (int it = 0; done < n;) {
     if (it > n + 8) return fail3(m, PM_E_DEVICE, "colouring made no progress");
-    k_jp<<<grid(n), kB, 0, m->s>>>(st, m->A, n, m->act, m->col, m->col2, sseed, m->ctr);
-    k_jp_commit<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, m->col2);
+    for (int b = 0; b < kJpBatch; ++b, ++it) {
+      k_jp<<<grid(n), kB, 0, m->s>>>(st, m->A, n, m->act, m->col, m->col2, m->blk, sseed, m->ctr);
+      k_jp_commit<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, m->col2);
+    }
     H3(hipGetLastError());
     T3(read_ctr(m));
     if (m->hctr[K_ERR] & E_COLOURS) return fail3(m, PM_E_DEVICE, "more than 256 colours");
@@ -1080,7 +1233,7 @@ pm_status class_lists(pm3_mesh* m, int n, int ncol, std::vector<int>& off, std::
     T3(dgrow(m, &m->coff, 0, kMaxColours, false));
   }
   k_fill_int<<<1, 2 * kMaxColours, 0, m->s>>>(m->ccount, 2 * kMaxColours, 0);
-  k_class_count<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, m->ccount);
+  k_class_count<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, ncol, m->ccount);
   size.assign(ncol, 0);
   off.assign(ncol + 1, 0);
   H3(hipMemcpyAsync(m->hctr + K_COUNT, m->ccount, sizeof(int) * ncol, hipMemcpyDeviceToHost, m->s));
@@ -1090,7 +1243,8 @@ pm_status class_lists(pm3_mesh* m, int n, int ncol, std::vector<int>& off, std::
     off[c + 1] = off[c] + size[c];
   }
   H3(hipMemcpyAsync(m->coff, off.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, m->s));
-  k_class_place<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, m->coff, m->ccount + kMaxColours, m->cls);
+  k_class_place<<<std::max(1, (n + kB - 1) / kB), kB, 0, m->s>>>(m->A, n, m->col, ncol, m->coff,
+                                                                   m->ccount + kMaxColours, m->cls);
   H3(hipGetLastError());
   H3(hipStreamSynchronize(m->s));  // off's host copy is a local vector
   return PM_OK;
@@ -1217,7 +1371,7 @@ pm_status pm3_mesh_destroy(pm3_mesh* m) {
   dfree3(st.nn);
   dfree3(st.ne);
   for (int** p : {&m->cnt, &m->off, &m->cur, &m->flag, &m->scan, &m->partial, &m->A, &m->cls, &m->col, &m->col2,
-                  &m->mark, &m->tcnt, &m->tscan, &m->ccount, &m->coff, &m->ctr})
+                  &m->blk, &m->mark, &m->tcnt, &m->tscan, &m->ccount, &m->coff, &m->ctr})
     dfree3(*p);
   dfree3(m->act);
   dfree3(m->nxt);
