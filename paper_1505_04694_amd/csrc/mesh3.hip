@@ -47,7 +47,9 @@ enum {
   K_COMMIT = 5,     // collapses / accepted moves
   K_EDGES = 6,      // edges tested by refinement
   K_TOTAL = 7,      // scan total
-  K_CCOMMIT = 8,    // collapses of the class in progress (gates its row rebuild)
+  K_CCOMMIT = 8,    // collapses of the class in progress (gates its row commit)
+  K_ROOM = 9,       // a row commit ran out of room (pool stripe full, or a row past the wavefront form)
+  K_ROOMEP = 10,    // the epoch of the class whose commit ran out of room
   K_COUNT = 16
 };
 enum { E_MESH = 1, E_METRIC = 2, E_COLOURS = 4, E_LEAVES = 8 };
@@ -64,7 +66,8 @@ struct Store3 {
   uint8_t* valive = nullptr;
   int4* tet = nullptr;
   uint8_t* talive = nullptr;
-  int4* hdr = nullptr;  // (nn_off, nn_cnt, ne_off, ne_cnt)
+  int4* hdr = nullptr;  // (nn_off, nn_cnt, ne_off, ne_cnt); NN's slot is 3 x NE's
+  int* cap = nullptr;   // NE slot capacity of each row (NN's: 3 x)
   int* nn = nullptr;
   int* ne = nullptr;
 };
@@ -227,8 +230,7 @@ __global__ void k_orient(Store3 st, int* ctr) {
 
 // ---- rows from the element list ----------------------------------------------------------
 
-__global__ void k_ne_count(Store3 st, int* cnt, const int* __restrict__ gate = nullptr) {
-  if (gate && *gate == 0) return;
+__global__ void k_ne_count(Store3 st, int* cnt) {
   for (int t = gtid(); t < st.T; t += gstride()) {
     if (!st.talive[t]) continue;
     int4 e = st.tet[t];
@@ -263,43 +265,6 @@ __device__ void isort(int* a, int n) {
   }
 }
 
-// Loose rows for the rounds of a coarsening phase: NE(v) in any order, NN(v)
-// the other three vertices of each NE(v) element (repeats included). The
-// class kernels read rows only through order-free questions (is a same-class
-// neighbour of larger key present, the smallest candidate pair above the last
-// one, mark every neighbour), so loose rows give the same decisions as sorted
-// ones; sorted rows are built once the phase ends.
-__global__ void k_ne_fill_loose(Store3 st, const int* __restrict__ off, int* cur, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  for (int t = gtid(); t < st.T; t += gstride()) {
-    if (!st.talive[t]) continue;
-    int4 e = st.tet[t];
-    int id[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int pos = off[id[k]] + atomicAdd(&cur[id[k]], 1);
-      st.ne[pos] = t;
-      int* nb = st.nn + 3 * pos;
-      int q = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (j != k) nb[q++] = id[j];
-    }
-  }
-}
-
-__global__ void k_hdr_loose(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt,
-                            const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;
-  for (int v = gtid(); v < st.V; v += gstride()) st.hdr[v] = make_int4(3 * off[v], 3 * cnt[v], off[v], cnt[v]);
-}
-
-// fills p[0, n) with x unless the gate counter is zero (the class changed nothing)
-__global__ void k_fill_gated(int* p, int n, int x, const int* __restrict__ gate) {
-  if (*gate == 0) return;
-  for (int i = gtid(); i < n; i += gstride()) p[i] = x;
-}
-
 // Serial form for rows longer than a wavefront: sort NE(v) in place; NN(v) =
 // the sorted distinct other vertices of NE(v)'s elements, inserted one at a
 // time into a slot of three entries per NE entry (a binary search finds and
@@ -328,12 +293,14 @@ __device__ void rows_finish_serial(const Store3& st, int v, int o, int n) {
     }
   }
   st.hdr[v] = make_int4(3 * o, u, o, n);
+  st.cap[v] = n;
 }
 
 // Bitonic sorting networks across a wavefront, ascending. sort_lanes: one
-// value per lane (value i on lane i). sort_lanes4: four per lane (value i on
-// lane i / 4, register i % 4); pairs four or more apart are exchanged by
-// shuffles, nearer ones inside a lane.
+// value per lane (value i on lane i). sort_lanes_r<R>: R per lane (value i on
+// lane i / R, register i % R); pairs R or more apart are exchanged by
+// shuffles, nearer ones inside a lane. lanes_at<R>: each lane's value of
+// index i (its own i) from the R-per-lane layout.
 __device__ __forceinline__ int sort_lanes(int a) {
   int lane = __lane_id();
 #pragma unroll
@@ -346,25 +313,26 @@ __device__ __forceinline__ int sort_lanes(int a) {
     }
   return a;
 }
-__device__ __forceinline__ void sort_lanes4(int (&a)[4]) {
+template <int R>
+__device__ __forceinline__ void sort_lanes_r(int (&a)[R]) {
   int lane = __lane_id();
 #pragma unroll
-  for (int k = 2; k <= 4 * kWave; k <<= 1)
+  for (int k = 2; k <= R * kWave; k <<= 1)
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j >= 4) {
+      if (j >= R) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int i = 4 * lane + r;
-          int o = __shfl_xor(a[r], j >> 2);
+        for (int r = 0; r < R; ++r) {
+          int i = R * lane + r;
+          int o = __shfl_xor(a[r], j / R);
           bool up = (i & k) == 0, lo = (i & j) == 0;
           a[r] = lo == up ? min(a[r], o) : max(a[r], o);
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
           if (r & j) continue;
-          int r2 = r | j, i = 4 * lane + r;
+          int r2 = r | j, i = R * lane + r;
           bool up = (i & k) == 0;
           int x = a[r], y = a[r2];
           a[r] = up ? min(x, y) : max(x, y);
@@ -373,15 +341,252 @@ __device__ __forceinline__ void sort_lanes4(int (&a)[4]) {
       }
     }
 }
+template <int R>
+__device__ __forceinline__ int lanes_at(const int (&a)[R], int i) {
+  int src = i / R, q = i % R, out = INT_MAX;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int x = __shfl(a[r], src);
+    if (r == q) out = x;
+  }
+  return out;
+}
 
-// Sorted rows from the loose ones: NE(v) sorted; NN(v) = the sorted distinct
-// other vertices of NE(v)'s elements, in a slot of three entries per NE
-// entry. One wavefront per vertex: NE(v) one entry per lane through the lane
-// network; the three other vertices of each element in four slots per lane
-// (the fourth empty) through the four-per-lane network, repeats dropped by
-// comparing each slot with the one before it, and the rest placed by a
-// wavefront prefix sum. Rows of more than kWave elements take the serial form
-// on the wavefront's first lane.
+// Sorted distinct values of the R-per-lane layout `a` (sorted, INT_MAX for
+// none) written to dst[0, u) where dst is the same on every lane; returns u.
+template <int R>
+__device__ __forceinline__ int put_distinct(const int (&a)[R], int* dst) {
+  int lane = __lane_id();
+  int before = __shfl_up(a[R - 1], 1);
+  bool keep[R];
+  int mine = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int prev = r > 0 ? a[r - 1] : (lane > 0 ? before : INT_MIN);
+    keep[r] = a[r] != INT_MAX && a[r] != prev;
+    mine += keep[r] ? 1 : 0;
+  }
+  int incl = mine;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int x = __shfl_up(incl, d);
+    if (lane >= d) incl += x;
+  }
+  int pos = incl - mine;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (keep[r]) dst[pos++] = a[r];
+  return __shfl(incl, kWave - 1);
+}
+
+// ---- row commit after a collapse class ---------------------------------------------------------
+// The collapse kernel stamps every row its members change with the class
+// epoch (own) and records each committed member's target (rec). One
+// wavefront per stamped row x rebuilds it: the candidates are NE(x) and the
+// NE rows of the members collapsed onto x (neighbours of x whose record
+// names x); NE(x) = the sorted distinct candidates that are live and hold x,
+// NN(x) = the sorted distinct other vertices of those elements. The row is
+// written in place when it fits its slot, else in fresh space from one of
+// kTopStripes bump pointers (a stripe per row id modulo the count, each with
+// its own range of the pool). Rows past this form (NE above 4 kWave, an
+// absorbed row above 2 kWave, more than two absorbed rows) and a full stripe
+// set the room counter instead; the later classes of the round then stand
+// down and the host rebuilds every row before it runs them again.
+constexpr int kTopStripes = 64;
+constexpr int kTopStride = 16;  // ints between two stripes' bump pointers
+
+__device__ __forceinline__ void room3(int* ctr, int epoch) {
+  ctr[K_ROOMEP] = epoch;
+  atomicOr(&ctr[K_ROOM], 1);
+}
+
+// Row x from its candidates, RC slots per lane: NE(x) (slot o, count n)
+// followed by the rows of the absorbed members (za[j], counts ca[j], j <
+// nab), at most RC kWave candidates in all. RN = 2 RC slots per lane hold
+// the NN candidates. Writes the row in place when it holds at most capx
+// entries, else in fresh space of x's stripe (tops given), and returns
+// false, having written nothing, when the row has more than RN/4 kWave
+// entries or the stripe is full. Every lane of the wavefront makes this call.
+constexpr int kAbsMax = 8;  // absorbed rows a row commit takes
+template <int RC, int RN>
+__device__ __forceinline__ bool put_row3(const Store3& st, int x, int o, int n, int capx, const int (&za)[kAbsMax],
+                                         const int (&ca)[kAbsMax], int nab, int* tops, int64_t base, int64_t per) {
+  static_assert(RN == 2 * RC, "three other vertices per element, four slots each");
+  int lane = __lane_id();
+  int a[RC];
+#pragma unroll
+  for (int r = 0; r < RC; ++r) {
+    // candidate idx of the list NE(x), then the absorbed rows in turn
+    int idx = r * kWave + lane;
+    int src = -1;
+    if (idx < n) {
+      src = o + idx;
+    } else {
+      int q = idx - n;
+      for (int j = 0; j < nab; ++j) {
+        if (q < ca[j]) {
+          src = za[j] + q;
+          break;
+        }
+        q -= ca[j];
+      }
+    }
+    a[r] = src >= 0 ? st.ne[src] : -1;
+  }
+  {
+    int4 e[RC];
+    uint8_t al[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      e[r] = st.tet[max(a[r], 0)];
+      al[r] = st.talive[max(a[r], 0)];
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r) a[r] = a[r] >= 0 && al[r] && has4(e[r], x) ? a[r] : INT_MAX;
+  }
+  sort_lanes_r<RC>(a);
+  // repeats out, then sorted again: the distinct entries come first
+  {
+    int before = __shfl_up(a[RC - 1], 1);
+    bool dup[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+      int prev = r > 0 ? a[r - 1] : (lane > 0 ? before : INT_MIN);
+      dup[r] = a[r] != INT_MAX && a[r] == prev;
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+      if (dup[r]) a[r] = INT_MAX;
+  }
+  sort_lanes_r<RC>(a);
+  int m = 0;
+#pragma unroll
+  for (int r = 0; r < RC; ++r) m += a[r] != INT_MAX ? 1 : 0;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) m += __shfl_xor(m, d);
+  constexpr int K = RN / 4;  // elements per lane
+  if (m > K * kWave) return false;
+  int el[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) el[k] = lanes_at<RC>(a, lane + k * kWave);
+  // the slot: in place, else fresh space from the row's stripe
+  int off = o, cap = capx;
+  if (m > capx) {
+    int need = 2 * m;
+    int sidx = x % kTopStripes;
+    int got = 0;
+    if (lane == 0) got = atomicAdd(&tops[sidx * kTopStride], need);
+    got = __shfl(got, 0);
+    if ((int64_t)got + need > base + (int64_t)(sidx + 1) * per) return false;
+    off = got;
+    cap = need;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (lane + k * kWave < m) st.ne[off + k * kWave + lane] = el[k];
+  // NN: the other three vertices of each element, four slots per element
+  int b[RN];
+#pragma unroll
+  for (int r = 0; r < RN; ++r) b[r] = INT_MAX;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    if (lane + k * kWave < m) {
+      int4 f = st.tet[el[k]];
+      int id[4] = {f.x, f.y, f.z, f.w}, q = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (id[j] != x && q < 3) b[4 * k + q++] = id[j];
+    }
+  }
+  sort_lanes_r<RN>(b);
+  int u = put_distinct<RN>(b, st.nn + 3 * (int64_t)off);
+  if (lane == 0) {
+    st.hdr[x] = make_int4(3 * off, u, off, m);
+    st.cap[x] = cap;
+  }
+  return true;
+}
+
+// one stamped row (every lane of the wavefront)
+__device__ __forceinline__ void commit_row3(const Store3& st, int x, int epoch, const int2* __restrict__ rec,
+                                            int* tops, int64_t base, int64_t per, int* ctr) {
+  int lane = __lane_id();
+  int4 h = st.hdr[x];
+  int capx = st.cap[x];
+  if (h.y > 4 * kWave) {
+    if (lane == 0) room3(ctr, epoch);
+    return;
+  }
+  // members collapsed onto x: neighbours whose record names x
+  int w[4];
+  uint64_t bal[4];
+  int nab = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int j = k * kWave + lane;
+    w[k] = j < h.y ? st.nn[h.x + j] : -1;
+    int2 r = w[k] >= 0 ? rec[w[k]] : make_int2(-1, -1);
+    bal[k] = __ballot(r.x == epoch && r.y == x);
+    nab += __popcll(bal[k]);
+  }
+  int za[kAbsMax], ca[kAbsMax];
+  int tot = h.w;
+  if (nab <= kAbsMax) {
+    int got = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint64_t b = bal[k];
+      while (b) {
+        int l = __ffsll((unsigned long long)b) - 1;
+        b &= b - 1;
+        int z = __shfl(w[k], l);
+        int4 hz = st.hdr[z];
+        za[got] = hz.z;
+        ca[got] = hz.w;
+        tot += hz.w;
+        ++got;
+      }
+    }
+  }
+  // the smaller form when every candidate could be kept in it
+  bool ok = false;
+  if (nab <= kAbsMax && tot <= 2 * kWave)
+    ok = put_row3<4, 8>(st, x, h.z, h.w, capx, za, ca, nab, tops, base, per);
+  else if (nab <= kAbsMax && tot <= 8 * kWave)
+    ok = put_row3<8, 16>(st, x, h.z, h.w, capx, za, ca, nab, tops, base, per);
+  if (!ok && lane == 0) room3(ctr, epoch);
+}
+
+// Each wavefront takes a range of vertex slots, reads their stamps a
+// wavefront at a time and rebuilds the stamped rows in turn.
+__global__ void __launch_bounds__(256) k_commit3(Store3 st, int epoch, const int* __restrict__ own,
+                                                 const int2* __restrict__ rec, int* tops, int64_t base,
+                                                 int64_t per, int* ctr) {
+  if (ctr[K_CCOMMIT] == 0 || ctr[K_ROOM]) return;
+  int lane = __lane_id();
+  int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  int nw = (int)((int64_t)gridDim.x * blockDim.x / kWave);
+  int per_wave = (st.V + nw - 1) / nw;
+  int x0 = (int)min((int64_t)wid * per_wave, (int64_t)st.V), x1 = min(st.V, x0 + per_wave);
+  for (int c0 = x0; c0 < x1; c0 += kWave) {
+    int xi = c0 + lane;
+    uint64_t dm = __ballot(xi < x1 && own[xi] == epoch);
+    while (dm) {
+      int l = __ffsll((unsigned long long)dm) - 1;
+      dm &= dm - 1;
+      commit_row3(st, c0 + l, epoch, rec, tops, base, per, ctr);
+    }
+  }
+}
+
+// Sorted rows from the element lists gathered in build order: NE(v) sorted;
+// NN(v) = the sorted distinct other vertices of NE(v)'s elements, in a slot
+// of three entries per NE entry. One wavefront per vertex: NE(v) one entry
+// per lane through the lane network; the three other vertices of each
+// element in four slots per lane (the fourth empty) through the
+// four-per-lane network, repeats dropped by comparing each slot with the one
+// before it. Rows of more than kWave elements take the serial form on the
+// wavefront's first lane.
 __global__ void __launch_bounds__(256) k_rows_finish(Store3 st, const int* __restrict__ off, const int* __restrict__ cnt) {
   int lane = __lane_id();
   int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
@@ -389,7 +594,10 @@ __global__ void __launch_bounds__(256) k_rows_finish(Store3 st, const int* __res
   for (int v = wid; v < st.V; v += nw) {
     int o = off[v], n = cnt[v];
     if (n > kWave) {
-      if (lane == 0) rows_finish_serial(st, v, o, n);
+      // in place (capacity n), no absorbed rows: the row always fits
+      const int none[kAbsMax] = {};
+      if (n > 8 * kWave || !put_row3<8, 16>(st, v, o, n, n, none, none, 0, nullptr, 0, 0))
+        if (lane == 0) rows_finish_serial(st, v, o, n);
       continue;
     }
     bool has = lane < n;
@@ -405,30 +613,20 @@ __global__ void __launch_bounds__(256) k_rows_finish(Store3 st, const int* __res
     }
     t = sort_lanes(t);
     if (has) st.ne[o + lane] = t;
-    sort_lanes4(a);
-    int before = __shfl_up(a[3], 1);
-    bool keep[4];
-    int mine = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int prev = r > 0 ? a[r - 1] : (lane > 0 ? before : INT_MIN);
-      keep[r] = a[r] != INT_MAX && a[r] != prev;
-      mine += keep[r] ? 1 : 0;
+    sort_lanes_r<4>(a);
+    int u = put_distinct<4>(a, st.nn + 3 * o);
+    if (lane == 0) {
+      st.hdr[v] = make_int4(3 * o, u, o, n);
+      st.cap[v] = n;
     }
-    int incl = mine;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      int x = __shfl_up(incl, d);
-      if (lane >= d) incl += x;
-    }
-    int u = __shfl(incl, kWave - 1);
-    int pos = incl - mine;
-    int* nb = st.nn + 3 * o;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (keep[r]) nb[pos++] = a[r];
-    if (lane == 0) st.hdr[v] = make_int4(3 * o, u, o, n);
   }
+}
+
+// the stripes' bump pointers after a full row build: stripe s owns
+// [base + s per, base + (s + 1) per)
+__global__ void k_tops_init(int* tops, int64_t base, int64_t per) {
+  int s = (int)threadIdx.x;
+  if (s < kTopStripes) tops[s * kTopStride] = (int)(base + (int64_t)s * per);
 }
 
 // ---- colouring (Sec. 3.2) -----------------------------------------------------------------
@@ -600,7 +798,11 @@ __device__ __forceinline__ bool grp_any(bool p) {
 
 __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restrict__ list, int n,
                                                   const int* __restrict__ col, int c, uint64_t sseed, double L_low2,
-                                                  double qmin3, uint8_t* nxt, int* ctr) {
+                                                  double qmin3, uint8_t* nxt, int epoch, int* own, int2* rec,
+                                                  int* ctr) {
+  // an earlier class's row commit ran out of room: the host rebuilds the
+  // rows and runs this class again
+  if (ctr[K_ROOM]) return;
   int j0 = __lane_id() & (kL - 1);
   int gid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kL);
   bool act = gid < n;
@@ -683,11 +885,20 @@ __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restri
       else
         st.tet[t] = canon4(replace4(e, v, target));
     }
+    // the changed rows (every neighbour's, the target's among them) for the
+    // row commit, and the member's target
     for (int jb = 0; jb < h.y; jb += kL) {
       int j = jb + j0;
-      if (j < h.y) nxt[st.nn[h.x + j]] = 1;
+      if (j < h.y) {
+        int w = st.nn[h.x + j];
+        nxt[w] = 1;
+        own[w] = epoch;
+      }
     }
-    if (j0 == 0) st.valive[v] = 0;
+    if (j0 == 0) {
+      st.valive[v] = 0;
+      rec[v] = make_int2(epoch, target);
+    }
     cm = 1;
   }
   if (j0 != 0) ev = df = cm = 0;
@@ -1037,6 +1248,15 @@ struct pm3_mesh {
   double* qbuf = nullptr;
   int scap = 0, tscap = 0, pcap = 0;
   int64_t mcap = 0;
+  // row commit: per-vertex class stamps and member records, the stripes'
+  // bump pointers, the epoch of the last class, and the pool range above
+  // the last full build that the stripes share
+  int* own = nullptr;
+  int2* rec = nullptr;
+  int* tops = nullptr;
+  int epoch = 0;
+  int64_t top_base = 0, top_per = 0;
+  double headroom = 3.0;  // pool_headroom of the creation options
 };
 
 namespace {
@@ -1118,6 +1338,13 @@ pm_status reserve(pm3_mesh* m, int V, int T) {
     T3(dgrow(m, &m->blk, m->Vcap, nc, true));
     T3(dgrow(m, &m->act, m->Vcap, nc, true));
     T3(dgrow(m, &m->nxt, m->Vcap, nc, true));
+    T3(dgrow(m, &st.cap, m->Vcap, nc, true));
+    T3(dgrow(m, &m->own, m->Vcap, nc, true));
+    T3(dgrow(m, &m->rec, m->Vcap, nc, true));
+    // new vertex slots carry no class stamp or record
+    k_fill_int<<<grid(nc - m->Vcap), kB, 0, m->s>>>(m->own + m->Vcap, nc - m->Vcap, -1);
+    k_fill_int<<<grid(2 * (int64_t)(nc - m->Vcap)), kB, 0, m->s>>>((int*)(m->rec + m->Vcap), 2 * (nc - m->Vcap), -1);
+    H3(hipGetLastError());
     m->Vcap = nc;
   }
   if (T > m->Tcap) {
@@ -1148,39 +1375,41 @@ pm_status scan_total(pm3_mesh* m, const int* in, int* out, int n, int* total) {
 
 // every row from the live elements; sorted rows, or loose ones inside a
 // coarsening phase
-pm_status build_rows(pm3_mesh* m, bool sorted = true) {
+// Every row from the element list, packed and sorted; the pools keep the
+// headroom times the packed size free above it for the row commits of a
+// coarsening phase (a row that outgrows its slot moves, with twice the room,
+// and its old slot stays unused until the next full build), split into the
+// stripes' ranges. Clears the room counters.
+pm_status build_rows(pm3_mesh* m) {
   Store3& st = m->st;
   int V = st.V;
-  if (!sorted) {
-    // inside a coarsening phase: the element count only falls, so the rows fit
-    // their arrays, and the rebuild runs only if the class collapsed anything
-    // (the kernels check the class's counter): nothing is read back
-    const int* gate = m->ctr + K_CCOMMIT;
-    k_fill_gated<<<grid(V + 1), kB, 0, m->s>>>(m->cnt, V + 1, 0, gate);
-    k_ne_count<<<grid(st.T), kB, 0, m->s>>>(st, m->cnt, gate);
-    pm::scan_excl(m->cnt, m->off, V, m->ctr + K_TOTAL, m->partial, m->s);
-    k_fill_gated<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0, gate);
-    k_ne_fill_loose<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur, gate);
-    k_hdr_loose<<<grid(V), kB, 0, m->s>>>(st, m->off, m->cnt, gate);
-    H3(hipGetLastError());
-    return PM_OK;
-  }
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cnt, V + 1, 0);
   k_ne_count<<<grid(st.T), kB, 0, m->s>>>(st, m->cnt);
   int total = 0;
   T3(scan_total(m, m->cnt, m->off, V, &total));
-  if (total > m->necap) {
-    int64_t nc = std::max<int64_t>(total, m->necap + m->necap / 2);
+  int64_t want = total + (int64_t)(m->headroom * (double)total) + kTopStripes * 64;
+  if (want > m->necap) {
+    int64_t nc = std::max<int64_t>(want, m->necap + m->necap / 2);
+    if (3 * nc > INT32_MAX) return fail3(m, PM_E_NOMEM, "adjacency pool beyond 2^31 entries");
     T3(dgrow(m, &st.ne, m->necap, nc, false));
     T3(dgrow(m, &st.nn, m->nncap, 3 * nc, false));
-    T3(dgrow(m, &m->mark, m->mcap, 3 * nc, false));
     m->necap = nc;
     m->nncap = 3 * nc;
-    m->mcap = 3 * nc;
   }
+  // refinement marks NN entries of packed rows only
+  if (3 * (int64_t)total + 3 > m->mcap) {
+    int64_t nc = std::max<int64_t>(3 * (int64_t)total + 3, m->mcap + m->mcap / 2);
+    T3(dgrow(m, &m->mark, m->mcap, nc, false));
+    m->mcap = nc;
+  }
+  if (!m->tops) T3(dgrow(m, &m->tops, 0, kTopStripes * kTopStride, false));
   k_fill_int<<<grid(V + 1), kB, 0, m->s>>>(m->cur, V + 1, 0);
   k_ne_fill<<<grid(st.T), kB, 0, m->s>>>(st, m->off, m->cur);
   k_rows_finish<<<grid((int64_t)V * kWave), kB, 0, m->s>>>(st, m->off, m->cnt);
+  m->top_base = total;
+  m->top_per = (m->necap - total) / kTopStripes;
+  k_tops_init<<<1, kTopStripes, 0, m->s>>>(m->tops, m->top_base, m->top_per);
+  k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_ROOM, 2, 0);
   H3(hipGetLastError());
   return PM_OK;
 }
@@ -1311,6 +1540,12 @@ pm_status pm3_mesh_create(const pm3_mesh_desc* d, const pm_options* o, void* str
   if (!m) return PM_E_NOMEM;
   m->s = (hipStream_t)stream;
   m->seed = o->seed;
+  if (!(o->pool_headroom == 0.0 || (o->pool_headroom >= 1.0 && o->pool_headroom <= 64.0))) {
+    delete m;
+    g3_create_err = "pool_headroom: 0 (the default) or within [1, 64]";
+    return PM_E_ARG;
+  }
+  m->headroom = o->pool_headroom > 0.0 ? o->pool_headroom : 3.0;
   auto bail = [&](pm_status s) {
     g3_create_err = m->err.empty() ? std::string("pm3_mesh_create failed") : m->err;
     pm3_mesh_destroy(m);
@@ -1376,6 +1611,10 @@ pm_status pm3_mesh_destroy(pm3_mesh* m) {
   dfree3(m->act);
   dfree3(m->nxt);
   dfree3(m->qbuf);
+  dfree3(st.cap);
+  dfree3(m->own);
+  dfree3(m->rec);
+  dfree3(m->tops);
   if (m->hctr) (void)hipHostFree(m->hctr);
   delete m;
   return PM_OK;
@@ -1513,15 +1752,34 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
     sv[PM_S_COLOURS] += ncol;
     T3(class_lists(m, n, ncol, off, size));
     // the colouring zeroed the counters: the round's stats accumulate on the
-    // device and come back with the next list's length
-    for (int c = 0; c < ncol; ++c) {
-      if (size[c] == 0) continue;
-      k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_CCOMMIT, 1, 0);
-      int nb = (int)(((int64_t)size[c] * kL + kB - 1) / kB);
-      k_collapse<<<nb, kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3, m->nxt,
-                                       m->ctr);
-      H3(hipGetLastError());
-      T3(build_rows(m, false));
+    // device and come back with the next list's length. Each class: the
+    // collapses, then the commit of the rows they changed. A commit that runs
+    // out of room makes the round's later classes stand down; the host then
+    // rebuilds every row from the elements and runs those classes again.
+    std::vector<int> class_epoch(ncol, -1);
+    int c0 = 0;
+    for (;;) {
+      for (int c = c0; c < ncol; ++c) {
+        if (size[c] == 0) continue;
+        int ep = ++m->epoch;
+        class_epoch[c] = ep;
+        k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_CCOMMIT, 1, 0);
+        int nb = (int)(((int64_t)size[c] * kL + kB - 1) / kB);
+        k_collapse<<<nb, kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3,
+                                         m->nxt, ep, m->own, m->rec, m->ctr);
+        k_commit3<<<grid((int64_t)st.V * kWave), kB, 0, m->s>>>(st, ep, m->own, m->rec, m->tops, m->top_base,
+                                                                 m->top_per, m->ctr);
+        H3(hipGetLastError());
+      }
+      T3(read_ctr(m));
+      if (!m->hctr[K_ROOM]) break;
+      int failed = -1;
+      for (int c = 0; c < ncol; ++c)
+        if (class_epoch[c] == m->hctr[K_ROOMEP]) failed = c;
+      if (failed < c0) return fail3(m, PM_E_DEVICE, "row commit: room counter names no class of this round");
+      T3(build_rows(m));
+      ++sv[13];
+      c0 = failed + 1;
     }
     T3(select_list(m, 1, o->L_low2, &n));
     T3(read_ctr(m));

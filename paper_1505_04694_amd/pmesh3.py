@@ -68,7 +68,7 @@ def _check(h, status):
 class Mesh3:
     """Owning wrapper around a pm3_mesh handle (host or torch-device arrays)."""
 
-    def __init__(self, xyz, tet, metric, tags=None, seed: int = 0, stream=None):
+    def __init__(self, xyz, tet, metric, tags=None, seed: int = 0, stream=None, pool_headroom: float = 0.0):
         on_dev = hasattr(xyz, "data_ptr")
         if on_dev:
             keep = [xyz.contiguous(), tet.contiguous().int(), metric.contiguous(),
@@ -80,6 +80,8 @@ class Mesh3:
         d = MeshDesc3(_p(keep[0]), _p(keep[1]), _p(keep[2]), _p(keep[3]), keep[0].shape[0], keep[1].shape[0],
                       PM_MEM_DEVICE if on_dev else PM_MEM_HOST)
         o = pm_default_options(seed=seed)
+        if pool_headroom:
+            o.pool_headroom = pool_headroom
         h = C.c_void_p()
         if stream is None:
             import torch

@@ -153,6 +153,25 @@ def test_psi_benchmark_full_size_matches_the_oracle_result():
     assert abs(Q - gold["quality"][0]) <= 1e-12 * abs(Q) and abs(qmin - gold["quality"][1]) <= 1e-14 * qmin
 
 
+def test_commit_out_of_room_rebuilds_and_matches_the_oracle():
+    """Pools with the least headroom: row commits of the coarsening run out of
+    room, the host rebuilds every row from the elements and runs the round's
+    later classes again. Every phase still equals the oracle's."""
+    mi = inputs.psi_start3(17, target=40000.0)
+    om = OracleMesh3.from_input(mi, seed=0)
+    gm = Mesh3.from_input(mi, seed=0, pool_headroom=1.0)
+    rebuilt = 0
+    for it in range(2):
+        sg = gm.coarsen(it)
+        compare_stats(om.coarsen(it), sg, f"iteration {it} coarsen")
+        compare(om, gm, f"iteration {it} coarsen")
+        rebuilt += sg["room_rebuilds"]
+        compare_stats(om.refine(), gm.refine(), f"iteration {it} refine")
+        compare(om, gm, f"iteration {it} refine")
+    assert rebuilt > 0
+    checker3.check_mesh(gm.export(), rows=gm.rows())
+
+
 def test_single_element_and_nothing_to_do():
     # one tetrahedron: nothing to collapse (every vertex a cube corner), one
     # refinement pass of its long edges, smoothing of no interior vertex
