@@ -630,30 +630,35 @@ __global__ void k_tops_init(int* tops, int64_t base, int64_t per) {
 }
 
 // ---- colouring (Sec. 3.2) -----------------------------------------------------------------
-// One Jones-Plassmann iteration: a waiting vertex takes the first colour free
-// among its coloured neighbours once every active neighbour with a larger key
-// was coloured in an earlier iteration (colours read from `col`, the state
-// before this iteration; new ones written to `col2`). The result is the
-// greedy first-fit colouring in descending key order. A vertex that has to
-// wait remembers the neighbour it waits for (blk) and reads its row again
-// only once that neighbour has a colour. Counts go to the counters once per
-// wavefront.
-__global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t* __restrict__ act,
-                     const int* __restrict__ col, int* col2, int* blk, uint64_t sseed, int* ctr) {
+// One Jones-Plassmann iteration `it`: a waiting vertex takes the first colour
+// free among its coloured neighbours once every active neighbour with a
+// larger key was coloured in an earlier iteration. A colour is stored with
+// its iteration, (it << 8) | colour, and a neighbour coloured in this same
+// iteration counts as waiting, so the result does not depend on the order in
+// which the threads run: the greedy first-fit colouring in descending key
+// order. k_jp_strip leaves the colours alone once the colouring is done. A
+// vertex that has to wait remembers the neighbour it waits for (blk) and
+// reads its row again only once that neighbour has a colour. Counts go to
+// the counters once per wavefront.
+__device__ __forceinline__ bool coloured_before(int cw, int it) { return cw >= 0 && (cw >> 8) < it; }
+
+__global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t* __restrict__ act, int* col,
+                     int* blk, int it, uint64_t sseed, int* ctr) {
   int coloured = 0, ncol = 0;
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
     if (col[v] >= 0) continue;
     int b = blk[v];
-    if (b >= 0 && col[b] < 0) continue;
+    if (b >= 0 && !coloured_before(col[b], it)) continue;
     uint64_t kv = vkey(sseed, (uint32_t)v);
     int4 h = st.hdr[v];
     int wait = -1;
     uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
     for (int j = 0; j < h.y; ++j) {
       int w = st.nn[h.x + j];
-      int c = col[w];
-      if (c >= 0) {
+      int cw = col[w];
+      if (coloured_before(cw, it)) {
+        int c = cw & 0xFF;
         used[c >> 6] |= 1ull << (c & 63);
       } else if (act[w] && vkey(sseed, (uint32_t)w) > kv) {
         wait = w;
@@ -671,7 +676,7 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
       atomicOr(&ctr[K_ERR], E_COLOURS);
       c = kMaxColours - 1;
     }
-    col2[v] = c;
+    col[v] = (it << 8) | c;
     ++coloured;
     ncol = max(ncol, c + 1);
   }
@@ -686,10 +691,10 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
   }
 }
 
-__global__ void k_jp_commit(const int* __restrict__ A, int n, int* col, const int* __restrict__ col2) {
+__global__ void k_jp_strip(const int* __restrict__ A, int n, int* col) {
   for (int i = gtid(); i < n; i += gstride()) {
     int v = A[i];
-    if (col[v] < 0 && col2[v] >= 0) col[v] = col2[v];
+    if (col[v] >= 0) col[v] &= 0xFF;
   }
 }
 
@@ -1242,7 +1247,7 @@ struct pm3_mesh {
   int* hctr = nullptr;  // pinned mirror
   // scratch
   int *cnt = nullptr, *off = nullptr, *cur = nullptr, *flag = nullptr, *scan = nullptr, *partial = nullptr;
-  int *A = nullptr, *cls = nullptr, *col = nullptr, *col2 = nullptr, *blk = nullptr, *mark = nullptr,
+  int *A = nullptr, *cls = nullptr, *col = nullptr, *blk = nullptr, *mark = nullptr,
       *tcnt = nullptr, *tscan = nullptr, *ccount = nullptr, *coff = nullptr;
   uint8_t *act = nullptr, *nxt = nullptr;
   double* qbuf = nullptr;
@@ -1334,7 +1339,6 @@ pm_status reserve(pm3_mesh* m, int V, int T) {
     T3(dgrow(m, &m->A, m->Vcap, nc, true));
     T3(dgrow(m, &m->cls, m->Vcap, nc, true));
     T3(dgrow(m, &m->col, m->Vcap, nc, true));
-    T3(dgrow(m, &m->col2, m->Vcap, nc, true));
     T3(dgrow(m, &m->blk, m->Vcap, nc, true));
     T3(dgrow(m, &m->act, m->Vcap, nc, true));
     T3(dgrow(m, &m->nxt, m->Vcap, nc, true));
@@ -1432,7 +1436,6 @@ pm_status colour_list(pm3_mesh* m, int n, uint32_t ctx, int* ncol) {
   Store3& st = m->st;
   uint64_t sseed = stream_seed(m->seed, ctx);
   k_fill_int<<<grid(st.V), kB, 0, m->s>>>(m->col, st.V, -1);
-  k_fill_int<<<grid(st.V), kB, 0, m->s>>>(m->col2, st.V, -1);
   k_fill_u8<<<grid(st.V), kB, 0, m->s>>>(m->act, st.V, 0);
   k_jp_init<<<grid(n), kB, 0, m->s>>>(m->A, n, m->act, m->blk);
   T3(zero_ctr(m));
@@ -1441,16 +1444,17 @@ pm_status colour_list(pm3_mesh* m, int n, uint32_t ctx, int* ncol) {
   // the last vertex has its colour changes nothing)
   constexpr int kJpBatch = 4;
   for (int it = 0; done < n;) {
-    if (it > n + 8) return fail3(m, PM_E_DEVICE, "colouring made no progress");
-    for (int b = 0; b < kJpBatch; ++b, ++it) {
-      k_jp<<<grid(n), kB, 0, m->s>>>(st, m->A, n, m->act, m->col, m->col2, m->blk, sseed, m->ctr);
-      k_jp_commit<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, m->col2);
-    }
+    // the stamp keeps 23 bits of the iteration
+    if (it > n + 8 || it + kJpBatch >= (1 << 23)) return fail3(m, PM_E_DEVICE, "colouring made no progress");
+    for (int b = 0; b < kJpBatch; ++b, ++it)
+      k_jp<<<grid(n), kB, 0, m->s>>>(st, m->A, n, m->act, m->col, m->blk, it, sseed, m->ctr);
     H3(hipGetLastError());
     T3(read_ctr(m));
     if (m->hctr[K_ERR] & E_COLOURS) return fail3(m, PM_E_DEVICE, "more than 256 colours");
     done = m->hctr[K_COLOURED];
   }
+  if (n > 0) k_jp_strip<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col);
+  H3(hipGetLastError());
   *ncol = n > 0 ? m->hctr[K_NCOL] : 0;
   return PM_OK;
 }
@@ -1605,7 +1609,7 @@ pm_status pm3_mesh_destroy(pm3_mesh* m) {
   dfree3(st.hdr);
   dfree3(st.nn);
   dfree3(st.ne);
-  for (int** p : {&m->cnt, &m->off, &m->cur, &m->flag, &m->scan, &m->partial, &m->A, &m->cls, &m->col, &m->col2,
+  for (int** p : {&m->cnt, &m->off, &m->cur, &m->flag, &m->scan, &m->partial, &m->A, &m->cls, &m->col,
                   &m->blk, &m->mark, &m->tcnt, &m->tscan, &m->ccount, &m->coff, &m->ctr})
     dfree3(*p);
   dfree3(m->act);
