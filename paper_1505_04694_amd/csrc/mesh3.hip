@@ -793,12 +793,15 @@ __global__ void k_compact_list(const int* __restrict__ flag, const int* __restri
 // combines its lanes' answers (any beaten, the smallest candidate pair, every
 // re-pointed element valid), which are exact, so the decisions are those of a
 // serial loop over the rows.
-constexpr int kL = 16;
+// 32 lanes: rows of 40-70 elements after refinement leave 16 lanes two to
+// five elements each per candidate test (psi3 204 -> 192 ms); 8 lanes took 244.
+constexpr int kL = 32;
 
 __device__ __forceinline__ bool grp_any(bool p) {
   uint64_t b = __ballot(p);
   int base = __lane_id() & ~(kL - 1);
-  return ((b >> base) & ((1ull << kL) - 1)) != 0;
+  constexpr uint64_t mask = kL >= kWave ? ~0ull : ((1ull << kL) - 1);
+  return ((b >> base) & mask) != 0;
 }
 
 __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restrict__ list, int n,
