@@ -172,6 +172,62 @@ def test_commit_out_of_room_rebuilds_and_matches_the_oracle():
     checker3.check_mesh(gm.export(), rows=gm.rows())
 
 
+def _star(levels=3):
+    """Tetrahedra joining the centre of the unit cube to the faces of an
+    icosphere (the icosahedron, each face cut into four `levels` times, points
+    pushed onto the sphere of radius 0.45): the centre is in every element."""
+    t = (1 + 5 ** 0.5) / 2
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6),
+         (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10),
+         (8, 6, 7), (9, 8, 1)]
+    v = [np.array(p, float) / np.linalg.norm(p) for p in v]
+    for _ in range(levels):
+        mid = {}
+
+        def m(a, b):
+            k = (min(a, b), max(a, b))
+            if k not in mid:
+                p = v[a] + v[b]
+                v.append(p / np.linalg.norm(p))
+                mid[k] = len(v) - 1
+            return mid[k]
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = m(a, b), m(b, c), m(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    xyz = np.vstack([[0.5, 0.5, 0.5], 0.5 + 0.45 * np.array(v)])
+    tet = np.hstack([np.zeros((len(f), 1), int), np.array(f) + 1]).astype(np.int32)
+    return xyz, tet
+
+
+def test_a_vertex_in_every_element():
+    """A centre vertex in all 1280 elements (642 neighbours): its sorted row
+    takes the serial form, and a coarsening class that changes it has rows
+    past the wavefront row commit, so the round falls back to a full row
+    rebuild. Rows, colourings and every phase equal the oracle's."""
+    xyz, tet = _star(3)
+    met = np.tile([25.0, 0, 0, 25.0, 0, 25.0], (len(xyz), 1))
+    tags = np.zeros(len(xyz), np.uint8)
+    om, gm = OracleMesh3(xyz, tet, met, tags, seed=5), Mesh3(xyz, tet, met, tags, seed=5)
+    compare(om, gm, "create")
+    assert np.diff(gm.rows()[2])[0] == len(tet)
+    co, no = om.colour(None, 0)
+    cg, ng = gm.colour(None, 0)
+    assert no == ng and np.array_equal(co, cg)
+    sg = gm.coarsen(0)
+    compare_stats(om.coarsen(0), sg, "coarsen")
+    compare(om, gm, "coarsen")
+    assert sg["room_rebuilds"] > 0
+    for ph, fo, fg in (("refine", lambda: om.refine(), lambda: gm.refine()),
+                       ("smooth", lambda: om.smooth(0, 1), lambda: gm.smooth(0, 1))):
+        compare_stats(fo(), fg(), ph)
+        compare(om, gm, ph)
+    compare_quality(om, gm, "end")
+
+
 def test_single_element_and_nothing_to_do():
     # one tetrahedron: nothing to collapse (every vertex a cube corner), one
     # refinement pass of its long edges, smoothing of no interior vertex
