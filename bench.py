@@ -11,6 +11,7 @@ are edges tested by refinement (identical counts on the oracle).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--n 2049]
        python bench.py --config4                      (the 4097^2 workload, peak device memory)
+       python bench.py --config1                      (full-sweep ops/s at 1025^2 and 2049^2)
        python bench.py --psi 10                       (the paper's psi benchmark, 10 time steps)
        python bench.py --summarise-trace DIR --out PREFIX --command CMD [--title WORKLOAD]
        python bench.py --summarise-counters FETCH_DIR WRITE_DIR --out PREFIX --command CMD
@@ -347,6 +348,71 @@ def config4_run(n=4097, sweeps=2, seed=3):
                       "final": {"vertices": V, "triangles": T, "quality": q}, "phases": phases}), flush=True)
 
 
+def config1_run(sweeps=3):
+    """Full-sweep ops/s: config 1 (1025x1025 criss-cross grid, one-layer
+    metric, priority seed 0) through three sweeps coarsen -> refine -> swap ->
+    plain smoothing, and the same three sweeps on config 2's 2049x2049
+    jittered two-layer input (priority seed 1); each from device-resident
+    arrays, after an untimed warm-up on the 33x33 grid. The oracle runs the
+    config-1 sweeps on one host core, and its op counts are compared."""
+    import numpy as np
+    import torch
+    from paper_1505_04694_amd import inputs, pmesh
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    def run(mi, seed):
+        arrs = [torch.from_numpy(a).to(dev) for a in (mi.xy, mi.tri, mi.metric, mi.tags)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = pmesh.Mesh(*arrs, seed=seed)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ops, phases = 0, []
+        for s in range(sweeps):
+            tr = m.sweep(s, smooth_kind=0)
+            ops += sum(st["coloured"] + st["evaluated"] + st["edges"] for st in tr.values())
+            phases.append(tr)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        e = m.export()
+        V, T = m.sizes()
+        m.close()
+        return dict(create_ms=(t1 - t0) * 1e3, sweeps_ms=(t2 - t1) * 1e3, ops=ops, ops_per_s=ops / (t2 - t1),
+                    final={"vertices": V, "triangles": T}, phases=phases), e
+
+    run(inputs.config0(), 0)  # kernel loading and first allocations
+    mi1 = inputs.config1()
+    r1, e1 = run(mi1, 0)
+    log(f"config 1: {r1['sweeps_ms']:.1f} ms")
+    r2, _ = run(inputs.config2(), PRIO_SEED)
+    log(f"config 2 sweeps: {r2['sweeps_ms']:.1f} ms")
+    # the oracle on the config-1 sweeps, one core
+    from oracle.orc import OracleMesh
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
+        om = OracleMesh.from_input(mi1, seed=0)
+        t0 = time.perf_counter()
+        otr = [om.sweep(s, smooth_kind=0) for s in range(sweeps)]
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    ops_o = sum(st["coloured"] + st["evaluated"] + st["edges"] for tr in otr for st in tr.values())
+    eo = om.export()
+    same = bool(np.array_equal(eo["tri"][eo["talive"]], e1["tri"][e1["talive"]]))
+    model, ncpu, navail = host_cpu()
+    print(json.dumps({"workload": f"full sweeps: {sweeps} x (coarsen, refine, swap, plain smoothing) on the "
+                                  "1025x1025 grid with the one-layer metric (config 1) and on the 2049x2049 "
+                                  "jittered two-layer input (config 2)",
+                      "config1": {"vertices": mi1.V, "triangles": mi1.T, **r1,
+                                  "ops_equal_oracle": ops_o == r1["ops"], "topology_equal_oracle": same},
+                      "config2_sweeps": r2,
+                      "cpu_baseline": {"value": ops_o / dt, "unit": "ops/s", "cores": 1, "kind": "oracle",
+                                       "seconds": dt, "sample": f"config 1, the same {sweeps} sweeps, one run",
+                                       "host_cpu": model, "host_threads": ncpu}}), flush=True)
+
+
 def psi_run(steps=10, n=201, target=550e3, iterations=2):
     """The paper's synthetic benchmark: an isotropic n x n start adapted to
     the Hessian metric of the time-varying psi for about `target` elements
@@ -637,6 +703,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--config1", action="store_true",
+                    help="full-sweep ops/s on config 1 (1025^2) and config 2 (2049^2), oracle on config 1")
     ap.add_argument("--config4", action="store_true",
                     help="instead: the 4097x4097 workload, two sweeps with gradient smoothing, peak device memory")
     ap.add_argument("--psi", type=int, metavar="STEPS", default=0,
@@ -665,6 +733,9 @@ def main():
         sys.exit(2)
     if a.config4:
         config4_run()
+        return
+    if a.config1:
+        config1_run()
         return
     if a.psi:
         psi_run(a.psi)
