@@ -50,6 +50,7 @@ enum {
   K_CCOMMIT = 8,    // collapses of the class in progress (gates its row commit)
   K_ROOM = 9,       // a row commit ran out of room (pool stripe full, or a row past the wavefront form)
   K_ROOMEP = 10,    // the epoch of the class whose commit ran out of room
+  K_NROWS = 11,     // rows stamped by the class in progress (the length of its row list)
   K_COUNT = 16
 };
 enum { E_MESH = 1, E_METRIC = 2, E_COLOURS = 4, E_LEAVES = 8 };
@@ -557,8 +558,12 @@ __device__ __forceinline__ void commit_row3(const Store3& st, int x, int epoch, 
   if (!ok && lane == 0) room3(ctr, epoch);
 }
 
-// Each wavefront takes a range of vertex slots, reads their stamps a
-// wavefront at a time and rebuilds the stamped rows in turn.
+// Two launch shapes rebuild the same rows, each once. Vertex order (large
+// classes): each wavefront takes a range of vertex slots, reads their stamps
+// a wavefront at a time and rebuilds the stamped rows in turn, so
+// consecutive wavefronts read nearby rows. Row list (small classes): each
+// wavefront takes rows of the class's row list in a wavefront-strided loop,
+// and the grid is sized by the class rather than by the mesh.
 __global__ void __launch_bounds__(256) k_commit3(Store3 st, int epoch, const int* __restrict__ own,
                                                  const int2* __restrict__ rec, int* tops, int64_t base,
                                                  int64_t per, int* ctr) {
@@ -576,6 +581,24 @@ __global__ void __launch_bounds__(256) k_commit3(Store3 st, int epoch, const int
       dm &= dm - 1;
       commit_row3(st, c0 + l, epoch, rec, tops, base, per, ctr);
     }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_commit3_list(Store3 st, int epoch, const int* __restrict__ rows,
+                                                      const int2* __restrict__ rec, int* tops, int64_t base,
+                                                      int64_t per, int* ctr) {
+  if (ctr[K_CCOMMIT] == 0 || ctr[K_ROOM]) return;
+  int n = ctr[K_NROWS];
+  int wid = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  int nw = (int)((int64_t)gridDim.x * blockDim.x / kWave);
+  for (int i = wid; i < n; i += nw) commit_row3(st, rows[i], epoch, rec, tops, base, per, ctr);
+}
+
+// the start of a class: its collapse count and its row list emptied
+__global__ void k_class_start(int* ctr) {
+  if (threadIdx.x == 0) {
+    ctr[K_CCOMMIT] = 0;
+    ctr[K_NROWS] = 0;
   }
 }
 
@@ -806,8 +829,8 @@ __device__ __forceinline__ bool grp_any(bool p) {
 
 __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restrict__ list, int n,
                                                   const int* __restrict__ col, int c, uint64_t sseed, double L_low2,
-                                                  double qmin3, uint8_t* nxt, int epoch, int* own, int2* rec,
-                                                  int* ctr) {
+                                                  double qmin3, uint8_t* nxt, int epoch, int* own, int* rows,
+                                                  int2* rec, int* ctr) {
   // an earlier class's row commit ran out of room: the host rebuilds the
   // rows and runs this class again
   if (ctr[K_ROOM]) return;
@@ -894,13 +917,27 @@ __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restri
         st.tet[t] = canon4(replace4(e, v, target));
     }
     // the changed rows (every neighbour's, the target's among them) for the
-    // row commit, and the member's target
+    // row commit, stamped with the class epoch; with a row list (rows given)
+    // the first stamp of a row in this class also appends it to the list
+    // (one add per wavefront); and the member's target
     for (int jb = 0; jb < h.y; jb += kL) {
       int j = jb + j0;
+      int w = -1;
+      bool fresh = false;
       if (j < h.y) {
-        int w = st.nn[h.x + j];
+        w = st.nn[h.x + j];
         nxt[w] = 1;
-        own[w] = epoch;
+        if (rows)
+          fresh = atomicExch(&own[w], epoch) != epoch;
+        else
+          own[w] = epoch;
+      }
+      if (rows) {
+        uint64_t on = __ballot(true), fb = __ballot(fresh);
+        int lead = __ffsll((unsigned long long)on) - 1, at = 0;
+        if (__lane_id() == lead && fb) at = atomicAdd(&ctr[K_NROWS], __popcll(fb));
+        at = __shfl(at, lead);
+        if (fresh) rows[at + __popcll(fb & ((1ull << __lane_id()) - 1ull))] = w;
       }
     }
     if (j0 == 0) {
@@ -1260,6 +1297,7 @@ struct pm3_mesh {
   // bump pointers, the epoch of the last class, and the pool range above
   // the last full build that the stripes share
   int* own = nullptr;
+  int* rows = nullptr;  // the rows stamped by the class in progress, each once
   int2* rec = nullptr;
   int* tops = nullptr;
   int epoch = 0;
@@ -1348,6 +1386,7 @@ pm_status reserve(pm3_mesh* m, int V, int T) {
     T3(dgrow(m, &st.cap, m->Vcap, nc, true));
     T3(dgrow(m, &m->own, m->Vcap, nc, true));
     T3(dgrow(m, &m->rec, m->Vcap, nc, true));
+    T3(dgrow(m, &m->rows, m->Vcap, nc, false));
     // new vertex slots carry no class stamp or record
     k_fill_int<<<grid(nc - m->Vcap), kB, 0, m->s>>>(m->own + m->Vcap, nc - m->Vcap, -1);
     k_fill_int<<<grid(2 * (int64_t)(nc - m->Vcap)), kB, 0, m->s>>>((int*)(m->rec + m->Vcap), 2 * (nc - m->Vcap), -1);
@@ -1620,6 +1659,7 @@ pm_status pm3_mesh_destroy(pm3_mesh* m) {
   dfree3(m->qbuf);
   dfree3(st.cap);
   dfree3(m->own);
+  dfree3(m->rows);
   dfree3(m->rec);
   dfree3(m->tops);
   if (m->hctr) (void)hipHostFree(m->hctr);
@@ -1770,12 +1810,21 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
         if (size[c] == 0) continue;
         int ep = ++m->epoch;
         class_epoch[c] = ep;
-        k_fill_int<<<1, kB, 0, m->s>>>(m->ctr + K_CCOMMIT, 1, 0);
+        k_class_start<<<1, kWave, 0, m->s>>>(m->ctr);
+        // the row list while the class can stamp at most about an eighth of
+        // the rows (a wavefront for about every row a member's neighbours
+        // give, at most one grid's worth), else vertex order
+        int64_t reach = (int64_t)size[c] * 16;
+        bool listed = reach * 8 <= st.V;
         int nb = (int)(((int64_t)size[c] * kL + kB - 1) / kB);
         k_collapse<<<nb, kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->col, c, sseed, o->L_low2, qmin3,
-                                         m->nxt, ep, m->own, m->rec, m->ctr);
-        k_commit3<<<grid((int64_t)st.V * kWave), kB, 0, m->s>>>(st, ep, m->own, m->rec, m->tops, m->top_base,
-                                                                 m->top_per, m->ctr);
+                                         m->nxt, ep, m->own, listed ? m->rows : nullptr, m->rec, m->ctr);
+        if (listed)
+          k_commit3_list<<<grid(reach * kWave), kB, 0, m->s>>>(st, ep, m->rows, m->rec, m->tops, m->top_base,
+                                                              m->top_per, m->ctr);
+        else
+          k_commit3<<<grid((int64_t)st.V * kWave), kB, 0, m->s>>>(st, ep, m->own, m->rec, m->tops, m->top_base,
+                                                                   m->top_per, m->ctr);
         H3(hipGetLastError());
       }
       T3(read_ctr(m));
