@@ -665,44 +665,53 @@ __global__ void k_tops_init(int* tops, int64_t base, int64_t per) {
 // the counters once per wavefront.
 __device__ __forceinline__ bool coloured_before(int cw, int it) { return cw >= 0 && (cw >> 8) < it; }
 
-__global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t* __restrict__ act, int* col,
-                     int* blk, int it, uint64_t sseed, int* ctr) {
-  int coloured = 0, ncol = 0;
-  for (int i = gtid(); i < n; i += gstride()) {
-    int v = A[i];
-    if (col[v] >= 0) continue;
-    int b = blk[v];
-    if (b >= 0 && !coloured_before(col[b], it)) continue;
-    uint64_t kv = vkey(sseed, (uint32_t)v);
-    int4 h = st.hdr[v];
-    int wait = -1;
-    uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
-    for (int j = 0; j < h.y; ++j) {
-      int w = st.nn[h.x + j];
-      int cw = col[w];
-      if (coloured_before(cw, it)) {
-        int c = cw & 0xFF;
+// one visit of a waiting vertex v in iteration it: its colour (returned),
+// or -1 while a neighbour it has to wait for has none
+__device__ __forceinline__ int jp_visit(const Store3& st, int v, const uint8_t* __restrict__ act, int* col, int* blk,
+                                        int it, uint64_t sseed, int* ctr) {
+  int b = blk[v];
+  if (b >= 0 && !coloured_before(col[b], it)) return -1;
+  uint64_t kv = vkey(sseed, (uint32_t)v);
+  int4 h = st.hdr[v];
+  uint64_t used[kMaxColours / 64] = {0, 0, 0, 0};
+  // eight neighbours at a time: their ids, then their colours and activity
+  // flags, all in flight together; taken in row order as a serial loop
+  constexpr int B = 8;
+  for (int j0 = 0; j0 < h.y; j0 += B) {
+    int w[B], cw[B];
+    uint8_t aw[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) w[q] = j0 + q < h.y ? st.nn[h.x + j0 + q] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      cw[q] = w[q] >= 0 ? col[w[q]] : -1;
+      aw[q] = w[q] >= 0 ? act[w[q]] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (w[q] < 0) continue;
+      if (coloured_before(cw[q], it)) {
+        int c = cw[q] & 0xFF;
         used[c >> 6] |= 1ull << (c & 63);
-      } else if (act[w] && vkey(sseed, (uint32_t)w) > kv) {
-        wait = w;
-        break;
+      } else if (aw[q] && vkey(sseed, (uint32_t)w[q]) > kv) {
+        blk[v] = w[q];
+        return -1;
       }
     }
-    if (wait >= 0) {
-      blk[v] = wait;
-      continue;
-    }
-    int c = -1;
-    for (int q = 0; q < kMaxColours / 64 && c < 0; ++q)
-      if (~used[q]) c = q * 64 + __ffsll((long long)~used[q]) - 1;
-    if (c < 0) {
-      atomicOr(&ctr[K_ERR], E_COLOURS);
-      c = kMaxColours - 1;
-    }
-    col[v] = (it << 8) | c;
-    ++coloured;
-    ncol = max(ncol, c + 1);
   }
+  int c = -1;
+  for (int q = 0; q < kMaxColours / 64 && c < 0; ++q)
+    if (~used[q]) c = q * 64 + __ffsll((long long)~used[q]) - 1;
+  if (c < 0) {
+    atomicOr(&ctr[K_ERR], E_COLOURS);
+    c = kMaxColours - 1;
+  }
+  col[v] = (it << 8) | c;
+  return c;
+}
+
+// a wavefront's counts: vertices coloured and colours used
+__device__ __forceinline__ void jp_counts(int coloured, int ncol, int* ctr) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
     coloured += __shfl_xor(coloured, d);
@@ -712,6 +721,50 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
     atomicAdd(&ctr[K_COLOURED], coloured);
     atomicMax(&ctr[K_NCOL], ncol);
   }
+}
+
+__global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t* __restrict__ act, int* col,
+                     int* blk, int it, uint64_t sseed, int* ctr) {
+  int coloured = 0, ncol = 0;
+  for (int i = gtid(); i < n; i += gstride()) {
+    int v = A[i];
+    if (col[v] >= 0) continue;
+    int c = jp_visit(st, v, act, col, blk, it, sseed, ctr);
+    if (c >= 0) {
+      ++coloured;
+      ncol = max(ncol, c + 1);
+    }
+  }
+  jp_counts(coloured, ncol, ctr);
+}
+
+// Lists of at most kJpOne vertices (one per thread): one work-group runs the
+// same iterations to completion, separated by block barriers instead of
+// launches (at most n + 8 of them, as the host allows the chunked form). The
+// work-group's waves share one CU's vector L1, which their stores write
+// through, so every iteration sees the colours of the ones before it.
+constexpr int kJpOne = 1024;
+constexpr int kJpOneThreads = 1024;
+__global__ void __launch_bounds__(kJpOneThreads) k_jp_one(Store3 st, const int* __restrict__ A, int n,
+                                                          const uint8_t* __restrict__ act, int* col, int* blk,
+                                                          uint64_t sseed, int* ctr) {
+  int coloured = 0, ncol = 0;
+  for (int it = 0; it <= n + 8; ++it) {
+    bool waiting = false;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) {
+      int v = A[i];
+      if (col[v] >= 0) continue;
+      int c = jp_visit(st, v, act, col, blk, it, sseed, ctr);
+      if (c >= 0) {
+        ++coloured;
+        ncol = max(ncol, c + 1);
+      } else {
+        waiting = true;
+      }
+    }
+    if (!__syncthreads_or(waiting)) break;
+  }
+  jp_counts(coloured, ncol, ctr);
 }
 
 __global__ void k_jp_strip(const int* __restrict__ A, int n, int* col) {
@@ -1482,6 +1535,14 @@ pm_status colour_list(pm3_mesh* m, int n, uint32_t ctx, int* ncol) {
   k_jp_init<<<grid(n), kB, 0, m->s>>>(m->A, n, m->act, m->blk);
   T3(zero_ctr(m));
   int done = 0;
+  if (n > 0 && n <= kJpOne) {
+    k_jp_one<<<1, kJpOneThreads, 0, m->s>>>(st, m->A, n, m->act, m->col, m->blk, sseed, m->ctr);
+    H3(hipGetLastError());
+    T3(read_ctr(m));
+    if (m->hctr[K_ERR] & E_COLOURS) return fail3(m, PM_E_DEVICE, "more than 256 colours");
+    if (m->hctr[K_COLOURED] != n) return fail3(m, PM_E_DEVICE, "colouring made no progress");
+    done = n;
+  }
   // iterations in batches of kJpBatch between read-backs (an iteration after
   // the last vertex has its colour changes nothing)
   constexpr int kJpBatch = 4;
