@@ -1463,10 +1463,12 @@ pm_status reserve(pm3_mesh* m, int V, int T) {
 }
 
 // exclusive scan of n ints into out; returns the total
+// the scan's total, with every counter (the host copy is then as current as
+// after read_ctr)
 pm_status scan_total(pm3_mesh* m, const int* in, int* out, int n, int* total) {
   pm::scan_excl(in, out, n, m->ctr + K_TOTAL, m->partial, m->s);
   H3(hipGetLastError());
-  H3(hipMemcpyAsync(m->hctr + K_TOTAL, m->ctr + K_TOTAL, sizeof(int), hipMemcpyDeviceToHost, m->s));
+  H3(hipMemcpyAsync(m->hctr, m->ctr, sizeof(int) * K_COUNT, hipMemcpyDeviceToHost, m->s));
   H3(hipStreamSynchronize(m->s));
   *total = m->hctr[K_TOTAL];
   return PM_OK;
@@ -1898,8 +1900,7 @@ pm_status pm3_coarsen(pm3_mesh* m, const pm_options* o, pm_stats* out) {
       ++sv[13];
       c0 = failed + 1;
     }
-    T3(select_list(m, 1, o->L_low2, &n));
-    T3(read_ctr(m));
+    T3(select_list(m, 1, o->L_low2, &n));  // its read-back returns the round's counters too
     sv[PM_S_EVALUATED] += m->hctr[K_EVAL];
     sv[PM_S_DEFERRED] += m->hctr[K_DEFER];
     sv[PM_S_COMMITTED] += m->hctr[K_COMMIT];
@@ -1926,7 +1927,6 @@ pm_status pm3_refine(pm3_mesh* m, const pm_options* o, pm_stats* out) {
     k_mark<<<grid(V0), kB, 0, m->s>>>(st, o->L_up2, m->mark, m->cnt, m->ctr);
     int nv = 0;
     T3(scan_total(m, m->cnt, m->scan, V0, &nv));
-    T3(read_ctr(m));
     sv[PM_S_EDGES] += m->hctr[K_EDGES];
     if (nv == 0) {
       done = true;
@@ -1938,7 +1938,6 @@ pm_status pm3_refine(pm3_mesh* m, const pm_options* o, pm_stats* out) {
     k_split_count<<<grid(T0), kB, 0, m->s>>>(st, T0, m->mark, m->tcnt, m->ctr);
     int nt = 0;
     T3(scan_total(m, m->tcnt, m->tscan, T0, &nt));
-    T3(read_ctr(m));
     if (m->hctr[K_ERR] & E_LEAVES) return fail3(m, PM_E_DEVICE, "an element split into too many pieces");
     T3(reserve(m, V0 + nv, T0 + nt));
     k_split_write<<<grid(T0), kB, 0, m->s>>>(st, T0, m->mark, m->tscan);
