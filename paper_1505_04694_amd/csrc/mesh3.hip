@@ -893,14 +893,35 @@ __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restri
   int v = act ? list[gid] : 0;
   int4 h = act ? st.hdr[v] : make_int4(0, 0, 0, 0);
   uint64_t kv = vkey(sseed, (uint32_t)v);
+  // one pass over the row: re-validation, and each neighbour's metric
+  // length kept for the candidate search (rows of up to kC * kL entries;
+  // INFINITY marks a neighbour that is no candidate)
+  constexpr int kC = 2;
+  int cu[kC];
+  double cL[kC];
+#pragma unroll
+  for (int q = 0; q < kC; ++q) {
+    cu[q] = -1;
+    cL[q] = INFINITY;
+  }
   bool b = false;
-  for (int jb = 0; jb < h.y; jb += kL) {
+  for (int jb = 0, q = 0; jb < h.y; jb += kL, ++q) {
     int j = jb + j0;
     if (j < h.y) {
       int w = st.nn[h.x + j];
       b = b || (col[w] == c && vkey(sseed, (uint32_t)w) > kv);
+#pragma unroll
+      for (int r = 0; r < kC; ++r)
+        if (r == q) {
+          cu[r] = w;
+          if (tag_ok(st, v, w)) {
+            double L = len2(st, v, w);
+            if (L < L_low2) cL[r] = L;
+          }
+        }
     }
   }
+  bool cached = h.y <= kC * kL;
   bool beaten = grp_any(b);
   int ev = 0, df = 0, cm = 0;
   if (act && beaten) {
@@ -917,18 +938,33 @@ __global__ void __launch_bounds__(256) k_collapse(Store3 st, const int* __restri
     for (;;) {
       double bL = 0.0;
       int bu = -1;
-      for (int jb = 0; jb < h.y; jb += kL) {
-        int j = jb + j0;
-        if (j >= h.y) continue;
-        int u = st.nn[h.x + j];
-        if (!tag_ok(st, v, u)) continue;
-        double L = len2(st, v, u);
-        if (!(L < L_low2)) continue;
-        bool after = L > pL || (L == pL && u > pu);
-        bool before = bu < 0 || L < bL || (L == bL && u < bu);
-        if (after && before) {
-          bL = L;
-          bu = u;
+      if (cached) {
+#pragma unroll
+        for (int q = 0; q < kC; ++q) {
+          double L = cL[q];
+          int u = cu[q];
+          if (u < 0 || !(L < L_low2)) continue;
+          bool after = L > pL || (L == pL && u > pu);
+          bool before = bu < 0 || L < bL || (L == bL && u < bu);
+          if (after && before) {
+            bL = L;
+            bu = u;
+          }
+        }
+      } else {
+        for (int jb = 0; jb < h.y; jb += kL) {
+          int j = jb + j0;
+          if (j >= h.y) continue;
+          int u = st.nn[h.x + j];
+          if (!tag_ok(st, v, u)) continue;
+          double L = len2(st, v, u);
+          if (!(L < L_low2)) continue;
+          bool after = L > pL || (L == pL && u > pu);
+          bool before = bu < 0 || L < bL || (L == bL && u < bu);
+          if (after && before) {
+            bL = L;
+            bu = u;
+          }
         }
       }
 #pragma unroll
