@@ -806,6 +806,23 @@ __global__ void k_class_count(const int* __restrict__ A, int n, const int* __res
 // range per colour with a global add, and writes the entries there. The
 // order inside a class is not fixed; the members of a class are pairwise
 // non-adjacent and their decisions do not depend on it.
+// the classes' first slots: the exclusive prefix sums of the class sizes
+// (one work-group of kMaxColours threads)
+__global__ void k_class_offsets(const int* __restrict__ cnt, int ncol, int* off) {
+  __shared__ int s[kMaxColours];
+  int c = (int)threadIdx.x;
+  int own = c < ncol ? cnt[c] : 0;
+  s[c] = own;
+  __syncthreads();
+  for (int d = 1; d < kMaxColours; d <<= 1) {
+    int t = c >= d ? s[c - d] : 0;
+    __syncthreads();
+    s[c] += t;
+    __syncthreads();
+  }
+  if (c < ncol) off[c] = s[c] - own;
+}
+
 __global__ void k_class_place(const int* __restrict__ A, int n, const int* __restrict__ col, int ncol,
                               const int* __restrict__ off, int* cur, int* out) {
   __shared__ int h[kMaxColours], base[kMaxColours];
@@ -1606,21 +1623,22 @@ pm_status class_lists(pm3_mesh* m, int n, int ncol, std::vector<int>& off, std::
     T3(dgrow(m, &m->ccount, 0, 2 * kMaxColours, false));
     T3(dgrow(m, &m->coff, 0, kMaxColours, false));
   }
+  // sizes, offsets and placement on the device; one read-back of the sizes
+  // (the host computes the same offsets from them)
   k_fill_int<<<1, 2 * kMaxColours, 0, m->s>>>(m->ccount, 2 * kMaxColours, 0);
   k_class_count<<<grid(n), kB, 0, m->s>>>(m->A, n, m->col, ncol, m->ccount);
-  size.assign(ncol, 0);
-  off.assign(ncol + 1, 0);
+  k_class_offsets<<<1, kMaxColours, 0, m->s>>>(m->ccount, ncol, m->coff);
+  k_class_place<<<std::max(1, (n + kB - 1) / kB), kB, 0, m->s>>>(m->A, n, m->col, ncol, m->coff,
+                                                                   m->ccount + kMaxColours, m->cls);
+  H3(hipGetLastError());
   H3(hipMemcpyAsync(m->hctr + K_COUNT, m->ccount, sizeof(int) * ncol, hipMemcpyDeviceToHost, m->s));
   H3(hipStreamSynchronize(m->s));
+  size.assign(ncol, 0);
+  off.assign(ncol + 1, 0);
   for (int c = 0; c < ncol; ++c) {
     size[c] = m->hctr[K_COUNT + c];
     off[c + 1] = off[c] + size[c];
   }
-  H3(hipMemcpyAsync(m->coff, off.data(), sizeof(int) * ncol, hipMemcpyHostToDevice, m->s));
-  k_class_place<<<std::max(1, (n + kB - 1) / kB), kB, 0, m->s>>>(m->A, n, m->col, ncol, m->coff,
-                                                                   m->ccount + kMaxColours, m->cls);
-  H3(hipGetLastError());
-  H3(hipStreamSynchronize(m->s));  // off's host copy is a local vector
   return PM_OK;
 }
 
