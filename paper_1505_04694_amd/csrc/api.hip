@@ -1212,6 +1212,16 @@ void fill_defaults(pm_options* o) {
 
 }  // namespace
 
+namespace pm {
+hipError_t block_alloc(hipStream_t s, void** p, size_t bytes) {
+  size_t got = 0;
+  return cache_get(s, p, bytes, &got);
+}
+void block_free(void* p) {
+  if (p && cache_put(p) == 0) (void)hipFree(p);
+}
+}  // namespace pm
+
 extern "C" {
 
 const char* pm_version(void) { return "pmesh 0.1 gfx950"; }

@@ -1431,26 +1431,26 @@ pm_status fail3(pm3_mesh* m, pm_status st, const std::string& msg) {
     if (s_ != PM_OK) return s_;      \
   } while (0)
 
+// Device blocks come from the library's stream-ordered block cache: a block
+// freed on the handle's stream is reused only by later work on that stream,
+// so growing an array needs no wait before the old block is released.
 template <class T>
 pm_status dgrow(pm3_mesh* m, T** p, int64_t old_n, int64_t n, bool keep) {
   if (n <= old_n && *p) return PM_OK;
   T* q = nullptr;
-  if (hipMalloc((void**)&q, sizeof(T) * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
+  if (pm::block_alloc(m->s, (void**)&q, sizeof(T) * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
     (void)hipGetLastError();
     return fail3(m, PM_E_NOMEM, "device allocation failed");
   }
   if (keep && *p && old_n > 0) H3(hipMemcpyAsync(q, *p, sizeof(T) * (size_t)old_n, hipMemcpyDeviceToDevice, m->s));
-  if (*p) {
-    H3(hipStreamSynchronize(m->s));
-    H3(hipFree(*p));
-  }
+  if (*p) pm::block_free(*p);
   *p = q;
   return PM_OK;
 }
 
 template <class T>
 void dfree3(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) pm::block_free(p);
   p = nullptr;
 }
 
@@ -1661,11 +1661,10 @@ pm_status compact(pm3_mesh* m) {
   k_compact_v<<<grid(V), kB, 0, m->s>>>(st, m->scan, xyz, met, tag);
   k_compact_t<<<grid(T), kB, 0, m->s>>>(st, m->scan, m->tscan, tet);
   H3(hipGetLastError());
-  H3(hipStreamSynchronize(m->s));
-  H3(hipFree(st.xyz));
-  H3(hipFree(st.met));
-  H3(hipFree(st.tag));
-  H3(hipFree(st.tet));
+  dfree3(st.xyz);
+  dfree3(st.met);
+  dfree3(st.tag);
+  dfree3(st.tet);
   st.xyz = xyz;
   st.met = met;
   st.tag = tag;
@@ -1715,7 +1714,7 @@ pm_status pm3_mesh_create(const pm3_mesh_desc* d, const pm_options* o, void* str
     return s;
   };
   int V = (int)d->V, T = (int)d->T;
-  if (hipMalloc((void**)&m->ctr, sizeof(int) * K_COUNT) != hipSuccess ||
+  if (pm::block_alloc(m->s, (void**)&m->ctr, sizeof(int) * K_COUNT) != hipSuccess ||
       hipHostMalloc((void**)&m->hctr, sizeof(int) * (K_COUNT + 2 * kMaxColours), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return bail(PM_E_NOMEM);
