@@ -16,6 +16,7 @@
 
 #include "../../include/pm.h"
 #include "kern.hpp"
+#include "blocks.hpp"
 
 using namespace pm;
 

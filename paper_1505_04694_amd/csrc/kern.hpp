@@ -151,13 +151,6 @@ inline int grid_for(int64_t n, int maxg = 8192) {
   return (int)g;
 }
 
-// ---- api.hip ----
-// The process-wide stream-ordered cache of device blocks (a block freed on a
-// stream is handed out again only on that stream). block_free returns a
-// block that did not come from the cache to the driver.
-hipError_t block_alloc(hipStream_t s, void** p, size_t bytes);
-void block_free(void* p);
-
 // ---- store.hip ----
 // exclusive scan of n ints; writes the total to *total (device)
 void scan_excl(const int* in, int* out, int n, int* total, int* partial, hipStream_t s);

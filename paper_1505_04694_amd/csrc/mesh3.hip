@@ -23,6 +23,7 @@
 #include "../../include/pm3.h"
 #include "common.hpp"
 #include "kern.hpp"
+#include "blocks.hpp"
 
 namespace pm3 {
 
