@@ -1251,41 +1251,59 @@ __global__ void k_split_write(Store3 st, int T0, const int* __restrict__ mark, c
 
 // ---- smoothing (Sec. 2.4.4) -------------------------------------------------------------------------
 
-__device__ double patch_min_q3(const Store3& st, int v, int4 h, double4 p, bool& valid) {
-  valid = true;
-  double mn = 0.0;
-  for (int i = 0; i < h.w; ++i) {
-    Geo3 g = geo(st, st.tet[st.ne[h.z + i]], v, p);
-    if (!(vol6(g) > 0.0)) valid = false;
-    double q = qual3(g);
-    if (i == 0 || q < mn) mn = q;
-  }
-  return mn;
-}
-
-__global__ void k_smooth(Store3 st, const int* __restrict__ list, int n, int* ctr) {
+// One class of Laplacian moves with kSL lanes per member: lane j takes the
+// row entries j, j + kSL, ... . The group adds the neighbour terms in row
+// order by shuffles, so each sum is the serial loop's; each lane gathers an
+// element's geometry once for its old and its moved quality; the patch
+// minima fold as the serial loop folds them (the first element's value
+// taken as it is, later ones only when smaller, so a NaN counts only as the
+// first), and the moved patch's validity is a group AND.
+constexpr int kSL = 8;
+__global__ void __launch_bounds__(256) k_smooth(Store3 st, const int* __restrict__ list, int n, int* ctr) {
+  int lane = __lane_id();
+  int j0 = lane & (kSL - 1), base = lane & ~(kSL - 1);
+  int64_t ng = (int64_t)gridDim.x * blockDim.x / kSL;
   int ev = 0, cm = 0;
-  for (int i = gtid(); i < n; i += gstride()) {
-    int v = list[i];
+  // every branch below is uniform over a group (its member's data)
+  for (int64_t gi = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSL; gi < n; gi += ng) {
+    int v = list[gi];
     int4 h = st.hdr[v];
     double4 pv = st.xyz[v];
     Met6 mv = st.met[v];
     Met6 G{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double rx = 0.0, ry = 0.0, rz = 0.0;
-    for (int j = 0; j < h.y; ++j) {
-      int w = st.nn[h.x + j];
-      Met6 e = edge_met(mv, st.met[w]);
-      double4 pw = st.xyz[w];
-      double dx = pw.x - pv.x, dy = pw.y - pv.y, dz = pw.z - pv.z;
-      G.a00 = G.a00 + e.a00;
-      G.a01 = G.a01 + e.a01;
-      G.a02 = G.a02 + e.a02;
-      G.a11 = G.a11 + e.a11;
-      G.a12 = G.a12 + e.a12;
-      G.a22 = G.a22 + e.a22;
-      rx = rx + ((e.a00 * dx + e.a01 * dy) + e.a02 * dz);
-      ry = ry + ((e.a01 * dx + e.a11 * dy) + e.a12 * dz);
-      rz = rz + ((e.a02 * dx + e.a12 * dy) + e.a22 * dz);
+    for (int jb = 0; jb < h.y; jb += kSL) {
+      int j = jb + j0;
+      Met6 e{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      if (j < h.y) {
+        int w = st.nn[h.x + j];
+        e = edge_met(mv, st.met[w]);
+        double4 pw = st.xyz[w];
+        double dx = pw.x - pv.x, dy = pw.y - pv.y, dz = pw.z - pv.z;
+        tx = (e.a00 * dx + e.a01 * dy) + e.a02 * dz;
+        ty = (e.a01 * dx + e.a11 * dy) + e.a12 * dz;
+        tz = (e.a02 * dx + e.a12 * dy) + e.a22 * dz;
+      }
+      int cnt = min(kSL, h.y - jb);
+#pragma unroll
+      for (int k = 0; k < kSL; ++k) {
+        int src = base + k;
+        double s00 = __shfl(e.a00, src), s01 = __shfl(e.a01, src), s02 = __shfl(e.a02, src);
+        double s11 = __shfl(e.a11, src), s12 = __shfl(e.a12, src), s22 = __shfl(e.a22, src);
+        double sx = __shfl(tx, src), sy = __shfl(ty, src), sz = __shfl(tz, src);
+        if (k < cnt) {
+          G.a00 = G.a00 + s00;
+          G.a01 = G.a01 + s01;
+          G.a02 = G.a02 + s02;
+          G.a11 = G.a11 + s11;
+          G.a12 = G.a12 + s12;
+          G.a22 = G.a22 + s22;
+          rx = rx + sx;
+          ry = ry + sy;
+          rz = rz + sz;
+        }
+      }
     }
     double det = det3(G);
     double c00 = G.a11 * G.a22 - G.a12 * G.a12, c01 = G.a02 * G.a12 - G.a01 * G.a22,
@@ -1294,13 +1312,38 @@ __global__ void k_smooth(Store3 st, const int* __restrict__ list, int n, int* ct
     double4 p = make_double4(pv.x + ((c00 * rx + c01 * ry) + c02 * rz) / det,
                              pv.y + ((c01 * rx + c11 * ry) + c12 * rz) / det,
                              pv.z + ((c02 * rx + c12 * ry) + c22 * rz) / det, 0.0);
-    ++ev;
-    bool vo, vn;
-    double oldmin = patch_min_q3(st, v, h, pv, vo);
-    double newmin = patch_min_q3(st, v, h, p, vn);
+    if (j0 == 0) ++ev;
+    bool vn = true;
+    double mo = INFINITY, mn = INFINITY;
+    for (int kb = 0; kb < h.w; kb += kSL) {
+      int k = kb + j0;
+      if (k >= h.w) continue;
+      int4 t = st.tet[st.ne[h.z + k]];
+      Geo3 go = geo(st, t, v, pv);
+      Geo3 gn = go;
+      int id[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (id[q] == v) gn.p[q] = p;
+      if (!(vol6(gn) > 0.0)) vn = false;
+      double qo = qual3(go), qn = qual3(gn);
+      if (k == 0 || qo < mo) mo = qo;
+      if (k == 0 || qn < mn) mn = qn;
+    }
+    uint64_t gm = ((1ull << kSL) - 1ull) << base;
+    vn = (__ballot(!vn) & gm) == 0;
+    double oldmin = __shfl(mo, base), newmin = __shfl(mn, base);
+#pragma unroll
+    for (int k = 1; k < kSL; ++k) {
+      double a = __shfl(mo, base + k), b = __shfl(mn, base + k);
+      if (a < oldmin) oldmin = a;
+      if (b < newmin) newmin = b;
+    }
     if (!(vn && newmin >= oldmin)) continue;
-    st.xyz[v] = p;
-    ++cm;
+    if (j0 == 0) {
+      st.xyz[v] = p;
+      ++cm;
+    }
   }
   stripe_add(ctr, K_EVAL, ev);
   stripe_add(ctr, K_COMMIT, cm);
@@ -2025,7 +2068,7 @@ pm_status pm3_smooth(pm3_mesh* m, const pm_options* o, pm_stats* out) {
   T3(zero_ctr(m));
   for (int s = 0; s < o->smooth_sweeps; ++s)
     for (int c = 0; c < ncol; ++c)
-      if (size[c] > 0) k_smooth<<<grid(size[c]), kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->ctr);
+      if (size[c] > 0) k_smooth<<<grid((int64_t)size[c] * kSL), kB, 0, m->s>>>(st, m->cls + off[c], size[c], m->ctr);
   H3(hipGetLastError());
   T3(read_ctr(m));
   sv[PM_S_EVALUATED] = m->hctr[K_EVAL];
