@@ -107,8 +107,10 @@ def measured_traffic(name):
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
-def roofline(name, dom, copy_gbs, per_row=None):
-    """Achieved algorithmic bandwidth of the dominant kernel group over the timed steps."""
+def roofline(name, dom, copy_gbs, per_row=None, counters=True):
+    """Achieved algorithmic bandwidth of the dominant kernel group over the timed steps.
+    counters: the workload is the one the committed counter summary measured
+    (the 2049x2049 step); elsewhere traffic is null."""
     launches = max(dom["launches"], 1)
     bpu, unit = BYTES_PER_UNIT[name]
     units = dom["units"] / launches
@@ -116,7 +118,7 @@ def roofline(name, dom, copy_gbs, per_row=None):
     achieved = bpu * units / avg_s / 1e9 if avg_s > 0 else 0.0
     out = {"kernel": "commit" if name == "commit_ops" else name, "bound": "hbm", "achieved": round(achieved, 2),
            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-           "traffic": measured_traffic(name), "bytes_per_unit": bpu, "unit_of_work": unit,
+           "traffic": measured_traffic(name) if counters else None, "bytes_per_unit": bpu, "unit_of_work": unit,
            "units_per_launch": round(units, 1), "avg_launch_us": round(avg_s * 1e6, 2), "launches": dom["launches"],
            "copy_bandwidth_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 5)}
     if name == "commit_ops":
@@ -462,9 +464,9 @@ def psi_run(steps=10, n=201, target=550e3, iterations=2):
     prof = m.profile_read(pmesh.PROFILE_READS)
     dominant = max(pmesh.KERNELS, key=lambda k: prof[k]["ms"])
     if dominant == "commit":
-        rl = roofline("commit_ops", prof["commit_ops"], copy_gbs, per_row=prof["commit"])
+        rl = roofline("commit_ops", prof["commit_ops"], copy_gbs, per_row=prof["commit"], counters=False)
     else:
-        rl = roofline(dominant, prof[dominant], copy_gbs)
+        rl = roofline(dominant, prof[dominant], copy_gbs, counters=False)
     m.close()
     # the oracle on the first time step, from the same mesh and metric, one core
     cpu = psi_cpu_step(first, iterations)
