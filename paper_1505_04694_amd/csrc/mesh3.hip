@@ -741,7 +741,7 @@ __global__ void k_jp(Store3 st, const int* __restrict__ A, int n, const uint8_t*
 
 // Lists of at most kJpOne vertices (one per thread): one work-group runs the
 // same iterations to completion, separated by block barriers instead of
-// launches (at most n + 8 of them, as the host allows the chunked form). The
+// launches (at most n + 8 of them, as the host allows one launch each). The
 // work-group's waves share one CU's vector L1, which their stores write
 // through, so every iteration sees the colours of the ones before it.
 constexpr int kJpOne = 1024;
