@@ -73,3 +73,31 @@ def test_config4_two_sweeps_match_the_oracle_result():
         assert abs(got["xy_sum"] - want["xy_sum"]) <= 1e-12 * abs(want["xy_sum"])
     Q, qmin = gm.quality()
     assert abs(Q - gold["quality"][0]) <= 1e-12 * abs(Q) and qmin == gold["quality"][1]
+
+
+def test_full_batch_matches_the_oracle_golden():
+    """The whole batched workload (256 meshes of n log-uniform in [17, 513],
+    two sweeps, plain smoothing) through one batched handle, as the benchmark
+    runs it, against the oracle's run of every mesh alone
+    (tests/golden/make_batch256.py): the summed op counts, and each mesh's
+    final topology, tags and coordinates."""
+    import json
+    import os
+    from paper_1505_04694_amd import pmesh
+    from tests.golden.make_batch256 import COUNT, SEED, SWEEPS, summary
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch256.json")))
+    mis = inputs.config3(COUNT, SEED)
+    assert [mi.n for mi in mis] == [m["n"] for m in gold["meshes"]]
+    gb = pmesh.Batch.from_inputs(mis, seed=SEED)
+    ops = 0
+    for s in range(SWEEPS):
+        tr = gb.sweep(s)
+        ops += sum(st["coloured"] + st["evaluated"] + st["edges"] for st in tr.values())
+    assert ops == sum(m["ops"] for m in gold["meshes"])
+    for i, m in enumerate(gold["meshes"]):
+        got, want = summary(gb.export_mesh(i)), m["final"]
+        for k in ("V", "T", "tri", "tags"):
+            assert got[k] == want[k], f"mesh {i} (n = {m['n']}): {k}"
+        if got["xy"] != want["xy"]:
+            assert abs(got["xy_sum"] - want["xy_sum"]) <= 1e-12 * abs(want["xy_sum"]), f"mesh {i}: coordinates"
+    gb.close()
