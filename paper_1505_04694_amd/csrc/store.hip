@@ -97,7 +97,10 @@ __global__ void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, 
 int scan_partials_needed(int n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
 
 // short arrays: one block of 1024 threads, each scanning a contiguous piece
-constexpr int kScanSingle = 65536;
+// of at most eight entries (its loads are serial, two passes: longer pieces
+// made a 65536-entry scan take 100 us, against a few for the three-kernel
+// form)
+constexpr int kScanSingle = 8192;
 __global__ void __launch_bounds__(1024) k_scan_single(const int* __restrict__ in, int* __restrict__ out, int n,
                                                       int* __restrict__ total) {
   __shared__ int lds[1024 / kWave + 1];
